@@ -1,0 +1,74 @@
+"""Pins for the MLP oracle: finite differences, Adam's closed-form first
+step, and the network's affine regime."""
+import numpy as np
+
+from oracle import mlp
+from paper_1801_01134_amd import synth
+
+
+def _setup(B=12, seed=0):
+    rng = synth.rng_for(500, seed)
+    P = mlp.init_params(rng)
+    X = rng.normal(size=(B, 16))
+    t = np.exp(rng.normal(size=(B, 6)))
+    return P, X, mlp.targets(t)
+
+
+def test_gradients_match_central_differences():
+    P, X, tau = _setup()
+    _, G = mlp.loss_and_grad(P, X, tau)
+    rng = synth.rng_for(501)
+    for name in mlp.PARAM_NAMES:
+        flat = P[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+            w = flat[idx]
+            h = 1e-6 * max(1.0, abs(w))
+            flat[idx] = w + h
+            lp, _ = mlp.loss_and_grad(P, X, tau)
+            flat[idx] = w - h
+            lm, _ = mlp.loss_and_grad(P, X, tau)
+            flat[idx] = w
+            fd = (lp - lm) / (2 * h)
+            g = G[name].reshape(-1)[idx]
+            assert abs(fd - g) <= 1e-6 * max(1e-3, abs(g)) + 1e-9, (name, idx, fd, g)
+
+
+def test_adam_first_step_is_lr_times_sign():
+    P, X, tau = _setup()
+    _, G = mlp.loss_and_grad(P, X, tau)
+    before = {k: v.copy() for k, v in P.items()}
+    opt = mlp.Adam(P, lr=1e-3)
+    opt.step(P, G)
+    for k in P:
+        g = G[k]
+        big = np.abs(g) > 1e-4
+        step = before[k] - P[k]
+        assert np.allclose(step[big], 1e-3 * np.sign(g[big]), rtol=1e-4)
+
+
+def test_affine_regime_equals_matrix_chain():
+    rng = synth.rng_for(502)
+    P = {"W1": rng.uniform(0.1, 1, (64, 16)), "b1": rng.uniform(0.1, 1, 64),
+         "W2": rng.uniform(0.1, 1, (64, 64)), "b2": rng.uniform(0.1, 1, 64),
+         "W3": rng.uniform(-1, 1, (6, 64)), "b3": rng.uniform(-1, 1, 6)}
+    X = rng.uniform(0.1, 1, (5, 16))  # every pre-activation is positive
+    o, _ = mlp.forward(P, X)
+    want = np.zeros((5, 6))
+    for b in range(5):
+        h1 = [sum(P["W1"][i, j] * X[b, j] for j in range(16)) + P["b1"][i] for i in range(64)]
+        h2 = [sum(P["W2"][i, j] * h1[j] for j in range(64)) + P["b2"][i] for i in range(64)]
+        want[b] = [sum(P["W3"][i, j] * h2[j] for j in range(64)) + P["b3"][i] for i in range(6)]
+    assert np.allclose(o, want, rtol=1e-12)
+
+
+def test_targets_and_training_reduces_loss():
+    t = np.array([[2.0, 1.0, 4.0, 1.0, 8.0, 3.0]])
+    assert np.array_equal(mlp.targets(t), np.log2(t / 1.0))
+    rng = synth.rng_for(503)
+    X = rng.normal(size=(256, 16))
+    times = np.exp(0.3 * (X[:, :6] + 0.5 * X[:, 6:12]))  # learnable
+    tau = mlp.targets(times)
+    P = mlp.init_params(rng)
+    order = np.concatenate([rng.permutation(256) for _ in range(30)])
+    P2, losses = mlp.train(P, X, tau, order, batch=32, lr=3e-3)
+    assert np.mean(losses[-10:]) < 0.3 * np.mean(losses[:10])

@@ -1,0 +1,81 @@
+"""Pins for the selection oracle: features against brute force and
+constructed cases, the interpolation fit against known polynomials."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import select as S
+from paper_1801_01134_amd import synth
+
+
+def _brute_features(A):
+    n, m = A.n_rows, A.n_cols
+    lens = [int(A.rowptr[i + 1] - A.rowptr[i]) for i in range(n)]
+    nnz = sum(lens)
+    mean = nnz / n
+    f = [np.log2(n), np.log2(m), np.log2(nnz + 1), mean,
+         (np.sqrt(sum((L - mean) ** 2 for L in lens) / n) / mean) if mean else 0.0,
+         np.log2(1 + max(lens)), sum(1 for L in lens if L == 0) / n]
+    dist = [abs(int(A.colidx[p]) - i) for i in range(n) for p in range(A.rowptr[i], A.rowptr[i + 1])]
+    f.append(sum(dist) / len(dist) / max(n, m))
+    for (r, c) in oracle.SHAPES:
+        nb = 0
+        for t in range((n + r - 1) // r):
+            cols = [int(A.colidx[p]) for i in range(t * r, min(n, t * r + r))
+                    for p in range(A.rowptr[i], A.rowptr[i + 1])]
+            nb += oracle.min_cover_bruteforce(cols, c)
+        f.append(nnz / nb)
+    return np.array(f)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_features_against_bruteforce(seed):
+    A = synth.random_small(11, 19, 0.25, seed=seed)
+    if A.nnz == 0:
+        pytest.skip("empty draw")
+    f = S.features(A)
+    assert np.allclose(f[:14], _brute_features(A), rtol=1e-12, atol=1e-12)
+
+
+def test_single_value_block_share_constructed():
+    # entries 8 apart: every beta(1,8) block holds one value
+    a = np.zeros((4, 64))
+    a[:, ::8] = 1.0
+    assert S.features(synth.from_dense(a))[14] == 1.0
+    # dense rows: no single-value block
+    assert S.features(synth.from_dense(np.ones((3, 16))))[14] == 0.0
+    # row 0: one full block + one single; row 1: two singles -> 3 of 4 blocks
+    b = np.zeros((2, 32))
+    b[0, 0:8] = 1
+    b[0, 20] = 1
+    b[1, 3] = 1
+    b[1, 30] = 1
+    assert S.features(synth.from_dense(b))[14] == 0.75
+    # span feature: contiguous rows span exactly their length -> log2(1) = 0
+    assert S.features(synth.from_dense(np.ones((3, 16))))[15] == 0.0
+
+
+def test_interpolation_recovers_known_cubic():
+    rng = synth.rng_for(3)
+    avgs = rng.uniform(1, 30, size=(40, 6))
+    true = [np.array([0.001 * k, -0.03, 0.4 + 0.1 * k, 1.0 + k]) for k in range(6)]
+    speeds = np.stack([np.polyval(true[k], avgs[:, k]) for k in range(6)], axis=1)
+    model = S.fit_interpolation(avgs, speeds, degree=3)
+    for k in range(6):
+        assert np.allclose(model.coeffs[k], true[k], rtol=1e-8, atol=1e-10)
+    q = np.array([5.0, 6, 7, 8, 9, 10])
+    pred = model.predict(q)
+    assert np.allclose(pred, [np.polyval(true[k], q[k]) for k in range(6)])
+    assert model.select(q) == int(np.argmax(pred))
+    # outside the fitted range the prediction is held at the range edge
+    far = np.full(6, 1e6)
+    assert np.allclose(model.predict(far), [np.polyval(true[k], avgs[:, k].max()) for k in range(6)])
+
+
+def test_select_ties_take_lowest_index_and_regret():
+    m = S.Interpolation([np.array([1.0])] * 6, np.zeros(6), np.ones(6), 0)
+    assert m.select(np.zeros(6)) == 0
+    t = np.array([2.0, 1.0, 1.5, 4.0, 1.0, 3.0])
+    assert S.best_kernel(t) == 1
+    assert S.regret(t, 1) == 0.0 and S.regret(t, 4) == 0.0
+    assert S.regret(t, 0) == pytest.approx(1.0)
