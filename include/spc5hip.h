@@ -1,0 +1,169 @@
+/*
+ * spc5hip.h -- C ABI of the gfx950 (MI355X) library for the mask-block sparse
+ * matrix-vector product of Bramas & Kus, "Computing the sparse matrix vector
+ * product using block-based kernels without zero padding on processors with
+ * AVX-512 instructions" (PeerJ Computer Science, 2018).
+ *
+ * Storage format beta(r,c) (Design, "Block-based storage without zero
+ * padding", Eq. (1)): the matrix is cut into row intervals of r consecutive
+ * rows; each interval is covered by r x c blocks that start at row t*r and at
+ * any column. Per block the format keeps its left column and an r*c-bit mask;
+ * the values are packed in block order, row-major inside a block, with no
+ * padding. Supported shapes: (1,8) (2,4) (2,8) (4,4) (4,8) (8,4).
+ *
+ * Conventions for every entry point
+ *   - Return value: SPC_OK (0) or a negative spc_status. No C++ exception
+ *     crosses the ABI. spc_status_string() names a code; spc_last_error()
+ *     gives the detail of the most recent failure in the calling thread.
+ *   - Pointers are device pointers unless marked "host". They are owned by
+ *     the caller and never freed or retained by the library, except that a
+ *     plan (spc_plan, spc_batch) keeps the view it was built from: the caller
+ *     keeps those arrays alive and unchanged while the plan is used.
+ *   - Work is enqueued on the given HIP stream (NULL = default stream) and
+ *     returns before it completes, unless the entry point says it
+ *     synchronizes. Argument checks happen on the host before any launch.
+ *   - Library-owned objects (plans, batches, selectors) are created by
+ *     *_create and released by *_destroy.
+ *   - Index types: int32 row pointers and column indices, as the paper's
+ *     kernel uses (S_integer = 4 in Eq. (4)); int64 sizes and value offsets.
+ */
+#ifndef SPC5HIP_H
+#define SPC5HIP_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t spc_status;
+#define SPC_OK                       0
+#define SPC_ERR_INVALID_ARG         -1  /* null pointer, negative size, bad flag, misaligned array */
+#define SPC_ERR_UNSUPPORTED_SHAPE   -2  /* (r,c) is not one of the six shapes */
+#define SPC_ERR_CSR_UNSORTED_OR_DUP -3  /* a CSR row has decreasing or repeated columns */
+#define SPC_ERR_INDEX_RANGE         -4  /* column outside [0, n_cols) or row pointers not monotone */
+#define SPC_ERR_OVERFLOW            -5  /* a count does not fit the int32 index type */
+#define SPC_ERR_HIP                 -6  /* a HIP runtime call failed (detail in spc_last_error) */
+#define SPC_ERR_NO_MODEL            -7  /* selector has no trained network; use interpolation */
+#define SPC_ERR_CAPACITY            -8  /* a size exceeds a documented library limit */
+
+typedef enum { SPC_F32 = 0, SPC_F64 = 1 } spc_dtype;
+
+/* Shape indices used by the selector, in the paper's order of the six
+ * optimized kernels (Design, "Optimized kernel implementation"). */
+#define SPC_N_SHAPES 6
+/* 0 = (1,8), 1 = (2,4), 2 = (2,8), 3 = (4,4), 4 = (4,8), 5 = (8,4) */
+
+/* A beta(r,c) matrix as the caller's device arrays (a view; never freed).
+ *   block_rowptr int32[ceil(n_rows/r) + 1]  prefix pointers: the blocks of
+ *                interval t are block_rowptr[t] .. block_rowptr[t+1]-1
+ *                (Algorithm 1 indexes it this way)
+ *   block_colidx int32[n_blocks]  left column of each block (any column;
+ *                a block may reach past n_cols, those bits are zero)
+ *   block_masks  n_blocks masks of r*c bits stored as ceil(r*c/8)-byte
+ *                little-endian words: bit i*c + k set <=> the block holds
+ *                the entry (row t*r + i, column colidx + k). Bit 0 is the
+ *                leftmost column, as in the vexpand example of the
+ *                Vectorization section. The array must be 8-byte aligned and
+ *                readable for spc_mask_bytes(r, c, n_blocks) bytes.
+ *   values       nnz entries of dtype, block order, row-major in a block */
+typedef struct spc_beta_view {
+    int32_t r, c;
+    int32_t dtype;          /* spc_dtype */
+    int32_t reserved;
+    int64_t n_rows, n_cols, nnz, n_blocks;
+    const int32_t *block_rowptr;
+    const int32_t *block_colidx;
+    const void    *block_masks;
+    const void    *values;
+} spc_beta_view;
+
+const char *spc_status_string(spc_status s);
+const char *spc_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t spc_version(void);
+
+/* Shape index 0..5 of (r,c), or SPC_ERR_UNSUPPORTED_SHAPE. */
+spc_status spc_shape_index(int32_t r, int32_t c);
+
+/* Bytes the masks array of n_blocks blocks must span: n_blocks*r*c/8
+ * rounded up to a multiple of 8. Returns -1 for an unsupported shape. */
+int64_t spc_mask_bytes(int32_t r, int32_t c, int64_t n_blocks);
+
+/* ---------------------------------------------------------------------------
+ * Conversion CSR -> beta(r,c), on the device, in two calls so that the
+ * caller can size the output arrays (storage section; the paper gives only
+ * the format, so blocks are placed by the greedy leftmost cover: in each
+ * interval the next block starts at the smallest column not yet covered,
+ * which uses the fewest blocks).
+ *
+ * spc_beta_count: checks the CSR arrays (rowptr int32[n_rows+1] monotone from
+ *   0, colidx int32[rowptr[n_rows]] strictly increasing inside each row and
+ *   inside [0, n_cols)), counts the blocks of every interval and writes
+ *   block_rowptr_out int32[ceil(n_rows/r)+1] as prefix pointers. Stores the
+ *   block total in *n_blocks_out (host). Synchronizes the stream. Errors:
+ *   SPC_ERR_CSR_UNSORTED_OR_DUP, SPC_ERR_INDEX_RANGE, SPC_ERR_OVERFLOW (more
+ *   than 2^31-1 blocks), SPC_ERR_UNSUPPORTED_SHAPE, SPC_ERR_INVALID_ARG.
+ *   n_rows == 0 writes block_rowptr_out[0] = 0 and returns 0 blocks.
+ *
+ * spc_csr_to_beta: fills block_colidx_out[n_blocks], block_masks_out
+ *   (spc_mask_bytes bytes, padding zeroed) and values_out[nnz] (values are
+ *   moved bit for bit; for r = 1 they keep the CSR order, as the paper notes)
+ *   from the same CSR arrays and the block_rowptr of spc_beta_count.
+ *   Asynchronous. */
+spc_status spc_beta_count(int32_t r, int32_t c, int64_t n_rows, int64_t n_cols,
+                          const int32_t *rowptr, const int32_t *colidx,
+                          int32_t *block_rowptr_out, int64_t *n_blocks_out,
+                          hipStream_t stream);
+spc_status spc_csr_to_beta(int32_t r, int32_t c, int32_t dtype, int64_t n_rows, int64_t n_cols,
+                           const int32_t *rowptr, const int32_t *colidx, const void *values,
+                           const int32_t *block_rowptr, int32_t *block_colidx_out,
+                           void *block_masks_out, void *values_out, hipStream_t stream);
+
+/* beta(r,c) -> CSR on the device: rowptr_out int32[n_rows+1],
+ * colidx_out int32[nnz], values_out[nnz] (bitwise). Synchronizes. */
+spc_status spc_beta_to_csr(const spc_beta_view *A, int32_t *rowptr_out, int32_t *colidx_out,
+                           void *values_out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Plans: the row-interval partition the kernels run on (Design,
+ * "Parallelization": consecutive intervals grouped so that groups hold about
+ * the same number of blocks and no interval is split). A tile is one such
+ * group, processed by one workgroup; an interval with more blocks than a
+ * tile holds becomes a tile of its own. Creating a plan reads block_rowptr
+ * and the masks once and synchronizes the stream.
+ *   tile_bits  mask bits a tile may hold (blocks * r * c); 0 = default 2048;
+ *              one of 1024, 2048, 3072, 4032
+ *   xcd_remap  0 or 1 = give each of the 8 XCDs one contiguous range of
+ *              tiles (0 is the default), 2 = hardware round-robin order
+ * params == NULL (or all zeros) selects the defaults. */
+typedef struct spc_plan spc_plan;
+typedef struct spc_plan_params {
+    int32_t tile_bits;
+    int32_t xcd_remap;
+    int32_t reserved[6];
+} spc_plan_params;
+
+spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,
+                           spc_plan **plan_out, hipStream_t stream);
+spc_status spc_plan_destroy(spc_plan *plan);
+/* n_tiles, tiles taking the long-interval path, tile_bits actually used. */
+spc_status spc_plan_info(const spc_plan *plan, int64_t *n_tiles, int64_t *n_long,
+                         int32_t *tile_bits);
+
+/* ---------------------------------------------------------------------------
+ * y = A x (accumulate = 0) or y += A x (accumulate = 1; Algorithm 1 adds the
+ * row sums into y). x: n_cols entries, y: n_rows entries, both of A's dtype.
+ * Only stored entries touch y (an Inf or NaN in x under an unset mask bit
+ * does not reach y). Rows with no entries get +0 when accumulate = 0.
+ * Summation is in double precision for both dtypes, in an order fixed by
+ * the plan, so repeated calls give identical bits. plan must come from
+ * spc_plan_create on this same A. Asynchronous. */
+spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan, const void *x, void *y,
+                         int32_t accumulate, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPC5HIP_H */

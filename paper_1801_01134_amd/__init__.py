@@ -1,0 +1,10 @@
+"""MI355X (gfx950) library for the mask-block sparse matrix-vector product of
+Bramas & Kus (beta(r,c) storage without zero padding).
+
+The compute lives in libspc5hip.so (HIP kernels behind a C ABI declared in
+include/spc5hip.h); this package is its Python binding plus the seeded input
+generators in ``synth``.
+"""
+from . import synth  # noqa: F401
+from ._binding import (SHAPES, BetaMatrix, Plan, SpcError, beta_to_csr, csr_to_beta,  # noqa: F401
+                       lib, mask_bytes, spmv)

@@ -1,0 +1,251 @@
+"""ctypes binding of libspc5hip.so. Argument marshalling only: every step of
+conversion, planning and the products runs in the library's HIP kernels;
+torch tensors only carry device memory, and torch's current stream is the
+stream the library enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_int32, c_int64, c_void_p
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libspc5hip.so")
+SHAPES = ((1, 8), (2, 4), (2, 8), (4, 4), (4, 8), (8, 4))
+F32, F64 = 0, 1
+
+
+class SpcError(RuntimeError):
+    def __init__(self, code: int, name: str, detail: str):
+        super().__init__(f"{name} ({code}): {detail}")
+        self.code = code
+        self.name = name
+
+
+class BetaView(ctypes.Structure):
+    _fields_ = [("r", c_int32), ("c", c_int32), ("dtype", c_int32), ("reserved", c_int32),
+                ("n_rows", c_int64), ("n_cols", c_int64), ("nnz", c_int64), ("n_blocks", c_int64),
+                ("block_rowptr", c_void_p), ("block_colidx", c_void_p),
+                ("block_masks", c_void_p), ("values", c_void_p)]
+
+
+class PlanParams(ctypes.Structure):
+    _fields_ = [("tile_bits", c_int32), ("xcd_remap", c_int32), ("reserved", c_int32 * 6)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "spc_status_string": (c_char_p, [c_int32]),
+    "spc_last_error": (c_char_p, []),
+    "spc_version": (c_int32, []),
+    "spc_shape_index": (c_int32, [c_int32, c_int32]),
+    "spc_mask_bytes": (c_int64, [c_int32, c_int32, c_int64]),
+    "spc_beta_count": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
+                                 POINTER(c_int64), c_void_p]),
+    "spc_csr_to_beta": (c_int32, [c_int32, c_int32, c_int32, c_int64, c_int64, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "spc_beta_to_csr": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "spc_plan_create": (c_int32, [POINTER(BetaView), POINTER(PlanParams), POINTER(c_void_p), c_void_p]),
+    "spc_plan_destroy": (c_int32, [c_void_p]),
+    "spc_plan_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
+    "spc_spmv_beta": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1801_01134_amd.build` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def register(name: str, restype, argtypes):
+    """Declare the signature of a further entry point (used by sibling modules)."""
+    _SIGS[name] = (restype, argtypes)
+    if _lib is not None:
+        f = getattr(_lib, name)
+        f.restype = restype
+        f.argtypes = argtypes
+
+
+def check(status: int):
+    if status != 0:
+        L = lib()
+        raise SpcError(status, L.spc_status_string(status).decode(), L.spc_last_error().decode())
+
+
+def stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _dtype_code(dt) -> int:
+    if dt == torch.float64:
+        return F64
+    if dt == torch.float32:
+        return F32
+    raise TypeError(f"unsupported value dtype {dt}")
+
+
+def _dev(a, dtype=None, device="cuda"):
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device)
+        if dtype is not None:
+            t = t.to(dtype)
+        return t.contiguous()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device).contiguous()
+
+
+def mask_bytes(r: int, c: int, n_blocks: int) -> int:
+    return int(lib().spc_mask_bytes(r, c, n_blocks))
+
+
+class Plan:
+    """A tile plan (library-owned) for one BetaMatrix."""
+
+    def __init__(self, A: "BetaMatrix", tile_bits: int = 0, xcd_remap: int = 0):
+        self._A = A
+        self._view = A.view()
+        p = PlanParams(tile_bits, xcd_remap)
+        h = c_void_p()
+        check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
+                                    stream_ptr()))
+        self.handle = h
+
+    def info(self) -> dict:
+        nt, nl, tb = c_int64(), c_int64(), c_int32()
+        check(lib().spc_plan_info(self.handle, ctypes.byref(nt), ctypes.byref(nl), ctypes.byref(tb)))
+        return {"n_tiles": nt.value, "n_long": nl.value, "tile_bits": tb.value}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.spc_plan_destroy(h)
+            self.handle = None
+
+
+class BetaMatrix:
+    """A beta(r,c) matrix in device tensors (the arrays of the storage format)."""
+
+    def __init__(self, r, c, n_rows, n_cols, block_rowptr, block_colidx, block_masks, values):
+        self.r, self.c = int(r), int(c)
+        self.n_rows, self.n_cols = int(n_rows), int(n_cols)
+        self.block_rowptr = block_rowptr
+        self.block_colidx = block_colidx
+        self.block_masks = block_masks
+        self.values = values
+        self._plans = {}
+
+    @property
+    def dtype(self):
+        return self.values.dtype
+
+    @property
+    def nnz(self) -> int:
+        return int(self.values.numel())
+
+    @property
+    def n_blocks(self) -> int:
+        return int(self.block_colidx.numel())
+
+    @property
+    def shape_index(self) -> int:
+        return SHAPES.index((self.r, self.c))
+
+    def view(self) -> BetaView:
+        return BetaView(self.r, self.c, _dtype_code(self.values.dtype), 0, self.n_rows, self.n_cols,
+                        self.nnz, self.n_blocks, self.block_rowptr.data_ptr(),
+                        self.block_colidx.data_ptr() if self.n_blocks else None,
+                        self.block_masks.data_ptr() if self.n_blocks else None,
+                        self.values.data_ptr() if self.nnz else None)
+
+    def plan(self, tile_bits: int = 0, xcd_remap: int = 0) -> Plan:
+        key = (tile_bits, xcd_remap)
+        if key not in self._plans:
+            self._plans[key] = Plan(self, tile_bits, xcd_remap)
+        return self._plans[key]
+
+    def nbytes(self) -> int:
+        """Bytes of the four arrays as Eq. (1) counts them (masks unpadded)."""
+        return (self.values.numel() * self.values.element_size() + self.block_rowptr.numel() * 4
+                + self.block_colidx.numel() * 4 + self.n_blocks * self.r * self.c // 8)
+
+
+def csr_to_beta(r: int, c: int, rowptr, colidx, values, n_cols: int, dtype=None,
+                device="cuda") -> BetaMatrix:
+    """CSR (numpy arrays or tensors) -> BetaMatrix on the device."""
+    if (r, c) not in SHAPES:
+        raise SpcError(-2, "SPC_ERR_UNSUPPORTED_SHAPE", f"({r},{c})")
+    rp = _dev(rowptr, torch.int32, device)
+    ci = _dev(colidx, torch.int32, device)
+    v = _dev(values, dtype, device)
+    if ci.numel() == 0:  # the library wants valid pointers even when nothing is read
+        ci = torch.zeros(1, dtype=torch.int32, device=device)
+    n_rows = rp.numel() - 1
+    n_int = (n_rows + r - 1) // r
+    L = lib()
+    s = stream_ptr()
+    brow = torch.empty(n_int + 1, dtype=torch.int32, device=device)
+    nb = c_int64()
+    check(L.spc_beta_count(r, c, n_rows, n_cols, _ptr(rp), _ptr(ci), _ptr(brow), ctypes.byref(nb), s))
+    nb = nb.value
+    bcol = torch.empty(nb, dtype=torch.int32, device=device)
+    mb = mask_bytes(r, c, nb)
+    masks = (torch.empty(mb, dtype=torch.uint8, device=device) if mb
+             else torch.zeros(8, dtype=torch.uint8, device=device))
+    vout = torch.empty_like(v)
+    vin = v if v.numel() else torch.zeros(1, dtype=v.dtype, device=device)
+    bcol_p = bcol if nb else torch.zeros(1, dtype=torch.int32, device=device)
+    vout_p = vout if v.numel() else torch.zeros(1, dtype=v.dtype, device=device)
+    check(L.spc_csr_to_beta(r, c, _dtype_code(v.dtype), n_rows, n_cols, _ptr(rp), _ptr(ci),
+                            _ptr(vin), _ptr(brow), _ptr(bcol_p), _ptr(masks), _ptr(vout_p), s))
+    return BetaMatrix(r, c, n_rows, n_cols, brow, bcol, masks, vout)
+
+
+def beta_to_csr(A: BetaMatrix):
+    """BetaMatrix -> (rowptr, colidx, values) device tensors."""
+    rp = torch.empty(A.n_rows + 1, dtype=torch.int32, device=A.values.device)
+    ci = torch.empty(A.nnz, dtype=torch.int32, device=A.values.device)
+    v = torch.empty_like(A.values)
+    view = A.view()
+    check(lib().spc_beta_to_csr(ctypes.byref(view), _ptr(rp), _ptr(ci) if A.nnz else None,
+                                _ptr(v) if A.nnz else None, stream_ptr()))
+    return rp, ci, v
+
+
+def spmv(A: BetaMatrix, x: torch.Tensor, y: torch.Tensor | None = None, accumulate: bool = False,
+         plan: Plan | None = None) -> torch.Tensor:
+    """y = A x (or y += A x) on the device, in A's value type."""
+    if x.dtype != A.dtype or x.numel() != A.n_cols or not x.is_contiguous():
+        raise ValueError("x must be a contiguous vector of n_cols entries of A's dtype")
+    if y is None:
+        if accumulate:
+            raise ValueError("accumulate needs y")
+        y = torch.empty(A.n_rows, dtype=A.dtype, device=x.device)
+    elif y.dtype != A.dtype or y.numel() != A.n_rows or not y.is_contiguous():
+        raise ValueError("y must be a contiguous vector of n_rows entries of A's dtype")
+    plan = plan or A.plan()
+    view = plan._view
+    check(lib().spc_spmv_beta(ctypes.byref(view), plan.handle, _ptr(x), _ptr(y), int(accumulate),
+                              stream_ptr()))
+    return y

@@ -1,0 +1,118 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <type_traits>
+
+#include "spc5hip.h"
+
+namespace spc {
+
+// ---------------------------------------------------------------------------
+// Error reporting: a thread-local message behind spc_last_error().
+void set_error(const char *fmt, ...);
+spc_status hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define SPC_HIP(call)                                                            \
+    do {                                                                         \
+        hipError_t e_ = (call);                                                  \
+        if (e_ != hipSuccess) return ::spc::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define SPC_REQUIRE(cond, code, ...)        \
+    do {                                    \
+        if (!(cond)) {                      \
+            ::spc::set_error(__VA_ARGS__);  \
+            return (code);                  \
+        }                                   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Block shapes. Index order follows the paper's list of optimized kernels.
+constexpr int kShapeR[SPC_N_SHAPES] = {1, 2, 2, 4, 4, 8};
+constexpr int kShapeC[SPC_N_SHAPES] = {8, 4, 8, 4, 8, 4};
+
+inline int shape_of(int r, int c) {
+    for (int s = 0; s < SPC_N_SHAPES; ++s)
+        if (kShapeR[s] == r && kShapeC[s] == c) return s;
+    return -1;
+}
+
+template <int R_, int C_>
+struct Shape {
+    static constexpr int R = R_;
+    static constexpr int C = C_;
+    static constexpr int RC = R_ * C_;          // mask bits per block: 8, 16 or 32
+    static constexpr int BPW = 64 / RC;         // blocks per 64-bit mask word
+    static constexpr int MB = RC / 8;           // mask bytes per block
+    static constexpr uint32_t RCMASK = (RC == 32) ? 0xffffffffu : ((1u << RC) - 1u);
+    static constexpr uint32_t CMASK = (1u << C_) - 1u;
+};
+
+// Calls f(Shape<r,c>{}) for a runtime shape index.
+template <class F>
+inline auto with_shape(int s, F &&f) {
+    switch (s) {
+    case 0: return f(Shape<1, 8>{});
+    case 1: return f(Shape<2, 4>{});
+    case 2: return f(Shape<2, 8>{});
+    case 3: return f(Shape<4, 4>{});
+    case 4: return f(Shape<4, 8>{});
+    default: return f(Shape<8, 4>{});
+    }
+}
+
+template <class F>
+inline auto with_dtype(int dtype, F &&f) {
+    if (dtype == SPC_F64) return f(double{});
+    return f(float{});
+}
+
+inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Tile of a plan: the intervals [i0, i1) and the packed-value offset of the
+// tile's first block. 16 bytes, read with one scalar load per workgroup.
+struct TileDesc {
+    int64_t vbase;
+    int32_t i0;
+    int32_t i1;
+};
+
+// Validation of a view on the host.
+spc_status check_view(const spc_beta_view *A);
+
+// Exclusive prefix sum of n int32 counts into out[0..n] (int64), on stream.
+// temp must hold scan_temp_elems(n) int64. Asynchronous.
+int64_t scan_temp_elems(int64_t n);
+spc_status scan_counts_i64(const int32_t *counts, int64_t n, int64_t *out, int64_t *temp,
+                           hipStream_t stream);
+// Same, from int64 counts.
+spc_status scan_counts64_i64(const int64_t *counts, int64_t n, int64_t *out, int64_t *temp,
+                             hipStream_t stream);
+
+// Small RAII holder for device scratch used by setup routines (conversion,
+// plan creation); the SpMV entry points allocate nothing.
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 16); }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace spc
+
+struct spc_plan {
+    spc_beta_view A;
+    int shape;
+    int tile_bits;
+    int xcd_remap;
+    int device;
+    int64_t n_tiles;
+    int64_t n_long;
+    spc::TileDesc *d_tiles;
+};

@@ -1,0 +1,362 @@
+// y = A x over beta(r,c) on gfx950.
+//
+// The paper's kernel (Algorithm 1, Code 1) walks blocks one by one and
+// expands each block's packed values into a SIMD register with vexpand. The
+// GPU version keeps the idea -- a mask says which lanes receive the next
+// packed values -- at wavefront width: the masks of 64 / (r*c) consecutive
+// blocks form one 64-bit word, and lane l of a wavefront owns bit l of that
+// word. The word itself is the execution mask, the rank of a set bit among
+// the set bits below it (v_mbcnt) is the lane's offset into the packed
+// values, and popcount(word) advances the value cursor, so one wavefront step
+// is one vexpand over 64 mask bits, with contiguous (coalesced) value loads
+// and no padding anywhere.
+//
+// Work is split into tiles of whole row intervals (the paper's static
+// partition: consecutive intervals, about equal block counts, an interval is
+// never split). One workgroup of W wavefronts runs one tile:
+//   A. every wavefront loads the tile's mask words (<= 64), clears bits of
+//      blocks outside the tile and scans their popcounts, so each word's
+//      value offset is known without a sequential cursor;
+//   B. the wavefronts share the words; each active lane multiplies its value
+//      by x[colidx + k] and stores the product in LDS at the value's packed
+//      position (compact, in value order);
+//   C. one thread per (interval, block row) adds its products: for r = 1 the
+//      row's products are one contiguous LDS range; for r > 1 the thread
+//      walks the interval's masks and takes its row's c-bit slice of each.
+// Row sums are formed in double precision for both value types and written
+// once per row (no atomics), so results are deterministic.
+//
+// An interval with more blocks than a tile holds gets a tile of its own and
+// the long path: each lane keeps a running sum for its block row over many
+// words, and the sums of lanes of the same block row are combined at the end.
+#include "common.hpp"
+
+namespace spc {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = kWaves * 64;
+constexpr int kUnroll = 4;
+
+struct SpmvArgs {
+    const int32_t *brow;
+    const int32_t *bcol;
+    const uint64_t *mw;
+    const void *vals;
+    const void *x;
+    void *y;
+    const TileDesc *tiles;
+    int64_t n_rows;
+    int32_t n_tiles;
+    int32_t accumulate;
+    int32_t xcd_remap;
+    int32_t tiles_per_xcd;
+};
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned lane_rank(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Bits of block slots [lo, hi) of a word (slot = RC bits).
+template <int RC>
+__device__ __forceinline__ uint64_t slot_bits(int lo, int hi) {
+    uint64_t upto_hi = (hi * RC >= 64) ? ~0ull : ((1ull << (hi * RC)) - 1ull);
+    uint64_t below_lo = (lo * RC >= 64) ? ~0ull : ((1ull << (lo * RC)) - 1ull);
+    return upto_hi & ~below_lo;
+}
+
+template <class T>
+__device__ __forceinline__ T ldg_nt(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+// Lane l of the calling wavefront gets the tile's word l (global index
+// w0 + l), restricted to blocks [b0, b1).
+template <class Sh>
+__device__ __forceinline__ uint64_t tile_word(const uint64_t *mw, int w0, int nw, int b0, int b1, int l) {
+    if (l >= nw) return 0ull;
+    const int gw = w0 + l;
+    uint64_t m = mw[gw];
+    const int lo = max(b0 - gw * Sh::BPW, 0);
+    const int hi = min(b1 - gw * Sh::BPW, Sh::BPW);
+    return m & slot_bits<Sh::RC>(lo, hi);
+}
+
+// ---------------------------------------------------------------------------
+// Tile of whole intervals whose products fit the LDS buffer (TB values).
+template <class Sh, class T, int TB>
+__device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, int64_t vbase,
+                           uint64_t *s_wm, int *s_off, T *s_prod) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const T *__restrict__ x = static_cast<const T *>(a.x);
+
+    // A. words and their value offsets (every wavefront computes them)
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    const uint64_t wm = tile_word<Sh>(a.mw, w0, nw, b0, b1, lane);
+    const int cnt = __popcll(wm);
+    const int incl = wave_incl_scan(cnt);
+    const int excl = incl - cnt;
+    if (wid == 0) {
+        if (lane < nw) {
+            s_wm[lane] = wm;
+            s_off[lane] = excl;
+        }
+        if (lane == 0) {
+            s_wm[nw] = 0ull;
+            s_off[nw] = nw > 0 ? __builtin_amdgcn_readlane(incl, nw - 1) : 0;
+        }
+    }
+
+    // B. products, lane = mask bit
+    {
+        const int slot = lane / Sh::RC;
+        const int kcol = (lane % Sh::RC) % Sh::C;
+        const int k0 = (nw * wid) / kWaves, k1 = (nw * (wid + 1)) / kWaves;
+        for (int i = k0; i < k1; i += kUnroll) {
+            uint64_t M[kUnroll];
+            int off[kUnroll];
+            unsigned rk[kUnroll];
+            bool act[kUnroll];
+            int col[kUnroll];
+            T v[kUnroll], xv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const bool in = (i + u) < k1;
+                M[u] = in ? readlane64(wm, i + u) : 0ull;
+                off[u] = in ? __builtin_amdgcn_readlane(excl, i + u) : 0;
+                act[u] = (M[u] >> lane) & 1ull;
+                rk[u] = lane_rank(M[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (act[u]) {
+                    col[u] = ldg_nt(a.bcol + (int64_t)(w0 + i + u) * Sh::BPW + slot) + kcol;
+                    v[u] = ldg_nt(vals + vbase + off[u] + rk[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (act[u]) xv[u] = x[col[u]];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (act[u]) s_prod[off[u] + rk[u]] = v[u] * xv[u];
+        }
+    }
+    __syncthreads();
+
+    // C. one thread per (interval, block row)
+    T *__restrict__ y = static_cast<T *>(a.y);
+    const int npairs = (i1 - i0) * Sh::R;
+    for (int p = threadIdx.x; p < npairs; p += kThreads) {
+        const int I = i0 + p / Sh::R;
+        const int rho = p % Sh::R;
+        const int bs = a.brow[I], be = a.brow[I + 1];
+        double acc = 0.0;
+        bool any = false;  // the row has stored entries
+        if (bs < be) {
+            int wi = bs / Sh::BPW - w0;
+            int bit = (bs % Sh::BPW) * Sh::RC;
+            int vpos = s_off[wi] + __popcll(s_wm[wi] & ((1ull << bit) - 1ull));
+            if (Sh::R == 1) {
+                const int we = be / Sh::BPW - w0;
+                const int be_bit = (be % Sh::BPW) * Sh::RC;
+                const int vend = s_off[we] + __popcll(s_wm[we] & ((1ull << be_bit) - 1ull));
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = vpos;
+                for (; k + 4 <= vend; k += 4) {
+                    a0 += (double)s_prod[k];
+                    a1 += (double)s_prod[k + 1];
+                    a2 += (double)s_prod[k + 2];
+                    a3 += (double)s_prod[k + 3];
+                }
+                for (; k < vend; ++k) a0 += (double)s_prod[k];
+                acc = (a0 + a1) + (a2 + a3);
+                any = vend > vpos;
+            } else {
+                double a0 = 0.0, a1 = 0.0;
+                const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
+                for (int b = bs; b < be; ++b) {
+                    const uint32_t m = (uint32_t)(s_wm[wi] >> bit) & Sh::RCMASK;
+                    const uint32_t sub = (m >> (rho * Sh::C)) & Sh::CMASK;
+                    const int pos = vpos + __popc(m & below);
+                    const int n = __popc(sub);
+                    any |= n > 0;
+                    double part = 0.0;
+                    for (int k = 0; k < n; ++k) part += (double)s_prod[pos + k];
+                    if (b & 1) a1 += part; else a0 += part;
+                    vpos += __popc(m);
+                    bit += Sh::RC;
+                    if (bit == 64) {
+                        bit = 0;
+                        ++wi;
+                    }
+                }
+                acc = a0 + a1;
+            }
+        }
+        const int64_t row = (int64_t)I * Sh::R + rho;
+        if (row < a.n_rows) {
+            // accumulate: a row without entries is left untouched, as the
+            // paper's kernel skips empty intervals
+            if (a.accumulate) {
+                if (any) y[row] = (T)(acc + (double)y[row]);
+            } else {
+                y[row] = (T)acc;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One interval with more blocks than a tile holds.
+template <class Sh, class T>
+__device__ void tile_long(const SpmvArgs &a, int I, int b0, int b1, int64_t vbase, double *s_red) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const T *__restrict__ x = static_cast<const T *>(a.x);
+    const int slot = lane / Sh::RC;
+    const int kcol = (lane % Sh::RC) % Sh::C;
+    const int w0 = b0 / Sh::BPW;
+    const int nwt = (b1 - 1) / Sh::BPW - w0 + 1;
+    double acc0 = 0.0, acc1 = 0.0;
+    int64_t vrun = vbase;
+    for (int k = 0; k < nwt; k += 64) {
+        const int nw = min(64, nwt - k);
+        const uint64_t wm = tile_word<Sh>(a.mw, w0 + k, nw, b0, b1, lane);
+        const int cnt = __popcll(wm);
+        const int incl = wave_incl_scan(cnt);
+        const int excl = incl - cnt;
+        for (int i = wid; i < nw; i += kWaves * kUnroll) {
+            uint64_t M[kUnroll];
+            int off[kUnroll];
+            unsigned rk[kUnroll];
+            bool act[kUnroll];
+            int col[kUnroll];
+            T v[kUnroll], xv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int ii = i + u * kWaves;
+                const bool in = ii < nw;
+                M[u] = in ? readlane64(wm, ii) : 0ull;
+                off[u] = in ? __builtin_amdgcn_readlane(excl, ii) : 0;
+                act[u] = (M[u] >> lane) & 1ull;
+                rk[u] = lane_rank(M[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (act[u]) {
+                    col[u] = ldg_nt(a.bcol + (int64_t)(w0 + k + i + u * kWaves) * Sh::BPW + slot) + kcol;
+                    v[u] = ldg_nt(vals + vrun + off[u] + rk[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (act[u]) xv[u] = x[col[u]];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (act[u]) {
+                    if (u & 1) acc1 = __builtin_fma((double)v[u], (double)xv[u], acc1);
+                    else acc0 = __builtin_fma((double)v[u], (double)xv[u], acc0);
+                }
+            }
+        }
+        vrun += __builtin_amdgcn_readlane(incl, nw - 1);
+    }
+    double acc = acc0 + acc1;
+    // lanes of one block row: same (lane % RC) / C; add over column and slot bits
+#pragma unroll
+    for (int m = 1; m < Sh::C; m <<= 1) acc += __shfl_xor(acc, m, 64);
+#pragma unroll
+    for (int m = Sh::RC; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane < Sh::RC && (lane % Sh::C) == 0) s_red[wid * Sh::R + lane / Sh::C] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < Sh::R) {
+        const int rho = threadIdx.x;
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += s_red[w * Sh::R + rho];
+        const int64_t row = (int64_t)I * Sh::R + rho;
+        if (row < a.n_rows) {
+            T *__restrict__ y = static_cast<T *>(a.y);
+            if (a.accumulate) s += (double)y[row];
+            y[row] = (T)s;
+        }
+    }
+}
+
+template <int R, int C, class T, int TB>
+__global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    static_assert(TB / 64 + 1 <= 64, "a tile must fit 64 mask words");
+    __shared__ uint64_t s_wm[TB / 64 + 2];
+    __shared__ int s_off[TB / 64 + 2];
+    __shared__ T s_prod[TB];
+    __shared__ double s_red[kWaves * 8];
+    int t = blockIdx.x;
+    if (a.xcd_remap) t = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    const int b0 = a.brow[d.i0], b1 = a.brow[d.i1];
+    if (b1 - b0 > TB / Sh::RC) tile_long<Sh, T>(a, d.i0, b0, b1, d.vbase, s_red);
+    else tile_short<Sh, T, TB>(a, d.i0, d.i1, b0, b1, d.vbase, s_wm, s_off, s_prod);
+}
+
+template <int R, int C, class T>
+spc_status launch_tb(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    switch (tb) {
+    case 1024: hipLaunchKernelGGL((k_spmv<R, C, T, 1024>), grid, dim3(kThreads), 0, stream, a); break;
+    case 2048: hipLaunchKernelGGL((k_spmv<R, C, T, 2048>), grid, dim3(kThreads), 0, stream, a); break;
+    case 3072: hipLaunchKernelGGL((k_spmv<R, C, T, 3072>), grid, dim3(kThreads), 0, stream, a); break;
+    default: hipLaunchKernelGGL((k_spmv<R, C, T, 4032>), grid, dim3(kThreads), 0, stream, a); break;
+    }
+    SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
+}  // namespace
+
+int spmv_max_intervals_per_tile(int r) { return kThreads / r; }
+
+spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x, void *y, int accumulate,
+                       hipStream_t stream) {
+    SpmvArgs a;
+    a.brow = A->block_rowptr;
+    a.bcol = A->block_colidx;
+    a.mw = static_cast<const uint64_t *>(A->block_masks);
+    a.vals = A->values;
+    a.x = x;
+    a.y = y;
+    a.tiles = P->d_tiles;
+    a.n_rows = A->n_rows;
+    a.n_tiles = (int32_t)P->n_tiles;
+    a.accumulate = accumulate;
+    a.xcd_remap = P->xcd_remap;
+    a.tiles_per_xcd = (int32_t)div_up(P->n_tiles, 8);
+    dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)P->n_tiles);
+    return with_shape(P->shape, [&](auto sh) {
+        using Sh = decltype(sh);
+        return with_dtype(A->dtype, [&](auto tv) {
+            using T = decltype(tv);
+            return launch_tb<Sh::R, Sh::C, T>(P->tile_bits, grid, a, stream);
+        });
+    });
+}
+
+}  // namespace spc

@@ -1,0 +1,67 @@
+"""CPU-side checks of the C ABI: every declared symbol is exported, and the
+host-only helpers and argument checks behave as documented (no GPU calls)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_1801_01134_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DECL = re.compile(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\*?\s*(spc_\w+)\s*\(", re.M)
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        with open(h) as f:
+            names |= set(DECL.findall(f.read()))
+    return sorted(names)
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for must in ("spc_beta_count", "spc_csr_to_beta", "spc_beta_to_csr", "spc_plan_create",
+                 "spc_spmv_beta"):
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_symbols())
+def test_symbol_exported(name):
+    L = B.lib()
+    assert hasattr(L, name), f"{name} declared in include/ but not exported"
+
+
+def test_host_helpers():
+    L = B.lib()
+    assert L.spc_status_string(0) == b"SPC_OK"
+    assert L.spc_status_string(-2) == b"SPC_ERR_UNSUPPORTED_SHAPE"
+    assert [L.spc_shape_index(r, c) for r, c in B.SHAPES] == list(range(6))
+    assert L.spc_shape_index(3, 3) == -2
+    assert L.spc_mask_bytes(1, 8, 1) == 8 and L.spc_mask_bytes(1, 8, 8) == 8
+    assert L.spc_mask_bytes(1, 8, 9) == 16
+    assert L.spc_mask_bytes(4, 8, 3) == 16 and L.spc_mask_bytes(2, 8, 4) == 8
+    assert L.spc_mask_bytes(5, 5, 1) == -1
+    assert L.spc_version() >= 10000
+
+
+def test_argument_errors_before_any_launch():
+    L = B.lib()
+    nb = ctypes.c_int64()
+    # unsupported shape, negative sizes, null outputs: refused on the host
+    assert L.spc_beta_count(3, 3, 4, 4, None, None, None, ctypes.byref(nb), None) == -2
+    assert L.spc_beta_count(1, 8, -1, 4, None, None, None, ctypes.byref(nb), None) == -1
+    assert L.spc_beta_count(1, 8, 4, 4, None, None, None, ctypes.byref(nb), None) == -1
+    assert L.spc_beta_count(1, 8, 1 << 31, 4, None, None, None, ctypes.byref(nb), None) == -5
+    v = B.BetaView(3, 3, 1, 0, 4, 4, 0, 0, None, None, None, None)
+    h = ctypes.c_void_p()
+    assert L.spc_plan_create(ctypes.byref(v), None, ctypes.byref(h), None) == -2
+    v = B.BetaView(1, 8, 7, 0, 4, 4, 0, 0, None, None, None, None)
+    assert L.spc_plan_create(ctypes.byref(v), None, ctypes.byref(h), None) == -1
+    v = B.BetaView(1, 8, 1, 0, 4, 4, 2, 2, 16, 32, 12, 64)   # misaligned masks pointer
+    assert L.spc_plan_create(ctypes.byref(v), None, ctypes.byref(h), None) == -1
+    assert b"aligned" in L.spc_last_error()
+    assert L.spc_spmv_beta(None, None, None, None, 0, None) == -1
+    assert L.spc_plan_destroy(None) == 0

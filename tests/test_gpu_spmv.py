@@ -1,0 +1,221 @@
+"""GPU parity of conversion and SpMV against the CPU oracle.
+
+Bars: conversion and decoding bit-exact; SpMV per row |y - y_ref| <= 1e-13 *
+sum_j |a_ij x_j| (FP64) and <= 2e-6 * sum_j |a_ij x_j| (FP32, with y_ref and
+the bound computed in FP64 from the FP32-rounded inputs); integer-valued
+inputs bit-exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1801_01134_amd as spc
+from paper_1801_01134_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-13, torch.float32: 2e-6}
+NP = {torch.float64: np.float64, torch.float32: np.float32}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _empty_rows():
+    A = synth.uniform_random(3000, 3000, 3.0, seed=4)
+    lens = A.row_lengths()
+    keep = np.ones(A.n_rows, bool)
+    keep[100:1900] = False  # 1800 empty rows in a run
+    rows = np.repeat(np.arange(A.n_rows), lens)
+    m = keep[rows]
+    counts = np.bincount(rows[m], minlength=A.n_rows)
+    rp = np.zeros(A.n_rows + 1, np.int64)
+    np.cumsum(counts, out=rp[1:])
+    return synth.CSR(A.n_rows, A.n_cols, rp, A.colidx[m], A.values[m])
+
+
+def _dense_rows():
+    # a few rows far longer than a tile (the long path), among short rows
+    a = synth.uniform_random(600, 9000, 4.0, seed=5)
+    rows = np.repeat(np.arange(600), a.row_lengths())
+    cols = a.colidx.astype(np.int64)
+    extra_r = np.repeat(np.array([3, 4, 5, 250, 599]), 9000)
+    extra_c = np.tile(np.arange(9000), 5)
+    R = np.concatenate([rows, extra_r])
+    Cc = np.concatenate([cols, extra_c])
+    return synth._from_keys(600, 9000, R, Cc, synth.rng_for(55))
+
+
+CASES = {
+    "band4096": lambda: synth.band_plus_uniform(4096, seed=0),
+    "stencil13": lambda: synth.stencil27(13),                  # 2197 rows: ragged for every r
+    "stencil16": lambda: synth.stencil27(16),
+    "powerlaw": lambda: synth.powerlaw(3001, 3001, seed=2),     # rows up to 2000 entries
+    "fem3": lambda: synth.fem_blocks(700, 3, 6.0, 20, seed=3),
+    "fem6": lambda: synth.fem_blocks(300, 6, 5.0, 10, seed=3),
+    "banded": lambda: synth.banded(2500, 64, 0.4, seed=6),
+    "uniform": lambda: synth.uniform_random(5000, 4000, 12.0, seed=7),
+    "wide": lambda: synth.uniform_random(97, 20000, 300.0, seed=8),
+    "tall": lambda: synth.uniform_random(20000, 37, 3.0, seed=9),
+    "empty_rows": _empty_rows,
+    "dense_rows": _dense_rows,
+    "tiny1x1": lambda: synth.from_dense(np.array([[2.5]])),
+    "tiny3x5": lambda: synth.random_small(3, 5, 0.6, seed=10),
+    "all_empty": lambda: synth.CSR(10, 10, np.zeros(11, np.int64), np.zeros(0, np.int32), np.zeros(0)),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        _cache[name] = CASES[name]()
+    return _cache[name]
+
+
+def to_beta(A, r, c, dtype):
+    return spc.csr_to_beta(r, c, A.rowptr, A.colidx, torch.from_numpy(A.values).to(dtype), A.n_cols)
+
+
+def check_rows(y, y_ref, s_ref, tol, label):
+    err = np.abs(y.astype(np.float64) - y_ref)
+    bad = np.flatnonzero(~(err <= tol * s_ref))
+    assert bad.size == 0, (f"{label}: {bad.size} rows out of bound, e.g. row {bad[0]}: "
+                           f"y={y[bad[0]]!r} ref={y_ref[bad[0]]!r} bound={tol * s_ref[bad[0]]!r}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_conversion_bit_exact(name, rc):
+    r, c = rc
+    A = case(name)
+    say(f"[conv] {name} beta{rc} n={A.n_rows} nnz={A.nnz}")
+    ref = oracle.csr_to_beta(A, r, c)
+    B = to_beta(A, r, c, torch.float64)
+    assert B.n_blocks == ref.n_blocks
+    assert np.array_equal(B.block_rowptr.cpu().numpy(), ref.block_rowptr)
+    assert np.array_equal(B.block_colidx.cpu().numpy(), ref.block_colidx)
+    mb = B.block_masks.cpu().numpy()
+    assert np.array_equal(mb[:ref.n_blocks * r * c // 8], ref.mask_bytes())
+    assert not mb[ref.n_blocks * r * c // 8:].any()  # padding zeroed
+    assert np.array_equal(B.values.cpu().numpy().view(np.uint64), ref.values.view(np.uint64))
+    # device decoding returns the CSR arrays bit for bit
+    rp, ci, v = spc.beta_to_csr(B)
+    assert np.array_equal(rp.cpu().numpy(), A.rowptr)
+    assert np.array_equal(ci.cpu().numpy(), A.colidx)
+    assert np.array_equal(v.cpu().numpy().view(np.uint64), A.values.view(np.uint64))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_spmv_parity(name, rc, dtype):
+    r, c = rc
+    A = case(name).astype(NP[dtype])
+    say(f"[spmv] {name} beta{rc} {dtype} n={A.n_rows} nnz={A.nnz}")
+    x = synth.dense_vector(A.n_cols, 21, dtype=NP[dtype])
+    y_ref, s_ref = oracle.csr_spmv(A, x)
+    B = to_beta(A, r, c, dtype)
+    xd = torch.from_numpy(x).cuda()
+    y = spc.spmv(B, xd).cpu().numpy()
+    check_rows(y, y_ref, s_ref, TOL[dtype], f"{name} beta{rc}")
+    # accumulate: y0 + A x; rows without entries keep y0 exactly
+    y0 = synth.dense_vector(A.n_rows, 22, dtype=NP[dtype])
+    ya = spc.spmv(B, xd, torch.from_numpy(y0.copy()).cuda(), accumulate=True).cpu().numpy()
+    s_acc = s_ref + np.abs(y0.astype(np.float64))
+    check_rows(ya, y_ref + y0.astype(np.float64), s_acc, TOL[dtype], f"{name} beta{rc} accumulate")
+    empty = A.row_lengths() == 0
+    assert np.array_equal(ya[empty], y0[empty])
+    if empty.any():
+        assert np.all(y[empty] == 0) and not np.signbit(y[empty]).any()
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("tile_bits,remap", [(1024, 0), (2048, 2), (3072, 0), (4032, 1)])
+def test_plan_variants_and_determinism(rc, tile_bits, remap):
+    r, c = rc
+    say(f"[plan] beta{rc} tile_bits={tile_bits} remap={remap}")
+    A = case("powerlaw")
+    x = synth.dense_vector(A.n_cols, 23)
+    y_ref, s_ref = oracle.csr_spmv(A, x)
+    B = to_beta(A, r, c, torch.float64)
+    P = B.plan(tile_bits, remap)
+    info = P.info()
+    assert info["tile_bits"] == tile_bits and info["n_tiles"] > 0
+    xd = torch.from_numpy(x).cuda()
+    y1 = spc.spmv(B, xd, plan=P)
+    y2 = spc.spmv(B, xd, plan=P)
+    check_rows(y1.cpu().numpy(), y_ref, s_ref, 1e-13, f"beta{rc} tb{tile_bits}")
+    assert torch.equal(y1.view(torch.int64), y2.view(torch.int64))
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_integer_inputs_bit_exact(rc, dtype):
+    r, c = rc
+    say(f"[int] beta{rc} {dtype}")
+    A = synth.powerlaw(1500, 1500, seed=11)
+    A.values = np.round(A.values * 16)      # |a| <= 16
+    x = np.round(synth.dense_vector(A.n_cols, 24) * 16)
+    y_ref, _ = oracle.csr_spmv(A, x)        # exact: every partial sum is an integer < 2^24
+    B = to_beta(A.astype(NP[dtype]), r, c, dtype)
+    y = spc.spmv(B, torch.from_numpy(x.astype(NP[dtype])).cuda()).cpu().numpy()
+    assert np.array_equal(y.astype(np.float64), y_ref)
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_nonfinite_x_under_unset_bits_does_not_leak(rc):
+    r, c = rc
+    say(f"[inf] beta{rc}")
+    A = synth.random_small(64, 64, 0.15, seed=12)
+    j = 9
+    x = synth.dense_vector(64, 25)
+    x[j] = np.inf
+    B = to_beta(A, r, c, torch.float64)
+    y = spc.spmv(B, torch.from_numpy(x).cuda()).cpu().numpy()
+    has_j = np.zeros(A.n_rows, bool)
+    for i in range(A.n_rows):
+        has_j[i] = j in A.colidx[A.rowptr[i]:A.rowptr[i + 1]]
+    assert np.all(np.isfinite(y[~has_j]))
+    assert not np.any(np.isfinite(y[has_j]))
+
+
+def test_invalid_csr_is_refused():
+    say("[err] invalid csr")
+    A = synth.random_small(20, 20, 0.3, seed=13)
+    ci = A.colidx.copy()
+    i = int(np.flatnonzero(np.diff(A.rowptr) >= 2)[0])
+    p = A.rowptr[i]
+    ci[p], ci[p + 1] = ci[p + 1], ci[p]                         # unsorted row
+    with pytest.raises(spc.SpcError) as e:
+        spc.csr_to_beta(1, 8, A.rowptr, ci, A.values, A.n_cols)
+    assert e.value.code == -3
+    ci2 = A.colidx.copy()
+    ci2[-1] = 20                                                # out of range
+    with pytest.raises(spc.SpcError) as e:
+        spc.csr_to_beta(2, 4, A.rowptr, ci2, A.values, A.n_cols)
+    assert e.value.code == -4
+    rp = A.rowptr.copy()
+    rp[5] = rp[6] + 1                                           # decreasing
+    with pytest.raises(spc.SpcError) as e:
+        spc.csr_to_beta(4, 4, rp, A.colidx, A.values, A.n_cols)
+    assert e.value.code == -4
+
+
+def test_corrupt_view_is_refused_by_plan():
+    say("[err] corrupt view")
+    A = synth.random_small(40, 40, 0.3, seed=14)
+    B = to_beta(A, 1, 8, torch.float64)
+    B.block_colidx[0] = 40                                      # block runs past n_cols
+    with pytest.raises(spc.SpcError) as e:
+        B.plan()
+    assert e.value.code == -4
+    B2 = to_beta(A, 1, 8, torch.float64)
+    B2.values = B2.values[:-1].clone()                          # nnz disagrees with masks
+    with pytest.raises(spc.SpcError):
+        B2.plan()
