@@ -133,16 +133,25 @@ spc_status spc_beta_to_csr(const spc_beta_view *A, int32_t *rowptr_out, int32_t 
  * group, processed by one workgroup; an interval with more blocks than a
  * tile holds becomes a tile of its own. Creating a plan reads block_rowptr
  * and the masks once and synchronizes the stream.
- *   tile_bits  mask bits a tile may hold (blocks * r * c); 0 = default 2048;
- *              one of 1024, 2048, 3072, 4032
+ *   tile_bits  mode 1: mask bits a tile may hold (blocks * r * c); 0 = 2048;
+ *              one of 1024, 2048, 3072, 4032. Mode 0 sizes its tiles from
+ *              wave_chunks instead: (64 * wave_chunks - 1) * (16 / value size)
+ *              bits, so one wavefront's 16-byte loads cover a tile's values
  *   xcd_remap  0 or 1 = give each of the 8 XCDs one contiguous range of
  *              tiles (0 is the default), 2 = hardware round-robin order
+ *   mode       0 = one wavefront per tile, four independent tiles per
+ *              workgroup: all of a tile's streams are requested at once
+ *              (values with 16-byte loads), x is gathered one lane per value;
+ *              1 = one workgroup per tile, one lane per mask bit loads,
+ *              gathers and multiplies (the direct form of the vexpand step)
  * params == NULL (or all zeros) selects the defaults. */
 typedef struct spc_plan spc_plan;
 typedef struct spc_plan_params {
     int32_t tile_bits;
     int32_t xcd_remap;
-    int32_t reserved[6];
+    int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles */
+    int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4 or 8; 0 = 4 */
+    int32_t reserved[4];
 } spc_plan_params;
 
 spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,

@@ -32,7 +32,8 @@ class BetaView(ctypes.Structure):
 
 
 class PlanParams(ctypes.Structure):
-    _fields_ = [("tile_bits", c_int32), ("xcd_remap", c_int32), ("reserved", c_int32 * 6)]
+    _fields_ = [("tile_bits", c_int32), ("xcd_remap", c_int32), ("mode", c_int32),
+                ("wave_chunks", c_int32), ("reserved", c_int32 * 4)]
 
 
 _lib = None
@@ -123,10 +124,11 @@ def mask_bytes(r: int, c: int, n_blocks: int) -> int:
 class Plan:
     """A tile plan (library-owned) for one BetaMatrix."""
 
-    def __init__(self, A: "BetaMatrix", tile_bits: int = 0, xcd_remap: int = 0):
+    def __init__(self, A: "BetaMatrix", tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0,
+                 wave_chunks: int = 0):
         self._A = A
         self._view = A.view()
-        p = PlanParams(tile_bits, xcd_remap)
+        p = PlanParams(tile_bits, xcd_remap, mode, wave_chunks)
         h = c_void_p()
         check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
                                     stream_ptr()))
@@ -179,10 +181,10 @@ class BetaMatrix:
                         self.block_masks.data_ptr() if self.n_blocks else None,
                         self.values.data_ptr() if self.nnz else None)
 
-    def plan(self, tile_bits: int = 0, xcd_remap: int = 0) -> Plan:
-        key = (tile_bits, xcd_remap)
+    def plan(self, tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0, wave_chunks: int = 0) -> Plan:
+        key = (tile_bits, xcd_remap, mode, wave_chunks)
         if key not in self._plans:
-            self._plans[key] = Plan(self, tile_bits, xcd_remap)
+            self._plans[key] = Plan(self, tile_bits, xcd_remap, mode, wave_chunks)
         return self._plans[key]
 
     def nbytes(self) -> int:

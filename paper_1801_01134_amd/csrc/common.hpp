@@ -111,6 +111,8 @@ struct spc_plan {
     int shape;
     int tile_bits;
     int xcd_remap;
+    int mode;
+    int kq;
     int device;
     int64_t n_tiles;
     int64_t n_long;

@@ -16,7 +16,8 @@
 
 namespace spc {
 
-int spmv_max_intervals_per_tile(int r);
+int spmv_max_intervals_per_tile(int r, int mode);
+int wave_tile_bits(int dtype, int kq);
 
 namespace {
 
@@ -78,6 +79,10 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     const int remap_arg = params ? params->xcd_remap : 0;
     SPC_REQUIRE(remap_arg >= 0 && remap_arg <= 2, SPC_ERR_INVALID_ARG, "xcd_remap must be 0, 1 or 2");
     const int xcd_remap = remap_arg != 2;
+    const int mode = params ? params->mode : 0;
+    SPC_REQUIRE(mode == 0 || mode == 1, SPC_ERR_INVALID_ARG, "mode must be 0 or 1");
+    const int kq = params && params->wave_chunks ? params->wave_chunks : 4;
+    SPC_REQUIRE(kq == 2 || kq == 4 || kq == 8, SPC_ERR_INVALID_ARG, "wave_chunks must be 2, 4 or 8");
     SPC_REQUIRE(tile_bits == 1024 || tile_bits == 2048 || tile_bits == 3072 || tile_bits == 4032,
                 SPC_ERR_INVALID_ARG, "tile_bits must be 1024, 2048, 3072 or 4032 (got %d)", tile_bits);
     const int shape = shape_of(A->r, A->c);
@@ -97,8 +102,9 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
         SPC_REQUIRE(brow[t] <= brow[t + 1], SPC_ERR_INDEX_RANGE, "block_rowptr decreases at %lld",
                     (long long)t);
 
-    const int64_t target = tile_bits / rc;          // blocks per tile
-    const int64_t max_int = spmv_max_intervals_per_tile(r);
+    const int cap_bits = mode == 0 ? wave_tile_bits(A->dtype, kq) : tile_bits;
+    const int64_t target = cap_bits / rc;           // blocks per tile
+    const int64_t max_int = spmv_max_intervals_per_tile(r, mode);
     std::vector<TileDesc> tiles;
     tiles.reserve((size_t)(A->n_blocks / (target ? target : 1) + n_int / max_int + 2));
     int64_t n_long = 0;
@@ -127,8 +133,10 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     SPC_REQUIRE(P, SPC_ERR_CAPACITY, "out of host memory");
     P->A = *A;
     P->shape = shape;
-    P->tile_bits = tile_bits;
+    P->tile_bits = cap_bits;
+    P->kq = kq;
     P->xcd_remap = xcd_remap;
+    P->mode = mode;
     P->n_tiles = n_tiles;
     P->n_long = n_long;
     P->d_tiles = nullptr;

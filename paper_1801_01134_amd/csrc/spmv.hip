@@ -47,6 +47,7 @@ struct SpmvArgs {
     void *y;
     const TileDesc *tiles;
     int64_t n_rows;
+    int64_t nnz;
     int32_t n_tiles;
     int32_t accumulate;
     int32_t xcd_remap;
@@ -225,6 +226,293 @@ __device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, in
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Wavefront tiles (mode 0). A tile is small enough for one wavefront, and the
+// four wavefronts of a workgroup run four independent tiles with no barrier
+// between them, so a slow phase of one tile never holds up another and many
+// tiles per CU keep enough loads in flight. Per tile:
+//   1. request every stream at once: the packed values straight into
+//      registers with 16-byte loads (lane l takes chunks l, l+64, ...), the
+//      block columns, the mask words and the interval pointers;
+//   2. scan the words' popcounts; lane = mask bit writes each stored value's
+//      column at its packed position in LDS;
+//   3. lane = value: gather x for the lane's own values, store the products;
+//   4. L lanes per (interval, block row) add its products (L as large as the
+//      tile's row count allows) and combine their sums with shuffles.
+template <class Sh, class T, int KQ>
+struct WaveSmem {
+    static constexpr int E = 16 / sizeof(T);          // values per 16-byte chunk
+    static constexpr int WB = (64 * KQ - 1) * E;      // bits (so values) a tile may hold
+    static constexpr int NB = WB / Sh::RC;            // blocks a tile may hold
+    // NB blocks starting anywhere in a word span at most NB / BPW + 2 words;
+    // one more entry holds the sentinel after the last word
+    static constexpr int NW = NB / Sh::BPW + 3;
+    static constexpr int NI = 64 / Sh::R;             // intervals a tile may hold
+    uint64_t wm[NW];
+    int off[NW];
+    int brow[NI + 1];
+    int col[NB];
+    int cidx[WB];
+    T prod[WB];
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class Sh, class T, int KQ>
+__device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int b1, int64_t vbase,
+                          WaveSmem<Sh, T, KQ> &sm) {
+    using SM = WaveSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const T *__restrict__ x = static_cast<const T *>(a.x);
+    const int64_t vend = (t + 1 < a.n_tiles) ? a.tiles[t + 1].vbase : a.nnz;
+    const int nv = (int)(vend - vbase);
+    const int nI = i1 - i0;
+
+    // 1. all streams of the tile
+    const int64_t abase = vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(vbase - abase);
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    union Chunk {
+        V4 v;
+        T e[E];
+    };
+    Chunk ch[KQ];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+        const int q = lane + k * 64;
+        const int p0 = q * E - shift;
+        if (p0 >= 0 && p0 + E <= nv) {
+            ch[k].v = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(vals + abase) + q);
+        } else if (p0 + E > 0 && p0 < nv) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int p = p0 + e;
+                ch[k].e[e] = (p >= 0 && p < nv) ? vals[vbase + p] : T(0);
+            }
+        }
+    }
+    const int nblk = b1 - b0;
+    int colr[(SM::NB + 63) / 64];
+#pragma unroll
+    for (int k = 0; k < (SM::NB + 63) / 64; ++k) {
+        const int j = lane + 64 * k;
+        colr[k] = j < nblk ? ldg_nt(a.bcol + b0 + j) : 0;
+    }
+    const int br = lane < nI ? a.brow[i0 + lane] : 0;   // the end pointer is b1
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    const uint64_t wm = tile_word<Sh>(a.mw, w0, nw, b0, b1, lane);
+    const int cnt = __popcll(wm);
+    const int incl = wave_incl_scan(cnt);
+    const int excl = incl - cnt;
+    if (lane < nw) {
+        sm.wm[lane] = wm;
+        sm.off[lane] = excl;
+    }
+    if (lane == 0) {
+        sm.wm[nw] = 0ull;
+        sm.off[nw] = nw > 0 ? __builtin_amdgcn_readlane(incl, nw - 1) : 0;
+    }
+    if (lane < nI) sm.brow[lane] = br - b0;
+    if (lane == 0) sm.brow[nI] = b1 - b0;
+#pragma unroll
+    for (int k = 0; k < (SM::NB + 63) / 64; ++k) {
+        const int j = lane + 64 * k;
+        if (j < nblk) sm.col[j] = colr[k];
+    }
+    wave_sync();
+
+    // 2. column of every stored value, lane = mask bit
+    {
+        const int slot = lane / Sh::RC;
+        const int kcol = (lane % Sh::RC) % Sh::C;
+        const int sb = slot - (b0 - w0 * Sh::BPW);   // block index within the tile, word 0
+        for (int i = 0; i < nw; ++i) {
+            const uint64_t M = readlane64(wm, i);
+            const int off = __builtin_amdgcn_readlane(excl, i);
+            if ((M >> lane) & 1ull) sm.cidx[off + lane_rank(M)] = sm.col[i * Sh::BPW + sb] + kcol;
+        }
+    }
+    wave_sync();
+
+    // 3. products, lane = value
+    {
+        int cl[KQ][E];
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int p0 = (lane + k * 64) * E - shift;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int p = p0 + e;
+                cl[k][e] = (p >= 0 && p < nv) ? sm.cidx[p] : -1;
+            }
+        }
+        T xv[KQ][E];
+#pragma unroll
+        for (int k = 0; k < KQ; ++k)
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (cl[k][e] >= 0) xv[k][e] = x[cl[k][e]];
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) {
+            const int p0 = (lane + k * 64) * E - shift;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if (cl[k][e] >= 0) sm.prod[p0 + e] = ch[k].e[e] * xv[k][e];
+        }
+    }
+    wave_sync();
+
+    // 4. row sums: L lanes per (interval, block row)
+    const int npairs = nI * Sh::R;
+    int lg = 6;  // log2 L: largest with npairs * L <= 64
+    while (lg > 0 && (npairs << lg) > 64) --lg;
+    const int L = 1 << lg;
+    const int pair = lane >> lg, l = lane & (L - 1);
+    double acc = 0.0;
+    int n_here = 0;
+    if (pair < npairs) {
+        const int li = pair / Sh::R, rho = pair % Sh::R;
+        const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
+        const int sh0 = b0 - w0 * Sh::BPW;                  // slot of the tile's first block
+        if (Sh::R == 1) {
+            if (bs < be) {
+                const int gs = bs + sh0, ge = be + sh0;
+                const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
+                const int vs = sm.off[ws] + __popcll(sm.wm[ws] & ((1ull << ((gs % Sh::BPW) * Sh::RC)) - 1ull));
+                const int ve = sm.off[we] + __popcll(sm.wm[we] & ((1ull << ((ge % Sh::BPW) * Sh::RC)) - 1ull));
+                double a0 = 0.0, a1 = 0.0;
+                int k = vs + l;
+                for (; k + L < ve; k += 2 * L) {
+                    a0 += (double)sm.prod[k];
+                    a1 += (double)sm.prod[k + L];
+                }
+                if (k < ve) a0 += (double)sm.prod[k];
+                acc = a0 + a1;
+                n_here = ve - vs;
+            }
+        } else {
+            const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
+            for (int b = bs + l; b < be; b += L) {
+                const int g = b + sh0;
+                const int wi = g / Sh::BPW, bit = (g % Sh::BPW) * Sh::RC;
+                const uint64_t wv = sm.wm[wi];
+                const uint32_t m = (uint32_t)(wv >> bit) & Sh::RCMASK;
+                const uint32_t sub = (m >> (rho * Sh::C)) & Sh::CMASK;
+                const int pos = sm.off[wi] + __popcll(wv & ((1ull << bit) - 1ull)) + __popc(m & below);
+                const int n = __popc(sub);
+                n_here += n;
+                for (int k = 0; k < n; ++k) acc += (double)sm.prod[pos + k];
+            }
+        }
+    }
+    for (int m = L >> 1; m >= 1; m >>= 1) {
+        acc += __shfl_xor(acc, m, 64);
+        n_here += __shfl_xor(n_here, m, 64);
+    }
+    if (pair < npairs && l == 0) {
+        const int li = pair / Sh::R, rho = pair % Sh::R;
+        const int64_t row = (int64_t)(i0 + li) * Sh::R + rho;
+        if (row < a.n_rows) {
+            T *__restrict__ y = static_cast<T *>(a.y);
+            if (a.accumulate) {
+                if (n_here > 0) y[row] = (T)(acc + (double)y[row]);
+            } else {
+                y[row] = (T)acc;
+            }
+        }
+    }
+}
+
+// One interval longer than a wavefront tile, run by one wavefront: each lane
+// keeps the running sum of its block row over all the interval's words.
+template <class Sh, class T>
+__device__ void wave_long(const SpmvArgs &a, int I, int b0, int b1, int64_t vbase) {
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const T *__restrict__ x = static_cast<const T *>(a.x);
+    const int slot = lane / Sh::RC;
+    const int kcol = (lane % Sh::RC) % Sh::C;
+    const int w0 = b0 / Sh::BPW;
+    const int nwt = (b1 - 1) / Sh::BPW - w0 + 1;
+    double acc0 = 0.0, acc1 = 0.0;
+    int n_here = 0;  // stored entries this lane saw
+    int64_t vrun = vbase;
+    for (int k = 0; k < nwt; k += 64) {
+        const int nw = min(64, nwt - k);
+        const uint64_t wm = tile_word<Sh>(a.mw, w0 + k, nw, b0, b1, lane);
+        const int cnt = __popcll(wm);
+        const int incl = wave_incl_scan(cnt);
+        const int excl = incl - cnt;
+        for (int i = 0; i < nw; i += kUnroll) {
+            uint64_t M[kUnroll];
+            int off[kUnroll];
+            unsigned rk[kUnroll];
+            bool act[kUnroll];
+            int col[kUnroll];
+            T v[kUnroll], xv[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const bool in = (i + u) < nw;
+                M[u] = in ? readlane64(wm, i + u) : 0ull;
+                off[u] = in ? __builtin_amdgcn_readlane(excl, i + u) : 0;
+                act[u] = (M[u] >> lane) & 1ull;
+                rk[u] = lane_rank(M[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (act[u]) {
+                    col[u] = ldg_nt(a.bcol + (int64_t)(w0 + k + i + u) * Sh::BPW + slot) + kcol;
+                    v[u] = ldg_nt(vals + vrun + off[u] + rk[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (act[u]) xv[u] = x[col[u]];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                if (act[u]) {
+                    ++n_here;
+                    if (u & 1) acc1 = __builtin_fma((double)v[u], (double)xv[u], acc1);
+                    else acc0 = __builtin_fma((double)v[u], (double)xv[u], acc0);
+                }
+            }
+        }
+        vrun += __builtin_amdgcn_readlane(incl, nw - 1);
+    }
+    double acc = acc0 + acc1;
+    // sums over lanes of the same block row: xor over column bits, then slot bits
+#pragma unroll
+    for (int m = 1; m < Sh::C; m <<= 1) {
+        acc += __shfl_xor(acc, m, 64);
+        n_here += __shfl_xor(n_here, m, 64);
+    }
+#pragma unroll
+    for (int m = Sh::RC; m < 64; m <<= 1) {
+        acc += __shfl_xor(acc, m, 64);
+        n_here += __shfl_xor(n_here, m, 64);
+    }
+    if (lane < Sh::RC && (lane % Sh::C) == 0) {
+        const int rho = lane / Sh::C;
+        const int64_t row = (int64_t)I * Sh::R + rho;
+        if (row < a.n_rows) {
+            T *__restrict__ y = static_cast<T *>(a.y);
+            if (a.accumulate) {
+                if (n_here > 0) y[row] = (T)(acc + (double)y[row]);
+            } else {
+                y[row] = (T)acc;
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // One interval with more blocks than a tile holds.
 template <class Sh, class T>
@@ -237,6 +525,7 @@ __device__ void tile_long(const SpmvArgs &a, int I, int b0, int b1, int64_t vbas
     const int w0 = b0 / Sh::BPW;
     const int nwt = (b1 - 1) / Sh::BPW - w0 + 1;
     double acc0 = 0.0, acc1 = 0.0;
+    int n_here = 0;  // stored entries this lane saw
     int64_t vrun = vbase;
     for (int k = 0; k < nwt; k += 64) {
         const int nw = min(64, nwt - k);
@@ -301,14 +590,15 @@ __device__ void tile_long(const SpmvArgs &a, int I, int b0, int b1, int64_t vbas
     }
 }
 
+// Mode 1: one workgroup per tile (lane = mask bit throughout).
 template <int R, int C, class T, int TB>
-__global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs a) {
+__global__ __launch_bounds__(kThreads) void k_spmv_wg(SpmvArgs a) {
     using Sh = Shape<R, C>;
     static_assert(TB / 64 + 1 <= 64, "a tile must fit 64 mask words");
+    __shared__ double s_red[kWaves * 8];
     __shared__ uint64_t s_wm[TB / 64 + 2];
     __shared__ int s_off[TB / 64 + 2];
     __shared__ T s_prod[TB];
-    __shared__ double s_red[kWaves * 8];
     int t = blockIdx.x;
     if (a.xcd_remap) t = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
     if (t >= a.n_tiles) return;
@@ -318,13 +608,41 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs a) {
     else tile_short<Sh, T, TB>(a, d.i0, d.i1, b0, b1, d.vbase, s_wm, s_off, s_prod);
 }
 
+// Mode 0: one wavefront per tile, four independent tiles per workgroup.
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_wave(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = WaveSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = threadIdx.x >> 6;
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    const int b0 = a.brow[d.i0], b1 = a.brow[d.i1];
+    if (b1 - b0 > SM::NB) wave_long<Sh, T>(a, d.i0, b0, b1, d.vbase);
+    else wave_tile<Sh, T, KQ>(a, t, d.i0, d.i1, b0, b1, d.vbase, sm[wid]);
+}
+
 template <int R, int C, class T>
-spc_status launch_tb(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (tb) {
-    case 1024: hipLaunchKernelGGL((k_spmv<R, C, T, 1024>), grid, dim3(kThreads), 0, stream, a); break;
-    case 2048: hipLaunchKernelGGL((k_spmv<R, C, T, 2048>), grid, dim3(kThreads), 0, stream, a); break;
-    case 3072: hipLaunchKernelGGL((k_spmv<R, C, T, 3072>), grid, dim3(kThreads), 0, stream, a); break;
-    default: hipLaunchKernelGGL((k_spmv<R, C, T, 4032>), grid, dim3(kThreads), 0, stream, a); break;
+    case 1024: hipLaunchKernelGGL((k_spmv_wg<R, C, T, 1024>), grid, dim3(kThreads), 0, stream, a); break;
+    case 2048: hipLaunchKernelGGL((k_spmv_wg<R, C, T, 2048>), grid, dim3(kThreads), 0, stream, a); break;
+    case 3072: hipLaunchKernelGGL((k_spmv_wg<R, C, T, 3072>), grid, dim3(kThreads), 0, stream, a); break;
+    default: hipLaunchKernelGGL((k_spmv_wg<R, C, T, 4032>), grid, dim3(kThreads), 0, stream, a); break;
+    }
+    SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
+template <int R, int C, class T>
+spc_status launch_wave(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    switch (kq) {
+    case 2: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 2>), grid, dim3(kThreads), 0, stream, a); break;
+    case 8: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 8>), grid, dim3(kThreads), 0, stream, a); break;
+    default: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 4>), grid, dim3(kThreads), 0, stream, a); break;
     }
     SPC_HIP(hipGetLastError());
     return SPC_OK;
@@ -332,7 +650,14 @@ spc_status launch_tb(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
 
 }  // namespace
 
-int spmv_max_intervals_per_tile(int r) { return kThreads / r; }
+int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? 64 / r : kThreads / r; }
+
+// Tile capacity in mask bits for a mode and a chunk count (mode 0) or the
+// workgroup tile size (mode 1).
+int wave_tile_bits(int dtype, int kq) {
+    const int E = dtype == SPC_F64 ? 2 : 4;
+    return (64 * kq - 1) * E;
+}
 
 spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x, void *y, int accumulate,
                        hipStream_t stream) {
@@ -345,16 +670,25 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     a.y = y;
     a.tiles = P->d_tiles;
     a.n_rows = A->n_rows;
+    a.nnz = A->nnz;
     a.n_tiles = (int32_t)P->n_tiles;
     a.accumulate = accumulate;
     a.xcd_remap = P->xcd_remap;
-    a.tiles_per_xcd = (int32_t)div_up(P->n_tiles, 8);
-    dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)P->n_tiles);
+    // Wavefront tiles read values with 16-byte loads, so they need a 16-byte
+    // aligned values array; otherwise the same tiles run as workgroup tiles
+    // (any workgroup tile size at least as large as the plan's tiles works).
+    const bool aligned = (reinterpret_cast<uintptr_t>(A->values) & 15u) == 0;
+    const bool wave = P->mode == 0 && aligned;
+    const int wg_bits = P->mode == 1 ? P->tile_bits : (P->tile_bits <= 1024 ? 1024 : 2048);
+    const int64_t groups = wave ? div_up(P->n_tiles, kWaves) : P->n_tiles;
+    a.tiles_per_xcd = (int32_t)div_up(groups, 8);
+    dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)groups);
     return with_shape(P->shape, [&](auto sh) {
         using Sh = decltype(sh);
         return with_dtype(A->dtype, [&](auto tv) {
             using T = decltype(tv);
-            return launch_tb<Sh::R, Sh::C, T>(P->tile_bits, grid, a, stream);
+            if (!wave) return launch_wg<Sh::R, Sh::C, T>(wg_bits, grid, a, stream);
+            return launch_wave<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
         });
     });
 }

@@ -136,17 +136,21 @@ def test_spmv_parity(name, rc, dtype):
 
 
 @pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
-@pytest.mark.parametrize("tile_bits,remap", [(1024, 0), (2048, 2), (3072, 0), (4032, 1)])
-def test_plan_variants_and_determinism(rc, tile_bits, remap):
+@pytest.mark.parametrize("mode,tile_bits,chunks,remap", [
+    (0, 0, 2, 0), (0, 0, 4, 2), (0, 0, 8, 1),
+    (1, 1024, 0, 0), (1, 2048, 0, 2), (1, 3072, 0, 0), (1, 4032, 0, 1)])
+@pytest.mark.parametrize("name", ["powerlaw", "stencil13", "fem6", "dense_rows", "empty_rows"])
+def test_plan_variants_and_determinism(rc, mode, tile_bits, chunks, remap, name):
     r, c = rc
-    say(f"[plan] beta{rc} tile_bits={tile_bits} remap={remap}")
-    A = case("powerlaw")
+    say(f"[plan] {name} beta{rc} mode={mode} tile_bits={tile_bits} chunks={chunks} remap={remap}")
+    A = case(name)
     x = synth.dense_vector(A.n_cols, 23)
     y_ref, s_ref = oracle.csr_spmv(A, x)
     B = to_beta(A, r, c, torch.float64)
-    P = B.plan(tile_bits, remap)
+    P = B.plan(tile_bits, remap, mode, chunks)
     info = P.info()
-    assert info["tile_bits"] == tile_bits and info["n_tiles"] > 0
+    want_bits = tile_bits if mode == 1 else (64 * chunks - 1) * 2
+    assert info["tile_bits"] == want_bits and info["n_tiles"] > 0
     xd = torch.from_numpy(x).cuda()
     y1 = spc.spmv(B, xd, plan=P)
     y2 = spc.spmv(B, xd, plan=P)
@@ -219,3 +223,18 @@ def test_corrupt_view_is_refused_by_plan():
     B2.values = B2.values[:-1].clone()                          # nnz disagrees with masks
     with pytest.raises(spc.SpcError):
         B2.plan()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_values_not_16_byte_aligned(dtype):
+    say(f"[align] {dtype}")
+    A = case("fem3").astype(NP[dtype])
+    x = synth.dense_vector(A.n_cols, 26, dtype=NP[dtype])
+    y_ref, s_ref = oracle.csr_spmv(A, x)
+    B = to_beta(A, 2, 4, dtype)
+    buf = torch.empty(B.nnz + 1, dtype=dtype, device="cuda")
+    buf[1:] = B.values
+    B.values = buf[1:]                      # element-aligned, not 16-byte aligned
+    assert B.values.data_ptr() % 16 != 0
+    y = spc.spmv(B, torch.from_numpy(x).cuda()).cpu().numpy()
+    check_rows(y, y_ref, s_ref, TOL[dtype], "misaligned values")
