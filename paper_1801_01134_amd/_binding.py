@@ -212,9 +212,7 @@ def csr_to_beta(r: int, c: int, rowptr, colidx, values, n_cols: int, dtype=None,
     check(L.spc_beta_count(r, c, n_rows, n_cols, _ptr(rp), _ptr(ci), _ptr(brow), ctypes.byref(nb), s))
     nb = nb.value
     bcol = torch.empty(nb, dtype=torch.int32, device=device)
-    mb = mask_bytes(r, c, nb)
-    masks = (torch.empty(mb, dtype=torch.uint8, device=device) if mb
-             else torch.zeros(8, dtype=torch.uint8, device=device))
+    masks = torch.empty(mask_bytes(r, c, nb), dtype=torch.uint8, device=device)
     vout = torch.empty_like(v)
     vin = v if v.numel() else torch.zeros(1, dtype=v.dtype, device=device)
     bcol_p = bcol if nb else torch.zeros(1, dtype=torch.int32, device=device)

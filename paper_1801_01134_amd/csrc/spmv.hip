@@ -230,15 +230,16 @@ __device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, in
 // ---------------------------------------------------------------------------
 // Wavefront tiles (mode 0). A tile is small enough for one wavefront, and the
 // four wavefronts of a workgroup run four independent tiles with no barrier
-// between them, so a slow phase of one tile never holds up another and many
-// tiles per CU keep enough loads in flight. Per tile:
-//   1. request every stream at once: the packed values straight into
-//      registers with 16-byte loads (lane l takes chunks l, l+64, ...), the
-//      block columns, the mask words and the interval pointers;
-//   2. scan the words' popcounts; lane = mask bit writes each stored value's
-//      column at its packed position in LDS;
-//   3. lane = value: gather x for the lane's own values, store the products;
-//   4. L lanes per (interval, block row) add its products (L as large as the
+// between them, so a slow phase of one tile never holds up another. Per tile:
+//   1. request the tile's streams at once: the packed values with 16-byte
+//      loads (lane l takes chunks l, l+64, ...), the block columns, the
+//      interval pointers and the mask words;
+//   2. the values go to LDS in packed order; lane = mask bit then walks the
+//      mask words on the scalar unit: the word is the execution mask (an
+//      inverse ballot), the lane's rank among the word's set bits plus the
+//      running popcount is its value's slot, and the product with
+//      x[colidx + k] replaces the value in place;
+//   3. L lanes per (interval, block row) add its products (L as large as the
 //      tile's row count allows) and combine their sums with shuffles.
 template <class Sh, class T, int KQ>
 struct WaveSmem {
@@ -249,12 +250,12 @@ struct WaveSmem {
     // one more entry holds the sentinel after the last word
     static constexpr int NW = NB / Sh::BPW + 3;
     static constexpr int NI = 64 / Sh::R;             // intervals a tile may hold
+    static constexpr int NCOL = ((NB + 63) / 64) * 64;
     uint64_t wm[NW];
     int off[NW];
     int brow[NI + 1];
-    int col[NB];
-    int cidx[WB];
-    T prod[WB];
+    int col[NCOL];
+    T buf[64 * KQ * E];                               // packed values, then products
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -263,114 +264,130 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ uint64_t low_bits(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
 template <class Sh, class T, int KQ>
 __device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int b1, int64_t vbase,
                           WaveSmem<Sh, T, KQ> &sm) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
+    constexpr int NCR = SM::NCOL / 64;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
     const T *__restrict__ x = static_cast<const T *>(a.x);
-    const int64_t vend = (t + 1 < a.n_tiles) ? a.tiles[t + 1].vbase : a.nnz;
+    const bool last_tile = t + 1 >= a.n_tiles;
+    const int64_t vend = last_tile ? a.nnz : a.tiles[t + 1].vbase;
     const int nv = (int)(vend - vbase);
     const int nI = i1 - i0;
-
-    // 1. all streams of the tile
     const int64_t abase = vbase & ~(int64_t)(E - 1);
     const int shift = (int)(vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;          // chunks holding the tile's values
+    // the array's last chunk may reach past nnz: read it value by value
+    const int q_tail = (last_tile && abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+
+    // 1. all streams of the tile
     using V4 = __attribute__((ext_vector_type(4))) unsigned int;
-    union Chunk {
-        V4 v;
-        T e[E];
-    };
-    Chunk ch[KQ];
+    const V4 *__restrict__ vsrc = reinterpret_cast<const V4 *>(vals + abase);
+    V4 ch[KQ];
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
-        const int q = lane + k * 64;
-        const int p0 = q * E - shift;
-        if (p0 >= 0 && p0 + E <= nv) {
-            ch[k].v = __builtin_nontemporal_load(reinterpret_cast<const V4 *>(vals + abase) + q);
-        } else if (p0 + E > 0 && p0 < nv) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int p = p0 + e;
-                ch[k].e[e] = (p >= 0 && p < nv) ? vals[vbase + p] : T(0);
-            }
-        }
+        const int q = lane + 64 * k;
+        if (q < q_tail) ch[k] = __builtin_nontemporal_load(vsrc + q);
     }
     const int nblk = b1 - b0;
-    int colr[(SM::NB + 63) / 64];
+    int colr[NCR];
 #pragma unroll
-    for (int k = 0; k < (SM::NB + 63) / 64; ++k) {
+    for (int k = 0; k < NCR; ++k) {
         const int j = lane + 64 * k;
-        colr[k] = j < nblk ? ldg_nt(a.bcol + b0 + j) : 0;
+        if (j < nblk) colr[k] = ldg_nt(a.bcol + b0 + j);
     }
     const int br = lane < nI ? a.brow[i0 + lane] : 0;   // the end pointer is b1
     const int w0 = b0 / Sh::BPW;
     const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
-    const uint64_t wm = tile_word<Sh>(a.mw, w0, nw, b0, b1, lane);
-    const int cnt = __popcll(wm);
-    const int incl = wave_incl_scan(cnt);
-    const int excl = incl - cnt;
+    const int lo_slot = b0 - w0 * Sh::BPW;                  // slots of word 0 before the tile
+    const int hi_slot = b1 - (w0 + nw - 1) * Sh::BPW;       // slots of the last word inside it
+    uint64_t wl = 0;
     if (lane < nw) {
-        sm.wm[lane] = wm;
-        sm.off[lane] = excl;
+        wl = a.mw[w0 + lane];
+        if (lane == 0) wl &= ~low_bits(lo_slot * Sh::RC);
+        if (lane == nw - 1) wl &= low_bits(hi_slot * Sh::RC);
+    }
+    const int cnt = __popcll(wl);
+    const int incl = wave_incl_scan(cnt);
+
+    // values and block columns into LDS
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+        const int q = lane + 64 * k;
+        if (q < q_tail) *reinterpret_cast<V4 *>(&sm.buf[q * E]) = ch[k];
+    }
+    if (q_tail < nq && lane == 0) {
+        for (int e = 0; e < E; ++e) {
+            const int64_t g = abase + (int64_t)q_tail * E + e;
+            if (g < a.nnz) sm.buf[q_tail * E + e] = vals[g];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NCR; ++k) {
+        const int j = lane + 64 * k;
+        if (j < nblk) sm.col[j] = colr[k];
+    }
+    if (lane < nI) sm.brow[lane] = br - b0;
+    if (lane == 0) sm.brow[nI] = nblk;
+    if (lane < nw) {
+        sm.wm[lane] = wl;
+        sm.off[lane] = incl - cnt;
     }
     if (lane == 0) {
         sm.wm[nw] = 0ull;
         sm.off[nw] = nw > 0 ? __builtin_amdgcn_readlane(incl, nw - 1) : 0;
     }
-    if (lane < nI) sm.brow[lane] = br - b0;
-    if (lane == 0) sm.brow[nI] = b1 - b0;
-#pragma unroll
-    for (int k = 0; k < (SM::NB + 63) / 64; ++k) {
-        const int j = lane + 64 * k;
-        if (j < nblk) sm.col[j] = colr[k];
-    }
     wave_sync();
 
-    // 2. column of every stored value, lane = mask bit
+    // 2. products in place, lane = mask bit, words walked on the scalar unit
     {
+        constexpr int G = 8;                                  // words per group (one 64-byte scalar load)
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
-        const int sb = slot - (b0 - w0 * Sh::BPW);   // block index within the tile, word 0
-        for (int i = 0; i < nw; ++i) {
-            const uint64_t M = readlane64(wm, i);
-            const int off = __builtin_amdgcn_readlane(excl, i);
-            if ((M >> lane) & 1ull) sm.cidx[off + lane_rank(M)] = sm.col[i * Sh::BPW + sb] + kcol;
-        }
-    }
-    wave_sync();
-
-    // 3. products, lane = value
-    {
-        int cl[KQ][E];
+        const int col_lane = slot - lo_slot;                  // block index in word 0
+        const char *__restrict__ xb = reinterpret_cast<const char *>(x);
+        char *__restrict__ bb = reinterpret_cast<char *>(sm.buf);
+        int voff = shift;                                     // buffer slot of the next value
+        for (int i = 0; i < nw; i += G) {
+            // the masks array is readable 64 bytes past its last word, so a
+            // group may run past the tile's words; those words are cleared
+            const uint64_t *__restrict__ gp = a.mw + w0 + i;
+            uint64_t M[G];
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) {
-            const int p0 = (lane + k * 64) * E - shift;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int p = p0 + e;
-                cl[k][e] = (p >= 0 && p < nv) ? sm.cidx[p] : -1;
+            for (int j = 0; j < G; ++j) {
+                const int gi = i + j;
+                uint64_t m = gp[j];
+                if (gi == 0) m &= ~low_bits(lo_slot * Sh::RC);
+                if (gi == nw - 1) m &= low_bits(hi_slot * Sh::RC);
+                M[j] = gi < nw ? m : 0ull;
             }
-        }
-        T xv[KQ][E];
+            uint32_t pb[G], xo[G];
+            T v[G], xv[G];
 #pragma unroll
-        for (int k = 0; k < KQ; ++k)
+            for (int j = 0; j < G; ++j) {
+                if (__builtin_amdgcn_inverse_ballot_w64(M[j])) {
+                    pb[j] = (lane_rank(M[j]) + (uint32_t)voff) * (uint32_t)sizeof(T);
+                    xo[j] = (uint32_t)(sm.col[(i + j) * Sh::BPW + col_lane] + kcol) * (uint32_t)sizeof(T);
+                    v[j] = *reinterpret_cast<const T *>(bb + pb[j]);
+                }
+                voff += __popcll(M[j]);
+            }
 #pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (cl[k][e] >= 0) xv[k][e] = x[cl[k][e]];
+            for (int j = 0; j < G; ++j)
+                if (__builtin_amdgcn_inverse_ballot_w64(M[j])) xv[j] = *reinterpret_cast<const T *>(xb + xo[j]);
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) {
-            const int p0 = (lane + k * 64) * E - shift;
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (cl[k][e] >= 0) sm.prod[p0 + e] = ch[k].e[e] * xv[k][e];
+            for (int j = 0; j < G; ++j)
+                if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb[j]) = v[j] * xv[j];
         }
     }
     wave_sync();
 
-    // 4. row sums: L lanes per (interval, block row)
+    // 3. row sums: L lanes per (interval, block row)
     const int npairs = nI * Sh::R;
     int lg = 6;  // log2 L: largest with npairs * L <= 64
     while (lg > 0 && (npairs << lg) > 64) --lg;
@@ -381,35 +398,35 @@ __device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int 
     if (pair < npairs) {
         const int li = pair / Sh::R, rho = pair % Sh::R;
         const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
-        const int sh0 = b0 - w0 * Sh::BPW;                  // slot of the tile's first block
+        const T *__restrict__ prod = sm.buf + shift;
         if (Sh::R == 1) {
             if (bs < be) {
-                const int gs = bs + sh0, ge = be + sh0;
+                const int gs = bs + lo_slot, ge = be + lo_slot;
                 const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
-                const int vs = sm.off[ws] + __popcll(sm.wm[ws] & ((1ull << ((gs % Sh::BPW) * Sh::RC)) - 1ull));
-                const int ve = sm.off[we] + __popcll(sm.wm[we] & ((1ull << ((ge % Sh::BPW) * Sh::RC)) - 1ull));
+                const int vs = sm.off[ws] + __popcll(sm.wm[ws] & low_bits((gs % Sh::BPW) * Sh::RC));
+                const int ve = sm.off[we] + __popcll(sm.wm[we] & low_bits((ge % Sh::BPW) * Sh::RC));
                 double a0 = 0.0, a1 = 0.0;
                 int k = vs + l;
                 for (; k + L < ve; k += 2 * L) {
-                    a0 += (double)sm.prod[k];
-                    a1 += (double)sm.prod[k + L];
+                    a0 += (double)prod[k];
+                    a1 += (double)prod[k + L];
                 }
-                if (k < ve) a0 += (double)sm.prod[k];
+                if (k < ve) a0 += (double)prod[k];
                 acc = a0 + a1;
                 n_here = ve - vs;
             }
         } else {
             const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
             for (int b = bs + l; b < be; b += L) {
-                const int g = b + sh0;
+                const int g = b + lo_slot;
                 const int wi = g / Sh::BPW, bit = (g % Sh::BPW) * Sh::RC;
                 const uint64_t wv = sm.wm[wi];
                 const uint32_t m = (uint32_t)(wv >> bit) & Sh::RCMASK;
                 const uint32_t sub = (m >> (rho * Sh::C)) & Sh::CMASK;
-                const int pos = sm.off[wi] + __popcll(wv & ((1ull << bit) - 1ull)) + __popc(m & below);
+                const int pos = sm.off[wi] + __popcll(wv & low_bits(bit)) + __popc(m & below);
                 const int n = __popc(sub);
                 n_here += n;
-                for (int k = 0; k < n; ++k) acc += (double)sm.prod[pos + k];
+                for (int k = 0; k < n; ++k) acc += (double)prod[pos + k];
             }
         }
     }
@@ -616,7 +633,9 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave(SpmvArgs a) {
     __shared__ SM sm[kWaves];
     int g = blockIdx.x;
     if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
-    const int wid = threadIdx.x >> 6;
+    // the wavefront index is uniform; say so, so that everything derived from
+    // it (tile, block range, mask words) lives in scalar registers
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = g * kWaves + wid;
     if (t >= a.n_tiles) return;
     const TileDesc d = a.tiles[t];
@@ -674,11 +693,14 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     a.n_tiles = (int32_t)P->n_tiles;
     a.accumulate = accumulate;
     a.xcd_remap = P->xcd_remap;
-    // Wavefront tiles read values with 16-byte loads, so they need a 16-byte
-    // aligned values array; otherwise the same tiles run as workgroup tiles
-    // (any workgroup tile size at least as large as the plan's tiles works).
+    // Wavefront tiles read values with 16-byte loads and address x with 32-bit
+    // byte offsets, so they need a 16-byte aligned values array and x under
+    // 4 GiB; otherwise the same tiles run as workgroup tiles (any workgroup
+    // tile size at least as large as the plan's tiles works).
     const bool aligned = (reinterpret_cast<uintptr_t>(A->values) & 15u) == 0;
-    const bool wave = P->mode == 0 && aligned;
+    const size_t es = A->dtype == SPC_F64 ? 8 : 4;
+    const bool x32 = (uint64_t)A->n_cols * es <= 0xffffffffull;   // x addressed with 32-bit offsets
+    const bool wave = P->mode == 0 && aligned && x32;
     const int wg_bits = P->mode == 1 ? P->tile_bits : (P->tile_bits <= 1024 ? 1024 : 2048);
     const int64_t groups = wave ? div_up(P->n_tiles, kWaves) : P->n_tiles;
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
