@@ -88,9 +88,9 @@ int32_t spc_version(void);
 spc_status spc_shape_index(int32_t r, int32_t c);
 
 /* Bytes the masks array of n_blocks blocks must span: n_blocks*r*c/8
- * rounded up to a multiple of 8, plus 64 bytes that the kernels may read
- * (but never use) when they fetch 8 mask words at a time. Returns -1 for an
- * unsupported shape. */
+ * rounded up to a multiple of 8, plus 512 bytes that the kernels may read
+ * (but never use) when they fetch a tile's mask words in one go. Returns -1
+ * for an unsupported shape. */
 int64_t spc_mask_bytes(int32_t r, int32_t c, int64_t n_blocks);
 
 /* ---------------------------------------------------------------------------

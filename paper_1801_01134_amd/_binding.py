@@ -175,10 +175,12 @@ class BetaMatrix:
         return SHAPES.index((self.r, self.c))
 
     def view(self) -> BetaView:
+        # the masks array always exists (it carries the read-ahead padding);
+        # the other arrays may be empty, and then have no address
         return BetaView(self.r, self.c, _dtype_code(self.values.dtype), 0, self.n_rows, self.n_cols,
                         self.nnz, self.n_blocks, self.block_rowptr.data_ptr(),
                         self.block_colidx.data_ptr() if self.n_blocks else None,
-                        self.block_masks.data_ptr() if self.n_blocks else None,
+                        self.block_masks.data_ptr(),
                         self.values.data_ptr() if self.nnz else None)
 
     def plan(self, tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0, wave_chunks: int = 0) -> Plan:

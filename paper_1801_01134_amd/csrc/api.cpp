@@ -80,7 +80,7 @@ spc_status spc_shape_index(int32_t r, int32_t c) {
 int64_t spc_mask_bytes(int32_t r, int32_t c, int64_t n_blocks) {
     if (spc::shape_of(r, c) < 0 || n_blocks < 0) return -1;
     int64_t b = n_blocks * (r * c / 8);
-    return (b + 7) / 8 * 8 + 64;  // kernels read masks 8 words at a time
+    return (b + 7) / 8 * 8 + 512;  // kernels read up to 64 mask words at a time
 }
 
 }  // extern "C"

@@ -72,12 +72,15 @@ inline auto with_dtype(int dtype, F &&f) {
 inline int64_t div_up(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
-// Tile of a plan: the intervals [i0, i1) and the packed-value offset of the
-// tile's first block. 16 bytes, read with one scalar load per workgroup.
+// Tile of a plan: the intervals [i0, i1), their blocks [b0, b1), the
+// packed-value offset of the tile's first block and the tile's value count.
+// 32 bytes, read with one scalar load.
 struct TileDesc {
     int64_t vbase;
-    int32_t i0;
-    int32_t i1;
+    int32_t i0, i1;
+    int32_t b0, b1;
+    int32_t nv;
+    int32_t reserved;
 };
 
 // Validation of a view on the host.

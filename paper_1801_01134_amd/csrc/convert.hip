@@ -298,7 +298,7 @@ extern "C" spc_status spc_csr_to_beta(int32_t r, int32_t c, int32_t dtype, int64
     SPC_HIP(hipStreamSynchronize(stream));
     const int64_t used = (int64_t)nb * (r * c / 8), padded = spc_mask_bytes(r, c, nb);
     if (padded > used)
-        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(128), 0, stream,
+        hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(1024), 0, stream,
                            static_cast<uint8_t *>(block_masks_out), used, padded);
     with_shape(s, [&](auto sh) {
         using Sh = decltype(sh);

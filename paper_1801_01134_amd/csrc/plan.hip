@@ -111,7 +111,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     for (int64_t i = 0; i < n_int;) {
         const int64_t nb = brow[i + 1] - brow[i];
         if (nb > target) {
-            tiles.push_back({0, (int32_t)i, (int32_t)(i + 1)});
+            tiles.push_back({0, (int32_t)i, (int32_t)(i + 1), brow[i], brow[i + 1], 0, 0});
             ++n_long;
             ++i;
             continue;
@@ -124,7 +124,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
             blocks += b;
             ++i;
         }
-        tiles.push_back({0, (int32_t)start, (int32_t)i});
+        tiles.push_back({0, (int32_t)start, (int32_t)i, brow[start], brow[i], 0, 0});
     }
     const int64_t n_tiles = (int64_t)tiles.size();
     SPC_REQUIRE(n_tiles < (int64_t(1) << 31) / 8, SPC_ERR_CAPACITY, "too many tiles");
@@ -189,6 +189,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     int64_t run = 0;
     for (int64_t t = 0; t < n_tiles; ++t) {
         tiles[t].vbase = run;
+        tiles[t].nv = (int32_t)hcnt[t];
         run += hcnt[t];
     }
     if (run != A->nnz) {

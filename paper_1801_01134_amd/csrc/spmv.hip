@@ -48,6 +48,8 @@ struct SpmvArgs {
     const TileDesc *tiles;
     int64_t n_rows;
     int64_t nnz;
+    int64_t n_blocks;
+    int64_t n_cols;
     int32_t n_tiles;
     int32_t accumulate;
     int32_t xcd_remap;
@@ -243,19 +245,21 @@ __device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, in
 //      tile's row count allows) and combine their sums with shuffles.
 template <class Sh, class T, int KQ>
 struct WaveSmem {
+    static constexpr int G = 4;                       // mask words per scalar load
     static constexpr int E = 16 / sizeof(T);          // values per 16-byte chunk
     static constexpr int WB = (64 * KQ - 1) * E;      // bits (so values) a tile may hold
     static constexpr int NB = WB / Sh::RC;            // blocks a tile may hold
-    // NB blocks starting anywhere in a word span at most NB / BPW + 2 words;
-    // one more entry holds the sentinel after the last word
-    static constexpr int NW = NB / Sh::BPW + 3;
-    static constexpr int NI = 64 / Sh::R;             // intervals a tile may hold
-    static constexpr int NCOL = ((NB + 63) / 64) * 64;
-    uint64_t wm[NW];
-    int off[NW];
-    int brow[NI + 1];
-    int col[NCOL];
-    T buf[64 * KQ * E];                               // packed values, then products
+    // NB blocks starting anywhere in a word span at most NB / BPW + 2 words
+    static constexpr int NWMAX = NB / Sh::BPW + 2;
+    static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;   // 64-lane rounds of block columns
+    static constexpr int NCW = NWMAX * Sh::BPW;
+    static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
+    static constexpr int NBUF = 64 * KQ * E;
+    uint64_t wm[64];                                  // masked words, zero after the last
+    int off[64];                                      // value slot of each word's first bit
+    int brow[64];                                     // tile-relative interval pointers
+    int col[NCOL];                                    // column of every slot of the tile's words
+    T buf[NBUF + 64];                                 // packed values, then products
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -264,125 +268,151 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint64_t low_bits(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+__device__ __forceinline__ uint64_t low_bits(int n) {
+    return n <= 0 ? 0ull : n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP row shifts and broadcasts.
+__device__ __forceinline__ int wave_scan_dpp(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false); // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false); // row_bcast:31
+    return v;
+}
+
+// Lane-select from a 64-bit uniform mask without touching the exec mask.
+template <class V>
+__device__ __forceinline__ V pick(uint64_t m, V if_set, V if_clear) {
+    return __builtin_amdgcn_inverse_ballot_w64(m) ? if_set : if_clear;
+}
+
+// Raw buffer resources: loads past num_records return 0 and touch no memory,
+// which replaces every bounds test of the tile's streams.
+constexpr int kBufFlags = 0x00020000;   // gfx9 buffer descriptor word 3
+constexpr int kNT = 2;                  // non-temporal (streamed once)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, kBufFlags);
+}
+
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, int aux = 0);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off, int aux) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off, int aux) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 
 template <class Sh, class T, int KQ>
-__device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int b1, int64_t vbase,
-                          WaveSmem<Sh, T, KQ> &sm) {
+__device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr, WaveSmem<Sh, T, KQ> &sm) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
-    constexpr int NCR = SM::NCOL / 64;
+    constexpr int G = SM::G;
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
-    const T *__restrict__ x = static_cast<const T *>(a.x);
-    const bool last_tile = t + 1 >= a.n_tiles;
-    const int64_t vend = last_tile ? a.nnz : a.tiles[t + 1].vbase;
-    const int nv = (int)(vend - vbase);
-    const int nI = i1 - i0;
-    const int64_t abase = vbase & ~(int64_t)(E - 1);
-    const int shift = (int)(vbase - abase);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
     const int nq = (shift + nv + E - 1) / E;          // chunks holding the tile's values
-    // the array's last chunk may reach past nnz: read it value by value
-    const int q_tail = (last_tile && abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
-
-    // 1. all streams of the tile
-    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
-    const V4 *__restrict__ vsrc = reinterpret_cast<const V4 *>(vals + abase);
-    V4 ch[KQ];
-#pragma unroll
-    for (int k = 0; k < KQ; ++k) {
-        const int q = lane + 64 * k;
-        if (q < q_tail) ch[k] = __builtin_nontemporal_load(vsrc + q);
-    }
-    const int nblk = b1 - b0;
-    int colr[NCR];
-#pragma unroll
-    for (int k = 0; k < NCR; ++k) {
-        const int j = lane + 64 * k;
-        if (j < nblk) colr[k] = ldg_nt(a.bcol + b0 + j);
-    }
-    const int br = lane < nI ? a.brow[i0 + lane] : 0;   // the end pointer is b1
+    // the array's last chunk may reach past nnz: it is read value by value
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
     const int w0 = b0 / Sh::BPW;
     const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
     const int lo_slot = b0 - w0 * Sh::BPW;                  // slots of word 0 before the tile
-    const int hi_slot = b1 - (w0 + nw - 1) * Sh::BPW;       // slots of the last word inside it
-    uint64_t wl = 0;
-    if (lane < nw) {
-        wl = a.mw[w0 + lane];
-        if (lane == 0) wl &= ~low_bits(lo_slot * Sh::RC);
-        if (lane == nw - 1) wl &= low_bits(hi_slot * Sh::RC);
-    }
-    const int cnt = __popcll(wl);
-    const int incl = wave_incl_scan(cnt);
+    const int end_bit = (b1 - w0 * Sh::BPW) * Sh::RC;       // first bit after the tile, from word 0
+    const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
+    // columns of all slots of the tile's words: the blocks before b0 in the
+    // first word are never used (their bits are cleared), those after b1 in
+    // the last word are valid blocks of the next tile
+    const int cs0 = w0 * Sh::BPW;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
 
-    // values and block columns into LDS
+    // 1. every stream of the tile, as unguarded buffer loads: first the small
+    // ones the x gathers depend on (block columns, interval pointers, mask
+    // words), then the packed values, which are needed only after the gathers
+    // have been issued (loads complete in issue order)
+    const auto cr = rsrc(a.bcol + cs0, (uint32_t)ncs * 4u);
+    int colr[SM::NCR];
 #pragma unroll
-    for (int k = 0; k < KQ; ++k) {
-        const int q = lane + 64 * k;
-        if (q < q_tail) *reinterpret_cast<V4 *>(&sm.buf[q * E]) = ch[k];
-    }
-    if (q_tail < nq && lane == 0) {
-        for (int e = 0; e < E; ++e) {
-            const int64_t g = abase + (int64_t)q_tail * E + e;
-            if (g < a.nnz) sm.buf[q_tail * E + e] = vals[g];
-        }
-    }
+    for (int k = 0; k < SM::NCR; ++k)
+        colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
+    const int br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const auto wr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
+    uint64_t wl = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(wr, (uint32_t)(lane * 8), 0, 0));
+    const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
+    V4 ch[KQ];
 #pragma unroll
-    for (int k = 0; k < NCR; ++k) {
-        const int j = lane + 64 * k;
-        if (j < nblk) sm.col[j] = colr[k];
-    }
-    if (lane < nI) sm.brow[lane] = br - b0;
-    if (lane == 0) sm.brow[nI] = nblk;
-    if (lane < nw) {
-        sm.wm[lane] = wl;
-        sm.off[lane] = incl - cnt;
-    }
-    if (lane == 0) {
-        sm.wm[nw] = 0ull;
-        sm.off[nw] = nw > 0 ? __builtin_amdgcn_readlane(incl, nw - 1) : 0;
-    }
+    for (int k = 0; k < KQ; ++k)
+        ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
+
+    // metadata into LDS (unconditional: lanes past the ends write zeros and
+    // the sentinels -- word nw is zero, its offset is the tile's value count)
+    wl &= lane == 0 ? lo_mask : ~0ull;
+    wl &= low_bits(end_bit - 64 * lane);
+    const int cnt = __popcll(wl);
+    const int incl = wave_scan_dpp(cnt);
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k) sm.col[lane + 64 * k] = colr[k];
+    sm.brow[lane] = br - b0;
+    sm.wm[lane] = wl;
+    sm.off[lane] = incl - cnt;
     wave_sync();
 
-    // 2. products in place, lane = mask bit, words walked on the scalar unit
-    {
-        constexpr int G = 8;                                  // words per group (one 64-byte scalar load)
+    // 2. products in place, lane = mask bit, words walked on the scalar unit.
+    // All of the tile's words are loaded at once and all x gathers issued
+    // before the values are stored to LDS and the first product is formed. A
+    // lane whose bit is clear gathers out of range (0, no memory access) and
+    // does not store. The last word keeps the bits of the next tile's blocks:
+    // they sit above the tile's own bits, so they do not move the tile's
+    // slots, and their products land past the tile's values, where nothing
+    // reads them.
+    if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
+        constexpr int NWM = SM::NWMAX;
+        static_assert(NWM <= 64, "the masks array is padded for 64 words read past its end");
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
-        const int col_lane = slot - lo_slot;                  // block index in word 0
-        const char *__restrict__ xb = reinterpret_cast<const char *>(x);
         char *__restrict__ bb = reinterpret_cast<char *>(sm.buf);
-        int voff = shift;                                     // buffer slot of the next value
-        for (int i = 0; i < nw; i += G) {
-            // the masks array is readable 64 bytes past its last word, so a
-            // group may run past the tile's words; those words are cleared
-            const uint64_t *__restrict__ gp = a.mw + w0 + i;
-            uint64_t M[G];
+        const char *__restrict__ cb = reinterpret_cast<const char *>(sm.col) + slot * 4;
+        // the masks array is readable 512 bytes past its last word
+        const uint64_t *__restrict__ gp = a.mw + w0;
+        uint64_t M[NWM];
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int gi = i + j;
-                uint64_t m = gp[j];
-                if (gi == 0) m &= ~low_bits(lo_slot * Sh::RC);
-                if (gi == nw - 1) m &= low_bits(hi_slot * Sh::RC);
-                M[j] = gi < nw ? m : 0ull;
+        for (int j = 0; j < NWM; ++j) {
+            uint64_t m = gp[j];                                     // one wide scalar load
+            if (j == 0) m &= lo_mask;
+            M[j] = j < nw ? m : 0ull;
+        }
+        T xv[NWM];
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            const int c = *reinterpret_cast<const int *>(cb + 4 * j * Sh::BPW);
+            xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+        }
+        // the values, now that the gathers are in flight
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = ch[k];
+        if (q_tail < nq) {
+            if (lane < E) {
+                const int64_t g = abase + (int64_t)q_tail * E + lane;
+                if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
             }
-            uint32_t pb[G], xo[G];
-            T v[G], xv[G];
+        }
+        wave_sync();
+        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the next value
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if (__builtin_amdgcn_inverse_ballot_w64(M[j])) {
-                    pb[j] = (lane_rank(M[j]) + (uint32_t)voff) * (uint32_t)sizeof(T);
-                    xo[j] = (uint32_t)(sm.col[(i + j) * Sh::BPW + col_lane] + kcol) * (uint32_t)sizeof(T);
-                    v[j] = *reinterpret_cast<const T *>(bb + pb[j]);
-                }
-                voff += __popcll(M[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < G; ++j)
-                if (__builtin_amdgcn_inverse_ballot_w64(M[j])) xv[j] = *reinterpret_cast<const T *>(xb + xo[j]);
-#pragma unroll
-            for (int j = 0; j < G; ++j)
-                if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb[j]) = v[j] * xv[j];
+        for (int j = 0; j < NWM; ++j) {
+            const uint32_t pb = lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte;
+            const T v = *reinterpret_cast<const T *>(bb + pb);
+            if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb) = v * xv[j];
+            vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
         }
     }
     wave_sync();
@@ -395,10 +425,10 @@ __device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int 
     const int pair = lane >> lg, l = lane & (L - 1);
     double acc = 0.0;
     int n_here = 0;
+    const T *__restrict__ prod = sm.buf + shift;
     if (pair < npairs) {
         const int li = pair / Sh::R, rho = pair % Sh::R;
         const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
-        const T *__restrict__ prod = sm.buf + shift;
         if (Sh::R == 1) {
             if (bs < be) {
                 const int gs = bs + lo_slot, ge = be + lo_slot;
@@ -413,7 +443,7 @@ __device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int 
                 }
                 if (k < ve) a0 += (double)prod[k];
                 acc = a0 + a1;
-                n_here = ve - vs;
+                n_here = ve - vs;                            // same for every lane of the pair
             }
         } else {
             const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
@@ -430,13 +460,12 @@ __device__ void wave_tile(const SpmvArgs &a, int t, int i0, int i1, int b0, int 
             }
         }
     }
-    for (int m = L >> 1; m >= 1; m >>= 1) {
-        acc += __shfl_xor(acc, m, 64);
-        n_here += __shfl_xor(n_here, m, 64);
-    }
+    for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (Sh::R > 1 && a.accumulate)
+        for (int m = L >> 1; m >= 1; m >>= 1) n_here += __shfl_xor(n_here, m, 64);
     if (pair < npairs && l == 0) {
         const int li = pair / Sh::R, rho = pair % Sh::R;
-        const int64_t row = (int64_t)(i0 + li) * Sh::R + rho;
+        const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
         if (row < a.n_rows) {
             T *__restrict__ y = static_cast<T *>(a.y);
             if (a.accumulate) {
@@ -639,9 +668,12 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave(SpmvArgs a) {
     const int t = g * kWaves + wid;
     if (t >= a.n_tiles) return;
     const TileDesc d = a.tiles[t];
-    const int b0 = a.brow[d.i0], b1 = a.brow[d.i1];
-    if (b1 - b0 > SM::NB) wave_long<Sh, T>(a, d.i0, b0, b1, d.vbase);
-    else wave_tile<Sh, T, KQ>(a, t, d.i0, d.i1, b0, b1, d.vbase, sm[wid]);
+    if (d.b1 - d.b0 > SM::NB) {
+        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+    } else {
+        const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+        wave_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+    }
 }
 
 template <int R, int C, class T>
@@ -669,7 +701,8 @@ spc_status launch_wave(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream)
 
 }  // namespace
 
-int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? 64 / r : kThreads / r; }
+// Mode 0 loads a tile's interval pointers one per lane, the end pointer included.
+int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? (r == 1 ? 63 : 64 / r) : kThreads / r; }
 
 // Tile capacity in mask bits for a mode and a chunk count (mode 0) or the
 // workgroup tile size (mode 1).
@@ -690,6 +723,8 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     a.tiles = P->d_tiles;
     a.n_rows = A->n_rows;
     a.nnz = A->nnz;
+    a.n_blocks = A->n_blocks;
+    a.n_cols = A->n_cols;
     a.n_tiles = (int32_t)P->n_tiles;
     a.accumulate = accumulate;
     a.xcd_remap = P->xcd_remap;
@@ -699,7 +734,7 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     // tile size at least as large as the plan's tiles works).
     const bool aligned = (reinterpret_cast<uintptr_t>(A->values) & 15u) == 0;
     const size_t es = A->dtype == SPC_F64 ? 8 : 4;
-    const bool x32 = (uint64_t)A->n_cols * es <= 0xffffffffull;   // x addressed with 32-bit offsets
+    const bool x32 = (uint64_t)A->n_cols * es < 0xf0000000ull;    // x addressed with 32-bit offsets
     const bool wave = P->mode == 0 && aligned && x32;
     const int wg_bits = P->mode == 1 ? P->tile_bits : (P->tile_bits <= 1024 ? 1024 : 2048);
     const int64_t groups = wave ? div_up(P->n_tiles, kWaves) : P->n_tiles;

@@ -40,10 +40,11 @@ def test_host_helpers():
     assert L.spc_status_string(-2) == b"SPC_ERR_UNSUPPORTED_SHAPE"
     assert [L.spc_shape_index(r, c) for r, c in B.SHAPES] == list(range(6))
     assert L.spc_shape_index(3, 3) == -2
-    assert L.spc_mask_bytes(1, 8, 1) == 8 + 64 and L.spc_mask_bytes(1, 8, 8) == 8 + 64
-    assert L.spc_mask_bytes(1, 8, 9) == 16 + 64
-    assert L.spc_mask_bytes(4, 8, 3) == 16 + 64 and L.spc_mask_bytes(2, 8, 4) == 8 + 64
-    assert L.spc_mask_bytes(1, 8, 0) == 64
+    pad = 512
+    assert L.spc_mask_bytes(1, 8, 1) == 8 + pad and L.spc_mask_bytes(1, 8, 8) == 8 + pad
+    assert L.spc_mask_bytes(1, 8, 9) == 16 + pad
+    assert L.spc_mask_bytes(4, 8, 3) == 16 + pad and L.spc_mask_bytes(2, 8, 4) == 8 + pad
+    assert L.spc_mask_bytes(1, 8, 0) == pad
     assert L.spc_mask_bytes(5, 5, 1) == -1
     assert L.spc_version() >= 10000
 

@@ -238,3 +238,22 @@ def test_values_not_16_byte_aligned(dtype):
     assert B.values.data_ptr() % 16 != 0
     y = spc.spmv(B, torch.from_numpy(x).cuda()).cpu().numpy()
     check_rows(y, y_ref, s_ref, TOL[dtype], "misaligned values")
+
+
+def test_empty_matrix_with_null_masks_pointer():
+    # a matrix without blocks may come with no masks array at all
+    say("[null masks] all-empty matrix, view without a masks pointer")
+    import ctypes
+    from paper_1801_01134_amd import _binding as Bd
+    A = case("all_empty")
+    B = to_beta(A, 1, 8, torch.float64)
+    v = B.view()
+    v.block_masks = None
+    h = ctypes.c_void_p()
+    Bd.check(Bd.lib().spc_plan_create(ctypes.byref(v), None, ctypes.byref(h), Bd.stream_ptr()))
+    x = torch.ones(A.n_cols, dtype=torch.float64, device="cuda")
+    y = torch.full((A.n_rows,), 7.0, dtype=torch.float64, device="cuda")
+    Bd.check(Bd.lib().spc_spmv_beta(ctypes.byref(v), h, ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(y.data_ptr()), 0, Bd.stream_ptr()))
+    assert torch.all(y == 0)
+    Bd.lib().spc_plan_destroy(h)
