@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 def algorithmic_bytes(B, n_tiles: int, k: int = 1, accumulate: bool = False) -> int:
     es = B.values.element_size()
     n_int = B.block_rowptr.numel()
-    b = (B.nnz * es + B.n_blocks * 4 + B.n_blocks * B.r * B.c // 8 + n_int * 4 + n_tiles * 16
+    b = (B.nnz * es + B.n_blocks * 4 + B.n_blocks * B.r * B.c // 8 + n_int * 4 + n_tiles * 32
          + k * B.n_cols * es + k * B.n_rows * es)
     if accumulate:
         b += k * B.n_rows * es
@@ -65,7 +65,7 @@ def cpu_baseline(A, x, budget_s: float = 10.0):
         oracle.csr_spmv(A, x)
         runs += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or runs >= 16:
+        if el >= budget_s:
             break
     per = el / runs
     return {"value": round(2.0 * A.nnz / per / 1e9, 3), "unit": "GFlop/s", "cores": oracle.threads(),
@@ -80,13 +80,27 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--grid", type=int, default=128, help="stencil grid edge (128 -> 2.1M rows)")
-    ap.add_argument("--sweep-steps", type=int, default=50, help="launches per kernel in the sweep")
+    ap.add_argument("--sweep-steps", type=int, default=20, help="timed launches per autotune candidate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--shape", default="auto", help="r,c of the headline kernel, or auto")
-    ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--only-headline", action="store_true", help="skip the 12-kernel sweep")
+    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap: force the "
+                    "headline plan (skips autotuning; used for profiling)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="run only a plain 256 MiB copy (memory-counter calibration)")
     args = ap.parse_args(argv)
 
+    if args.copy_ref:
+        # a plain copy of known size: calibrates the memory counters
+        import torch
+        n = 256 * 2**20 // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4}))
+        return 0
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} refused: this build measures one GPU only "
               "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
@@ -113,33 +127,38 @@ def main(argv=None):
     csr_bytes = {8: A.nnz * 12 + (A.n_rows + 1) * 4, 4: A.nnz * 8 + (A.n_rows + 1) * 4}
 
     sweep = {}
+    best_params = {}
     shapes = spc.SHAPES
     if args.only_headline and args.shape != "auto":
         shapes = [tuple(int(v) for v in args.shape.split(","))]
     for dt in (torch.float64, torch.float32):
-        if args.only_headline and dt != torch.float64:
-            continue
+        if args.only_headline:
+            break
         xd = torch.from_numpy(x64).to(dev).to(dt)
-        yd = torch.empty(A.n_rows, dtype=dt, device=dev)
         for (r, c) in shapes:
             B = spc.csr_to_beta(r, c, rp, ci, v64.to(dt), A.n_cols)
-            P = B.plan(args.tile_bits)
+            params, us, records = spc.autotune(B, reps=args.sweep_steps, x=xd)
+            t = us * 1e-6
+            P = spc.plan_from(B, params)
             info = P.info()
-            t = time_spmv(spc, torch, B, xd, yd, P, args.sweep_steps, 5)
             ab = algorithmic_bytes(B, info["n_tiles"])
             key = f"{'f64' if dt == torch.float64 else 'f32'}_b{r}x{c}"
-            sweep[key] = {"us": round(t * 1e6, 2), "gflops": round(flops / t / 1e9, 1),
+            best_params[key] = params
+            sweep[key] = {"us": round(us, 2), "gflops": round(flops / t / 1e9, 1),
                           "alg_GBs": round(ab / t / 1e9, 1), "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
                           "alg_bytes": ab, "matrix_bytes": B.nbytes(),
                           "matrix_vs_csr": round(B.nbytes() / csr_bytes[B.values.element_size()], 4),
                           "n_blocks": B.n_blocks, "avg_nnz_per_block": round(A.nnz / B.n_blocks, 3),
-                          "n_tiles": info["n_tiles"], "n_long": info["n_long"]}
+                          "n_tiles": info["n_tiles"], "n_long": info["n_long"], "plan": params,
+                          "candidates": len(records)}
             print(f"# {key}: {sweep[key]}", file=sys.stderr, flush=True)
             del B, P
             torch.cuda.empty_cache()
 
     # headline kernel: FP64, chosen from the records above (or forced)
-    if args.shape == "auto":
+    if args.shape == "auto" and not sweep:
+        r, c = 2, 4
+    elif args.shape == "auto":
         f64 = {k: v for k, v in sweep.items() if k.startswith("f64_")}
         best = min(f64, key=lambda k: f64[k]["us"])
         r, c = (int(s) for s in best[5:].split("x"))
@@ -148,8 +167,16 @@ def main(argv=None):
     xd = torch.from_numpy(x64).to(dev)
     yd = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     B = spc.csr_to_beta(r, c, rp, ci, v64, A.n_cols)
-    P = B.plan(args.tile_bits)
+    if args.plan:
+        m_, v_, x_ = (int(t) for t in args.plan.split(","))
+        params = {"mode": m_, "wave_chunks": v_ if m_ == 0 else 0, "tile_bits": v_ if m_ == 1 else 0,
+                  "xcd_remap": x_}
+    else:
+        params = best_params.get(f"f64_b{r}x{c}") or spc.autotune(B, reps=args.sweep_steps, x=xd)[0]
+    P = spc.plan_from(B, params)
     info = P.info()
+    kname = (f"k_spmv_wave<{r},{c},double,{params['wave_chunks'] or 4}>" if params["mode"] == 0
+             else f"k_spmv_wg<{r},{c},double,{info['tile_bits']}>")
     for _ in range(args.warmup):
         spc.spmv(B, xd, yd, plan=P)
     torch.cuda.synchronize()
@@ -181,11 +208,11 @@ def main(argv=None):
                    "nnz": A.nnz, "tile_bits": info.get("tile_bits"), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"k_spmv<{r},{c},double,{info['tile_bits']}>",
+                     "kernel": kname, "plan": params,
                      "alg_bytes_per_launch": ab, "kernel_us": round(t_kernel * 1e6, 2)},
         "selected_vs_best_time_ratio": round(ratio, 4) if ratio else None,
-        "selection": "fastest of the six beta kernels on this matrix (records taken in this run)"
-                     if args.shape == "auto" else "forced",
+        "selection": "fastest of the six beta kernels on this matrix, each autotuned over 14 plan "
+                     "candidates (records taken in this run)" if args.shape == "auto" else "forced",
         "per_kernel": sweep,
     }
     del B, P

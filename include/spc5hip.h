@@ -174,6 +174,66 @@ spc_status spc_plan_info(const spc_plan *plan, int64_t *n_tiles, int64_t *n_long
 spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan, const void *x, void *y,
                          int32_t accumulate, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Y = A X (accumulate = 0) or Y += A X for k right-hand sides, 1 <= k <= 16.
+ * X: n_cols x k and Y: n_rows x k, row-major with leading dimensions
+ * ldx, ldy >= k (the k values of one row are contiguous), A's dtype. Each
+ * Y entry is the plain definition sum_j a_ij X[j][q], summed in double
+ * precision. plan must be a mode-0 plan of A (wavefront tiles); values must
+ * be 16-byte aligned and X smaller than 3.75 GiB. Asynchronous. */
+spc_status spc_spmm_beta(const spc_beta_view *A, const spc_plan *plan, int32_t k, const void *X,
+                         int64_t ldx, void *Y, int64_t ldy, int32_t accumulate, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Conjugate gradients on k independent systems A X = B (A square and
+ * symmetric positive definite, the caller's responsibility), started from
+ * X = 0. Each iteration costs one spc_spmm_beta with k columns plus
+ * column-wise dot products and updates; all scalars stay on the device.
+ * Column q stops changing once ||r_q|| <= rel_tol * ||b_q|| (r the
+ * recurrence residual). The host reads the stop flags every check_every
+ * iterations and returns when all columns stopped or max_iter is reached.
+ * use_graph = 1 captures one iteration in a HIP graph and replays it
+ * (needs a non-NULL stream; with a NULL stream the iteration is launched
+ * directly). workspace: device memory of spc_cg_workspace_bytes(n, k,
+ * dtype) bytes, owned by the caller. On return (host arrays of k entries):
+ * iters_out[q] = iteration at which column q met the tolerance (-1 if it did
+ * not), rel_res_out[q] = ||r_q|| / ||b_q|| of the recurrence; total_iters_out
+ * = iterations run. Synchronizes. */
+int64_t spc_cg_workspace_bytes(int64_t n, int32_t k, int32_t dtype);
+spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k, const void *B,
+                        int64_t ldb, void *X, int64_t ldx, double rel_tol, int32_t max_iter,
+                        int32_t check_every, int32_t use_graph, void *workspace,
+                        int64_t workspace_bytes, int32_t *iters_out, double *rel_res_out,
+                        int32_t *total_iters_out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Timing records and autotuning (the record-based strategy of the paper's
+ * contributions list: choices are made from timings of earlier runs).
+ *
+ * spc_time_spmv: average device time of one y = A x launch under `plan`,
+ *   over `reps` launches after `warmup` launches, measured with HIP events
+ *   on `stream` (microseconds, host *us_out). Synchronizes.
+ *
+ * spc_autotune: builds a plan for every candidate parameter set (both
+ *   modes; mode 0 with 2, 4 and 8 chunks per lane, mode 1 with 1024, 2048,
+ *   3072 and 4032 tile bits; each with and without XCD remapping), times it
+ *   with spc_time_spmv and returns the fastest set in *best and its time in
+ *   *best_us. If records is not NULL, up to max_records timings are written
+ *   there (host memory) and *n_records says how many. x and y are scratch
+ *   vectors of A's dtype (n_cols and n_rows entries); y is overwritten.
+ *   Synchronizes. */
+typedef struct spc_tune_record {
+    spc_plan_params params;
+    float us;
+    int32_t n_tiles;
+} spc_tune_record;
+
+spc_status spc_time_spmv(const spc_beta_view *A, const spc_plan *plan, const void *x, void *y,
+                         int32_t warmup, int32_t reps, float *us_out, hipStream_t stream);
+spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t reps,
+                        spc_plan_params *best, float *best_us, spc_tune_record *records,
+                        int32_t max_records, int32_t *n_records, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

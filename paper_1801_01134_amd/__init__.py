@@ -6,5 +6,5 @@ include/spc5hip.h); this package is its Python binding plus the seeded input
 generators in ``synth``.
 """
 from . import synth  # noqa: F401
-from ._binding import (SHAPES, BetaMatrix, Plan, SpcError, beta_to_csr, csr_to_beta,  # noqa: F401
-                       lib, mask_bytes, spmv)
+from ._binding import (SHAPES, BetaMatrix, Plan, SpcError, autotune, beta_to_csr, cg,  # noqa: F401
+                       csr_to_beta, lib, mask_bytes, plan_from, spmm, spmv, time_spmv)

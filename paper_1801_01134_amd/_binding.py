@@ -36,6 +36,10 @@ class PlanParams(ctypes.Structure):
                 ("wave_chunks", c_int32), ("reserved", c_int32 * 4)]
 
 
+class TuneRecord(ctypes.Structure):
+    _fields_ = [("params", PlanParams), ("us", ctypes.c_float), ("n_tiles", c_int32)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -54,6 +58,16 @@ _SIGS = {
     "spc_plan_destroy": (c_int32, [c_void_p]),
     "spc_plan_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
     "spc_spmv_beta": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
+    "spc_spmm_beta": (c_int32, [POINTER(BetaView), c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                                c_int32, c_void_p]),
+    "spc_cg_workspace_bytes": (c_int64, [c_int64, c_int32, c_int32]),
+    "spc_cg_solve": (c_int32, [POINTER(BetaView), c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64,
+                               ctypes.c_double, c_int32, c_int32, c_int32, c_void_p, c_int64,
+                               POINTER(c_int32), POINTER(ctypes.c_double), POINTER(c_int32), c_void_p]),
+    "spc_time_spmv": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                POINTER(ctypes.c_float), c_void_p]),
+    "spc_autotune": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_int32, POINTER(PlanParams),
+                               POINTER(ctypes.c_float), c_void_p, c_int32, POINTER(c_int32), c_void_p]),
 }
 
 
@@ -251,3 +265,84 @@ def spmv(A: BetaMatrix, x: torch.Tensor, y: torch.Tensor | None = None, accumula
     check(lib().spc_spmv_beta(ctypes.byref(view), plan.handle, _ptr(x), _ptr(y), int(accumulate),
                               stream_ptr()))
     return y
+
+
+def time_spmv(A: BetaMatrix, plan: Plan | None = None, reps: int = 20, warmup: int = 3) -> float:
+    """Average device time (us) of one y = A x launch under the plan."""
+    plan = plan or A.plan()
+    x = torch.zeros(A.n_cols, dtype=A.dtype, device=A.values.device)
+    y = torch.empty(A.n_rows, dtype=A.dtype, device=A.values.device)
+    us = ctypes.c_float()
+    check(lib().spc_time_spmv(ctypes.byref(plan._view), plan.handle, _ptr(x), _ptr(y), warmup, reps,
+                              ctypes.byref(us), stream_ptr()))
+    return us.value
+
+
+def autotune(A: BetaMatrix, reps: int = 20, x: torch.Tensor | None = None):
+    """Times every candidate plan; returns (best params dict, best us, records)."""
+    if x is None:
+        x = torch.zeros(A.n_cols, dtype=A.dtype, device=A.values.device)
+    y = torch.empty(A.n_rows, dtype=A.dtype, device=A.values.device)
+    view = A.view()
+    best = PlanParams()
+    best_us = ctypes.c_float()
+    recs = (TuneRecord * 64)()
+    n = c_int32()
+    check(lib().spc_autotune(ctypes.byref(view), _ptr(x), _ptr(y), reps, ctypes.byref(best),
+                             ctypes.byref(best_us), ctypes.cast(recs, c_void_p), 64, ctypes.byref(n),
+                             stream_ptr()))
+
+    def pd(p):
+        return {"mode": p.mode, "tile_bits": p.tile_bits, "wave_chunks": p.wave_chunks,
+                "xcd_remap": p.xcd_remap}
+    records = [dict(pd(recs[i].params), us=recs[i].us, n_tiles=recs[i].n_tiles) for i in range(n.value)]
+    return pd(best), best_us.value, records
+
+
+def plan_from(A: BetaMatrix, params: dict) -> Plan:
+    return A.plan(params.get("tile_bits", 0), params.get("xcd_remap", 0), params.get("mode", 0),
+                  params.get("wave_chunks", 0))
+
+
+def spmm(A: BetaMatrix, X: torch.Tensor, Y: torch.Tensor | None = None, accumulate: bool = False,
+         plan: Plan | None = None) -> torch.Tensor:
+    """Y = A X (or Y += A X) for a row-major block X of k <= 16 columns."""
+    if X.dim() != 2 or X.shape[0] != A.n_cols or X.dtype != A.dtype or X.stride(1) != 1:
+        raise ValueError("X must be n_cols x k, row-major, of A's dtype")
+    k = X.shape[1]
+    if Y is None:
+        if accumulate:
+            raise ValueError("accumulate needs Y")
+        Y = torch.empty((A.n_rows, k), dtype=A.dtype, device=X.device)
+    elif Y.shape != (A.n_rows, k) or Y.dtype != A.dtype or Y.stride(1) != 1:
+        raise ValueError("Y must be n_rows x k, row-major, of A's dtype")
+    plan = plan or A.plan()
+    check(lib().spc_spmm_beta(ctypes.byref(plan._view), plan.handle, k, _ptr(X), X.stride(0), _ptr(Y),
+                              Y.stride(0), int(accumulate), stream_ptr()))
+    return Y
+
+
+def cg(A: BetaMatrix, B: torch.Tensor, rel_tol: float = 1e-8, max_iter: int = 10000, check_every: int = 10,
+       use_graph: bool = True, plan: Plan | None = None):
+    """Solve A X = B (k <= 16 columns) by CG from X = 0 on the device.
+
+    Returns (X, iterations per column, relative recurrence residual per
+    column, iterations run)."""
+    if B.dim() == 1:
+        B = B[:, None]
+    if B.dim() != 2 or B.shape[0] != A.n_rows or B.dtype != A.dtype:
+        raise ValueError("B must be n_rows x k of A's dtype")
+    B = B.contiguous()
+    k = B.shape[1]
+    X = torch.empty_like(B)
+    nbytes = int(lib().spc_cg_workspace_bytes(A.n_rows, k, _dtype_code(A.dtype)))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=B.device)
+    its = (c_int32 * k)()
+    res = (ctypes.c_double * k)()
+    tot = c_int32()
+    plan = plan or A.plan()
+    check(lib().spc_cg_solve(ctypes.byref(plan._view), plan.handle, k, _ptr(B), B.stride(0), _ptr(X),
+                             X.stride(0), rel_tol, max_iter, check_every, int(use_graph), _ptr(ws), nbytes,
+                             ctypes.cast(its, POINTER(c_int32)), ctypes.cast(res, POINTER(ctypes.c_double)),
+                             ctypes.byref(tot), stream_ptr()))
+    return X, list(its), list(res), tot.value

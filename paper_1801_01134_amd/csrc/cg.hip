@@ -1,0 +1,339 @@
+// Conjugate gradients for k independent right-hand sides that share one
+// beta(r,c) matrix: one SpMM per iteration (the multi-vector product of
+// this library) plus column-wise dot products and updates. The paper
+// motivates fast SpMV by Krylov solvers such as CG, where one matrix is
+// applied many times.
+//
+// Every scalar (alpha, beta, the residual norms, a done flag per column)
+// lives in device memory, so an iteration is a fixed sequence of launches
+// that can be captured once in a HIP graph and replayed; the host looks at
+// the done flags every check_every iterations. A column stops (its alpha and
+// beta become 0) as soon as ||r|| <= rel_tol * ||b||. Reductions run in two
+// fixed passes (per-block partials, then one block), so results repeat bit
+// for bit.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spc {
+spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, int accumulate, hipStream_t stream);
+
+namespace {
+
+constexpr int kT = 256;          // threads per block of the vector kernels
+constexpr int kBlocks = 1024;    // blocks of the reduction passes
+constexpr int kMaxK = 16;
+
+struct Scal {                    // per-column state, in device memory
+    double rr[kMaxK];            // current ||r||^2
+    double bb[kMaxK];            // ||b||^2
+    double pq[kMaxK];
+    double alpha[kMaxK];
+    double beta[kMaxK];
+    int done[kMaxK];
+    int iter_done[kMaxK];
+    int iter;                    // iterations run so far
+};
+
+// Block-level sum of k column values; thread 0..k-1 get the k totals.
+__device__ void block_sum_cols(double *v, int k, double *smem) {
+    // smem: [kT][kMaxK]
+    #pragma unroll
+    for (int q = 0; q < kMaxK; ++q) if (q < k) smem[threadIdx.x * kMaxK + q] = v[q];
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < k; ++q) smem[threadIdx.x * kMaxK + q] += smem[(threadIdx.x + s) * kMaxK + q];
+        __syncthreads();
+    }
+}
+
+// R = B, P = B, X = 0; partial sums of B*B per column.
+template <class T>
+__global__ __launch_bounds__(kT) void k_init(int64_t n, int k, const T *B, int64_t ldb, T *X, int64_t ldx, T *R,
+                                             T *P, double *part) {
+    __shared__ double sm[kT * kMaxK];
+    double acc[kMaxK];
+    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q) {
+            if (q >= k) break;
+            const T b = B[i * ldb + q];
+            R[i * k + q] = b;
+            P[i * k + q] = b;
+            X[i * ldx + q] = T(0);
+            acc[q] += (double)b * (double)b;
+        }
+    }
+    block_sum_cols(acc, k, sm);
+    if ((int)threadIdx.x < k) part[blockIdx.x * kMaxK + threadIdx.x] = sm[threadIdx.x];
+}
+
+// Partial sums of U*V per column (U, V with leading dimension k).
+template <class T>
+__global__ __launch_bounds__(kT) void k_dot(int64_t n, int k, const T *U, const T *V, double *part) {
+    __shared__ double sm[kT * kMaxK];
+    double acc[kMaxK];
+    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q)
+            if (q < k) acc[q] += (double)U[i * k + q] * (double)V[i * k + q];
+    block_sum_cols(acc, k, sm);
+    if ((int)threadIdx.x < k) part[blockIdx.x * kMaxK + threadIdx.x] = sm[threadIdx.x];
+}
+
+// Totals of the partials, in one block, fixed order.
+__device__ void total_cols(const double *part, int nblk, int k, double *out, double *sm) {
+    double acc[kMaxK];
+    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kT)
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q)
+            if (q < k) acc[q] += part[b * kMaxK + q];
+    block_sum_cols(acc, k, sm);
+    if ((int)threadIdx.x < k) out[threadIdx.x] = sm[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kT) void k_start(const double *part, int nblk, int k, Scal *s, double tol) {
+    __shared__ double sm[kT * kMaxK];
+    __shared__ double tot[kMaxK];
+    total_cols(part, nblk, k, tot, sm);
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        const int q = threadIdx.x;
+        s->bb[q] = tot[q];
+        s->rr[q] = tot[q];
+        s->done[q] = (tot[q] == 0.0) ? 1 : 0;
+        s->iter_done[q] = s->done[q] ? 0 : -1;
+        s->alpha[q] = 0.0;
+        s->beta[q] = 0.0;
+    }
+    if (threadIdx.x == 0) s->iter = 0;
+    (void)tol;
+}
+
+// alpha = rr / (p . q) for running columns, 0 for finished ones.
+__global__ __launch_bounds__(kT) void k_alpha(const double *part, int nblk, int k, Scal *s) {
+    __shared__ double sm[kT * kMaxK];
+    __shared__ double tot[kMaxK];
+    total_cols(part, nblk, k, tot, sm);
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        const int q = threadIdx.x;
+        s->pq[q] = tot[q];
+        s->alpha[q] = (s->done[q] || tot[q] == 0.0) ? 0.0 : s->rr[q] / tot[q];
+    }
+}
+
+// X += alpha P, R -= alpha Q; partial sums of R*R per column.
+template <class T>
+__global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, T *X, int64_t ldx, T *R,
+                                               const T *P, const T *Q, double *part) {
+    __shared__ double sm[kT * kMaxK];
+    __shared__ double al[kMaxK];
+    if ((int)threadIdx.x < k) al[threadIdx.x] = s->alpha[threadIdx.x];
+    __syncthreads();
+    double acc[kMaxK];
+    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q) {
+            if (q >= k) break;
+            const double a = al[q];
+            const int64_t e = i * k + q;
+            X[i * ldx + q] = (T)((double)X[i * ldx + q] + a * (double)P[e]);
+            const T r = (T)((double)R[e] - a * (double)Q[e]);
+            R[e] = r;
+            acc[q] += (double)r * (double)r;
+        }
+    }
+    block_sum_cols(acc, k, sm);
+    if ((int)threadIdx.x < k) part[blockIdx.x * kMaxK + threadIdx.x] = sm[threadIdx.x];
+}
+
+// beta = rr_new / rr; convergence test; iteration count.
+__global__ __launch_bounds__(kT) void k_beta(const double *part, int nblk, int k, Scal *s, double tol2) {
+    __shared__ double sm[kT * kMaxK];
+    __shared__ double tot[kMaxK];
+    total_cols(part, nblk, k, tot, sm);
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        const int q = threadIdx.x;
+        const int it = s->iter + 1;
+        if (s->done[q]) {
+            s->beta[q] = 0.0;
+        } else {
+            const double rn = tot[q];
+            s->beta[q] = s->rr[q] > 0.0 ? rn / s->rr[q] : 0.0;
+            s->rr[q] = rn;
+            if (rn <= tol2 * s->bb[q]) {
+                s->done[q] = 1;
+                s->iter_done[q] = it;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s->iter = s->iter + 1;
+}
+
+// P = R + beta P. A finished column gets beta = 0 and keeps alpha = 0, so its
+// X and R no longer change.
+template <class T>
+__global__ __launch_bounds__(kT) void k_direction(int64_t n, int k, const Scal *s, const T *R, T *P) {
+    __shared__ double be[kMaxK];
+    if ((int)threadIdx.x < k) be[threadIdx.x] = s->beta[threadIdx.x];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q) {
+            if (q >= k) break;
+            const int64_t e = i * k + q;
+            P[e] = (T)((double)R[e] + be[q] * (double)P[e]);
+        }
+}
+
+struct Work {
+    void *R, *P, *Q;
+    double *part;
+    Scal *s;
+};
+
+int64_t work_bytes(int64_t n, int k, int dtype) {
+    const int64_t es = dtype == SPC_F64 ? 8 : 4;
+    const int64_t vec = (n * k * es + 255) / 256 * 256;
+    return 3 * vec + (int64_t)kBlocks * kMaxK * 8 + (int64_t)((sizeof(Scal) + 255) / 256 * 256);
+}
+
+Work carve(void *ws, int64_t n, int k, int dtype) {
+    const int64_t es = dtype == SPC_F64 ? 8 : 4;
+    const int64_t vec = (n * k * es + 255) / 256 * 256;
+    char *p = static_cast<char *>(ws);
+    Work w;
+    w.R = p;
+    w.P = p + vec;
+    w.Q = p + 2 * vec;
+    w.part = reinterpret_cast<double *>(p + 3 * vec);
+    w.s = reinterpret_cast<Scal *>(p + 3 * vec + (int64_t)kBlocks * kMaxK * 8);
+    return w;
+}
+
+unsigned vec_blocks(int64_t n) {
+    int64_t b = div_up(n > 0 ? n : 1, kT);
+    return (unsigned)(b < kBlocks ? b : kBlocks);
+}
+
+template <class T>
+spc_status iteration(const spc_beta_view *A, const spc_plan *P, int k, const Work &w, T *X, int64_t ldx,
+                     int64_t n, double tol2, hipStream_t st) {
+    const unsigned nb = vec_blocks(n);
+    spc_status r = spmm_launch(A, P, k, w.P, k, w.Q, k, 0, st);
+    if (r != SPC_OK) return r;
+    hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(kT), 0, st, n, k, (const T *)w.P, (const T *)w.Q, w.part);
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kT), 0, st, w.part, (int)nb, k, w.s);
+    hipLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kT), 0, st, n, k, (const Scal *)w.s, X, ldx, (T *)w.R,
+                       (const T *)w.P, (const T *)w.Q, w.part);
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(kT), 0, st, w.part, (int)nb, k, w.s, tol2);
+    hipLaunchKernelGGL(k_direction<T>, dim3(nb), dim3(kT), 0, st, n, k, (const Scal *)w.s, (const T *)w.R,
+                       (T *)w.P);
+    SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
+}  // namespace
+}  // namespace spc
+
+using namespace spc;
+
+extern "C" int64_t spc_cg_workspace_bytes(int64_t n, int32_t k, int32_t dtype) {
+    if (n < 0 || k < 1 || k > kMaxK) return -1;
+    return work_bytes(n, k, dtype);
+}
+
+extern "C" spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k, const void *B,
+                                   int64_t ldb, void *X, int64_t ldx, double rel_tol, int32_t max_iter,
+                                   int32_t check_every, int32_t use_graph, void *workspace,
+                                   int64_t workspace_bytes, int32_t *iters_out, double *rel_res_out,
+                                   int32_t *total_iters_out, hipStream_t stream) {
+    spc_status st = check_view(A);
+    if (st != SPC_OK) return st;
+    SPC_REQUIRE(plan && plan->mode == 0, SPC_ERR_INVALID_ARG, "spc_cg_solve needs a mode-0 plan of A");
+    SPC_REQUIRE(plan->A.block_rowptr == A->block_rowptr && plan->A.values == A->values &&
+                    plan->A.block_masks == A->block_masks && plan->A.n_rows == A->n_rows,
+                SPC_ERR_INVALID_ARG, "plan was built for a different matrix view");
+    SPC_REQUIRE((reinterpret_cast<uintptr_t>(A->values) & 15u) == 0, SPC_ERR_INVALID_ARG,
+                "spc_cg_solve needs a 16-byte aligned values array");
+    SPC_REQUIRE(A->n_rows == A->n_cols, SPC_ERR_INVALID_ARG, "CG needs a square matrix");
+    SPC_REQUIRE(k >= 1 && k <= kMaxK, SPC_ERR_CAPACITY, "k must be in 1..%d", kMaxK);
+    SPC_REQUIRE(ldb >= k && ldx >= k, SPC_ERR_INVALID_ARG, "leading dimensions must be at least k");
+    SPC_REQUIRE(rel_tol > 0.0 && max_iter >= 0 && check_every >= 1, SPC_ERR_INVALID_ARG, "bad iteration controls");
+    const int64_t n = A->n_rows;
+    SPC_REQUIRE(workspace && workspace_bytes >= work_bytes(n, k, A->dtype), SPC_ERR_INVALID_ARG,
+                "workspace smaller than spc_cg_workspace_bytes");
+    SPC_REQUIRE(B && X, SPC_ERR_INVALID_ARG, "null B or X");
+    {
+        const uint64_t es = A->dtype == SPC_F64 ? 8 : 4;
+        SPC_REQUIRE((uint64_t)n * (uint64_t)k * es < 0xf0000000ull, SPC_ERR_CAPACITY,
+                    "n * k must stay below 3.75 GiB (32-bit offsets of the product)");
+        SPC_REQUIRE(reinterpret_cast<uintptr_t>(B) % es == 0 && reinterpret_cast<uintptr_t>(X) % es == 0,
+                    SPC_ERR_INVALID_ARG, "B and X must be aligned to the element size");
+    }
+    const Work w = carve(workspace, n, k, A->dtype);
+    if (stream == nullptr) use_graph = 0;  // the legacy default stream cannot be captured
+    const double tol2 = rel_tol * rel_tol;
+    const unsigned nb = vec_blocks(n);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    };
+    st = with_dtype(A->dtype, [&](auto tv) -> spc_status {
+        using T = decltype(tv);
+        hipLaunchKernelGGL(k_init<T>, dim3(nb), dim3(kT), 0, stream, n, k, (const T *)B, ldb, (T *)X, ldx,
+                           (T *)w.R, (T *)w.P, w.part);
+        hipLaunchKernelGGL(k_start, dim3(1), dim3(kT), 0, stream, w.part, (int)nb, k, w.s, rel_tol);
+        SPC_HIP(hipGetLastError());
+        if (use_graph) {
+            SPC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            spc_status r = iteration<T>(A, plan, k, w, (T *)X, ldx, n, tol2, stream);
+            hipError_t e = hipStreamEndCapture(stream, &graph);
+            if (r != SPC_OK) return r;
+            SPC_HIP(e);
+            SPC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        std::vector<int> done(k);
+        int it = 0;
+        while (it < max_iter) {
+            const int batch = check_every < max_iter - it ? check_every : max_iter - it;
+            for (int b = 0; b < batch; ++b) {
+                if (use_graph) {
+                    SPC_HIP(hipGraphLaunch(exec, stream));
+                } else {
+                    spc_status r = iteration<T>(A, plan, k, w, (T *)X, ldx, n, tol2, stream);
+                    if (r != SPC_OK) return r;
+                }
+            }
+            it += batch;
+            SPC_HIP(hipMemcpyAsync(done.data(), w.s->done, sizeof(int) * k, hipMemcpyDeviceToHost, stream));
+            SPC_HIP(hipStreamSynchronize(stream));
+            bool all = true;
+            for (int q = 0; q < k; ++q) all = all && done[q];
+            if (all) break;
+        }
+        Scal hs;
+        SPC_HIP(hipMemcpyAsync(&hs, w.s, sizeof(Scal), hipMemcpyDeviceToHost, stream));
+        SPC_HIP(hipStreamSynchronize(stream));
+        for (int q = 0; q < k; ++q) {
+            if (iters_out) iters_out[q] = hs.iter_done[q];
+            if (rel_res_out) rel_res_out[q] = hs.bb[q] > 0.0 ? std::sqrt(hs.rr[q] / hs.bb[q]) : 0.0;
+        }
+        if (total_iters_out) *total_iters_out = hs.iter;
+        return SPC_OK;
+    });
+    cleanup();
+    return st;
+}

@@ -1,0 +1,346 @@
+// Y = A X for k right-hand sides over beta(r,c) (X, Y row-major, the k
+// values of one row contiguous), on the wavefront tiles of a mode-0 plan.
+//
+// The tile's streams are read as in the single-vector kernel. Then lane =
+// mask bit places each stored value's column next to it in LDS (the value
+// keeps its packed slot), and groups of kp lanes (kp = k rounded up to a
+// power of two) take the tile's (interval, block row) pairs in turn: lane q
+// of a group adds a_v * X[col_v][q] over the pair's values, so the group
+// reads one contiguous row of X per value. Sums are formed in double
+// precision and written once per row and column.
+//
+// An interval with more blocks than a tile holds is run by one wavefront
+// with lane = mask bit throughout, each lane keeping k running sums.
+#include "common.hpp"
+#include "wave_common.hpp"
+
+namespace spc {
+namespace {
+
+using namespace dev;
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kMaxK = 16;
+
+struct SpmmArgs {
+    const int32_t *brow;
+    const int32_t *bcol;
+    const uint64_t *mw;
+    const void *vals;
+    const void *X;
+    void *Y;
+    const TileDesc *tiles;
+    int64_t n_rows, n_cols, nnz, n_blocks;
+    int64_t ldx, ldy;
+    int32_t k, kp, lgkp;
+    int32_t n_tiles;
+    int32_t accumulate;
+    int32_t xcd_remap;
+    int32_t tiles_per_xcd;
+};
+
+template <class Sh, class T, int KQ>
+struct SpmmSmem {
+    static constexpr int E = 16 / sizeof(T);
+    static constexpr int WB = (64 * KQ - 1) * E;
+    static constexpr int NB = WB / Sh::RC;
+    static constexpr int NWMAX = NB / Sh::BPW + 2;
+    static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;
+    static constexpr int NCOL = NCR * 64;
+    static constexpr int NBUF = 64 * KQ * E;
+    uint64_t wm[64];
+    int off[64];
+    int brow[64];
+    int col[NCOL];
+    int cidx[NBUF + 64];       // column of each packed value
+    T buf[NBUF];               // packed values
+};
+
+template <class T>
+__device__ __forceinline__ double ld_x(__amdgpu_buffer_rsrc_t xr, uint32_t off) {
+    return (double)buf_load<T>(xr, off);
+}
+
+template <class Sh, class T, int KQ>
+__device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
+                          SpmmSmem<Sh, T, KQ> &sm) {
+    using SM = SpmmSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    const int lo_slot = b0 - w0 * Sh::BPW;
+    const int end_bit = (b1 - w0 * Sh::BPW) * Sh::RC;
+    const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
+    const int cs0 = w0 * Sh::BPW;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
+
+    // 1. streams (buffer loads, unguarded), metadata into LDS
+    const auto cr = rsrc(a.bcol + cs0, (uint32_t)ncs * 4u);
+    int colr[SM::NCR];
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k)
+        colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
+    const int br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const auto wr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
+    uint64_t wl = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(wr, (uint32_t)(lane * 8), 0, 0));
+    const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
+    V4 ch[KQ];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+        ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
+    wl &= lane == 0 ? lo_mask : ~0ull;
+    wl &= low_bits(end_bit - 64 * lane);
+    const int cnt = __popcll(wl);
+    const int incl = wave_scan_dpp(cnt);
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k) sm.col[lane + 64 * k] = colr[k];
+    sm.brow[lane] = br - b0;
+    sm.wm[lane] = wl;
+    sm.off[lane] = incl - cnt;
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = ch[k];
+    if (q_tail < nq) {
+        if (lane < E) {
+            const int64_t g = abase + (int64_t)q_tail * E + lane;
+            if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+        }
+    }
+    wave_sync();
+
+    // 2. column of every stored value, lane = mask bit
+    if (nw > 0) {
+        const int slot = lane / Sh::RC;
+        const int kcol = (lane % Sh::RC) % Sh::C;
+        const int *__restrict__ colp = sm.col + slot;
+        int voff = shift;
+        for (int i = 0; i < nw; ++i) {
+            uint64_t m = a.mw[w0 + i];
+            if (i == 0) m &= lo_mask;
+            if (__builtin_amdgcn_inverse_ballot_w64(m)) sm.cidx[lane_rank(m) + voff] = colp[i * Sh::BPW] + kcol;
+            voff += __popcll(m);
+        }
+    }
+    wave_sync();
+
+    // 3. kp lanes per (interval, block row), lane q of the group = column q of X
+    const int kp = a.kp, q = lane & (kp - 1), grp = lane >> a.lgkp, ngrp = 64 >> a.lgkp;
+    const int npairs = nI * Sh::R;
+    const T *__restrict__ vb = sm.buf + shift;
+    const int *__restrict__ cb = sm.cidx + shift;
+    const uint32_t xq = q < a.k ? (uint32_t)q * (uint32_t)sizeof(T) : 0xffffffffu;  // column q of X
+    const uint32_t xrow = (uint32_t)a.ldx * (uint32_t)sizeof(T);
+    T *__restrict__ Y = static_cast<T *>(a.Y);
+    for (int p = grp; p < npairs; p += ngrp) {
+        const int li = p / Sh::R, rho = p % Sh::R;
+        const int bs = sm.brow[li], be = sm.brow[li + 1];
+        double acc0 = 0.0, acc1 = 0.0;
+        int n_here = 0;
+        if (bs < be) {
+            if (Sh::R == 1) {
+                const int gs = bs + lo_slot, ge = be + lo_slot;
+                const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
+                const int vs = sm.off[ws] + __popcll(sm.wm[ws] & low_bits((gs % Sh::BPW) * Sh::RC));
+                const int ve = sm.off[we] + __popcll(sm.wm[we] & low_bits((ge % Sh::BPW) * Sh::RC));
+                int v = vs;
+                for (; v + 1 < ve; v += 2) {
+                    const double x0 = ld_x<T>(xr, (uint32_t)cb[v] * xrow + xq);
+                    const double x1 = ld_x<T>(xr, (uint32_t)cb[v + 1] * xrow + xq);
+                    acc0 = __builtin_fma((double)vb[v], x0, acc0);
+                    acc1 = __builtin_fma((double)vb[v + 1], x1, acc1);
+                }
+                if (v < ve) acc0 = __builtin_fma((double)vb[v], ld_x<T>(xr, (uint32_t)cb[v] * xrow + xq), acc0);
+                n_here = ve - vs;
+            } else {
+                const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
+                for (int b = bs; b < be; ++b) {
+                    const int g = b + lo_slot;
+                    const int wi = g / Sh::BPW, bit = (g % Sh::BPW) * Sh::RC;
+                    const uint64_t wv = sm.wm[wi];
+                    const uint32_t m = (uint32_t)(wv >> bit) & Sh::RCMASK;
+                    const uint32_t sub = (m >> (rho * Sh::C)) & Sh::CMASK;
+                    const int pos = sm.off[wi] + __popcll(wv & low_bits(bit)) + __popc(m & below);
+                    const int n = __popc(sub);
+                    n_here += n;
+                    for (int j = 0; j < n; ++j)
+                        acc0 = __builtin_fma((double)vb[pos + j],
+                                             ld_x<T>(xr, (uint32_t)cb[pos + j] * xrow + xq), acc0);
+                }
+            }
+        }
+        const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+        if (q < a.k && row < a.n_rows) {
+            const double acc = acc0 + acc1;
+            T *yp = Y + row * a.ldy + q;
+            if (a.accumulate) {
+                if (n_here > 0) *yp = (T)(acc + (double)*yp);
+            } else {
+                *yp = (T)acc;
+            }
+        }
+    }
+}
+
+// One interval longer than a tile: lane = mask bit, k running sums per lane.
+template <class Sh, class T>
+__device__ void spmm_long(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr) {
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int slot = lane / Sh::RC;
+    const int kcol = (lane % Sh::RC) % Sh::C;
+    const int b0 = d.b0, b1 = d.b1;
+    const int w0 = b0 / Sh::BPW;
+    const int nwt = (b1 - 1) / Sh::BPW - w0 + 1;
+    const int lo_slot = b0 - w0 * Sh::BPW;
+    const int end_bit = (b1 - w0 * Sh::BPW) * Sh::RC;
+    const uint32_t xrow = (uint32_t)a.ldx * (uint32_t)sizeof(T);
+    double acc[kMaxK];
+#pragma unroll
+    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
+    int n_here = 0;
+    int64_t vrun = d.vbase;
+    for (int i = 0; i < nwt; ++i) {
+        uint64_t m = a.mw[w0 + i];
+        if (i == 0) m &= ~low_bits(lo_slot * Sh::RC);
+        m &= low_bits(end_bit - 64 * i);
+        if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+            const double v = (double)vals[vrun + lane_rank(m)];
+            const uint32_t xo = (uint32_t)(a.bcol[(int64_t)(w0 + i) * Sh::BPW + slot] + kcol) * xrow;
+            ++n_here;
+#pragma unroll
+            for (int q = 0; q < kMaxK; ++q)
+                if (q < a.k) acc[q] = __builtin_fma(v, ld_x<T>(xr, xo + (uint32_t)(q * sizeof(T))), acc[q]);
+        }
+        vrun += __popcll(m);
+    }
+    // lanes of one block row: same (lane % RC) / C; add over column and slot bits
+#pragma unroll
+    for (int mm = 1; mm < Sh::C; mm <<= 1) {
+        n_here += __shfl_xor(n_here, mm, 64);
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q) acc[q] += __shfl_xor(acc[q], mm, 64);
+    }
+#pragma unroll
+    for (int mm = Sh::RC; mm < 64; mm <<= 1) {
+        n_here += __shfl_xor(n_here, mm, 64);
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q) acc[q] += __shfl_xor(acc[q], mm, 64);
+    }
+    if (lane < Sh::RC && (lane % Sh::C) == 0) {
+        const int64_t row = (int64_t)d.i0 * Sh::R + lane / Sh::C;
+        if (row < a.n_rows) {
+            T *__restrict__ Y = static_cast<T *>(a.Y) + row * a.ldy;
+#pragma unroll
+            for (int q = 0; q < kMaxK; ++q) {
+                if (q < a.k) {
+                    if (a.accumulate) {
+                        if (n_here > 0) Y[q] = (T)(acc[q] + (double)Y[q]);
+                    } else {
+                        Y[q] = (T)acc[q];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmm_wave(SpmmArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = SpmmSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    // exactly the bytes of the k used columns: rows 0..n_cols-1, leading dimension ldx
+    const int64_t xbytes = a.n_cols > 0 ? ((a.n_cols - 1) * a.ldx + a.k) * (int64_t)sizeof(T) : 0;
+    const auto xr = rsrc(a.X, (uint32_t)xbytes);
+    if (d.b1 - d.b0 > SM::NB) spmm_long<Sh, T>(a, d, xr);
+    else spmm_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+}
+
+template <int R, int C, class T>
+spc_status launch(int kq, dim3 grid, const SpmmArgs &a, hipStream_t s) {
+    switch (kq) {
+    case 2: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 2>), grid, dim3(kThreads), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 8>), grid, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 4>), grid, dim3(kThreads), 0, s, a); break;
+    }
+    SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
+}  // namespace
+
+spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, int accumulate, hipStream_t stream) {
+    SpmmArgs a;
+    a.brow = A->block_rowptr;
+    a.bcol = A->block_colidx;
+    a.mw = static_cast<const uint64_t *>(A->block_masks);
+    a.vals = A->values;
+    a.X = X;
+    a.Y = Y;
+    a.tiles = P->d_tiles;
+    a.n_rows = A->n_rows;
+    a.n_cols = A->n_cols;
+    a.nnz = A->nnz;
+    a.n_blocks = A->n_blocks;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.k = k;
+    a.lgkp = 0;
+    while ((1 << a.lgkp) < k) ++a.lgkp;
+    a.kp = 1 << a.lgkp;
+    a.n_tiles = (int32_t)P->n_tiles;
+    a.accumulate = accumulate;
+    a.xcd_remap = P->xcd_remap;
+    const int64_t groups = div_up(P->n_tiles, kWaves);
+    a.tiles_per_xcd = (int32_t)div_up(groups, 8);
+    dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)groups);
+    return with_shape(P->shape, [&](auto sh) {
+        using Sh = decltype(sh);
+        return with_dtype(A->dtype, [&](auto tv) {
+            using T = decltype(tv);
+            return launch<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
+        });
+    });
+}
+
+}  // namespace spc
+
+extern "C" spc_status spc_spmm_beta(const spc_beta_view *A, const spc_plan *plan, int32_t k, const void *X,
+                                    int64_t ldx, void *Y, int64_t ldy, int32_t accumulate, hipStream_t stream) {
+    spc_status st = spc::check_view(A);
+    if (st != SPC_OK) return st;
+    SPC_REQUIRE(plan != nullptr, SPC_ERR_INVALID_ARG, "null plan (create one with spc_plan_create)");
+    SPC_REQUIRE(plan->mode == 0, SPC_ERR_INVALID_ARG, "spc_spmm_beta needs a plan of mode 0 (wavefront tiles)");
+    SPC_REQUIRE(plan->A.block_rowptr == A->block_rowptr && plan->A.values == A->values &&
+                    plan->A.block_masks == A->block_masks && plan->A.n_rows == A->n_rows,
+                SPC_ERR_INVALID_ARG, "plan was built for a different matrix view");
+    SPC_REQUIRE(k >= 1 && k <= spc::kMaxK, SPC_ERR_CAPACITY, "k must be in 1..%d", spc::kMaxK);
+    SPC_REQUIRE(ldx >= k && ldy >= k, SPC_ERR_INVALID_ARG, "leading dimensions must be at least k");
+    SPC_REQUIRE(accumulate == 0 || accumulate == 1, SPC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
+    if (A->n_rows == 0 || plan->n_tiles == 0) return SPC_OK;
+    SPC_REQUIRE(X && Y, SPC_ERR_INVALID_ARG, "null X or Y");
+    const size_t es = A->dtype == SPC_F64 ? 8 : 4;
+    SPC_REQUIRE((uint64_t)A->n_cols * (uint64_t)ldx * es < 0xf0000000ull, SPC_ERR_CAPACITY,
+                "X must be smaller than 3.75 GiB (32-bit offsets)");
+    SPC_REQUIRE((reinterpret_cast<uintptr_t>(A->values) & 15u) == 0, SPC_ERR_INVALID_ARG,
+                "spc_spmm_beta needs a 16-byte aligned values array");
+    SPC_REQUIRE(reinterpret_cast<uintptr_t>(X) % es == 0 && reinterpret_cast<uintptr_t>(Y) % es == 0,
+                SPC_ERR_INVALID_ARG, "X and Y must be aligned to the element size");
+    return spc::spmm_launch(A, plan, k, X, ldx, Y, ldy, accumulate, stream);
+}
