@@ -40,6 +40,32 @@ def algorithmic_bytes(B, n_tiles: int, k: int = 1, accumulate: bool = False) -> 
     return b
 
 
+def measured_traffic(kname: str, shape, params: dict, m: int):
+    """HBM bytes per launch from the committed memory-counter summary of this
+    kernel, if the kernel sources are still the ones that were measured
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading); else
+    None."""
+    import glob
+    import hashlib
+    if m != 128:
+        return None
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.traffic.json"))):
+        with open(f) as fh:
+            rec = json.load(fh)
+        if rec.get("kernel") != kname or rec.get("shape") != list(shape):
+            continue
+        if {k: rec["plan"].get(k, 0) for k in ("mode", "wave_chunks", "tile_bits", "xcd_remap")} != \
+                {k: params.get(k, 0) for k in ("mode", "wave_chunks", "tile_bits", "xcd_remap")}:
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() == rec["sha256"]:
+            return {"bytes": rec["traffic_bytes_per_launch"], "source": os.path.relpath(f, ROOT)}
+    return None
+
+
 def time_spmv(spc, torch, B, x, y, plan, steps: int, warmup: int):
     """Average device time of one launch (HIP events on the current stream)."""
     for _ in range(warmup):
@@ -194,6 +220,7 @@ def main(argv=None):
     ab = algorithmic_bytes(B, info["n_tiles"])
     achieved = ab / t_kernel / 1e9
     value = flops / (wall / args.steps) / 1e9
+    traffic = measured_traffic(kname, (r, c), params, m)
     f64_times = {k: v["us"] for k, v in sweep.items() if k.startswith("f64_")}
     sel_key = f"f64_b{r}x{c}"
     ratio = (f64_times[sel_key] / min(f64_times.values())) if sel_key in f64_times and f64_times else None
@@ -207,7 +234,9 @@ def main(argv=None):
                                f"beta({r},{c}) kernel", "shape": [r, c], "n_rows": A.n_rows,
                    "nnz": A.nnz, "tile_bits": info.get("tile_bits"), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic_source": traffic["source"] if traffic else "no counter record for this kernel build",
                      "kernel": kname, "plan": params,
                      "alg_bytes_per_launch": ab, "kernel_us": round(t_kernel * 1e6, 2)},
         "selected_vs_best_time_ratio": round(ratio, 4) if ratio else None,
