@@ -234,6 +234,108 @@ spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t 
                         spc_plan_params *best, float *best_us, spc_tune_record *records,
                         int32_t max_records, int32_t *n_records, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Matrix features for kernel selection, from the CSR structure alone (section
+ * "Performance prediction and optimal kernel selection": the block counts
+ * that drive the per-kernel prediction are obtained without converting).
+ * rowptr int32[n_rows+1] (monotone from 0 to nnz) and colidx int32[nnz]
+ * (strictly increasing in each row, inside [0, n_cols)) are device arrays.
+ * features_out (host, 16 floats):
+ *    0 log2(n_rows)       1 log2(n_cols)       2 log2(nnz + 1)
+ *    3 mean entries per row                    4 std / mean of row lengths
+ *    5 log2(1 + longest row)                   6 share of empty rows
+ *    7 mean |j - i| over entries / max(n_rows, n_cols)
+ *    8..13 Avg(r,c) = nnz / N_b(r,c) for the six shapes (0 if no block)
+ *   14 share of beta(1,8) blocks that hold one value
+ *   15 mean over non-empty rows of log2((last col - first col + 1) / length)
+ * N_b(r,c) is the block count of the greedy leftmost cover, i.e. exactly
+ * the n_blocks spc_beta_count returns. n_blocks_out (host, 6 entries, may be
+ * NULL) receives them. Counts and sums are exact integers except entry 15
+ * (double); the 16 entries are rounded to float once at the end.
+ * Errors: SPC_ERR_INVALID_ARG (n_rows or n_cols < 1), SPC_ERR_INDEX_RANGE,
+ * SPC_ERR_CSR_UNSORTED_OR_DUP, SPC_ERR_OVERFLOW. Synchronizes the stream. */
+#define SPC_N_FEATURES 16
+spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
+                               const int32_t *colidx, float *features_out, int64_t *n_blocks_out,
+                               hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU network in FP32 whose
+ * forward, backward and Adam steps run in this library's kernels. The paper
+ * selects kernels from recorded speeds with one polynomial per kernel
+ * (section "Performance polynomial interpolation") and names selection from
+ * several matrix properties as future work (Conclusions); the network is
+ * that extension. Definitions:
+ *   x^   = (x - mu) / sd                 (per feature; training statistics)
+ *   h1   = relu(W1 x^ + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
+ *   tau  = log2(t / min_k t_k)           (time relative to the best shape)
+ *   loss = mean over the batch and the 6 outputs of (o - tau)^2
+ *   choice = argmin_k o_k (lowest index on ties)
+ *   Adam: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected, constant lr.
+ * params: SPC_MLP_N_PARAMS floats, in this order, row-major [out][in]:
+ *   W1[64][16], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].
+ * X: n x 16 feature rows (float, row-major); times, tau: n x 6.
+ * All arrays are device memory unless marked host. */
+#define SPC_MLP_N_IN 16
+#define SPC_MLP_N_HIDDEN 64
+#define SPC_MLP_N_OUT 6
+#define SPC_MLP_N_PARAMS 5638
+#define SPC_MLP_MAX_BATCH 64
+
+/* mu, sd (16 each): mean and population standard deviation of the columns
+ * of X (sd < 1e-12 is replaced by 1). Asynchronous. */
+spc_status spc_mlp_standardizer(const float *X, int32_t n, float *mu_out, float *sd_out, hipStream_t stream);
+/* tau = log2(t / row minimum) for n rows of 6 positive times. Asynchronous. */
+spc_status spc_mlp_targets(const float *times, int32_t n, float *tau_out, hipStream_t stream);
+/* Loss and gradient (SPC_MLP_N_PARAMS floats) of one batch: rows (host,
+ * batch entries in [0, n)) pick the batch from X and tau; 1 <= batch <= 64.
+ * loss_out: one device float. Synchronizes. */
+spc_status spc_mlp_loss_grad(const float *params, const float *mu, const float *sd, const float *X,
+                             const float *tau, int32_t n, const int32_t *rows, int32_t batch,
+                             float *grad_out, float *loss_out, hipStream_t stream);
+/* n_steps Adam steps, step s on the rows order[s*batch .. s*batch+batch-1]
+ * (host array, entries in [0, n)). params, adam_m, adam_v (each
+ * SPC_MLP_N_PARAMS floats) are updated in place; step0 = Adam steps already
+ * taken (bias correction continues from there). losses_out[s] = loss of step
+ * s before its update. One workgroup runs all steps in one launch.
+ * Synchronizes. */
+spc_status spc_mlp_train(float *params, float *adam_m, float *adam_v, int32_t step0, float lr,
+                         const float *mu, const float *sd, const float *X, const float *tau, int32_t n,
+                         const int32_t *order, int32_t n_steps, int32_t batch, float *losses_out,
+                         hipStream_t stream);
+/* Scores (n x 6, may be NULL) and choices (n, may be NULL) for n feature
+ * rows. Asynchronous. */
+spc_status spc_mlp_infer(const float *params, const float *mu, const float *sd, const float *X, int32_t n,
+                         float *scores_out, int32_t *choice_out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Selector object (library-owned). Interpolation: per shape, a least-squares
+ * polynomial of speed against Avg(r,c) over n records (avg, speed: host
+ * n x 6 doubles, speed in GFlop/s), degree lowered to (distinct Avg values -
+ * 1) when records are few; a query's Avg (features 8..13) is clamped to the
+ * fitted range and the highest predicted speed wins (lowest index on ties).
+ * MLP: spc_selector_set_mlp copies a trained network (host arrays) to the
+ * current device; the smallest score wins.
+ * spc_select_kernel: features = host float[16] (spc_matrix_features);
+ * method SPC_SEL_INTERP or SPC_SEL_MLP; *shape_out = 0..5; scores_out (host
+ * float[6], may be NULL) = predicted GFlop/s (interpolation) or predicted
+ * log2 time ratios (MLP). SPC_ERR_NO_MODEL when the method has no model, so
+ * the caller can fall back to the other one. Synchronizes (MLP). */
+#define SPC_SEL_INTERP 0
+#define SPC_SEL_MLP 1
+typedef struct spc_selector spc_selector;
+spc_status spc_selector_create(spc_selector **out);
+spc_status spc_selector_destroy(spc_selector *sel);
+spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, const double *avg, const double *speed,
+                                   int32_t degree);
+/* Coefficients (host 6 x 4 doubles, lowest power first, zero above the
+ * degree) and fitted Avg ranges (host 6 doubles each, may be NULL). */
+spc_status spc_selector_interp_coeffs(const spc_selector *sel, double *coeffs_out, double *lo_out,
+                                      double *hi_out);
+spc_status spc_selector_set_mlp(spc_selector *sel, const float *params, const float *mu, const float *sd);
+spc_status spc_select_kernel(spc_selector *sel, const float *features, int32_t method, int32_t *shape_out,
+                             float *scores_out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,25 @@ _SIGS = {
                                 POINTER(ctypes.c_float), c_void_p]),
     "spc_autotune": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_int32, POINTER(PlanParams),
                                POINTER(ctypes.c_float), c_void_p, c_int32, POINTER(c_int32), c_void_p]),
+    "spc_matrix_features": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_void_p, POINTER(ctypes.c_float),
+                                      POINTER(c_int64), c_void_p]),
+    "spc_mlp_standardizer": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "spc_mlp_targets": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "spc_mlp_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32),
+                                    c_int32, c_void_p, c_void_p, c_void_p]),
+    "spc_mlp_train": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_int32, POINTER(c_int32), c_int32, c_int32, c_void_p, c_void_p]),
+    "spc_mlp_infer": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+    "spc_selector_create": (c_int32, [POINTER(c_void_p)]),
+    "spc_selector_destroy": (c_int32, [c_void_p]),
+    "spc_selector_fit_interp": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_double), POINTER(ctypes.c_double),
+                                          c_int32]),
+    "spc_selector_interp_coeffs": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(ctypes.c_double),
+                                             POINTER(ctypes.c_double)]),
+    "spc_selector_set_mlp": (c_int32, [c_void_p, POINTER(ctypes.c_float), POINTER(ctypes.c_float),
+                                       POINTER(ctypes.c_float)]),
+    "spc_select_kernel": (c_int32, [c_void_p, POINTER(ctypes.c_float), c_int32, POINTER(c_int32),
+                                    POINTER(ctypes.c_float), c_void_p]),
 }
 
 
@@ -346,3 +365,159 @@ def cg(A: BetaMatrix, B: torch.Tensor, rel_tol: float = 1e-8, max_iter: int = 10
                              ctypes.cast(its, POINTER(c_int32)), ctypes.cast(res, POINTER(ctypes.c_double)),
                              ctypes.byref(tot), stream_ptr()))
     return X, list(its), list(res), tot.value
+
+
+def matrix_features(rowptr, colidx, n_cols: int, device="cuda"):
+    """The 16 selection features of a CSR matrix and its six greedy block
+    counts, computed on the device without conversion.
+    Returns (float32 numpy array [16], int64 numpy array [6])."""
+    import numpy as np
+    rp = torch.as_tensor(rowptr, dtype=torch.int32, device=device)
+    ci = torch.as_tensor(colidx, dtype=torch.int32, device=device)
+    n_rows = rp.numel() - 1
+    nnz = ci.numel()
+    if nnz == 0:
+        ci = torch.zeros(1, dtype=torch.int32, device=device)
+    f = (ctypes.c_float * 16)()
+    nb = (c_int64 * 6)()
+    check(lib().spc_matrix_features(n_rows, n_cols, nnz, _ptr(rp), _ptr(ci), f, nb, stream_ptr()))
+    return np.array(list(f), dtype=np.float32), np.array(list(nb), dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# Learned selector (MLP) and interpolation selector
+
+MLP_N_PARAMS = 5638
+MLP_MAX_BATCH = 64
+SEL_INTERP, SEL_MLP = 0, 1
+
+
+def _f32_cuda(t, shape=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+def _i32_host(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(POINTER(c_int32))
+
+
+def mlp_standardizer(X: torch.Tensor):
+    """(mu, sd) of the n x 16 feature rows, on the device."""
+    n = X.shape[0]
+    _f32_cuda(X, (n, 16))
+    mu = torch.empty(16, dtype=torch.float32, device=X.device)
+    sd = torch.empty(16, dtype=torch.float32, device=X.device)
+    check(lib().spc_mlp_standardizer(_ptr(X), n, _ptr(mu), _ptr(sd), stream_ptr()))
+    return mu, sd
+
+
+def mlp_targets(times: torch.Tensor) -> torch.Tensor:
+    n = times.shape[0]
+    _f32_cuda(times, (n, 6))
+    tau = torch.empty_like(times)
+    check(lib().spc_mlp_targets(_ptr(times), n, _ptr(tau), stream_ptr()))
+    return tau
+
+
+def mlp_loss_grad(params, mu, sd, X, tau, rows):
+    """Loss and gradient of one batch (rows: host indices into X/tau)."""
+    n = X.shape[0]
+    for t, shp in ((params, (MLP_N_PARAMS,)), (mu, (16,)), (sd, (16,)), (X, (n, 16)), (tau, (n, 6))):
+        _f32_cuda(t, shp)
+    r, rp = _i32_host(rows)
+    grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    check(lib().spc_mlp_loss_grad(_ptr(params), _ptr(mu), _ptr(sd), _ptr(X), _ptr(tau), n, rp, r.size,
+                                  _ptr(grad), _ptr(loss), stream_ptr()))
+    return float(loss.item()), grad
+
+
+def mlp_train(params, adam_m, adam_v, step0: int, lr: float, mu, sd, X, tau, order, batch: int):
+    """Adam steps over batches order[s*batch:(s+1)*batch] (host indices);
+    params and moments are updated in place. Returns the per-step losses."""
+    n = X.shape[0]
+    for t, shp in ((params, (MLP_N_PARAMS,)), (adam_m, (MLP_N_PARAMS,)), (adam_v, (MLP_N_PARAMS,)),
+                   (mu, (16,)), (sd, (16,)), (X, (n, 16)), (tau, (n, 6))):
+        _f32_cuda(t, shp)
+    o, op = _i32_host(order)
+    steps = o.size // batch
+    losses = torch.empty(max(1, steps), dtype=torch.float32, device=X.device)
+    check(lib().spc_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), step0, lr, _ptr(mu), _ptr(sd), _ptr(X),
+                              _ptr(tau), n, op, steps, batch, _ptr(losses), stream_ptr()))
+    return losses[:steps]
+
+
+def mlp_infer(params, mu, sd, X):
+    """(scores n x 6, choice n) of the network for n feature rows."""
+    n = X.shape[0]
+    for t, shp in ((params, (MLP_N_PARAMS,)), (mu, (16,)), (sd, (16,)), (X, (n, 16))):
+        _f32_cuda(t, shp)
+    scores = torch.empty((n, 6), dtype=torch.float32, device=X.device)
+    choice = torch.empty(n, dtype=torch.int32, device=X.device)
+    check(lib().spc_mlp_infer(_ptr(params), _ptr(mu), _ptr(sd), _ptr(X), n, _ptr(scores), _ptr(choice),
+                              stream_ptr()))
+    return scores, choice
+
+
+class Selector:
+    """Library-owned selector: interpolation fit and/or a trained network."""
+
+    def __init__(self):
+        h = c_void_p()
+        check(lib().spc_selector_create(ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.spc_selector_destroy(h)
+            self.handle = None
+
+    def fit_interp(self, avg, speed, degree: int = 3):
+        import numpy as np
+        a = np.ascontiguousarray(avg, dtype=np.float64)
+        v = np.ascontiguousarray(speed, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != 6 or v.shape != a.shape:
+            raise ValueError("avg and speed must be n x 6")
+        check(lib().spc_selector_fit_interp(self.handle, a.shape[0], a.ctypes.data_as(POINTER(ctypes.c_double)),
+                                            v.ctypes.data_as(POINTER(ctypes.c_double)), degree))
+        return self
+
+    def interp_coeffs(self):
+        import numpy as np
+        c = np.zeros((6, 4))
+        lo = np.zeros(6)
+        hi = np.zeros(6)
+        dp = POINTER(ctypes.c_double)
+        check(lib().spc_selector_interp_coeffs(self.handle, c.ctypes.data_as(dp), lo.ctypes.data_as(dp),
+                                               hi.ctypes.data_as(dp)))
+        return c, lo, hi
+
+    def set_mlp(self, params, mu, sd):
+        import numpy as np
+        fp = POINTER(ctypes.c_float)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        m = np.ascontiguousarray(mu, dtype=np.float32)
+        s_ = np.ascontiguousarray(sd, dtype=np.float32)
+        if p.size != MLP_N_PARAMS or m.size != 16 or s_.size != 16:
+            raise ValueError("params must hold 5638 floats, mu and sd 16 each")
+        check(lib().spc_selector_set_mlp(self.handle, p.ctypes.data_as(fp), m.ctypes.data_as(fp),
+                                         s_.ctypes.data_as(fp)))
+        return self
+
+    def select(self, features, method: int = SEL_MLP):
+        """(shape index, scores[6]) for one host feature vector."""
+        import numpy as np
+        f = np.ascontiguousarray(features, dtype=np.float32)
+        if f.size != 16:
+            raise ValueError("features must hold 16 floats")
+        out = c_int32()
+        sc = (ctypes.c_float * 6)()
+        check(lib().spc_select_kernel(self.handle, f.ctypes.data_as(POINTER(ctypes.c_float)), method,
+                                      ctypes.byref(out), sc, stream_ptr() if method == SEL_MLP else None))
+        return int(out.value), np.array(list(sc), dtype=np.float32)

@@ -1,0 +1,267 @@
+// Matrix features for kernel selection, computed from the CSR structure
+// without building any beta(r,c) array (section "Performance prediction and
+// optimal kernel selection": the per-kernel block counts are obtained
+// without conversion, so the prediction stays cheap).
+//
+// One thread takes a group of 8 consecutive rows. For every shape it runs the
+// greedy leftmost cover of the group's intervals (r = 8: the group; r = 4:
+// its two halves; r = 2: its four pairs; r = 1: each row): the next block
+// starts at the smallest column not yet covered and spans c columns, which is
+// the cover the conversion builds, so the counts equal the converted N_b.
+// The same pass checks the CSR and takes the row statistics. Per-block
+// partial sums are combined by one block in a fixed order, so the result
+// does not depend on scheduling.
+#include <climits>
+#include <cmath>
+
+#include "common.hpp"
+
+namespace spc {
+namespace {
+
+constexpr int kFT = 256;     // threads per block
+constexpr int kGroup = 8;    // rows per thread (the tallest shape)
+
+enum : int { kErrNone = 0, kErrRange = 1, kErrOrder = 2 };
+
+// Partial sums of one block (all integers exact; the log term in double).
+struct FeatSums {
+    int64_t nb[SPC_N_SHAPES];  // greedy block counts per shape
+    int64_t single18;          // beta(1,8) blocks holding one value
+    int64_t empty_rows;
+    int64_t sum_len2;          // sum of squared row lengths
+    int64_t sum_dist;          // sum over entries of |j - i|
+    int64_t max_len;
+    int64_t nonempty_rows;
+    double sum_log_span;       // sum over non-empty rows of log2(span / length)
+    double pad;
+};
+constexpr int kSumWords = sizeof(FeatSums) / 8;
+static_assert(sizeof(FeatSums) == 14 * 8, "FeatSums layout");
+
+// Greedy cover of NR consecutive rows (first row F of the group) with blocks
+// c columns wide. lo/hi: the rows' ranges in colidx (hi == lo for rows that
+// do not exist or were refused).
+template <int NR, int F, int C>
+__device__ __forceinline__ int64_t cover(const int32_t *__restrict__ col, const int (&lo)[kGroup],
+                                         const int (&hi)[kGroup]) {
+    int p[NR];
+    int64_t h[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        p[r] = lo[F + r];
+        h[r] = p[r] < hi[F + r] ? (int64_t)col[p[r]] : INT64_MAX;
+    }
+    int64_t count = 0;
+    int64_t end = INT64_MIN;  // first column not covered by the last block
+    while (true) {
+        int64_t s = INT64_MAX;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            while (h[r] < end) {
+                ++p[r];
+                h[r] = p[r] < hi[F + r] ? (int64_t)col[p[r]] : INT64_MAX;
+            }
+            s = h[r] < s ? h[r] : s;
+        }
+        if (s == INT64_MAX) break;
+        ++count;
+        end = s + C;
+    }
+    return count;
+}
+
+template <int NR, int C, int G>
+__device__ __forceinline__ int64_t cover_all(const int32_t *__restrict__ col, const int (&lo)[kGroup],
+                                             const int (&hi)[kGroup]) {
+    if constexpr (G * NR >= kGroup) {
+        return 0;
+    } else {
+        return cover<NR, G * NR, C>(col, lo, hi) + cover_all<NR, C, G + 1>(col, lo, hi);
+    }
+}
+
+__device__ void block_reduce(FeatSums &v, FeatSums *sm, int64_t *out_words) {
+    int64_t *w = reinterpret_cast<int64_t *>(&v);
+    int64_t *s = reinterpret_cast<int64_t *>(sm);
+#pragma unroll
+    for (int k = 0; k < kSumWords; ++k) s[threadIdx.x * kSumWords + k] = w[k];
+    __syncthreads();
+    for (int st = kFT / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            FeatSums &a = sm[threadIdx.x];
+            const FeatSums &b = sm[threadIdx.x + st];
+#pragma unroll
+            for (int q = 0; q < SPC_N_SHAPES; ++q) a.nb[q] += b.nb[q];
+            a.single18 += b.single18;
+            a.empty_rows += b.empty_rows;
+            a.sum_len2 += b.sum_len2;
+            a.sum_dist += b.sum_dist;
+            a.max_len = a.max_len > b.max_len ? a.max_len : b.max_len;
+            a.nonempty_rows += b.nonempty_rows;
+            a.sum_log_span += b.sum_log_span;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kSumWords) out_words[threadIdx.x] = s[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kFT) void k_features(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                                  const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, int64_t *part,
+                                                  int *err) {
+    __shared__ FeatSums sm[kFT];
+    FeatSums v = {};
+    const int64_t n_groups = (n_rows + kGroup - 1) / kGroup;
+    const int64_t g = (int64_t)blockIdx.x * kFT + threadIdx.x;
+    if (g < n_groups) {
+        int lo[kGroup], hi[kGroup];
+        int bad = kErrNone;
+#pragma unroll
+        for (int r = 0; r < kGroup; ++r) {
+            const int64_t i = g * kGroup + r;
+            lo[r] = hi[r] = 0;
+            if (i >= n_rows) continue;
+            const int64_t a = rowptr[i], b = rowptr[i + 1];
+            if (a < 0 || b < a || b > nnz || (i == 0 && a != 0) || (i == n_rows - 1 && b != nnz)) {
+                bad |= kErrRange;
+                continue;
+            }
+            // row statistics and the CSR check
+            const int len = (int)(b - a);
+            int64_t prev = -1;
+            int64_t dist = 0;
+            bool row_ok = true;
+            for (int64_t p = a; p < b; ++p) {
+                const int64_t j = col[p];
+                if (j < 0 || j >= n_cols) {
+                    bad |= kErrRange;
+                    row_ok = false;
+                    break;
+                }
+                if (j <= prev) {
+                    bad |= kErrOrder;
+                    row_ok = false;
+                    break;
+                }
+                prev = j;
+                dist += j > i ? j - i : i - j;
+            }
+            if (!row_ok) continue;
+            lo[r] = (int)a;
+            hi[r] = (int)b;
+            v.sum_len2 += (int64_t)len * len;
+            v.sum_dist += dist;
+            v.max_len = len > v.max_len ? len : v.max_len;
+            if (len == 0) {
+                ++v.empty_rows;
+            } else {
+                ++v.nonempty_rows;
+                const double span = (double)(col[b - 1] - col[a] + 1);
+                v.sum_log_span += log2(span / (double)len);
+                // beta(1,8) cover of this row, with the values of each block
+                int64_t p = a;
+                while (p < b) {
+                    const int64_t s = col[p];
+                    int n_in = 0;
+                    while (p < b && col[p] < s + 8) {
+                        ++p;
+                        ++n_in;
+                    }
+                    ++v.nb[0];
+                    if (n_in == 1) ++v.single18;
+                }
+            }
+        }
+        if (bad) {
+            atomicOr(err, bad);
+        } else {
+            v.nb[1] = cover_all<2, 4, 0>(col, lo, hi);
+            v.nb[2] = cover_all<2, 8, 0>(col, lo, hi);
+            v.nb[3] = cover_all<4, 4, 0>(col, lo, hi);
+            v.nb[4] = cover_all<4, 8, 0>(col, lo, hi);
+            v.nb[5] = cover_all<8, 4, 0>(col, lo, hi);
+        }
+    }
+    block_reduce(v, sm, part + (int64_t)blockIdx.x * kSumWords);
+}
+
+// Sum of the per-block partials in one block, fixed order.
+__global__ __launch_bounds__(kFT) void k_features_total(const int64_t *part, int64_t n_part, int64_t *out) {
+    __shared__ FeatSums sm[kFT];
+    FeatSums v = {};
+    for (int64_t b = threadIdx.x; b < n_part; b += kFT) {
+        const FeatSums &p = *reinterpret_cast<const FeatSums *>(part + b * kSumWords);
+#pragma unroll
+        for (int q = 0; q < SPC_N_SHAPES; ++q) v.nb[q] += p.nb[q];
+        v.single18 += p.single18;
+        v.empty_rows += p.empty_rows;
+        v.sum_len2 += p.sum_len2;
+        v.sum_dist += p.sum_dist;
+        v.max_len = v.max_len > p.max_len ? v.max_len : p.max_len;
+        v.nonempty_rows += p.nonempty_rows;
+        v.sum_log_span += p.sum_log_span;
+    }
+    block_reduce(v, sm, out);
+}
+
+}  // namespace
+}  // namespace spc
+
+using namespace spc;
+
+extern "C" spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
+                                          const int32_t *colidx, float *features_out,
+                                          int64_t *n_blocks_out, hipStream_t stream) {
+    SPC_REQUIRE(n_rows >= 1 && n_cols >= 1 && nnz >= 0, SPC_ERR_INVALID_ARG,
+                "features need n_rows >= 1, n_cols >= 1 and nnz >= 0");
+    SPC_REQUIRE(n_rows < (int64_t(1) << 31) && n_cols < (int64_t(1) << 31) && nnz < (int64_t(1) << 31),
+                SPC_ERR_OVERFLOW, "sizes exceed the int32 index range");
+    SPC_REQUIRE(rowptr && (colidx || nnz == 0) && features_out, SPC_ERR_INVALID_ARG, "null argument");
+    const int64_t n_groups = (n_rows + kGroup - 1) / kGroup;
+    const int64_t n_blk = div_up(n_groups, kFT);
+    DevBuf buf;
+    const size_t part_bytes = (size_t)(n_blk + 1) * sizeof(FeatSums);
+    SPC_HIP(buf.alloc(part_bytes + 256));
+    int64_t *part = buf.as<int64_t>();
+    int64_t *total = part + n_blk * kSumWords;
+    int *err = reinterpret_cast<int *>(buf.as<char>() + part_bytes);
+    SPC_HIP(hipMemsetAsync(err, 0, sizeof(int), stream));
+    hipLaunchKernelGGL(k_features, dim3((unsigned)n_blk), dim3(kFT), 0, stream, n_rows, n_cols, nnz, rowptr,
+                       colidx ? colidx : reinterpret_cast<const int32_t *>(rowptr), part, err);
+    hipLaunchKernelGGL(k_features_total, dim3(1), dim3(kFT), 0, stream, part, n_blk, total);
+    SPC_HIP(hipGetLastError());
+    FeatSums t;
+    int herr = 0;
+    SPC_HIP(hipMemcpyAsync(&t, total, sizeof(t), hipMemcpyDeviceToHost, stream));
+    SPC_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, stream));
+    SPC_HIP(hipStreamSynchronize(stream));
+    SPC_REQUIRE(!(herr & kErrRange), SPC_ERR_INDEX_RANGE,
+                "CSR row pointers not monotone from 0 to nnz, or a column outside [0, n_cols)");
+    SPC_REQUIRE(!(herr & kErrOrder), SPC_ERR_CSR_UNSORTED_OR_DUP, "a CSR row has unsorted or repeated columns");
+
+    const double n = (double)n_rows, m = (double)n_cols, z = (double)nnz;
+    double f[16] = {};
+    f[0] = std::log2(n);
+    f[1] = std::log2(m);
+    f[2] = std::log2(z + 1.0);
+    const double mean = z / n;
+    f[3] = mean;
+    if (nnz > 0) {
+        // n^2 * variance = n * sum(len^2) - nnz^2, exact in 128-bit integers
+        const __int128 v2 = (__int128)n_rows * t.sum_len2 - (__int128)nnz * nnz;
+        f[4] = std::sqrt((double)v2) / n / mean;
+    }
+    f[5] = std::log2(1.0 + (double)t.max_len);
+    f[6] = (double)t.empty_rows / n;
+    if (nnz > 0) f[7] = (double)t.sum_dist / z / (n > m ? n : m);
+    for (int s = 0; s < SPC_N_SHAPES; ++s) f[8 + s] = t.nb[s] ? z / (double)t.nb[s] : 0.0;
+    if (nnz > 0) {
+        f[14] = t.nb[0] ? (double)t.single18 / (double)t.nb[0] : 0.0;
+        f[15] = t.nonempty_rows ? t.sum_log_span / (double)t.nonempty_rows : 0.0;
+    }
+    for (int k = 0; k < 16; ++k) features_out[k] = (float)f[k];
+    if (n_blocks_out)
+        for (int s = 0; s < SPC_N_SHAPES; ++s) n_blocks_out[s] = t.nb[s];
+    return SPC_OK;
+}

@@ -1,0 +1,67 @@
+"""The library's interpolation selector (host code behind the C ABI, no GPU
+call) against the oracle's fit: same coefficients up to least-squares
+rounding, same clamped predictions, same choices where the choice is not a
+near tie."""
+import numpy as np
+import pytest
+
+from oracle import select as osel
+import paper_1801_01134_amd as spc
+from paper_1801_01134_amd import synth
+
+
+def _records(seed, n, noise):
+    rng = synth.rng_for(77, seed)
+    avg = np.stack([rng.uniform(1.0, 8.0 * (k + 1), size=n) for k in range(6)], axis=1)
+    speed = np.stack([30 + 12 * np.log(avg[:, k]) - 0.02 * avg[:, k] ** 2 + (k - 2) * 5.0
+                      + noise * rng.standard_normal(n) for k in range(6)], axis=1)
+    return avg, speed
+
+
+@pytest.mark.parametrize("seed,n,degree", [(0, 50, 3), (1, 400, 3), (2, 7, 2), (3, 30, 1), (4, 12, 0)])
+def test_interp_fit_matches_oracle(seed, n, degree):
+    avg, speed = _records(seed, n, noise=2.0)
+    ref = osel.fit_interpolation(avg, speed, degree=degree)
+    sel = spc.Selector().fit_interp(avg, speed, degree)
+    c, lo, hi = sel.interp_coeffs()
+    assert np.array_equal(lo, avg.min(axis=0)) and np.array_equal(hi, avg.max(axis=0))
+    for k in range(6):
+        want = ref.coeffs[k][::-1]  # numpy: highest power first
+        got = c[k, :want.size]
+        assert np.allclose(got, want, rtol=1e-8, atol=1e-9 * np.abs(want).max())
+        assert np.all(c[k, want.size:] == 0.0)
+    rng = synth.rng_for(78, seed)
+    for _ in range(50):
+        q = rng.uniform(0.0, 60.0, size=6)
+        f = np.zeros(16, np.float32)
+        f[8:14] = q
+        shape, scores = sel.select(f, spc.SEL_INTERP)
+        pred = ref.predict(f[8:14].astype(np.float64))
+        assert np.allclose(scores, pred.astype(np.float32), rtol=1e-6, atol=1e-5)
+        top = np.sort(pred)[::-1]
+        if top[0] - top[1] > 1e-6 * abs(top[0]):
+            assert shape == ref.select(f[8:14].astype(np.float64))
+
+
+def test_interp_few_distinct_points_lower_the_degree():
+    avg = np.tile(np.array([[2.0, 3, 4, 5, 6, 7]]), (5, 1))
+    avg[:2] += 1.0  # two distinct values per shape
+    speed = avg * 3.0 + 1.0
+    ref = osel.fit_interpolation(avg, speed, degree=3)
+    c, _, _ = spc.Selector().fit_interp(avg, speed, 3).interp_coeffs()
+    for k in range(6):
+        assert ref.coeffs[k].size == 2
+        assert np.allclose(c[k, :2], ref.coeffs[k][::-1]) and np.all(c[k, 2:] == 0)
+
+
+def test_selector_errors():
+    sel = spc.Selector()
+    f = np.zeros(16, np.float32)
+    with pytest.raises(spc.SpcError) as e:
+        sel.select(f, spc.SEL_INTERP)
+    assert e.value.code == -7  # no model yet
+    with pytest.raises(spc.SpcError) as e:
+        sel.fit_interp(np.full((3, 6), np.nan), np.ones((3, 6)))
+    assert e.value.code == -1
+    with pytest.raises(spc.SpcError):
+        sel.fit_interp(np.ones((3, 6)), np.ones((3, 6)), degree=4)
