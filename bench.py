@@ -1,18 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark: SpMV over beta(r,c) on the 27-point stencil of a 128^3 grid.
 
-Workload (synthetic, seeded): 2,097,152 rows, 55,742,968 nonzeros, natural
-ordering, diagonal 27, off-diagonals and x drawn from U[-1, 1]. Every block
-shape (1,8) (2,4) (2,8) (4,4) (4,8) (8,4) is converted on the device and
-timed in FP64 and FP32; the headline is the FP64 product with the kernel the
-library selects for this matrix (the fastest of the six on the records taken
-here). A step is one y = A x with that kernel, inputs resident in HBM.
+Headline workload (synthetic, seeded): 2,097,152 rows, 55,742,968 nonzeros,
+natural ordering, diagonal 27, off-diagonals and x drawn from U[-1, 1]. Every
+block shape (1,8) (2,4) (2,8) (4,4) (4,8) (8,4) is converted on the device
+and timed in FP64 and FP32, each autotuned over its plan candidates; the
+headline is the FP64 product with the fastest of the six (the kernel the
+timing records select for this matrix). A step is one y = A x with that
+kernel, inputs resident in HBM.
 
 Flop count per product: 2 * nnz (the paper's GFlop/s definition). The
 roofline figure divides the algorithmic bytes of one launch (values, block
 columns, masks, interval pointers, tile descriptors, x and y, each once) by
 the average kernel duration measured with HIP events on the launch stream,
 against the MI355X HBM peak of 8 TB/s.
+
+Further sections of the same JSON line (each can be switched off):
+  selection   the learned selector (network) and the interpolation pick a
+              shape for the headline matrix from its features alone; their
+              kernel's time over the best kernel's time; held-out regrets
+              of both on the recorded selector population
+  batched     64 matrices (rows log-uniform in [10k, 500k], Poisson(16.8)
+              uniform columns + Poisson(2.4) dense 3x3 blocks per block row),
+              each in the shape the selector picks, as one launch versus 64
+              launches (plain and graph-captured)
+  cg          CG on the SPD 27-point matrix of a 192^3 grid (7,077,888 rows,
+              189,119,224 nonzeros) with k = 1, 4, 8, 16 right-hand sides,
+              FP64 to 1e-8 and FP32 to 1e-5, true residuals recomputed by
+              the FP64 CSR oracle on the host
 
 Prints one JSON line. --gpus N with N > 1 is refused: this build runs one GPU.
 """
@@ -22,12 +37,20 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MODEL_DIR = os.path.join(ROOT, "paper_1801_01134_amd", "records")
+RECORDS = os.path.join(MODEL_DIR, "selector_records_mi355x.jsonl")
+MODEL = os.path.join(MODEL_DIR, "selector_mlp_mi355x.json")
+
+
+def log(*a):
+    print("#", *a, file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(B, n_tiles: int, k: int = 1, accumulate: bool = False) -> int:
@@ -66,19 +89,21 @@ def measured_traffic(kname: str, shape, params: dict, m: int):
     return None
 
 
-def time_spmv(spc, torch, B, x, y, plan, steps: int, warmup: int):
-    """Average device time of one launch (HIP events on the current stream)."""
-    for _ in range(warmup):
-        spc.spmv(B, x, y, plan=plan)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        spc.spmv(B, x, y, plan=plan)
-    e1.record()
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps * 1e-3  # seconds
+def event_time(torch, fn, steps: int, warmup: int, stream=None) -> float:
+    """Average seconds per call of fn, HIP events on the stream it launches on."""
+    s = stream or torch.cuda.current_stream()
+    with torch.cuda.stream(s):
+        for _ in range(warmup):
+            fn()
+        s.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            fn()
+        e1.record(s)
+        s.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / steps
 
 
 def cpu_baseline(A, x, budget_s: float = 10.0):
@@ -100,6 +125,198 @@ def cpu_baseline(A, x, budget_s: float = 10.0):
                       f"(mean {per * 1e3:.1f} ms each, {el:.1f} s total)"}
 
 
+# ---------------------------------------------------------------------------
+# workload generation in worker processes (forked before the GPU is touched)
+
+def _gen_batched(args):
+    i, tmp = args
+    import numpy as np
+
+    from paper_1801_01134_amd import synth
+    A = synth.batched_matrix(i)
+    base = os.path.join(tmp, f"b{i}")
+    np.save(base + "_rp.npy", A.rowptr)
+    np.save(base + "_ci.npy", A.colidx)
+    np.save(base + "_v.npy", A.values)
+    return i, A.n_rows, A.n_cols, base
+
+
+def _gen_cg(args):
+    m, tmp = args
+    import numpy as np
+
+    from paper_1801_01134_amd import synth
+    A = synth.stencil27(m, diag=26.1, offdiag=-1.0)
+    base = os.path.join(tmp, f"cg{m}")
+    np.save(base + "_rp.npy", A.rowptr)
+    np.save(base + "_ci.npy", A.colidx)
+    np.save(base + "_v.npy", A.values)
+    return m, A.n_rows, A.n_cols, base
+
+
+def _load_csr(base, n_rows, n_cols):
+    import numpy as np
+
+    from paper_1801_01134_amd import synth
+    A = synth.CSR(n_rows, n_cols, np.load(base + "_rp.npy"), np.load(base + "_ci.npy"), np.load(base + "_v.npy"))
+    for suf in ("_rp.npy", "_ci.npy", "_v.npy"):
+        os.remove(base + suf)
+    return A
+
+
+# ---------------------------------------------------------------------------
+# sections
+
+def load_selector(spc):
+    """(Selector with interpolation and, if present, the network; held-out
+    evaluation of both) from the committed records and model."""
+    from paper_1801_01134_amd import records as R
+    if not os.path.exists(RECORDS):
+        return None, None, None
+    recs = R.load(RECORDS)
+    train, test = R.split(recs)
+    Xtr, Ttr, Atr, Gtr = R.arrays(train)
+    sel = spc.Selector().fit_interp(Atr, Gtr, 3)
+    model = None
+    if os.path.exists(MODEL):
+        with open(MODEL) as f:
+            model = json.load(f)
+        sel.set_mlp(model["params"], model["mu"], model["sd"])
+    held_out, _ = R.evaluate(train, test, model) if model else (None, None)
+    return sel, model, held_out
+
+
+def select_shape(spc, sel, model, feat):
+    if sel is None:
+        return None, None
+    si = sel.select(feat, spc.SEL_INTERP)[0]
+    sm = sel.select(feat, spc.SEL_MLP)[0] if model else None
+    return sm, si
+
+
+def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, warmup: int):
+    dev = torch.device("cuda")
+    results = pool.map(_gen_batched, [(i, tmp) for i in range(n_mat)])
+    Bs, xs, ys, shapes = [], [], [], []
+    from paper_1801_01134_amd import synth
+    total_nnz = 0
+    for i, n_rows, n_cols, base in results:
+        A = _load_csr(base, n_rows, n_cols)
+        rp = torch.from_numpy(A.rowptr).to(dev)
+        ci = torch.from_numpy(A.colidx).to(dev)
+        feat, _ = spc.matrix_features(rp, ci, A.n_cols)
+        s = None
+        if sel is not None:
+            s = select_shape(spc, sel, model, feat)[0 if model else 1]
+        s = 0 if s is None else s
+        r, c = spc.SHAPES[s]
+        Bs.append(spc.csr_to_beta(r, c, rp, ci, torch.from_numpy(A.values).to(dev), A.n_cols))
+        xs.append(torch.from_numpy(synth.dense_vector(A.n_cols, 400 + i)).to(dev))
+        ys.append(torch.empty(A.n_rows, dtype=torch.float64, device=dev))
+        shapes.append(s)
+        total_nnz += A.nnz
+        del rp, ci
+    batch = spc.Batch(Bs).set_vectors(xs, ys)
+    plans = [B.plan() for B in Bs]
+    ab = sum(algorithmic_bytes(B, P.info()["n_tiles"]) for B, P in zip(Bs, plans))
+    flops = 2.0 * total_nnz
+    out = {"matrices": n_mat, "nnz_total": total_nnz, "rows_total": sum(B.n_rows for B in Bs),
+           "shape_share": [shapes.count(k) for k in range(6)], "alg_bytes": ab,
+           "n_tiles": batch.info()["n_tiles"]}
+
+    def sep():
+        for B, x, y, P in zip(Bs, xs, ys, plans):
+            spc.spmv(B, x, y, plan=P)
+
+    sep()
+    torch.cuda.synchronize()
+    ref = [y.clone() for y in ys]
+    side = torch.cuda.Stream()
+    variants = {"one_launch": (lambda: batch.run(), None),
+                "one_launch_persistent_2048wg": (lambda: batch.run(grid_blocks=2048), None),
+                "one_launch_graph": (lambda: batch.run(use_graph=True), side),
+                "separate_launches": (sep, None)}
+    for name, (fn, st) in variants.items():
+        t = event_time(torch, fn, steps, warmup, st)
+        out[name] = {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1),
+                     "alg_GBs": round(ab / t / 1e9, 1), "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
+    # 64 launches captured in one graph
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        sep()
+    t = event_time(torch, g.replay, steps, warmup, side)
+    out["separate_launches_graph"] = {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1),
+                                      "alg_GBs": round(ab / t / 1e9, 1),
+                                      "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
+    batch.run()
+    torch.cuda.synchronize()
+    out["bitwise_equal_to_separate"] = all(torch.equal(a, b) for a, b in zip(ys, ref))
+    out["speedup_one_launch_vs_separate"] = round(out["separate_launches"]["us"] / out["one_launch"]["us"], 3)
+    return out
+
+
+def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
+    import numpy as np
+
+    from oracle import cg as ocg
+    from paper_1801_01134_amd import synth
+    dev = torch.device("cuda")
+    _, n_rows, n_cols, base = pool.apply(_gen_cg, ((m, tmp),))
+    A = _load_csr(base, n_rows, n_cols)
+    rp = torch.from_numpy(A.rowptr).to(dev)
+    ci = torch.from_numpy(A.colidx).to(dev)
+    out = {"grid": m, "n": A.n_rows, "nnz": A.nnz, "runs": []}
+    for dt, kset, tol in ((torch.float64, ks, 1e-8), (torch.float32, fp32_ks, 1e-5)):
+        vals = torch.from_numpy(A.values).to(dev).to(dt)
+        # shape and tile size: the faster SpMM at the largest k among two shapes x three chunk counts
+        best = None
+        kmax = max(kset)
+        for (r, c) in ((2, 4), (4, 8)):
+            B = spc.csr_to_beta(r, c, rp, ci, vals, A.n_cols)
+            X = torch.from_numpy(synth.dense_block(A.n_cols, kmax, 700)).to(dev).to(dt)
+            for kq in (2, 4, 8):
+                P = B.plan(0, 0, 0, kq)
+                t = event_time(torch, lambda: spc.spmm(B, X, plan=P), 10, 2)
+                if best is None or t < best[0]:
+                    best = (t, (r, c), kq)
+            del B, X
+            torch.cuda.empty_cache()
+        (r, c), kq = best[1], best[2]
+        B = spc.csr_to_beta(r, c, rp, ci, vals, A.n_cols)
+        P = B.plan(0, 0, 0, kq)
+        for k in kset:
+            Bm = synth.dense_block(A.n_cols, k, 701 + k)
+            Bd = torch.from_numpy(Bm).to(dev).to(dt)
+            X = torch.from_numpy(synth.dense_block(A.n_cols, k, 702)).to(dev).to(dt)
+            t_spmm = event_time(torch, lambda: spc.spmm(B, X, plan=P), 10, 2)
+            s = torch.cuda.Stream()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(s):
+                Xs, its, res, total = spc.cg(B, Bd, rel_tol=tol, max_iter=5000, check_every=25, plan=P)
+            s.synchronize()
+            wall = time.perf_counter() - t0
+            Xh = Xs.cpu().numpy().astype(np.float64)
+            Bh = Bd.cpu().numpy().astype(np.float64)
+            true = ocg.true_residual(A, Xh, Bh) / np.linalg.norm(Bh, axis=0)
+            ab = algorithmic_bytes(B, P.info()["n_tiles"], k=k)
+            out["runs"].append({
+                "dtype": "f64" if dt == torch.float64 else "f32", "k": k, "shape": [r, c], "wave_chunks": kq,
+                "rel_tol": tol, "iterations": its, "iterations_run": total,
+                "true_rel_residual_max": float(true.max()),
+                "converged": bool(all(i > 0 for i in its) and true.max() <= 10 * tol),
+                "cg_ms": round(wall * 1e3, 2), "ms_per_iteration": round(wall * 1e3 / max(1, total), 4),
+                "spmm_us": round(t_spmm * 1e6, 1), "spmm_gflops": round(2.0 * A.nnz * k / t_spmm / 1e9, 1),
+                "spmm_alg_GBs": round(ab / t_spmm / 1e9, 1),
+                "spmm_hbm_frac": round(ab / t_spmm / 1e9 / HBM_PEAK_GBS, 4),
+                "spmm_share_of_iteration": round(t_spmm * total / wall, 3) if total else None})
+            log(f"cg {out['runs'][-1]}")
+            del X, Xs, Bd
+        del B, P, vals
+        torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +326,12 @@ def main(argv=None):
     ap.add_argument("--sweep-steps", type=int, default=20, help="timed launches per autotune candidate")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--shape", default="auto", help="r,c of the headline kernel, or auto")
-    ap.add_argument("--only-headline", action="store_true", help="skip the 12-kernel sweep")
+    ap.add_argument("--only-headline", action="store_true", help="skip the sweep and every extra section")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-select", action="store_true")
+    ap.add_argument("--batched-matrices", type=int, default=64)
+    ap.add_argument("--cg-grid", type=int, default=192)
     ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap: force the "
                     "headline plan (skips autotuning; used for profiling)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -131,8 +353,30 @@ def main(argv=None):
         print(f"bench.py: --gpus {args.gpus} refused: this build measures one GPU only "
               "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
         return 2
+    extras = not args.only_headline
+    do_batched = extras and not args.no_batched
+    do_cg = extras and not args.no_cg
+    do_select = extras and not args.no_select
 
-    import numpy as np
+    # worker processes for the CPU-side matrix generation, forked before any GPU call
+    pool = None
+    tmp = tempfile.mkdtemp(prefix="spc_bench_")
+    if do_batched or do_cg:
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(12)
+
+    try:
+        return run(args, pool, tmp, do_batched, do_cg, do_select)
+    finally:
+        if pool is not None:
+            pool.terminate()
+            pool.join()
+        for f in os.listdir(tmp):
+            os.remove(os.path.join(tmp, f))
+        os.rmdir(tmp)
+
+
+def run(args, pool, tmp, do_batched, do_cg, do_select):
     import torch
 
     import paper_1801_01134_amd as spc
@@ -144,8 +388,7 @@ def main(argv=None):
     t_gen = time.perf_counter()
     A = synth.stencil27(m, diag=27.0)
     x64 = synth.dense_vector(A.n_cols, 1)
-    print(f"# generated {m}^3 stencil: n={A.n_rows} nnz={A.nnz} in {time.perf_counter() - t_gen:.1f}s",
-          file=sys.stderr, flush=True)
+    log(f"generated {m}^3 stencil: n={A.n_rows} nnz={A.nnz} in {time.perf_counter() - t_gen:.1f}s")
     rp = torch.from_numpy(A.rowptr).to(dev)
     ci = torch.from_numpy(A.colidx).to(dev)
     v64 = torch.from_numpy(A.values).to(dev)
@@ -154,14 +397,11 @@ def main(argv=None):
 
     sweep = {}
     best_params = {}
-    shapes = spc.SHAPES
-    if args.only_headline and args.shape != "auto":
-        shapes = [tuple(int(v) for v in args.shape.split(","))]
     for dt in (torch.float64, torch.float32):
         if args.only_headline:
             break
         xd = torch.from_numpy(x64).to(dev).to(dt)
-        for (r, c) in shapes:
+        for (r, c) in spc.SHAPES:
             B = spc.csr_to_beta(r, c, rp, ci, v64.to(dt), A.n_cols)
             params, us, records = spc.autotune(B, reps=args.sweep_steps, x=xd)
             t = us * 1e-6
@@ -177,11 +417,11 @@ def main(argv=None):
                           "n_blocks": B.n_blocks, "avg_nnz_per_block": round(A.nnz / B.n_blocks, 3),
                           "n_tiles": info["n_tiles"], "n_long": info["n_long"], "plan": params,
                           "candidates": len(records)}
-            print(f"# {key}: {sweep[key]}", file=sys.stderr, flush=True)
+            log(f"{key}: {sweep[key]}")
             del B, P
             torch.cuda.empty_cache()
 
-    # headline kernel: FP64, chosen from the records above (or forced)
+    # headline kernel: FP64, the fastest in the records above (or forced)
     if args.shape == "auto" and not sweep:
         r, c = 2, 4
     elif args.shape == "auto":
@@ -221,9 +461,28 @@ def main(argv=None):
     achieved = ab / t_kernel / 1e9
     value = flops / (wall / args.steps) / 1e9
     traffic = measured_traffic(kname, (r, c), params, m)
-    f64_times = {k: v["us"] for k, v in sweep.items() if k.startswith("f64_")}
-    sel_key = f"f64_b{r}x{c}"
-    ratio = (f64_times[sel_key] / min(f64_times.values())) if sel_key in f64_times and f64_times else None
+    del B, P
+
+    # selection: shapes picked from the matrix's features alone
+    selection = None
+    ratio = None
+    sel = model = None
+    if do_select:
+        sel, model, held_out = load_selector(spc)
+        feat, nb = spc.matrix_features(rp, ci, A.n_cols)
+        f64_times = {k: v["us"] for k, v in sweep.items() if k.startswith("f64_")}
+        selection = {"features": [round(float(v), 5) for v in feat], "held_out_regret": held_out}
+        if sel is not None and f64_times:
+            sm, si = select_shape(spc, sel, model, feat)
+            t_best = min(f64_times.values())
+            for name, s_ in (("mlp", sm), ("interpolation", si)):
+                if s_ is None:
+                    continue
+                key = f"f64_b{spc.SHAPES[s_][0]}x{spc.SHAPES[s_][1]}"
+                selection[name] = {"shape": list(spc.SHAPES[s_]), "time_ratio": round(f64_times[key] / t_best, 4)}
+            ratio = selection.get("mlp", selection.get("interpolation", {})).get("time_ratio")
+        elif not f64_times:
+            selection["note"] = "no sweep (only-headline): ratios need every shape's time"
 
     out = {
         "metric": "SpMV GFlop/s + HBM GB/s % of peak; selected-vs-best kernel time ratio",
@@ -239,12 +498,20 @@ def main(argv=None):
                      "traffic_source": traffic["source"] if traffic else "no counter record for this kernel build",
                      "kernel": kname, "plan": params,
                      "alg_bytes_per_launch": ab, "kernel_us": round(t_kernel * 1e6, 2)},
-        "selected_vs_best_time_ratio": round(ratio, 4) if ratio else None,
-        "selection": "fastest of the six beta kernels on this matrix, each autotuned over 14 plan "
-                     "candidates (records taken in this run)" if args.shape == "auto" else "forced",
+        "selected_vs_best_time_ratio": ratio,
+        "headline_selection": "fastest of the six beta kernels on this matrix, each autotuned over its plan "
+                              "candidates (records taken in this run)" if args.shape == "auto" else "forced",
+        "selection": selection,
         "per_kernel": sweep,
     }
-    del B, P
+    if do_batched:
+        out["batched"] = batched_section(spc, torch, sel, model, pool, tmp, args.batched_matrices,
+                                         max(5, args.steps // 10), 3)
+        log(f"batched: {out['batched']}")
+        torch.cuda.empty_cache()
+    if do_cg:
+        out["cg"] = cg_section(spc, torch, pool, tmp, args.cg_grid, (1, 4, 8, 16), (1, 16))
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, x64)
     print(json.dumps(out), flush=True)

@@ -235,6 +235,36 @@ spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t 
                         int32_t max_records, int32_t *n_records, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched products: y_i = A_i x_i (or y_i += A_i x_i) for `count` matrices
+ * of uneven sizes and any of the six shapes, in ONE kernel launch. Each
+ * matrix is partitioned as spc_plan_create would (whole intervals, about
+ * equal blocks per tile, section "Parallelization"); the tiles of all
+ * matrices form one list that the launch runs, each wavefront switching on
+ * its tile's matrix and shape.
+ *
+ * spc_batch_create: views (host array of count views, all of one dtype,
+ *   values 16-byte aligned, x of each under 3.75 GiB); params: NULL or a
+ *   mode-0 parameter set (wave_chunks). The batch keeps the views: their
+ *   arrays must stay alive and unchanged. Synchronizes.
+ * spc_batch_set_vectors: xs, ys = host arrays of count device pointers (x_i
+ *   with n_cols_i entries, y_i with n_rows_i entries). Copies them to the
+ *   batch's device table with a synchronous copy; do not call it while a
+ *   batched launch of this batch is still running.
+ * spc_spmv_batched: grid_blocks = 0 launches one wavefront per tile;
+ *   grid_blocks > 0 launches that many workgroups that loop over the tile
+ *   list (persistent). use_graph = 1 captures the launch once in a HIP graph
+ *   (needs a non-NULL stream; recaptured when accumulate or grid_blocks
+ *   change) and replays it. Asynchronous. */
+typedef struct spc_batch spc_batch;
+spc_status spc_batch_create(int32_t count, const spc_beta_view *views, const spc_plan_params *params,
+                            spc_batch **out, hipStream_t stream);
+spc_status spc_batch_destroy(spc_batch *batch);
+spc_status spc_batch_info(const spc_batch *batch, int64_t *n_tiles, int64_t *n_long);
+spc_status spc_batch_set_vectors(spc_batch *batch, const void *const *xs, void *const *ys);
+spc_status spc_spmv_batched(spc_batch *batch, int32_t accumulate, int32_t grid_blocks, int32_t use_graph,
+                            hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Matrix features for kernel selection, from the CSR structure alone (section
  * "Performance prediction and optimal kernel selection": the block counts
  * that drive the per-kernel prediction are obtained without converting).

@@ -70,6 +70,11 @@ _SIGS = {
                                POINTER(ctypes.c_float), c_void_p, c_int32, POINTER(c_int32), c_void_p]),
     "spc_matrix_features": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_void_p, POINTER(ctypes.c_float),
                                       POINTER(c_int64), c_void_p]),
+    "spc_batch_create": (c_int32, [c_int32, POINTER(BetaView), POINTER(PlanParams), POINTER(c_void_p), c_void_p]),
+    "spc_batch_destroy": (c_int32, [c_void_p]),
+    "spc_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
+    "spc_batch_set_vectors": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),
+    "spc_spmv_batched": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
     "spc_mlp_standardizer": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
     "spc_mlp_targets": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "spc_mlp_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32),
@@ -521,3 +526,46 @@ class Selector:
         check(lib().spc_select_kernel(self.handle, f.ctypes.data_as(POINTER(ctypes.c_float)), method,
                                       ctypes.byref(out), sc, stream_ptr() if method == SEL_MLP else None))
         return int(out.value), np.array(list(sc), dtype=np.float32)
+
+
+class Batch:
+    """Many BetaMatrix products in one launch (library-owned batch)."""
+
+    def __init__(self, mats: list, wave_chunks: int = 0):
+        if not mats:
+            raise ValueError("need at least one matrix")
+        self.mats = list(mats)
+        self._views = (BetaView * len(mats))(*[m.view() for m in mats])
+        p = PlanParams(0, 0, 0, wave_chunks)
+        h = c_void_p()
+        check(lib().spc_batch_create(len(mats), self._views, ctypes.byref(p), ctypes.byref(h), stream_ptr()))
+        self.handle = h
+        self._xs = self._ys = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.spc_batch_destroy(h)
+            self.handle = None
+
+    def info(self) -> dict:
+        nt, nl = c_int64(), c_int64()
+        check(lib().spc_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(nl)))
+        return {"n_tiles": nt.value, "n_long": nl.value}
+
+    def set_vectors(self, xs: list, ys: list):
+        if len(xs) != len(self.mats) or len(ys) != len(self.mats):
+            raise ValueError("one x and one y per matrix")
+        for A, x, y in zip(self.mats, xs, ys):
+            if x.numel() != A.n_cols or y.numel() != A.n_rows or x.dtype != A.dtype or y.dtype != A.dtype \
+                    or not x.is_contiguous() or not y.is_contiguous():
+                raise ValueError("x_i / y_i must be contiguous vectors of A_i's sizes and dtype")
+        n = len(self.mats)
+        xa = (c_void_p * n)(*[x.data_ptr() for x in xs])
+        ya = (c_void_p * n)(*[y.data_ptr() for y in ys])
+        check(lib().spc_batch_set_vectors(self.handle, xa, ya))
+        self._xs, self._ys = list(xs), list(ys)  # keep them alive
+        return self
+
+    def run(self, accumulate: bool = False, grid_blocks: int = 0, use_graph: bool = False):
+        check(lib().spc_spmv_batched(self.handle, int(accumulate), grid_blocks, int(use_graph), stream_ptr()))

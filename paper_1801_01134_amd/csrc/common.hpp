@@ -83,6 +83,25 @@ struct TileDesc {
     int32_t reserved;
 };
 
+// One matrix of a batch, as the batched kernel reads it (device table).
+struct BatchMat {
+    const int32_t *brow;
+    const int32_t *bcol;
+    const uint64_t *mw;
+    const void *vals;
+    const void *x;
+    void *y;
+    int64_t n_rows, nnz, n_blocks, n_cols;
+    int32_t shape;
+    int32_t reserved;
+};
+
+// Batched product over a concatenated tile list (TileDesc::reserved holds
+// the matrix index). grid_blocks 0: one wavefront per tile; > 0: that many
+// workgroups loop over the tiles.
+spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
+                          int accumulate, int grid_blocks, hipStream_t stream);
+
 // Validation of a view on the host.
 spc_status check_view(const spc_beta_view *A);
 

@@ -612,6 +612,68 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave(SpmvArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Batched: tiles of many matrices in one launch. A wavefront reads its tile,
+// the tile's matrix (TileDesc::reserved) and switches on that matrix's shape;
+// tile, matrix and shape are uniform across the wavefront, so the switch is a
+// scalar branch. The LDS of a wavefront is the largest of the six layouts.
+template <class T, int KQ>
+union BatchSmem {
+    WaveSmem<Shape<1, 8>, T, KQ> s0;
+    WaveSmem<Shape<2, 4>, T, KQ> s1;
+    WaveSmem<Shape<2, 8>, T, KQ> s2;
+    WaveSmem<Shape<4, 4>, T, KQ> s3;
+    WaveSmem<Shape<4, 8>, T, KQ> s4;
+    WaveSmem<Shape<8, 4>, T, KQ> s5;
+};
+
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void batched_tile(const SpmvArgs &a, const TileDesc &d, WaveSmem<Sh, T, KQ> &sm) {
+    if (d.b1 - d.b0 > WaveSmem<Sh, T, KQ>::NB) {
+        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+    } else {
+        const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+        wave_tile<Sh, T, KQ>(a, d, xr, sm);
+    }
+}
+
+template <class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_batched(const BatchMat *__restrict__ mats,
+                                                           const TileDesc *__restrict__ tiles, int64_t n_tiles,
+                                                           int accumulate) {
+    __shared__ BatchSmem<T, KQ> sm[kWaves];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += (int64_t)gridDim.x * kWaves) {
+        const TileDesc d = tiles[t];
+        const BatchMat &M = mats[d.reserved];
+        SpmvArgs a;
+        a.brow = M.brow;
+        a.bcol = M.bcol;
+        a.mw = M.mw;
+        a.vals = M.vals;
+        a.x = M.x;
+        a.y = M.y;
+        a.tiles = tiles;
+        a.n_rows = M.n_rows;
+        a.nnz = M.nnz;
+        a.n_blocks = M.n_blocks;
+        a.n_cols = M.n_cols;
+        a.n_tiles = 0;
+        a.accumulate = accumulate;
+        a.xcd_remap = 0;
+        a.tiles_per_xcd = 0;
+        wave_sync();  // the previous tile's LDS reads are done before this tile writes
+        switch (M.shape) {
+        case 0: batched_tile<Shape<1, 8>, T, KQ>(a, d, sm[wid].s0); break;
+        case 1: batched_tile<Shape<2, 4>, T, KQ>(a, d, sm[wid].s1); break;
+        case 2: batched_tile<Shape<2, 8>, T, KQ>(a, d, sm[wid].s2); break;
+        case 3: batched_tile<Shape<4, 4>, T, KQ>(a, d, sm[wid].s3); break;
+        case 4: batched_tile<Shape<4, 8>, T, KQ>(a, d, sm[wid].s4); break;
+        default: batched_tile<Shape<8, 4>, T, KQ>(a, d, sm[wid].s5); break;
+        }
+    }
+}
+
 template <int R, int C, class T>
 spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (tb) {
@@ -636,6 +698,32 @@ spc_status launch_wave(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream)
 }
 
 }  // namespace
+
+spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
+                          int accumulate, int grid_blocks, hipStream_t stream) {
+    if (n_tiles == 0) return SPC_OK;
+    const int64_t groups = div_up(n_tiles, kWaves);
+    const unsigned grid = (unsigned)(grid_blocks > 0 && grid_blocks < groups ? grid_blocks : groups);
+    return with_dtype(dtype, [&](auto tv) -> spc_status {
+        using T = decltype(tv);
+        switch (kq) {
+        case 2:
+            hipLaunchKernelGGL((k_spmv_batched<T, 2>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                               n_tiles, accumulate);
+            break;
+        case 8:
+            hipLaunchKernelGGL((k_spmv_batched<T, 8>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                               n_tiles, accumulate);
+            break;
+        default:
+            hipLaunchKernelGGL((k_spmv_batched<T, 4>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                               n_tiles, accumulate);
+            break;
+        }
+        SPC_HIP(hipGetLastError());
+        return SPC_OK;
+    });
+}
 
 // Mode 0 loads a tile's interval pointers one per lane, the end pointer included.
 int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? (r == 1 ? 63 : 64 / r) : kThreads / r; }

@@ -1,0 +1,275 @@
+"""Timing records of the six beta(r,c) kernels and the selectors built on them.
+
+The paper chooses a kernel from timings recorded on earlier runs (its
+record-based strategy): one polynomial per kernel of speed against Avg(r,c)
+(section "Performance polynomial interpolation"). This module
+
+  * collects records: for each matrix of the seeded selector population,
+    the 16 device features (spc_matrix_features), and for each of the six
+    shapes the device conversion followed by the autotuner
+    (spc_autotune: every plan candidate timed with HIP events); one JSON line
+    per matrix;
+  * fits the interpolation selector (spc_selector_fit_interp) and trains the
+    network on the device (spc_mlp_standardizer / spc_mlp_targets /
+    spc_mlp_train) from a training split of the records;
+  * evaluates both on the held-out split by regret = t_selected / t_best - 1
+    using the recorded times.
+
+Command line:
+  python -m paper_1801_01134_amd.records collect --first 0 --count 2000 --out recs.jsonl
+  python -m paper_1801_01134_amd.records train --records recs.jsonl --out model.json
+  python -m paper_1801_01134_amd.records evaluate --records recs.jsonl --model model.json
+
+Matrix generation is CPU work (numpy); a pool of worker processes, started
+before this process touches the GPU, keeps the device busy.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+SHAPES = [(1, 8), (2, 4), (2, 8), (4, 4), (4, 8), (8, 4)]
+DEFAULT_MIN_ROWS = 50_000
+DEFAULT_MAX_ROWS = 1_000_000
+TRAIN_FRACTION = 0.8
+
+
+# ---------------------------------------------------------------------------
+# collection
+
+def _generate(args):
+    """Worker: build matrix `index` and park its CSR structure in files."""
+    index, min_rows, max_rows, tmp = args
+    from . import synth
+    t0 = time.perf_counter()
+    fam, A = synth.selector_matrix(index, min_rows, max_rows)
+    base = os.path.join(tmp, f"m{index}")
+    np.save(base + "_rp.npy", A.rowptr)
+    np.save(base + "_ci.npy", A.colidx)
+    return index, fam, A.n_rows, A.n_cols, base, time.perf_counter() - t0
+
+
+def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int = 12,
+            min_rows: int = DEFAULT_MIN_ROWS, max_rows: int = DEFAULT_MAX_ROWS, log=sys.stderr):
+    import multiprocessing as mp
+    # the pool is forked before this process initialises the GPU
+    ctx = mp.get_context("fork")
+    tmp = tempfile.mkdtemp(prefix="spc_records_")
+    pool = ctx.Pool(workers)
+    try:
+        import torch
+
+        from . import _binding as b
+        dev = torch.device("cuda")
+        gen = torch.Generator(device=dev)
+        pending = []
+        todo = list(range(first, first + count))
+        window = 2 * workers
+        t_start = time.perf_counter()
+        with open(out_path, "a") as out:
+            while todo or pending:
+                while todo and len(pending) < window:
+                    i = todo.pop(0)
+                    pending.append(pool.apply_async(_generate, ((i, min_rows, max_rows, tmp),)))
+                index, fam, n_rows, n_cols, base, t_gen = pending.pop(0).get()
+                rp = torch.from_numpy(np.load(base + "_rp.npy")).to(dev)
+                ci = torch.from_numpy(np.load(base + "_ci.npy")).to(dev)
+                os.remove(base + "_rp.npy")
+                os.remove(base + "_ci.npy")
+                nnz = ci.numel()
+                gen.manual_seed(1801 * 100003 + index)
+                vals = torch.empty(max(1, nnz), dtype=torch.float64, device=dev).uniform_(-1.0, 1.0,
+                                                                                        generator=gen)[:nnz]
+                x = torch.empty(n_cols, dtype=torch.float64, device=dev).uniform_(-1.0, 1.0, generator=gen)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                feat, nb = b.matrix_features(rp, ci, n_cols)
+                t_feat = time.perf_counter() - t0
+                us, dflt, params, ntiles = [], [], [], []
+                for (r, c) in SHAPES:
+                    B = b.csr_to_beta(r, c, rp, ci, vals, n_cols)
+                    p, t, recs = b.autotune(B, reps=reps, x=x)
+                    us.append(float(t))
+                    params.append(p)
+                    d = [q["us"] for q in recs if q["mode"] == 0 and q["wave_chunks"] in (0, 4)
+                         and q["xcd_remap"] == 0]
+                    dflt.append(float(d[0]) if d else float("nan"))
+                    ntiles.append(int(next((q["n_tiles"] for q in recs if q["mode"] == p["mode"]
+                                            and q["wave_chunks"] == p["wave_chunks"]
+                                            and q["tile_bits"] == p["tile_bits"]
+                                            and q["xcd_remap"] == p["xcd_remap"]), -1)))
+                    del B
+                rec = {"index": index, "family": fam, "n_rows": n_rows, "n_cols": n_cols, "nnz": nnz,
+                       "features": [float(v) for v in feat], "n_blocks": [int(v) for v in nb],
+                       "us": us, "us_default_plan": dflt, "params": params, "n_tiles": ntiles,
+                       "gflops": [2.0 * nnz / (t * 1e-6) / 1e9 for t in us],
+                       "features_ms": t_feat * 1e3, "gen_s": t_gen}
+                out.write(json.dumps(rec) + "\n")
+                out.flush()
+                print(f"[records] {index} {fam} n={n_rows} nnz={nnz} best={int(np.argmin(us))} "
+                      f"us={[round(t, 1) for t in us]} ({time.perf_counter() - t_start:.0f}s)",
+                      file=log, flush=True)
+                del rp, ci, vals, x
+    finally:
+        pool.terminate()
+        pool.join()
+        for f in os.listdir(tmp):
+            os.remove(os.path.join(tmp, f))
+        os.rmdir(tmp)
+
+
+def load(path: str) -> list[dict]:
+    with open(path) as f:
+        recs = [json.loads(line) for line in f if line.strip()]
+    recs.sort(key=lambda r: r["index"])
+    return recs
+
+
+def split(recs: list[dict], train_fraction: float = TRAIN_FRACTION):
+    """Deterministic split by matrix index: the lowest indices train."""
+    n_train = int(round(train_fraction * len(recs)))
+    return recs[:n_train], recs[n_train:]
+
+
+def arrays(recs: list[dict]):
+    X = np.array([r["features"] for r in recs], dtype=np.float32)
+    T = np.array([r["us"] for r in recs], dtype=np.float64)
+    avg = X[:, 8:14].astype(np.float64)
+    G = np.array([r["gflops"] for r in recs], dtype=np.float64)
+    return X, T, avg, G
+
+
+# ---------------------------------------------------------------------------
+# selectors
+
+def train_mlp(X: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 64, lr: float = 2e-3,
+              seed: int = 0):
+    """Trains the network on the device. Returns (params, mu, sd, losses)
+    as numpy arrays. Learning rate: lr for the first half of the epochs, then
+    lr/4 and lr/16 (Adam's step count continues across the stages)."""
+    import torch
+
+    from . import _binding as b
+    from . import synth
+    dev = torch.device("cuda")
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).to(dev)
+    Td = torch.from_numpy(np.ascontiguousarray(T, dtype=np.float32)).to(dev)
+    mu, sd = b.mlp_standardizer(Xd)
+    tau = b.mlp_targets(Td)
+    rng = synth.rng_for(60, seed)
+    P = np.zeros(b.MLP_N_PARAMS, dtype=np.float32)
+    # He-uniform weights, zero biases (same recipe as the oracle's init)
+    o = 0
+    for (n_out, n_in) in ((64, 16), (64, 64), (6, 64)):
+        lim = np.sqrt(6.0 / n_in)
+        P[o:o + n_out * n_in] = rng.uniform(-lim, lim, size=n_out * n_in)
+        o += n_out * n_in + n_out
+    p = torch.from_numpy(P).to(dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    n = X.shape[0]
+    steps_per_epoch = n // batch
+    stages = [(epochs // 2, lr), (epochs // 4, lr / 4), (epochs - epochs // 2 - epochs // 4, lr / 16)]
+    step0 = 0
+    losses = []
+    for ep, lr_s in stages:
+        order = np.concatenate([rng.permutation(n)[:steps_per_epoch * batch] for _ in range(ep)]).astype(np.int32)
+        L = b.mlp_train(p, m, v, step0, lr_s, mu, sd, Xd, tau, order, batch)
+        losses.append(L.cpu().numpy())
+        step0 += ep * steps_per_epoch
+    return (p.cpu().numpy(), mu.cpu().numpy(), sd.cpu().numpy(),
+            np.concatenate(losses) if losses else np.zeros(0))
+
+
+def regrets(T: np.ndarray, choice: np.ndarray) -> np.ndarray:
+    return T[np.arange(T.shape[0]), choice] / T.min(axis=1) - 1.0
+
+
+def summary(reg: np.ndarray) -> dict:
+    return {"mean": float(reg.mean()), "geomean_ratio_minus_1": float(np.exp(np.mean(np.log1p(reg))) - 1.0),
+            "p90": float(np.quantile(reg, 0.9)), "max": float(reg.max()),
+            "within_5pct": float(np.mean(reg <= 0.05)), "exact": float(np.mean(reg == 0.0))}
+
+
+def evaluate(train: list[dict], test: list[dict], model: dict | None = None, epochs: int = 400):
+    """Fits both selectors on `train` (or uses `model`) and reports held-out
+    regrets for the network, the interpolation, and fixed shapes."""
+    import torch
+
+    from . import _binding as b
+    Xtr, Ttr, Atr, Gtr = arrays(train)
+    Xte, Tte, Ate, Gte = arrays(test)
+    sel = b.Selector().fit_interp(Atr, Gtr, 3)
+    if model is None:
+        t0 = time.perf_counter()
+        P, mu, sd, losses = train_mlp(Xtr, Ttr, epochs=epochs)
+        t_train = time.perf_counter() - t0
+        model = {"params": P.tolist(), "mu": mu.tolist(), "sd": sd.tolist(),
+                 "final_loss": float(losses[-1]) if losses.size else None, "train_s": t_train,
+                 "epochs": epochs, "n_train": len(train)}
+    dev = torch.device("cuda")
+    P = torch.tensor(model["params"], dtype=torch.float32, device=dev)
+    mu = torch.tensor(model["mu"], dtype=torch.float32, device=dev)
+    sd = torch.tensor(model["sd"], dtype=torch.float32, device=dev)
+    _, ch_mlp = b.mlp_infer(P, mu, sd, torch.from_numpy(Xte).to(dev))
+    ch_mlp = ch_mlp.cpu().numpy().astype(np.int64)
+    ch_int = np.array([sel.select(x, b.SEL_INTERP)[0] for x in Xte], dtype=np.int64)
+    best_avg = int(np.argmin(np.mean(Ttr / Ttr.min(axis=1, keepdims=True), axis=0)))
+    out = {"n_train": len(train), "n_test": len(test),
+           "mlp": summary(regrets(Tte, ch_mlp)),
+           "interpolation": summary(regrets(Tte, ch_int)),
+           "fixed_b1x8": summary(regrets(Tte, np.zeros(len(test), np.int64))),
+           f"fixed_best_on_train_{SHAPES[best_avg][0]}x{SHAPES[best_avg][1]}":
+               summary(regrets(Tte, np.full(len(test), best_avg, np.int64))),
+           "best_shape_share": np.bincount(Tte.argmin(axis=1), minlength=6).tolist(),
+           "mlp_choice_share": np.bincount(ch_mlp, minlength=6).tolist(),
+           "interp_choice_share": np.bincount(ch_int, minlength=6).tolist()}
+    return out, model
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--first", type=int, default=0)
+    c.add_argument("--count", type=int, default=2000)
+    c.add_argument("--out", required=True)
+    c.add_argument("--reps", type=int, default=5)
+    c.add_argument("--workers", type=int, default=12)
+    c.add_argument("--min-rows", type=int, default=DEFAULT_MIN_ROWS)
+    c.add_argument("--max-rows", type=int, default=DEFAULT_MAX_ROWS)
+    t = sub.add_parser("train")
+    t.add_argument("--records", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--epochs", type=int, default=400)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--records", required=True)
+    e.add_argument("--model", default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "collect":
+        collect(a.first, a.count, a.out, a.reps, a.workers, a.min_rows, a.max_rows)
+    elif a.cmd == "train":
+        tr, te = split(load(a.records))
+        res, model = evaluate(tr, te, epochs=a.epochs)
+        with open(a.out, "w") as f:
+            json.dump(model, f)
+        print(json.dumps(res))
+    else:
+        tr, te = split(load(a.records))
+        model = None
+        if a.model:
+            with open(a.model) as f:
+                model = json.load(f)
+        res, _ = evaluate(tr, te, model)
+        print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
