@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MODEL_DIR = os.path.join(ROOT, "paper_1801_01134_amd", "records")
-RECORDS = os.path.join(MODEL_DIR, "selector_records_mi355x.jsonl")
+RECORDS = [os.path.join(MODEL_DIR, f) for f in ("selector_records_mi355x.jsonl", "structured_records_mi355x.jsonl")]
 MODEL = os.path.join(MODEL_DIR, "selector_mlp_mi355x.json")
 
 
@@ -171,9 +171,10 @@ def load_selector(spc):
     """(Selector with interpolation and, if present, the network; held-out
     evaluation of both) from the committed records and model."""
     from paper_1801_01134_amd import records as R
-    if not os.path.exists(RECORDS):
+    paths = [p for p in RECORDS if os.path.exists(p)]
+    if not paths:
         return None, None, None
-    recs = R.load(RECORDS)
+    recs = R.load(*paths)
     train, test = R.split(recs)
     Xtr, Ttr, Atr, Gtr = R.arrays(train)
     sel = spc.Selector().fit_interp(Atr, Gtr, 3)
@@ -235,8 +236,11 @@ def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, w
     variants = {"one_launch": (lambda: batch.run(), None),
                 "one_launch_persistent_2048wg": (lambda: batch.run(grid_blocks=2048), None),
                 "one_launch_graph": (lambda: batch.run(use_graph=True), side),
+                "one_launch_shape_switching_kernel": (lambda: batch.run(), None),
                 "separate_launches": (sep, None)}
+    out["single_shape_kernel"] = batch.info()["single_shape"] >= 0
     for name, (fn, st) in variants.items():
+        batch.set_kernel(name == "one_launch_shape_switching_kernel")
         t = event_time(torch, fn, steps, warmup, st)
         out[name] = {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1),
                      "alg_GBs": round(ab / t / 1e9, 1), "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
@@ -248,6 +252,7 @@ def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, w
     out["separate_launches_graph"] = {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1),
                                       "alg_GBs": round(ab / t / 1e9, 1),
                                       "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
+    batch.set_kernel(False)
     batch.run()
     torch.cuda.synchronize()
     out["bitwise_equal_to_separate"] = all(torch.equal(a, b) for a, b in zip(ys, ref))

@@ -254,12 +254,18 @@ spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t 
  *   grid_blocks > 0 launches that many workgroups that loop over the tile
  *   list (persistent). use_graph = 1 captures the launch once in a HIP graph
  *   (needs a non-NULL stream; recaptured when accumulate or grid_blocks
- *   change) and replays it. Asynchronous. */
+ *   change) and replays it. Asynchronous.
+ * When all matrices share one shape the launch uses a kernel built for that
+ * shape (no per-tile shape switch; that shape's registers and LDS only);
+ * spc_batch_set_kernel(batch, 1) forces the shape-switching kernel anyway
+ * (0 restores the choice). spc_batch_info reports the shared shape index in
+ * *single_shape (-1 when shapes differ). */
 typedef struct spc_batch spc_batch;
 spc_status spc_batch_create(int32_t count, const spc_beta_view *views, const spc_plan_params *params,
                             spc_batch **out, hipStream_t stream);
 spc_status spc_batch_destroy(spc_batch *batch);
-spc_status spc_batch_info(const spc_batch *batch, int64_t *n_tiles, int64_t *n_long);
+spc_status spc_batch_info(const spc_batch *batch, int64_t *n_tiles, int64_t *n_long, int32_t *single_shape);
+spc_status spc_batch_set_kernel(spc_batch *batch, int32_t general);
 spc_status spc_batch_set_vectors(spc_batch *batch, const void *const *xs, void *const *ys);
 spc_status spc_spmv_batched(spc_batch *batch, int32_t accumulate, int32_t grid_blocks, int32_t use_graph,
                             hipStream_t stream);

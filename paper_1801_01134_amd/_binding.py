@@ -72,7 +72,8 @@ _SIGS = {
                                       POINTER(c_int64), c_void_p]),
     "spc_batch_create": (c_int32, [c_int32, POINTER(BetaView), POINTER(PlanParams), POINTER(c_void_p), c_void_p]),
     "spc_batch_destroy": (c_int32, [c_void_p]),
-    "spc_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64)]),
+    "spc_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
+    "spc_batch_set_kernel": (c_int32, [c_void_p, c_int32]),
     "spc_batch_set_vectors": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),
     "spc_spmv_batched": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
     "spc_mlp_standardizer": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
@@ -549,9 +550,14 @@ class Batch:
             self.handle = None
 
     def info(self) -> dict:
-        nt, nl = c_int64(), c_int64()
-        check(lib().spc_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(nl)))
-        return {"n_tiles": nt.value, "n_long": nl.value}
+        nt, nl, ss = c_int64(), c_int64(), c_int32()
+        check(lib().spc_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(nl), ctypes.byref(ss)))
+        return {"n_tiles": nt.value, "n_long": nl.value, "single_shape": ss.value}
+
+    def set_kernel(self, general: bool):
+        """general=True forces the shape-switching kernel even for one shape."""
+        check(lib().spc_batch_set_kernel(self.handle, int(general)))
+        return self
 
     def set_vectors(self, xs: list, ys: list):
         if len(xs) != len(self.mats) or len(ys) != len(self.mats):

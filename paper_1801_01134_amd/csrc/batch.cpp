@@ -25,6 +25,8 @@ struct spc_batch {
     hipGraphExec_t exec = nullptr;
     int g_accumulate = -1;
     int g_grid = -1;
+    int single_shape = -1;  // shape index shared by all matrices, else -1
+    int force_general = 0;  // run the shape-switching kernel even for one shape
 };
 
 namespace {
@@ -112,6 +114,9 @@ extern "C" spc_status spc_batch_create(int32_t count, const spc_beta_view *views
         m.reserved = 0;
     }
     b->n_tiles = (int64_t)all.size();
+    b->single_shape = b->h_mats[0].shape;
+    for (int i = 1; i < count; ++i)
+        if (b->h_mats[i].shape != b->single_shape) b->single_shape = -1;
     if ((he = hipMalloc(&b->d_mats, sizeof(BatchMat) * count)) != hipSuccess ||
         (he = hipMalloc(&b->d_tiles, sizeof(TileDesc) * (all.empty() ? 1 : all.size()))) != hipSuccess ||
         (he = hipMemcpy(b->d_tiles, all.data(), sizeof(TileDesc) * all.size(), hipMemcpyHostToDevice)) !=
@@ -128,10 +133,19 @@ extern "C" spc_status spc_batch_destroy(spc_batch *b) {
     return SPC_OK;
 }
 
-extern "C" spc_status spc_batch_info(const spc_batch *b, int64_t *n_tiles, int64_t *n_long) {
+extern "C" spc_status spc_batch_info(const spc_batch *b, int64_t *n_tiles, int64_t *n_long, int32_t *single_shape) {
     SPC_REQUIRE(b != nullptr, SPC_ERR_INVALID_ARG, "null batch");
     if (n_tiles) *n_tiles = b->n_tiles;
     if (n_long) *n_long = b->n_long;
+    if (single_shape) *single_shape = b->single_shape;
+    return SPC_OK;
+}
+
+extern "C" spc_status spc_batch_set_kernel(spc_batch *b, int32_t general) {
+    SPC_REQUIRE(b != nullptr, SPC_ERR_INVALID_ARG, "null batch");
+    SPC_REQUIRE(general == 0 || general == 1, SPC_ERR_INVALID_ARG, "general must be 0 or 1");
+    if (b->force_general != general) drop_graph(b);
+    b->force_general = general;
     return SPC_OK;
 }
 
@@ -162,13 +176,14 @@ extern "C" spc_status spc_spmv_batched(spc_batch *b, int32_t accumulate, int32_t
     SPC_REQUIRE(accumulate == 0 || accumulate == 1, SPC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     SPC_REQUIRE(grid_blocks >= 0, SPC_ERR_INVALID_ARG, "grid_blocks must be >= 0");
     SPC_REQUIRE(!use_graph || stream != nullptr, SPC_ERR_INVALID_ARG, "graph capture needs a non-NULL stream");
+    const int single = b->force_general ? -1 : b->single_shape;
     if (!use_graph) return batched_launch(b->dtype, b->kq, b->d_mats, b->d_tiles, b->n_tiles, accumulate,
-                                          grid_blocks, stream);
+                                          grid_blocks, single, stream);
     if (!b->exec || b->g_accumulate != accumulate || b->g_grid != grid_blocks) {
         drop_graph(b);
         SPC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         spc_status st = batched_launch(b->dtype, b->kq, b->d_mats, b->d_tiles, b->n_tiles, accumulate,
-                                       grid_blocks, stream);
+                                       grid_blocks, single, stream);
         hipError_t he = hipStreamEndCapture(stream, &b->graph);
         if (st != SPC_OK) {
             drop_graph(b);

@@ -23,7 +23,7 @@ spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const v
 namespace {
 
 constexpr int kT = 256;          // threads per block of the vector kernels
-constexpr int kBlocks = 1024;    // blocks of the reduction passes
+constexpr int kBlocks = 4096;    // most blocks of the vector kernels
 constexpr int kMaxK = 16;
 
 struct Scal {                    // per-column state, in device memory
@@ -37,68 +37,116 @@ struct Scal {                    // per-column state, in device memory
     int iter;                    // iterations run so far
 };
 
-// Block-level sum of k column values; thread 0..k-1 get the k totals.
-__device__ void block_sum_cols(double *v, int k, double *smem) {
-    // smem: [kT][kMaxK]
-    #pragma unroll
-    for (int q = 0; q < kMaxK; ++q) if (q < k) smem[threadIdx.x * kMaxK + q] = v[q];
+// Vector kernels. The n x k arrays R, P, Q (leading dimension k) are walked
+// as flat arrays, one element per thread and step: thread t of the grid
+// takes elements t, t + S, t + 2S, ... with S = (threads / k) * k, so a
+// thread always meets the same column q = t mod k and every load is
+// coalesced. X and B (leading dimensions ldx, ldb) are addressed as
+// (e / k) * ld + q. Per-column sums: each thread keeps one partial; a
+// block adds the partials of its threads column by column in a fixed
+// order; a second pass adds the blocks' sums in a fixed order.
+constexpr int kU = 4;  // independent elements in flight per thread
+
+struct Flat {
+    int64_t N, S;      // elements, grid step
+    int64_t t;         // this thread's first element (t < S, else idle)
+    int q;             // its column
+};
+
+__device__ __forceinline__ Flat flat(int64_t n, int k) {
+    Flat f;
+    f.N = n * k;
+    const int64_t threads = (int64_t)gridDim.x * kT;
+    f.S = threads / k * k;
+    f.t = (int64_t)blockIdx.x * kT + threadIdx.x;
+    f.q = (int)(f.t % k);
+    return f;
+}
+
+// part[blockIdx][q] = sum of v over this block's threads of column q.
+__device__ void block_cols(double v, int k, const Flat &f, double *red, double *part) {
+    red[threadIdx.x] = f.t < f.S ? v : 0.0;
     __syncthreads();
-    for (int s = kT / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int q = 0; q < k; ++q) smem[threadIdx.x * kMaxK + q] += smem[(threadIdx.x + s) * kMaxK + q];
-        __syncthreads();
+    if ((int)threadIdx.x < k) {
+        const int64_t base = (int64_t)blockIdx.x * kT;
+        double s = 0.0;
+        for (int u = 0; u < kT; ++u)
+            if ((int)((base + u) % k) == (int)threadIdx.x) s += red[u];
+        part[(int64_t)blockIdx.x * kMaxK + threadIdx.x] = s;
     }
 }
 
 // R = B, P = B, X = 0; partial sums of B*B per column.
 template <class T>
-__global__ __launch_bounds__(kT) void k_init(int64_t n, int k, const T *B, int64_t ldb, T *X, int64_t ldx, T *R,
-                                             T *P, double *part) {
-    __shared__ double sm[kT * kMaxK];
-    double acc[kMaxK];
-    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
-#pragma unroll
-        for (int q = 0; q < kMaxK; ++q) {
-            if (q >= k) break;
-            const T b = B[i * ldb + q];
-            R[i * k + q] = b;
-            P[i * k + q] = b;
-            X[i * ldx + q] = T(0);
-            acc[q] += (double)b * (double)b;
+__global__ __launch_bounds__(kT) void k_init(int64_t n, int k, const T *__restrict__ B, int64_t ldb,
+                                             T *__restrict__ X, int64_t ldx, T *__restrict__ R,
+                                             T *__restrict__ P, double *part) {
+    __shared__ double red[kT];
+    const Flat f = flat(n, k);
+    double acc = 0.0;
+    if (f.t < f.S) {
+        for (int64_t e = f.t; e < f.N; e += f.S) {
+            const int64_t i = e / k;
+            const T b = B[i * ldb + f.q];
+            R[e] = b;
+            P[e] = b;
+            X[i * ldx + f.q] = T(0);
+            acc += (double)b * (double)b;
         }
     }
-    block_sum_cols(acc, k, sm);
-    if ((int)threadIdx.x < k) part[blockIdx.x * kMaxK + threadIdx.x] = sm[threadIdx.x];
+    block_cols(acc, k, f, red, part);
 }
 
-// Partial sums of U*V per column (U, V with leading dimension k).
+// Partial sums of U*V per column.
 template <class T>
-__global__ __launch_bounds__(kT) void k_dot(int64_t n, int k, const T *U, const T *V, double *part) {
-    __shared__ double sm[kT * kMaxK];
-    double acc[kMaxK];
-    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+__global__ __launch_bounds__(kT) void k_dot(int64_t n, int k, const T *__restrict__ U, const T *__restrict__ V,
+                                            double *part) {
+    __shared__ double red[kT];
+    const Flat f = flat(n, k);
+    double a0 = 0.0, a1 = 0.0;
+    if (f.t < f.S) {
+        int64_t e = f.t;
+        for (; e + (kU - 1) * f.S < f.N; e += kU * f.S) {
+            T u[kU], v[kU];
 #pragma unroll
-        for (int q = 0; q < kMaxK; ++q)
-            if (q < k) acc[q] += (double)U[i * k + q] * (double)V[i * k + q];
-    block_sum_cols(acc, k, sm);
-    if ((int)threadIdx.x < k) part[blockIdx.x * kMaxK + threadIdx.x] = sm[threadIdx.x];
+            for (int j = 0; j < kU; ++j) {
+                u[j] = U[e + j * f.S];
+                v[j] = V[e + j * f.S];
+            }
+#pragma unroll
+            for (int j = 0; j < kU; ++j) {
+                if (j & 1) a1 += (double)u[j] * (double)v[j];
+                else a0 += (double)u[j] * (double)v[j];
+            }
+        }
+        for (; e < f.N; e += f.S) a0 += (double)U[e] * (double)V[e];
+    }
+    block_cols(a0 + a1, k, f, red, part);
 }
 
-// Totals of the partials, in one block, fixed order.
+// Totals of the partials of nblk blocks, in one block, fixed order.
 __device__ void total_cols(const double *part, int nblk, int k, double *out, double *sm) {
+    // thread t < kT adds blocks t, t + kT, ... for every column; then the
+    // kT partials of each column are added in thread order
     double acc[kMaxK];
+#pragma unroll
     for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kT)
 #pragma unroll
         for (int q = 0; q < kMaxK; ++q)
-            if (q < k) acc[q] += part[b * kMaxK + q];
-    block_sum_cols(acc, k, sm);
-    if ((int)threadIdx.x < k) out[threadIdx.x] = sm[threadIdx.x];
+            if (q < k) acc[q] += part[(int64_t)b * kMaxK + q];
+#pragma unroll
+    for (int q = 0; q < kMaxK; ++q)
+        if (q < k) sm[threadIdx.x * kMaxK + q] = acc[q];
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double s = 0.0;
+        for (int u = 0; u < kT; ++u) s += sm[u * kMaxK + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
 }
 
-__global__ __launch_bounds__(kT) void k_start(const double *part, int nblk, int k, Scal *s, double tol) {
+__global__ __launch_bounds__(kT) void k_start(const double *part, int nblk, int k, Scal *s) {
     __shared__ double sm[kT * kMaxK];
     __shared__ double tot[kMaxK];
     total_cols(part, nblk, k, tot, sm);
@@ -113,7 +161,6 @@ __global__ __launch_bounds__(kT) void k_start(const double *part, int nblk, int 
         s->beta[q] = 0.0;
     }
     if (threadIdx.x == 0) s->iter = 0;
-    (void)tol;
 }
 
 // alpha = rr / (p . q) for running columns, 0 for finished ones.
@@ -131,28 +178,43 @@ __global__ __launch_bounds__(kT) void k_alpha(const double *part, int nblk, int 
 
 // X += alpha P, R -= alpha Q; partial sums of R*R per column.
 template <class T>
-__global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, T *X, int64_t ldx, T *R,
-                                               const T *P, const T *Q, double *part) {
-    __shared__ double sm[kT * kMaxK];
-    __shared__ double al[kMaxK];
-    if ((int)threadIdx.x < k) al[threadIdx.x] = s->alpha[threadIdx.x];
-    __syncthreads();
-    double acc[kMaxK];
-    for (int q = 0; q < kMaxK; ++q) acc[q] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+__global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, T *__restrict__ X, int64_t ldx,
+                                               T *__restrict__ R, const T *__restrict__ P,
+                                               const T *__restrict__ Q, double *part) {
+    __shared__ double red[kT];
+    const Flat f = flat(n, k);
+    double a0 = 0.0, a1 = 0.0;
+    if (f.t < f.S) {
+        const double al = s->alpha[f.q];
+        int64_t e = f.t;
+        for (; e + (kU - 1) * f.S < f.N; e += kU * f.S) {
+            T x[kU], r[kU], p[kU], qq[kU];
 #pragma unroll
-        for (int q = 0; q < kMaxK; ++q) {
-            if (q >= k) break;
-            const double a = al[q];
-            const int64_t e = i * k + q;
-            X[i * ldx + q] = (T)((double)X[i * ldx + q] + a * (double)P[e]);
-            const T r = (T)((double)R[e] - a * (double)Q[e]);
-            R[e] = r;
-            acc[q] += (double)r * (double)r;
+            for (int j = 0; j < kU; ++j) {
+                const int64_t ej = e + j * f.S;
+                x[j] = X[(ej / k) * ldx + f.q];
+                r[j] = R[ej];
+                p[j] = P[ej];
+                qq[j] = Q[ej];
+            }
+#pragma unroll
+            for (int j = 0; j < kU; ++j) {
+                const int64_t ej = e + j * f.S;
+                X[(ej / k) * ldx + f.q] = (T)((double)x[j] + al * (double)p[j]);
+                const T rn = (T)((double)r[j] - al * (double)qq[j]);
+                R[ej] = rn;
+                if (j & 1) a1 += (double)rn * (double)rn;
+                else a0 += (double)rn * (double)rn;
+            }
+        }
+        for (; e < f.N; e += f.S) {
+            X[(e / k) * ldx + f.q] = (T)((double)X[(e / k) * ldx + f.q] + al * (double)P[e]);
+            const T rn = (T)((double)R[e] - al * (double)Q[e]);
+            R[e] = rn;
+            a0 += (double)rn * (double)rn;
         }
     }
-    block_sum_cols(acc, k, sm);
-    if ((int)threadIdx.x < k) part[blockIdx.x * kMaxK + threadIdx.x] = sm[threadIdx.x];
+    block_cols(a0 + a1, k, f, red, part);
 }
 
 // beta = rr_new / rr; convergence test; iteration count.
@@ -183,17 +245,23 @@ __global__ __launch_bounds__(kT) void k_beta(const double *part, int nblk, int k
 // P = R + beta P. A finished column gets beta = 0 and keeps alpha = 0, so its
 // X and R no longer change.
 template <class T>
-__global__ __launch_bounds__(kT) void k_direction(int64_t n, int k, const Scal *s, const T *R, T *P) {
-    __shared__ double be[kMaxK];
-    if ((int)threadIdx.x < k) be[threadIdx.x] = s->beta[threadIdx.x];
-    __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+__global__ __launch_bounds__(kT) void k_direction(int64_t n, int k, const Scal *s, const T *__restrict__ R,
+                                                  T *__restrict__ P) {
+    const Flat f = flat(n, k);
+    if (f.t >= f.S) return;
+    const double be = s->beta[f.q];
+    int64_t e = f.t;
+    for (; e + (kU - 1) * f.S < f.N; e += kU * f.S) {
+        T r[kU], p[kU];
 #pragma unroll
-        for (int q = 0; q < kMaxK; ++q) {
-            if (q >= k) break;
-            const int64_t e = i * k + q;
-            P[e] = (T)((double)R[e] + be[q] * (double)P[e]);
+        for (int j = 0; j < kU; ++j) {
+            r[j] = R[e + j * f.S];
+            p[j] = P[e + j * f.S];
         }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) P[e + j * f.S] = (T)((double)r[j] + be * (double)p[j]);
+    }
+    for (; e < f.N; e += f.S) P[e] = (T)((double)R[e] + be * (double)P[e]);
 }
 
 struct Work {
@@ -221,15 +289,17 @@ Work carve(void *ws, int64_t n, int k, int dtype) {
     return w;
 }
 
-unsigned vec_blocks(int64_t n) {
-    int64_t b = div_up(n > 0 ? n : 1, kT);
+// Blocks of the vector kernels: enough for kU elements per thread and
+// step, at most kBlocks.
+unsigned vec_blocks(int64_t n, int k) {
+    const int64_t b = div_up(n > 0 ? n * k : 1, (int64_t)kT * kU);
     return (unsigned)(b < kBlocks ? b : kBlocks);
 }
 
 template <class T>
 spc_status iteration(const spc_beta_view *A, const spc_plan *P, int k, const Work &w, T *X, int64_t ldx,
                      int64_t n, double tol2, hipStream_t st) {
-    const unsigned nb = vec_blocks(n);
+    const unsigned nb = vec_blocks(n, k);
     spc_status r = spmm_launch(A, P, k, w.P, k, w.Q, k, 0, st);
     if (r != SPC_OK) return r;
     hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(kT), 0, st, n, k, (const T *)w.P, (const T *)w.Q, w.part);
@@ -284,7 +354,7 @@ extern "C" spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan,
     const Work w = carve(workspace, n, k, A->dtype);
     if (stream == nullptr) use_graph = 0;  // the legacy default stream cannot be captured
     const double tol2 = rel_tol * rel_tol;
-    const unsigned nb = vec_blocks(n);
+    const unsigned nb = vec_blocks(n, k);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     auto cleanup = [&]() {
@@ -295,7 +365,7 @@ extern "C" spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan,
         using T = decltype(tv);
         hipLaunchKernelGGL(k_init<T>, dim3(nb), dim3(kT), 0, stream, n, k, (const T *)B, ldb, (T *)X, ldx,
                            (T *)w.R, (T *)w.P, w.part);
-        hipLaunchKernelGGL(k_start, dim3(1), dim3(kT), 0, stream, w.part, (int)nb, k, w.s, rel_tol);
+        hipLaunchKernelGGL(k_start, dim3(1), dim3(kT), 0, stream, w.part, (int)nb, k, w.s);
         SPC_HIP(hipGetLastError());
         if (use_graph) {
             SPC_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));

@@ -98,9 +98,10 @@ struct BatchMat {
 
 // Batched product over a concatenated tile list (TileDesc::reserved holds
 // the matrix index). grid_blocks 0: one wavefront per tile; > 0: that many
-// workgroups loop over the tiles.
+// workgroups loop over the tiles. single_shape: the shape index when all
+// matrices share it (a kernel without the shape switch), else -1.
 spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
-                          int accumulate, int grid_blocks, hipStream_t stream);
+                          int accumulate, int grid_blocks, int single_shape, hipStream_t stream);
 
 // Validation of a view on the host.
 spc_status check_view(const spc_beta_view *A);

@@ -1,12 +1,12 @@
 // Y = A X for k right-hand sides over beta(r,c) (X, Y row-major, the k
 // values of one row contiguous), on the wavefront tiles of a mode-0 plan.
 //
-// The tile's streams are read as in the single-vector kernel. Then lane =
-// mask bit places each stored value's column next to it in LDS (the value
-// keeps its packed slot), and groups of kp lanes (kp = k rounded up to a
-// power of two) take the tile's (interval, block row) pairs in turn: lane q
-// of a group adds a_v * X[col_v][q] over the pair's values, so the group
-// reads one contiguous row of X per value. Sums are formed in double
+// The matrix is streamed once for all k columns: a tile's values, columns,
+// masks and interval pointers are read as in the single-vector kernel, and
+// each lane keeps the value of its mask bit for every word of the tile. The
+// k columns are then taken one after the other, each exactly like one
+// single-vector product over the tile (all x gathers of the tile in flight
+// together, products in LDS, L lanes per row). Sums are formed in double
 // precision and written once per row and column.
 //
 // An interval with more blocks than a tile holds is run by one wavefront
@@ -33,7 +33,7 @@ struct SpmmArgs {
     const TileDesc *tiles;
     int64_t n_rows, n_cols, nnz, n_blocks;
     int64_t ldx, ldy;
-    int32_t k, kp, lgkp;
+    int32_t k;
     int32_t n_tiles;
     int32_t accumulate;
     int32_t xcd_remap;
@@ -47,26 +47,28 @@ struct SpmmSmem {
     static constexpr int NB = WB / Sh::RC;
     static constexpr int NWMAX = NB / Sh::BPW + 2;
     static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;
-    static constexpr int NCOL = NCR * 64;
+    static constexpr int NCW = NWMAX * Sh::BPW;
+    static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
-    uint64_t wm[64];
-    int off[64];
-    int brow[64];
-    int col[NCOL];
-    int cidx[NBUF + 64];       // column of each packed value
-    T buf[NBUF];               // packed values
+    uint64_t wm[64];           // masked words, zero after the last
+    int off[64];               // value slot of each word's first bit
+    int brow[64];              // tile-relative interval pointers
+    int col[NCOL];             // column of every slot of the tile's words
+    T buf[NBUF + 64];          // packed values, then the products of one column
 };
 
-template <class T>
-__device__ __forceinline__ double ld_x(__amdgpu_buffer_rsrc_t xr, uint32_t off) {
-    return (double)buf_load<T>(xr, off);
-}
-
+// One tile, all k columns. The tile's streams are read once; every lane
+// keeps the values of its mask bits and their X row offsets in registers;
+// then for each column q the x gathers of all words are issued together,
+// the products go to LDS in packed order and L lanes per (interval, block
+// row) add them, as in the single-vector kernel.
 template <class Sh, class T, int KQ>
 __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
                           SpmmSmem<Sh, T, KQ> &sm) {
     using SM = SpmmSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
+    constexpr int NWM = SM::NWMAX;
+    static_assert(NWM <= 64, "the masks array is padded for 64 words read past its end");
     using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
@@ -117,52 +119,79 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     }
     wave_sync();
 
-    // 2. column of every stored value, lane = mask bit
-    if (nw > 0) {
-        const int slot = lane / Sh::RC;
-        const int kcol = (lane % Sh::RC) % Sh::C;
-        const int *__restrict__ colp = sm.col + slot;
-        int voff = shift;
-        for (int i = 0; i < nw; ++i) {
-            uint64_t m = a.mw[w0 + i];
-            if (i == 0) m &= lo_mask;
-            if (__builtin_amdgcn_inverse_ballot_w64(m)) sm.cidx[lane_rank(m) + voff] = colp[i * Sh::BPW] + kcol;
-            voff += __popcll(m);
+    // 2. per word: this lane's value and X row offset (lane = mask bit)
+    uint64_t M[NWM];
+    T v[NWM];
+    uint32_t xo[NWM];
+    const int slot = lane / Sh::RC;
+    const int kcol = (lane % Sh::RC) % Sh::C;
+    const uint32_t xrow = (uint32_t)a.ldx * (uint32_t)sizeof(T);
+    {
+        const uint64_t *__restrict__ gp = a.mw + w0;  // readable 512 bytes past the last word
+        uint32_t vslot = (uint32_t)shift;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            uint64_t m = nw > 0 ? gp[j] : 0ull;
+            if (j == 0) m &= lo_mask;
+            M[j] = j < nw ? m : 0ull;
+            const uint32_t s = lane_rank(M[j]) + vslot;
+            v[j] = sm.buf[s < (uint32_t)(SM::NBUF + 64) ? s : 0u];
+            const int c = sm.col[j * Sh::BPW + slot];
+            xo[j] = pick(M[j], (uint32_t)(c + kcol) * xrow, 0xffffffffu);
+            vslot += (uint32_t)__popcll(M[j]);
         }
     }
-    wave_sync();
-
-    // 3. kp lanes per (interval, block row), lane q of the group = column q of X
-    const int kp = a.kp, q = lane & (kp - 1), grp = lane >> a.lgkp, ngrp = 64 >> a.lgkp;
+    // row-sum layout, fixed for all columns
     const int npairs = nI * Sh::R;
-    const T *__restrict__ vb = sm.buf + shift;
-    const int *__restrict__ cb = sm.cidx + shift;
-    const uint32_t xq = q < a.k ? (uint32_t)q * (uint32_t)sizeof(T) : 0xffffffffu;  // column q of X
-    const uint32_t xrow = (uint32_t)a.ldx * (uint32_t)sizeof(T);
+    // log2 L: the largest L with npairs * L <= 64 (npairs is 1..64)
+    const int lg = npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
+    const int L = 1 << lg;
+    const int pair = lane >> lg, l = lane & (L - 1);
+    char *__restrict__ bb = reinterpret_cast<char *>(sm.buf);
+    const T *__restrict__ prod = sm.buf + shift;
     T *__restrict__ Y = static_cast<T *>(a.Y);
-    for (int p = grp; p < npairs; p += ngrp) {
-        const int li = p / Sh::R, rho = p % Sh::R;
-        const int bs = sm.brow[li], be = sm.brow[li + 1];
-        double acc0 = 0.0, acc1 = 0.0;
+
+    for (int q = 0; q < a.k; ++q) {
+        // 3. gathers of column q for all words, then the products in place
+        T xv[NWM];
+        const uint32_t qb = (uint32_t)q * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) xv[j] = buf_load<T>(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb);
+        wave_sync();  // the previous column's sums have read the products
+        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            const uint32_t pb = lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte;
+            if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb) = v[j] * xv[j];
+            vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
+        }
+        wave_sync();
+
+        // 4. row sums: L lanes per (interval, block row)
+        double acc = 0.0;
         int n_here = 0;
-        if (bs < be) {
+        if (pair < npairs) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int bs = sm.brow[li], be = sm.brow[li + 1];
             if (Sh::R == 1) {
-                const int gs = bs + lo_slot, ge = be + lo_slot;
-                const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
-                const int vs = sm.off[ws] + __popcll(sm.wm[ws] & low_bits((gs % Sh::BPW) * Sh::RC));
-                const int ve = sm.off[we] + __popcll(sm.wm[we] & low_bits((ge % Sh::BPW) * Sh::RC));
-                int v = vs;
-                for (; v + 1 < ve; v += 2) {
-                    const double x0 = ld_x<T>(xr, (uint32_t)cb[v] * xrow + xq);
-                    const double x1 = ld_x<T>(xr, (uint32_t)cb[v + 1] * xrow + xq);
-                    acc0 = __builtin_fma((double)vb[v], x0, acc0);
-                    acc1 = __builtin_fma((double)vb[v + 1], x1, acc1);
+                if (bs < be) {
+                    const int gs = bs + lo_slot, ge = be + lo_slot;
+                    const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
+                    const int vs = sm.off[ws] + __popcll(sm.wm[ws] & low_bits((gs % Sh::BPW) * Sh::RC));
+                    const int ve = sm.off[we] + __popcll(sm.wm[we] & low_bits((ge % Sh::BPW) * Sh::RC));
+                    double a0 = 0.0, a1 = 0.0;
+                    int k = vs + l;
+                    for (; k + L < ve; k += 2 * L) {
+                        a0 += (double)prod[k];
+                        a1 += (double)prod[k + L];
+                    }
+                    if (k < ve) a0 += (double)prod[k];
+                    acc = a0 + a1;
+                    n_here = ve - vs;
                 }
-                if (v < ve) acc0 = __builtin_fma((double)vb[v], ld_x<T>(xr, (uint32_t)cb[v] * xrow + xq), acc0);
-                n_here = ve - vs;
             } else {
                 const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
-                for (int b = bs; b < be; ++b) {
+                for (int b = bs + l; b < be; b += L) {
                     const int g = b + lo_slot;
                     const int wi = g / Sh::BPW, bit = (g % Sh::BPW) * Sh::RC;
                     const uint64_t wv = sm.wm[wi];
@@ -171,23 +200,36 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                     const int pos = sm.off[wi] + __popcll(wv & low_bits(bit)) + __popc(m & below);
                     const int n = __popc(sub);
                     n_here += n;
-                    for (int j = 0; j < n; ++j)
-                        acc0 = __builtin_fma((double)vb[pos + j],
-                                             ld_x<T>(xr, (uint32_t)cb[pos + j] * xrow + xq), acc0);
+                    T pr[Sh::C];
+#pragma unroll
+                    for (int t = 0; t < Sh::C; ++t) pr[t] = prod[pos + t];
+#pragma unroll
+                    for (int t = 0; t < Sh::C; ++t)
+                        if (t < n) acc += (double)pr[t];
                 }
             }
         }
-        const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
-        if (q < a.k && row < a.n_rows) {
-            const double acc = acc0 + acc1;
-            T *yp = Y + row * a.ldy + q;
-            if (a.accumulate) {
-                if (n_here > 0) *yp = (T)(acc + (double)*yp);
-            } else {
-                *yp = (T)acc;
+        for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        if (Sh::R > 1 && a.accumulate)
+            for (int m = L >> 1; m >= 1; m >>= 1) n_here += __shfl_xor(n_here, m, 64);
+        if (pair < npairs && l == 0) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+            if (row < a.n_rows) {
+                T *yp = Y + row * a.ldy + q;
+                if (a.accumulate) {
+                    if (n_here > 0) *yp = (T)(acc + (double)*yp);
+                } else {
+                    *yp = (T)acc;
+                }
             }
         }
     }
+}
+
+template <class T>
+__device__ __forceinline__ double ld_x(__amdgpu_buffer_rsrc_t xr, uint32_t off) {
+    return (double)buf_load<T>(xr, off);
 }
 
 // One interval longer than a tile: lane = mask bit, k running sums per lane.
@@ -301,9 +343,6 @@ spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const v
     a.ldx = ldx;
     a.ldy = ldy;
     a.k = k;
-    a.lgkp = 0;
-    while ((1 << a.lgkp) < k) ++a.lgkp;
-    a.kp = 1 << a.lgkp;
     a.n_tiles = (int32_t)P->n_tiles;
     a.accumulate = accumulate;
     a.xcd_remap = P->xcd_remap;

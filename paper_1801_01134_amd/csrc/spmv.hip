@@ -342,21 +342,28 @@ __device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_
             }
         }
         wave_sync();
+        // every lane reads its slot of every word first (the slot is inside
+        // the buffer even where the bit is clear), so the LDS reads overlap;
+        // only lanes whose bit is set write their product back
+        uint32_t pb[NWM];
+        T pv[NWM];
         uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the next value
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
-            const uint32_t pb = lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte;
-            const T v = *reinterpret_cast<const T *>(bb + pb);
-            if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb) = v * xv[j];
+            pb[j] = lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte;
+            pv[j] = *reinterpret_cast<const T *>(bb + pb[j]);
             vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
         }
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+            if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb[j]) = pv[j] * xv[j];
     }
     wave_sync();
 
     // 3. row sums: L lanes per (interval, block row)
     const int npairs = nI * Sh::R;
-    int lg = 6;  // log2 L: largest with npairs * L <= 64
-    while (lg > 0 && (npairs << lg) > 64) --lg;
+    // log2 L: the largest L with npairs * L <= 64 (npairs is 1..64)
+    const int lg = npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
     const int L = 1 << lg;
     const int pair = lane >> lg, l = lane & (L - 1);
     double acc = 0.0;
@@ -392,7 +399,14 @@ __device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_
                 const int pos = sm.off[wi] + __popcll(wv & low_bits(bit)) + __popc(m & below);
                 const int n = __popc(sub);
                 n_here += n;
-                for (int k = 0; k < n; ++k) acc += (double)prod[pos + k];
+                // the block row's n products are prod[pos .. pos+n-1]; read
+                // all C slots at once (inside the buffer) and keep the first n
+                T pr[Sh::C];
+#pragma unroll
+                for (int k = 0; k < Sh::C; ++k) pr[k] = prod[pos + k];
+#pragma unroll
+                for (int k = 0; k < Sh::C; ++k)
+                    if (k < n) acc += (double)pr[k];
             }
         }
     }
@@ -674,6 +688,58 @@ __global__ __launch_bounds__(kThreads) void k_spmv_batched(const BatchMat *__res
     }
 }
 
+// A batch whose matrices all have shape S: no switch, and only that shape's
+// LDS layout, so occupancy matches the single-matrix kernel.
+template <int S, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_batched_fixed(const BatchMat *__restrict__ mats,
+                                                                 const TileDesc *__restrict__ tiles, int64_t n_tiles,
+                                                                 int accumulate) {
+    using Sh = Shape<kShapeR[S], kShapeC[S]>;
+    __shared__ WaveSmem<Sh, T, KQ> sm[kWaves];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += (int64_t)gridDim.x * kWaves) {
+        const TileDesc d = tiles[t];
+        const BatchMat &M = mats[d.reserved];
+        SpmvArgs a;
+        a.brow = M.brow;
+        a.bcol = M.bcol;
+        a.mw = M.mw;
+        a.vals = M.vals;
+        a.x = M.x;
+        a.y = M.y;
+        a.tiles = tiles;
+        a.n_rows = M.n_rows;
+        a.nnz = M.nnz;
+        a.n_blocks = M.n_blocks;
+        a.n_cols = M.n_cols;
+        a.n_tiles = 0;
+        a.accumulate = accumulate;
+        a.xcd_remap = 0;
+        a.tiles_per_xcd = 0;
+        wave_sync();
+        batched_tile<Sh, T, KQ>(a, d, sm[wid]);
+    }
+}
+
+template <int S, class T>
+void launch_batched_fixed(int kq, unsigned grid, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
+                          int accumulate, hipStream_t stream) {
+    switch (kq) {
+    case 2:
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 2>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 8>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    default:
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 4>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    }
+}
+
 template <int R, int C, class T>
 spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (tb) {
@@ -700,12 +766,24 @@ spc_status launch_wave(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream)
 }  // namespace
 
 spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
-                          int accumulate, int grid_blocks, hipStream_t stream) {
+                          int accumulate, int grid_blocks, int single_shape, hipStream_t stream) {
     if (n_tiles == 0) return SPC_OK;
     const int64_t groups = div_up(n_tiles, kWaves);
     const unsigned grid = (unsigned)(grid_blocks > 0 && grid_blocks < groups ? grid_blocks : groups);
     return with_dtype(dtype, [&](auto tv) -> spc_status {
         using T = decltype(tv);
+        if (single_shape >= 0) {
+            switch (single_shape) {
+            case 0: launch_batched_fixed<0, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 1: launch_batched_fixed<1, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 2: launch_batched_fixed<2, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 3: launch_batched_fixed<3, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 4: launch_batched_fixed<4, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            default: launch_batched_fixed<5, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            }
+            SPC_HIP(hipGetLastError());
+            return SPC_OK;
+        }
         switch (kq) {
         case 2:
             hipLaunchKernelGGL((k_spmv_batched<T, 2>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,

@@ -43,12 +43,16 @@ TRAIN_FRACTION = 0.8
 # ---------------------------------------------------------------------------
 # collection
 
+POPULATIONS = ("selector", "structured")
+
+
 def _generate(args):
     """Worker: build matrix `index` and park its CSR structure in files."""
-    index, min_rows, max_rows, tmp = args
+    index, min_rows, max_rows, tmp, population = args
     from . import synth
     t0 = time.perf_counter()
-    fam, A = synth.selector_matrix(index, min_rows, max_rows)
+    gen = synth.selector_matrix if population == "selector" else synth.structured_matrix
+    fam, A = gen(index, min_rows, max_rows)
     base = os.path.join(tmp, f"m{index}")
     np.save(base + "_rp.npy", A.rowptr)
     np.save(base + "_ci.npy", A.colidx)
@@ -56,7 +60,10 @@ def _generate(args):
 
 
 def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int = 12,
-            min_rows: int = DEFAULT_MIN_ROWS, max_rows: int = DEFAULT_MAX_ROWS, log=sys.stderr):
+            min_rows: int = DEFAULT_MIN_ROWS, max_rows: int = DEFAULT_MAX_ROWS, population: str = "selector",
+            log=sys.stderr):
+    if population not in POPULATIONS:
+        raise ValueError(f"population must be one of {POPULATIONS}")
     import multiprocessing as mp
     # the pool is forked before this process initialises the GPU
     ctx = mp.get_context("fork")
@@ -76,7 +83,7 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
             while todo or pending:
                 while todo and len(pending) < window:
                     i = todo.pop(0)
-                    pending.append(pool.apply_async(_generate, ((i, min_rows, max_rows, tmp),)))
+                    pending.append(pool.apply_async(_generate, ((i, min_rows, max_rows, tmp, population),)))
                 index, fam, n_rows, n_cols, base, t_gen = pending.pop(0).get()
                 rp = torch.from_numpy(np.load(base + "_rp.npy")).to(dev)
                 ci = torch.from_numpy(np.load(base + "_ci.npy")).to(dev)
@@ -105,7 +112,8 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
                                             and q["tile_bits"] == p["tile_bits"]
                                             and q["xcd_remap"] == p["xcd_remap"]), -1)))
                     del B
-                rec = {"index": index, "family": fam, "n_rows": n_rows, "n_cols": n_cols, "nnz": nnz,
+                rec = {"population": population, "index": index, "family": fam, "n_rows": n_rows,
+                       "n_cols": n_cols, "nnz": nnz,
                        "features": [float(v) for v in feat], "n_blocks": [int(v) for v in nb],
                        "us": us, "us_default_plan": dflt, "params": params, "n_tiles": ntiles,
                        "gflops": [2.0 * nnz / (t * 1e-6) / 1e9 for t in us],
@@ -124,17 +132,27 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
         os.rmdir(tmp)
 
 
-def load(path: str) -> list[dict]:
-    with open(path) as f:
-        recs = [json.loads(line) for line in f if line.strip()]
-    recs.sort(key=lambda r: r["index"])
+def load(*paths: str) -> list[dict]:
+    recs = []
+    for path in paths:
+        with open(path) as f:
+            recs += [json.loads(line) for line in f if line.strip()]
+    for r in recs:
+        r.setdefault("population", "selector")
+    recs.sort(key=lambda r: (POPULATIONS.index(r["population"]), r["index"]))
     return recs
 
 
 def split(recs: list[dict], train_fraction: float = TRAIN_FRACTION):
-    """Deterministic split by matrix index: the lowest indices train."""
-    n_train = int(round(train_fraction * len(recs)))
-    return recs[:n_train], recs[n_train:]
+    """Deterministic split of each population by matrix index: the lowest
+    indices train, the rest are held out."""
+    train, test = [], []
+    for pop in POPULATIONS:
+        part = [r for r in recs if r["population"] == pop]
+        n_train = int(round(train_fraction * len(part)))
+        train += part[:n_train]
+        test += part[n_train:]
+    return train, test
 
 
 def arrays(recs: list[dict]):
@@ -221,6 +239,14 @@ def evaluate(train: list[dict], test: list[dict], model: dict | None = None, epo
     ch_mlp = ch_mlp.cpu().numpy().astype(np.int64)
     ch_int = np.array([sel.select(x, b.SEL_INTERP)[0] for x in Xte], dtype=np.int64)
     best_avg = int(np.argmin(np.mean(Ttr / Ttr.min(axis=1, keepdims=True), axis=0)))
+    pops = np.array([r["population"] for r in test])
+    by_pop = {}
+    for pop in POPULATIONS:
+        m = pops == pop
+        if m.any():
+            by_pop[pop] = {"n": int(m.sum()), "mlp": summary(regrets(Tte[m], ch_mlp[m])),
+                           "interpolation": summary(regrets(Tte[m], ch_int[m])),
+                           "fixed_b1x8": summary(regrets(Tte[m], np.zeros(int(m.sum()), np.int64)))}
     out = {"n_train": len(train), "n_test": len(test),
            "mlp": summary(regrets(Tte, ch_mlp)),
            "interpolation": summary(regrets(Tte, ch_int)),
@@ -229,7 +255,8 @@ def evaluate(train: list[dict], test: list[dict], model: dict | None = None, epo
                summary(regrets(Tte, np.full(len(test), best_avg, np.int64))),
            "best_shape_share": np.bincount(Tte.argmin(axis=1), minlength=6).tolist(),
            "mlp_choice_share": np.bincount(ch_mlp, minlength=6).tolist(),
-           "interp_choice_share": np.bincount(ch_int, minlength=6).tolist()}
+           "interp_choice_share": np.bincount(ch_int, minlength=6).tolist(),
+           "by_population": by_pop}
     return out, model
 
 
@@ -244,24 +271,25 @@ def main(argv=None):
     c.add_argument("--workers", type=int, default=12)
     c.add_argument("--min-rows", type=int, default=DEFAULT_MIN_ROWS)
     c.add_argument("--max-rows", type=int, default=DEFAULT_MAX_ROWS)
+    c.add_argument("--population", default="selector", choices=POPULATIONS)
     t = sub.add_parser("train")
-    t.add_argument("--records", required=True)
+    t.add_argument("--records", required=True, nargs="+")
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=400)
     e = sub.add_parser("evaluate")
-    e.add_argument("--records", required=True)
+    e.add_argument("--records", required=True, nargs="+")
     e.add_argument("--model", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
-        collect(a.first, a.count, a.out, a.reps, a.workers, a.min_rows, a.max_rows)
+        collect(a.first, a.count, a.out, a.reps, a.workers, a.min_rows, a.max_rows, a.population)
     elif a.cmd == "train":
-        tr, te = split(load(a.records))
+        tr, te = split(load(*a.records))
         res, model = evaluate(tr, te, epochs=a.epochs)
         with open(a.out, "w") as f:
             json.dump(model, f)
         print(json.dumps(res))
     else:
-        tr, te = split(load(a.records))
+        tr, te = split(load(*a.records))
         model = None
         if a.model:
             with open(a.model) as f:

@@ -340,6 +340,67 @@ def selector_matrix(index: int, min_rows: int = 50_000, max_rows: int = 4_000_00
     return fam, uniform_random(n, n, float(rng.uniform(2, 40)), seed=s)
 
 
+# --------------------------------------------------------------------------
+# Structured grid operators: 2-D 5/9-point and 3-D 7/27-point stencils in
+# natural order idx = x + mx (y + my z), truncated at the boundary, with an
+# optional random dropout of off-diagonal entries.
+# --------------------------------------------------------------------------
+STENCILS = {
+    "5pt": [(0, dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1) if abs(dy) + abs(dx) <= 1],
+    "9pt": [(0, dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)],
+    "7pt": [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+            if abs(dz) + abs(dy) + abs(dx) <= 1],
+    "27pt": [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)],
+}
+
+
+def grid_stencil(mx: int, my: int, mz: int, kind: str, keep: float = 1.0, seed: int = 0) -> CSR:
+    n = mx * my * mz
+    rng = rng_for(8, mx, my, mz, seed)
+    offs = sorted(STENCILS[kind], key=lambda o: o[0] * mx * my + o[1] * mx + o[2])
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % mx
+    y = (idx // mx) % my
+    z = idx // (mx * my)
+    valid = []
+    counts = np.zeros(n, dtype=np.int64)
+    for (dz, dy, dx) in offs:
+        ok = (x + dx >= 0) & (x + dx < mx) & (y + dy >= 0) & (y + dy < my) & (z + dz >= 0) & (z + dz < mz)
+        if keep < 1.0 and (dz, dy, dx) != (0, 0, 0):
+            ok &= rng.random(n) < keep
+        valid.append(ok)
+        counts += ok
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    nnz = int(rowptr[-1])
+    if nnz >= 2**31:
+        raise ValueError("nnz does not fit int32")
+    colidx = np.empty(nnz, dtype=np.int32)
+    start = rowptr[:-1].copy()
+    for (dz, dy, dx), ok in zip(offs, valid):
+        pos = start[ok]
+        colidx[pos] = (idx[ok] + dz * mx * my + dy * mx + dx).astype(np.int32)
+        start[ok] += 1
+    return CSR(n, n, rowptr, colidx, rng.uniform(-1.0, 1.0, size=nnz))
+
+
+def structured_matrix(index: int, min_rows: int = 50_000, max_rows: int = 4_000_000) -> tuple[str, CSR]:
+    """Matrix `index` of the structured (grid operator) population."""
+    rng = rng_for(50, index)
+    kind = ("5pt", "9pt", "7pt", "27pt")[index % 4]
+    n = float(np.exp(rng.uniform(np.log(min_rows), np.log(max_rows))))
+    keep = 1.0 if rng.random() < 0.5 else float(rng.uniform(0.5, 1.0))
+    if kind in ("5pt", "9pt"):
+        mx = max(2, int(round(np.sqrt(n * rng.uniform(0.25, 4.0)))))
+        my = max(2, int(round(n / mx)))
+        mz = 1
+    else:
+        mx = max(2, int(round((n * rng.uniform(0.25, 4.0)) ** (1.0 / 3.0))))
+        my = max(2, int(round(np.sqrt(n / mx * rng.uniform(0.5, 2.0)))))
+        mz = max(2, int(round(n / (mx * my))))
+    return f"stencil{kind}", grid_stencil(mx, my, mz, kind, keep, seed=int(rng.integers(0, 2**31)))
+
+
 def batched_matrix(index: int, min_rows: int = 10_000, max_rows: int = 500_000) -> CSR:
     rng = rng_for(40, index)
     n = int(np.exp(rng.uniform(np.log(min_rows), np.log(max_rows))))

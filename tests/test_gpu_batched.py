@@ -122,3 +122,29 @@ def test_batch_refuses_bad_arguments():
     with pytest.raises(ValueError):
         b.set_vectors([torch.zeros(3, dtype=torch.float64, device="cuda")],
                       [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")])
+
+
+@pytest.mark.parametrize("shape", [0, 1, 5])
+def test_single_shape_kernel_equals_general_kernel(shape):
+    say(f"[batched] single shape {shape}")
+    mats, _ = pop()
+    r, c = spc.SHAPES[shape]
+    Bs, xs, ys, refs = [], [], [], []
+    for k, A in enumerate(mats):
+        Bs.append(spc.csr_to_beta(r, c, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols))
+        x = synth.dense_vector(A.n_cols, 90 + k)
+        xs.append(torch.from_numpy(x).cuda())
+        ys.append(torch.zeros(A.n_rows, dtype=torch.float64, device="cuda"))
+        refs.append(oracle.csr_spmv(A, x))
+    batch = spc.Batch(Bs).set_vectors(xs, ys)
+    assert batch.info()["single_shape"] == shape
+    batch.run()
+    torch.cuda.synchronize()
+    fixed = [y.clone() for y in ys]
+    for y, (y_ref, s) in zip(fixed, refs):
+        assert np.all(np.abs(y.cpu().numpy() - y_ref) <= 1e-13 * s)
+    batch.set_kernel(True).run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(ys, fixed))
+    for B, x, y0 in zip(Bs, xs, fixed):
+        assert torch.equal(spc.spmv(B, x), y0)
