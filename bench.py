@@ -77,8 +77,8 @@ def measured_traffic(kname: str, shape, params: dict, m: int):
             rec = json.load(fh)
         if rec.get("kernel") != kname or rec.get("shape") != list(shape):
             continue
-        if {k: rec["plan"].get(k, 0) for k in ("mode", "wave_chunks", "tile_bits", "xcd_remap")} != \
-                {k: params.get(k, 0) for k in ("mode", "wave_chunks", "tile_bits", "xcd_remap")}:
+        keys = ("mode", "wave_chunks", "tile_bits", "xcd_remap", "pipeline")
+        if {k: rec["plan"].get(k, 0) for k in keys} != {k: params.get(k, 0) for k in keys}:
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
@@ -337,8 +337,8 @@ def main(argv=None):
     ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--batched-matrices", type=int, default=64)
     ap.add_argument("--cg-grid", type=int, default=192)
-    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap: force the "
-                    "headline plan (skips autotuning; used for profiling)")
+    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap[,pipeline]: force "
+                    "the headline plan (skips autotuning; used for profiling)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a plain 256 MiB copy (memory-counter calibration)")
     args = ap.parse_args(argv)
@@ -439,15 +439,16 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     yd = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
     B = spc.csr_to_beta(r, c, rp, ci, v64, A.n_cols)
     if args.plan:
-        m_, v_, x_ = (int(t) for t in args.plan.split(","))
+        fields = [int(t) for t in args.plan.split(",")]
+        m_, v_, x_ = fields[:3]
         params = {"mode": m_, "wave_chunks": v_ if m_ == 0 else 0, "tile_bits": v_ if m_ == 1 else 0,
-                  "xcd_remap": x_}
+                  "xcd_remap": x_, "pipeline": fields[3] if len(fields) > 3 else 0}
     else:
         params = best_params.get(f"f64_b{r}x{c}") or spc.autotune(B, reps=args.sweep_steps, x=xd)[0]
     P = spc.plan_from(B, params)
     info = P.info()
-    kname = (f"k_spmv_wave<{r},{c},double,{params['wave_chunks'] or 4}>" if params["mode"] == 0
-             else f"k_spmv_wg<{r},{c},double,{info['tile_bits']}>")
+    kname = (f"k_spmv_wave{'_pipe' if params.get('pipeline') else ''}<{r},{c},double,{params['wave_chunks'] or 4}>"
+             if params["mode"] == 0 else f"k_spmv_wg<{r},{c},double,{info['tile_bits']}>")
     for _ in range(args.warmup):
         spc.spmv(B, xd, yd, plan=P)
     torch.cuda.synchronize()

@@ -153,7 +153,11 @@ typedef struct spc_plan_params {
     int32_t xcd_remap;
     int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles */
     int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4 or 8; 0 = 4 */
-    int32_t reserved[4];
+    int32_t pipeline;       /* mode 0: 0 = one wavefront per tile; 1 = persistent wavefronts (as
+                               many workgroups as fit on the device) that load their next tile
+                               while working on the current one; N > 1 = the same with at most N
+                               workgroups */
+    int32_t reserved[3];
 } spc_plan_params;
 
 spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,
@@ -215,8 +219,9 @@ spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k,
  *   on `stream` (microseconds, host *us_out). Synchronizes.
  *
  * spc_autotune: builds a plan for every candidate parameter set (both
- *   modes; mode 0 with 2, 4 and 8 chunks per lane, mode 1 with 1024, 2048,
- *   3072 and 4032 tile bits; each with and without XCD remapping), times it
+ *   modes; mode 0 with 2, 4 and 8 chunks per lane, one wavefront per tile or
+ *   pipelined; mode 1 with 1024, 2048, 3072 and 4032 tile bits; each with
+ *   and without XCD remapping where the grid order applies), times it
  *   with spc_time_spmv and returns the fastest set in *best and its time in
  *   *best_us. If records is not NULL, up to max_records timings are written
  *   there (host memory) and *n_records says how many. x and y are scratch

@@ -33,7 +33,7 @@ class BetaView(ctypes.Structure):
 
 class PlanParams(ctypes.Structure):
     _fields_ = [("tile_bits", c_int32), ("xcd_remap", c_int32), ("mode", c_int32),
-                ("wave_chunks", c_int32), ("reserved", c_int32 * 4)]
+                ("wave_chunks", c_int32), ("pipeline", c_int32), ("reserved", c_int32 * 3)]
 
 
 class TuneRecord(ctypes.Structure):
@@ -164,10 +164,10 @@ class Plan:
     """A tile plan (library-owned) for one BetaMatrix."""
 
     def __init__(self, A: "BetaMatrix", tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0,
-                 wave_chunks: int = 0):
+                 wave_chunks: int = 0, pipeline: int = 0):
         self._A = A
         self._view = A.view()
-        p = PlanParams(tile_bits, xcd_remap, mode, wave_chunks)
+        p = PlanParams(tile_bits, xcd_remap, mode, wave_chunks, pipeline)
         h = c_void_p()
         check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
                                     stream_ptr()))
@@ -222,10 +222,11 @@ class BetaMatrix:
                         self.block_masks.data_ptr(),
                         self.values.data_ptr() if self.nnz else None)
 
-    def plan(self, tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0, wave_chunks: int = 0) -> Plan:
-        key = (tile_bits, xcd_remap, mode, wave_chunks)
+    def plan(self, tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0, wave_chunks: int = 0,
+             pipeline: int = 0) -> Plan:
+        key = (tile_bits, xcd_remap, mode, wave_chunks, pipeline)
         if key not in self._plans:
-            self._plans[key] = Plan(self, tile_bits, xcd_remap, mode, wave_chunks)
+            self._plans[key] = Plan(self, tile_bits, xcd_remap, mode, wave_chunks, pipeline)
         return self._plans[key]
 
     def nbytes(self) -> int:
@@ -319,14 +320,14 @@ def autotune(A: BetaMatrix, reps: int = 20, x: torch.Tensor | None = None):
 
     def pd(p):
         return {"mode": p.mode, "tile_bits": p.tile_bits, "wave_chunks": p.wave_chunks,
-                "xcd_remap": p.xcd_remap}
+                "xcd_remap": p.xcd_remap, "pipeline": p.pipeline}
     records = [dict(pd(recs[i].params), us=recs[i].us, n_tiles=recs[i].n_tiles) for i in range(n.value)]
     return pd(best), best_us.value, records
 
 
 def plan_from(A: BetaMatrix, params: dict) -> Plan:
     return A.plan(params.get("tile_bits", 0), params.get("xcd_remap", 0), params.get("mode", 0),
-                  params.get("wave_chunks", 0))
+                  params.get("wave_chunks", 0), params.get("pipeline", 0))
 
 
 def spmm(A: BetaMatrix, X: torch.Tensor, Y: torch.Tensor | None = None, accumulate: bool = False,

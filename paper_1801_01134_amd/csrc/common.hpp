@@ -103,6 +103,9 @@ struct BatchMat {
 spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
                           int accumulate, int grid_blocks, int single_shape, hipStream_t stream);
 
+// Workgroups of the pipelined mode-0 kernel resident at once (occupancy x CUs).
+spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out);
+
 // Validation of a view on the host.
 spc_status check_view(const spc_beta_view *A);
 
@@ -136,6 +139,8 @@ struct spc_plan {
     int xcd_remap;
     int mode;
     int kq;
+    int pipeline;  // mode 0: persistent wavefronts that prefetch their next tile
+    int resident;  // workgroups of the pipelined kernel resident at once
     int device;
     int64_t n_tiles;
     int64_t n_long;

@@ -82,6 +82,9 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     const int mode = params ? params->mode : 0;
     SPC_REQUIRE(mode == 0 || mode == 1, SPC_ERR_INVALID_ARG, "mode must be 0 or 1");
     const int kq = params && params->wave_chunks ? params->wave_chunks : 4;
+    const int pipeline = params ? params->pipeline : 0;
+    SPC_REQUIRE(pipeline >= 0, SPC_ERR_INVALID_ARG, "pipeline must be >= 0");
+    SPC_REQUIRE(!(pipeline && mode != 0), SPC_ERR_INVALID_ARG, "pipeline applies to mode 0 only");
     SPC_REQUIRE(kq == 2 || kq == 4 || kq == 8, SPC_ERR_INVALID_ARG, "wave_chunks must be 2, 4 or 8");
     SPC_REQUIRE(tile_bits == 1024 || tile_bits == 2048 || tile_bits == 3072 || tile_bits == 4032,
                 SPC_ERR_INVALID_ARG, "tile_bits must be 1024, 2048, 3072 or 4032 (got %d)", tile_bits);
@@ -135,6 +138,17 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     P->shape = shape;
     P->tile_bits = cap_bits;
     P->kq = kq;
+    P->pipeline = pipeline > 0;
+    P->resident = 0;
+    if (pipeline) {
+        int g = 0;
+        spc_status rs = spmv_resident_groups(shape, A->dtype, kq, &g);
+        if (rs != SPC_OK) {
+            delete P;
+            return rs;
+        }
+        P->resident = pipeline > 1 && pipeline < g ? pipeline : g;
+    }
     P->xcd_remap = xcd_remap;
     P->mode = mode;
     P->n_tiles = n_tiles;

@@ -34,6 +34,7 @@ struct SpmmArgs {
     int64_t n_rows, n_cols, nnz, n_blocks;
     int64_t ldx, ldy;
     int32_t k;
+    int32_t wide;        // columns taken G = 16 / sizeof(T) at a time (see spmm_tile)
     int32_t n_tiles;
     int32_t accumulate;
     int32_t xcd_remap;
@@ -50,11 +51,8 @@ struct SpmmSmem {
     static constexpr int NCW = NWMAX * Sh::BPW;
     static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
-    uint64_t wm[64];           // masked words, zero after the last
-    int off[64];               // value slot of each word's first bit
     int brow[64];              // tile-relative interval pointers
-    int col[NCOL];             // column of every slot of the tile's words
-    T buf[NBUF + 64];          // packed values, then the products of one column
+    T buf[NBUF + 64];          // packed values, then the unpacked products of one column
 };
 
 // One tile, all k columns. The tile's streams are read once; every lane
@@ -93,22 +91,12 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
     const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
     const int br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
-    const auto wr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
-    uint64_t wl = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(wr, (uint32_t)(lane * 8), 0, 0));
     const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
     V4 ch[KQ];
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
         ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
-    wl &= lane == 0 ? lo_mask : ~0ull;
-    wl &= low_bits(end_bit - 64 * lane);
-    const int cnt = __popcll(wl);
-    const int incl = wave_scan_dpp(cnt);
-#pragma unroll
-    for (int k = 0; k < SM::NCR; ++k) sm.col[lane + 64 * k] = colr[k];
     sm.brow[lane] = br - b0;
-    sm.wm[lane] = wl;
-    sm.off[lane] = incl - cnt;
 #pragma unroll
     for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = ch[k];
     if (q_tail < nq) {
@@ -136,7 +124,8 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
             M[j] = j < nw ? m : 0ull;
             const uint32_t s = lane_rank(M[j]) + vslot;
             v[j] = sm.buf[s < (uint32_t)(SM::NBUF + 64) ? s : 0u];
-            const int c = sm.col[j * Sh::BPW + slot];
+            // the column of slot j BPW + slot: register (j BPW) / 64 of lane (j BPW + slot) mod 64
+            const int c = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, colr[(j * Sh::BPW) / 64]);
             xo[j] = pick(M[j], (uint32_t)(c + kcol) * xrow, 0xffffffffu);
             vslot += (uint32_t)__popcll(M[j]);
         }
@@ -147,80 +136,104 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     const int lg = npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
     const int L = 1 << lg;
     const int pair = lane >> lg, l = lane & (L - 1);
-    char *__restrict__ bb = reinterpret_cast<char *>(sm.buf);
-    const T *__restrict__ prod = sm.buf + shift;
     T *__restrict__ Y = static_cast<T *>(a.Y);
-
-    for (int q = 0; q < a.k; ++q) {
-        // 3. gathers of column q for all words, then the products in place
-        T xv[NWM];
-        const uint32_t qb = (uint32_t)q * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) xv[j] = buf_load<T>(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb);
-        wave_sync();  // the previous column's sums have read the products
-        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-            const uint32_t pb = lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte;
-            if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb) = v[j] * xv[j];
-            vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
-        }
-        wave_sync();
-
-        // 4. row sums: L lanes per (interval, block row)
-        double acc = 0.0;
-        int n_here = 0;
-        if (pair < npairs) {
-            const int li = pair / Sh::R, rho = pair % Sh::R;
-            const int bs = sm.brow[li], be = sm.brow[li + 1];
-            if (Sh::R == 1) {
-                if (bs < be) {
-                    const int gs = bs + lo_slot, ge = be + lo_slot;
-                    const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
-                    const int vs = sm.off[ws] + __popcll(sm.wm[ws] & low_bits((gs % Sh::BPW) * Sh::RC));
-                    const int ve = sm.off[we] + __popcll(sm.wm[we] & low_bits((ge % Sh::BPW) * Sh::RC));
-                    double a0 = 0.0, a1 = 0.0;
-                    int k = vs + l;
-                    for (; k + L < ve; k += 2 * L) {
-                        a0 += (double)prod[k];
-                        a1 += (double)prod[k + L];
-                    }
-                    if (k < ve) a0 += (double)prod[k];
-                    acc = a0 + a1;
-                    n_here = ve - vs;
-                }
-            } else {
-                const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
-                for (int b = bs + l; b < be; b += L) {
-                    const int g = b + lo_slot;
-                    const int wi = g / Sh::BPW, bit = (g % Sh::BPW) * Sh::RC;
-                    const uint64_t wv = sm.wm[wi];
-                    const uint32_t m = (uint32_t)(wv >> bit) & Sh::RCMASK;
-                    const uint32_t sub = (m >> (rho * Sh::C)) & Sh::CMASK;
-                    const int pos = sm.off[wi] + __popcll(wv & low_bits(bit)) + __popc(m & below);
-                    const int n = __popc(sub);
-                    n_here += n;
-                    T pr[Sh::C];
-#pragma unroll
-                    for (int t = 0; t < Sh::C; ++t) pr[t] = prod[pos + t];
-#pragma unroll
-                    for (int t = 0; t < Sh::C; ++t)
-                        if (t < n) acc += (double)pr[t];
-                }
+    // whether each row holds an entry (accumulate leaves empty rows alone)
+    bool stored = false;
+    if (pair < npairs) {
+        const int li = pair / Sh::R, rho = pair % Sh::R;
+        const int bs = sm.brow[li], be = sm.brow[li + 1];
+        if (Sh::R == 1) {
+            stored = be > bs;
+        } else if (a.accumulate) {
+            for (int b = bs + l; b < be; b += L) {
+                const unsigned g = (unsigned)(b + lo_slot);
+                const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
+                stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
             }
         }
-        for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if (Sh::R > 1 && a.accumulate)
-            for (int m = L >> 1; m >= 1; m >>= 1) n_here += __shfl_xor(n_here, m, 64);
-        if (pair < npairs && l == 0) {
-            const int li = pair / Sh::R, rho = pair % Sh::R;
-            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
-            if (row < a.n_rows) {
-                T *yp = Y + row * a.ldy + q;
-                if (a.accumulate) {
-                    if (n_here > 0) *yp = (T)(acc + (double)*yp);
+    }
+    if (Sh::R > 1 && a.accumulate)
+        for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
+    static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
+
+    // Columns are taken in groups of G = 16 / sizeof(T) when the launch says
+    // every group is one aligned 16-byte piece of an X row (a.wide): one
+    // 128-bit gather per lane and word then serves G columns, so each X line
+    // is fetched once per group instead of once per column.
+    constexpr int G = 16 / (int)sizeof(T);
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    const int step = a.wide ? G : 1;
+    for (int q0 = 0; q0 < a.k; q0 += step) {
+        // 3. gathers of the group's columns for all words
+        T xg[NWM][G];
+        const uint32_t qb = (uint32_t)q0 * (uint32_t)sizeof(T);
+        if (a.wide) {
+#pragma unroll
+            for (int j = 0; j < NWM; ++j) {
+                const V4 w = __builtin_amdgcn_raw_buffer_load_b128(
+                    xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb, 0, 0);
+                const T *wv = reinterpret_cast<const T *>(&w);
+#pragma unroll
+                for (int g = 0; g < G; ++g) xg[j][g] = wv[g];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NWM; ++j) {
+                xg[j][0] = buf_load<T>(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb);
+#pragma unroll
+                for (int g = 1; g < G; ++g) xg[j][g] = T(0);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (g >= step) break;
+            const int q = q0 + g;
+            // products of column q, unpacked: bit l of word j at entry 64 j + l
+            wave_sync();  // the values (first column) or the previous column's sums are read
+            T *__restrict__ pw = sm.buf + lane;
+#pragma unroll
+            for (int j = 0; j < NWM; ++j)
+                if (j < nw) pw[64 * j] = pick(M[j], v[j] * xg[j][g], T(0));
+            wave_sync();
+
+            // 4. row sums: L lanes per (interval, block row)
+            double acc = 0.0;
+            const T *__restrict__ pu = sm.buf;
+            if (pair < npairs) {
+                const int li = pair / Sh::R, rho = pair % Sh::R;
+                const int bs = sm.brow[li], be = sm.brow[li + 1];
+                if (Sh::R == 1) {
+                    const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+                    double a0 = 0.0, a1 = 0.0;
+                    int k = es + l;
+                    for (; k + L < ee; k += 2 * L) {
+                        a0 += (double)pu[k];
+                        a1 += (double)pu[k + L];
+                    }
+                    if (k < ee) a0 += (double)pu[k];
+                    acc = a0 + a1;
                 } else {
-                    *yp = (T)acc;
+                    for (int b = bs + l; b < be; b += L) {
+                        const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
+                        T pr[Sh::C];
+#pragma unroll
+                        for (int t = 0; t < Sh::C; ++t) pr[t] = e[t];
+#pragma unroll
+                        for (int t = 0; t < Sh::C; ++t) acc += (double)pr[t];
+                    }
+                }
+            }
+            for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+            if (pair < npairs && l == 0) {
+                const int li = pair / Sh::R, rho = pair % Sh::R;
+                const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+                if (row < a.n_rows) {
+                    T *yp = Y + row * a.ldy + q;
+                    if (a.accumulate) {
+                        if (stored) *yp = (T)(acc + (double)*yp);
+                    } else {
+                        *yp = (T)acc;
+                    }
                 }
             }
         }
@@ -343,6 +356,11 @@ spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const v
     a.ldx = ldx;
     a.ldy = ldy;
     a.k = k;
+    {
+        // groups of G columns are whole aligned 16-byte pieces of every X row
+        const int64_t es = A->dtype == SPC_F64 ? 8 : 4, G = 16 / es;
+        a.wide = (k % G == 0) && ((ldx * es) % 16 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    }
     a.n_tiles = (int32_t)P->n_tiles;
     a.accumulate = accumulate;
     a.xcd_remap = P->xcd_remap;

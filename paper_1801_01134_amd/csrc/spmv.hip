@@ -238,18 +238,60 @@ struct WaveSmem {
     static constexpr int NCW = NWMAX * Sh::BPW;
     static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
-    uint64_t wm[64];                                  // masked words, zero after the last
-    int off[64];                                      // value slot of each word's first bit
     int brow[64];                                     // tile-relative interval pointers
-    int col[NCOL];                                    // column of every slot of the tile's words
-    T buf[NBUF + 64];                                 // packed values, then products
+    T buf[NBUF + 64];                                 // packed values, then unpacked products
 };
 
+// Registers holding one tile's streams while their loads are in flight.
 template <class Sh, class T, int KQ>
-__device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr, WaveSmem<Sh, T, KQ> &sm) {
+struct TileIn {
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    int colr[WaveSmem<Sh, T, KQ>::NCR];
+    int br;
+    V4 ch[KQ];
+};
+
+// Issues every stream of a tile as unguarded buffer loads: first the small
+// ones the x gathers depend on (block columns, interval pointers, mask
+// words), then the packed values, which are needed only after the gathers
+// have been issued (loads complete in issue order).
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
-    constexpr int G = SM::G;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    // columns of all slots of the tile's words: the blocks before b0 in the
+    // first word are never used (their bits are cleared), those after b1 in
+    // the last word are valid blocks of the next tile
+    const int cs0 = w0 * Sh::BPW;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
+    const auto cr = rsrc(a.bcol + cs0, (uint32_t)ncs * 4u);
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k)
+        in.colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
+    in.br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+        in.ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
+}
+
+// Everything after the stream loads: metadata and values into LDS, the x
+// gathers and products, the row sums and the y stores.
+template <class Sh, class T, int KQ>
+__device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in, __amdgpu_buffer_rsrc_t xr,
+                         WaveSmem<Sh, T, KQ> &sm) {
+    using SM = WaveSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
     using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
@@ -264,59 +306,26 @@ __device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_
     const int lo_slot = b0 - w0 * Sh::BPW;                  // slots of word 0 before the tile
     const int end_bit = (b1 - w0 * Sh::BPW) * Sh::RC;       // first bit after the tile, from word 0
     const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
-    // columns of all slots of the tile's words: the blocks before b0 in the
-    // first word are never used (their bits are cleared), those after b1 in
-    // the last word are valid blocks of the next tile
-    const int cs0 = w0 * Sh::BPW;
-    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
-
-    // 1. every stream of the tile, as unguarded buffer loads: first the small
-    // ones the x gathers depend on (block columns, interval pointers, mask
-    // words), then the packed values, which are needed only after the gathers
-    // have been issued (loads complete in issue order)
-    const auto cr = rsrc(a.bcol + cs0, (uint32_t)ncs * 4u);
-    int colr[SM::NCR];
-#pragma unroll
-    for (int k = 0; k < SM::NCR; ++k)
-        colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
-    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
-    const int br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
-    const auto wr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
-    uint64_t wl = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(wr, (uint32_t)(lane * 8), 0, 0));
-    const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
-    V4 ch[KQ];
-#pragma unroll
-    for (int k = 0; k < KQ; ++k)
-        ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
-
-    // metadata into LDS (unconditional: lanes past the ends write zeros and
-    // the sentinels -- word nw is zero, its offset is the tile's value count)
-    wl &= lane == 0 ? lo_mask : ~0ull;
-    wl &= low_bits(end_bit - 64 * lane);
-    const int cnt = __popcll(wl);
-    const int incl = wave_scan_dpp(cnt);
-#pragma unroll
-    for (int k = 0; k < SM::NCR; ++k) sm.col[lane + 64 * k] = colr[k];
-    sm.brow[lane] = br - b0;
-    sm.wm[lane] = wl;
-    sm.off[lane] = incl - cnt;
+    // interval pointers into LDS (lanes past the tile's intervals write what
+    // the out-of-range loads returned; nothing reads them)
+    sm.brow[lane] = in.br - b0;
     wave_sync();
 
-    // 2. products in place, lane = mask bit, words walked on the scalar unit.
-    // All of the tile's words are loaded at once and all x gathers issued
-    // before the values are stored to LDS and the first product is formed. A
-    // lane whose bit is clear gathers out of range (0, no memory access) and
-    // does not store. The last word keeps the bits of the next tile's blocks:
-    // they sit above the tile's own bits, so they do not move the tile's
-    // slots, and their products land past the tile's values, where nothing
-    // reads them.
+    // 2. products, lane = mask bit, words walked on the scalar unit. All of
+    // the tile's words are loaded at once and all x gathers issued before
+    // the values are stored to LDS. A lane whose bit is clear gathers out of
+    // range (0, no memory access). Products are stored UNPACKED: the product
+    // of bit l of word j goes to entry 64 j + l (zero where the bit is clear),
+    // so block row rho of tile slot g is the C entries from g RC + rho C on.
+    // The last word keeps the bits of the next tile's blocks; their entries
+    // are never read.
+    static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
     if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
         constexpr int NWM = SM::NWMAX;
         static_assert(NWM <= 64, "the masks array is padded for 64 words read past its end");
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
         char *__restrict__ bb = reinterpret_cast<char *>(sm.buf);
-        const char *__restrict__ cb = reinterpret_cast<const char *>(sm.col) + slot * 4;
         // the masks array is readable 512 bytes past its last word
         const uint64_t *__restrict__ gp = a.mw + w0;
         uint64_t M[NWM];
@@ -327,14 +336,17 @@ __device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_
             M[j] = j < nw ? m : 0ull;
         }
         T xv[NWM];
+        // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
+        // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes)
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
-            const int c = *reinterpret_cast<const int *>(cb + 4 * j * Sh::BPW);
+            const int src = ((j * Sh::BPW) % 64 + slot) * 4;
+            const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
             xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
         }
         // the values, now that the gathers are in flight
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = ch[k];
+        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
         if (q_tail < nq) {
             if (lane < E) {
                 const int64_t g = abase + (int64_t)q_tail * E + lane;
@@ -342,89 +354,88 @@ __device__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_
             }
         }
         wave_sync();
-        // every lane reads its slot of every word first (the slot is inside
-        // the buffer even where the bit is clear), so the LDS reads overlap;
-        // only lanes whose bit is set write their product back
-        uint32_t pb[NWM];
+        // each lane reads the value of its bit in every word (the slot is
+        // inside the buffer even where the bit is clear)
         T pv[NWM];
-        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the next value
+        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
-            pb[j] = lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte;
-            pv[j] = *reinterpret_cast<const T *>(bb + pb[j]);
+            pv[j] = *reinterpret_cast<const T *>(bb + lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte);
             vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
         }
+        wave_sync();  // all values are read before the products overwrite them
+        T *__restrict__ pu = sm.buf + lane;
 #pragma unroll
         for (int j = 0; j < NWM; ++j)
-            if (__builtin_amdgcn_inverse_ballot_w64(M[j])) *reinterpret_cast<T *>(bb + pb[j]) = pv[j] * xv[j];
+            if (j < nw) pu[64 * j] = pick(M[j], pv[j] * xv[j], T(0));
     }
     wave_sync();
 
-    // 3. row sums: L lanes per (interval, block row)
+    // 3. row sums: L lanes per (interval, block row), over the unpacked products
     const int npairs = nI * Sh::R;
     // log2 L: the largest L with npairs * L <= 64 (npairs is 1..64)
     const int lg = npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
     const int L = 1 << lg;
     const int pair = lane >> lg, l = lane & (L - 1);
     double acc = 0.0;
-    int n_here = 0;
-    const T *__restrict__ prod = sm.buf + shift;
+    bool stored = false;  // the row holds at least one entry (accumulate leaves other rows alone)
+    const T *__restrict__ pu = sm.buf;
     if (pair < npairs) {
         const int li = pair / Sh::R, rho = pair % Sh::R;
         const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
         if (Sh::R == 1) {
-            if (bs < be) {
-                const int gs = bs + lo_slot, ge = be + lo_slot;
-                const int ws = gs / Sh::BPW, we = ge / Sh::BPW;
-                const int vs = sm.off[ws] + __popcll(sm.wm[ws] & low_bits((gs % Sh::BPW) * Sh::RC));
-                const int ve = sm.off[we] + __popcll(sm.wm[we] & low_bits((ge % Sh::BPW) * Sh::RC));
-                double a0 = 0.0, a1 = 0.0;
-                int k = vs + l;
-                for (; k + L < ve; k += 2 * L) {
-                    a0 += (double)prod[k];
-                    a1 += (double)prod[k + L];
-                }
-                if (k < ve) a0 += (double)prod[k];
-                acc = a0 + a1;
-                n_here = ve - vs;                            // same for every lane of the pair
+            // the row's entries are contiguous: slots bs .. be-1, C entries each
+            const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+            double a0 = 0.0, a1 = 0.0;
+            int k = es + l;
+            for (; k + L < ee; k += 2 * L) {
+                a0 += (double)pu[k];
+                a1 += (double)pu[k + L];
             }
+            if (k < ee) a0 += (double)pu[k];
+            acc = a0 + a1;
+            stored = be > bs;  // every block holds at least one entry
         } else {
-            const uint32_t below = rho ? ((1u << (rho * Sh::C)) - 1u) : 0u;
             for (int b = bs + l; b < be; b += L) {
-                const int g = b + lo_slot;
-                const int wi = g / Sh::BPW, bit = (g % Sh::BPW) * Sh::RC;
-                const uint64_t wv = sm.wm[wi];
-                const uint32_t m = (uint32_t)(wv >> bit) & Sh::RCMASK;
-                const uint32_t sub = (m >> (rho * Sh::C)) & Sh::CMASK;
-                const int pos = sm.off[wi] + __popcll(wv & low_bits(bit)) + __popc(m & below);
-                const int n = __popc(sub);
-                n_here += n;
-                // the block row's n products are prod[pos .. pos+n-1]; read
-                // all C slots at once (inside the buffer) and keep the first n
+                const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
                 T pr[Sh::C];
 #pragma unroll
-                for (int k = 0; k < Sh::C; ++k) pr[k] = prod[pos + k];
+                for (int k = 0; k < Sh::C; ++k) pr[k] = e[k];
 #pragma unroll
-                for (int k = 0; k < Sh::C; ++k)
-                    if (k < n) acc += (double)pr[k];
+                for (int k = 0; k < Sh::C; ++k) acc += (double)pr[k];
+            }
+            if (a.accumulate) {
+                for (int b = bs + l; b < be; b += L) {
+                    const unsigned g = (unsigned)(b + lo_slot);
+                    const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
+                    stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
+                }
             }
         }
     }
     for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
     if (Sh::R > 1 && a.accumulate)
-        for (int m = L >> 1; m >= 1; m >>= 1) n_here += __shfl_xor(n_here, m, 64);
+        for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
     if (pair < npairs && l == 0) {
         const int li = pair / Sh::R, rho = pair % Sh::R;
         const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
         if (row < a.n_rows) {
             T *__restrict__ y = static_cast<T *>(a.y);
             if (a.accumulate) {
-                if (n_here > 0) y[row] = (T)(acc + (double)y[row]);
+                if (stored) y[row] = (T)(acc + (double)y[row]);
             } else {
                 y[row] = (T)acc;
             }
         }
     }
+}
+
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
+                                          WaveSmem<Sh, T, KQ> &sm) {
+    TileIn<Sh, T, KQ> in;
+    tile_issue<Sh, T, KQ>(a, d, in);
+    tile_run<Sh, T, KQ>(a, d, in, xr, sm);
 }
 
 // One interval longer than a wavefront tile, run by one wavefront: each lane
@@ -740,6 +751,48 @@ void launch_batched_fixed(int kq, unsigned grid, const BatchMat *d_mats, const T
     }
 }
 
+// Mode 0, pipelined: a persistent grid; each wavefront walks the tiles
+// t, t + S, t + 2S, ... (S = 4 x grid) and issues the next tile's stream
+// loads before it works on the current one, so the next tile's memory
+// latency overlaps the current tile's gathers and sums. Vector loads
+// complete in issue order, so waiting for the current tile's data does not
+// wait for the next tile's.
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = WaveSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int stride = (int)gridDim.x * kWaves;
+    int t = (int)blockIdx.x * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+    TileDesc d = a.tiles[t];
+    bool lng = d.b1 - d.b0 > SM::NB;
+    TileIn<Sh, T, KQ> cur;
+    if (!lng) tile_issue<Sh, T, KQ>(a, d, cur);
+    while (true) {
+        const int tn = t + stride;
+        const bool more = tn < a.n_tiles;
+        TileDesc dn = d;
+        bool lngn = true;
+        TileIn<Sh, T, KQ> nxt;
+        if (more) {
+            dn = a.tiles[tn];
+            lngn = dn.b1 - dn.b0 > SM::NB;
+            if (!lngn) tile_issue<Sh, T, KQ>(a, dn, nxt);
+        }
+        if (lng) wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+        else tile_run<Sh, T, KQ>(a, d, cur, xr, sm[wid]);
+        if (!more) break;
+        wave_sync();  // this tile's LDS reads are done before the next tile writes
+        t = tn;
+        d = dn;
+        lng = lngn;
+        cur = nxt;
+    }
+}
+
 template <int R, int C, class T>
 spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (tb) {
@@ -749,6 +802,31 @@ spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     default: hipLaunchKernelGGL((k_spmv_wg<R, C, T, 4032>), grid, dim3(kThreads), 0, stream, a); break;
     }
     SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
+template <int R, int C, class T>
+spc_status launch_wave_pipe(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    switch (kq) {
+    case 2: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 2>), grid, dim3(kThreads), 0, stream, a); break;
+    case 8: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 8>), grid, dim3(kThreads), 0, stream, a); break;
+    default: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 4>), grid, dim3(kThreads), 0, stream, a); break;
+    }
+    SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
+// Workgroups of the pipelined kernel that are resident at once on the device.
+template <int R, int C, class T>
+spc_status resident_groups(int kq, int *out) {
+    const void *f = kq == 2   ? reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 2>)
+                    : kq == 8 ? reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 8>)
+                              : reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 4>);
+    int per_cu = 0, dev = 0, cus = 0;
+    SPC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kThreads, 0));
+    SPC_HIP(hipGetDevice(&dev));
+    SPC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    *out = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
     return SPC_OK;
 }
 
@@ -803,6 +881,16 @@ spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileD
     });
 }
 
+spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out) {
+    return with_shape(shape, [&](auto sh) {
+        using Sh = decltype(sh);
+        return with_dtype(dtype, [&](auto tv) {
+            using T = decltype(tv);
+            return resident_groups<Sh::R, Sh::C, T>(kq, out);
+        });
+    });
+}
+
 // Mode 0 loads a tile's interval pointers one per lane, the end pointer included.
 int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? (r == 1 ? 63 : 64 / r) : kThreads / r; }
 
@@ -842,11 +930,14 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     const int64_t groups = wave ? div_up(P->n_tiles, kWaves) : P->n_tiles;
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
     dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)groups);
+    const bool pipe = wave && P->pipeline && P->resident > 0;
+    if (pipe) grid = dim3((unsigned)(groups < P->resident ? groups : (int64_t)P->resident));
     return with_shape(P->shape, [&](auto sh) {
         using Sh = decltype(sh);
         return with_dtype(A->dtype, [&](auto tv) {
             using T = decltype(tv);
             if (!wave) return launch_wg<Sh::R, Sh::C, T>(wg_bits, grid, a, stream);
+            if (pipe) return launch_wave_pipe<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
             return launch_wave<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
         });
     });

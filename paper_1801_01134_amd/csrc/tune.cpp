@@ -51,6 +51,10 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
             p.wave_chunks = kq;
             p.xcd_remap = remap;
             cands.push_back(p);
+            if (remap == 0) {
+                p.pipeline = 1;  // persistent: the grid order does not apply
+                cands.push_back(p);
+            }
         }
         for (int tb : {1024, 2048, 3072, 4032}) {
             spc_plan_params p{};

@@ -257,3 +257,32 @@ def test_empty_matrix_with_null_masks_pointer():
                                     ctypes.c_void_p(y.data_ptr()), 0, Bd.stream_ptr()))
     assert torch.all(y == 0)
     Bd.lib().spc_plan_destroy(h)
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("chunks", [2, 4, 8])
+@pytest.mark.parametrize("grid", [1, 3, 40])
+def test_pipelined_equals_one_tile_per_wave(rc, dtype, chunks, grid):
+    """Persistent wavefronts that prefetch their next tile (capped at `grid`
+    workgroups, so every wavefront walks many tiles) compute the same tiles
+    in the same order of operations: identical bits, also with accumulate."""
+    r, c = rc
+    say(f"[pipe] beta{rc} {dtype} chunks={chunks} grid={grid}")
+    for name in ("powerlaw", "dense_rows", "empty_rows", "stencil13"):
+        A = case(name).astype(NP[dtype])
+        x = synth.dense_vector(A.n_cols, 25).astype(NP[dtype])
+        B = to_beta(A, r, c, dtype)
+        xd = torch.from_numpy(x).cuda()
+        y0 = spc.spmv(B, xd, plan=B.plan(0, 0, 0, chunks))
+        P = B.plan(0, 0, 0, chunks, grid + 1)
+        y1 = spc.spmv(B, xd, plan=P)
+        assert torch.equal(y0, y1), name
+        base = torch.from_numpy(synth.dense_vector(A.n_rows, 26).astype(NP[dtype])).cuda()
+        ya = base.clone()
+        yb = base.clone()
+        spc.spmv(B, xd, ya, accumulate=True, plan=B.plan(0, 0, 0, chunks))
+        spc.spmv(B, xd, yb, accumulate=True, plan=P)
+        assert torch.equal(ya, yb), name
+    y_ref, s_ref = oracle.csr_spmv(A, x)
+    check_rows(y1.cpu().numpy().astype(np.float64), y_ref, s_ref, TOL[dtype], f"pipe beta{rc}")
