@@ -273,27 +273,22 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
     out = {"grid": m, "n": A.n_rows, "nnz": A.nnz, "runs": []}
     for dt, kset, tol in ((torch.float64, ks, 1e-8), (torch.float32, fp32_ks, 1e-5)):
         vals = torch.from_numpy(A.values).to(dev).to(dt)
-        # shape and tile size: the faster SpMM at the largest k among two shapes x three chunk counts
-        best = None
-        kmax = max(kset)
-        for (r, c) in ((2, 4), (4, 8)):
-            B = spc.csr_to_beta(r, c, rp, ci, vals, A.n_cols)
-            X = torch.from_numpy(synth.dense_block(A.n_cols, kmax, 700)).to(dev).to(dt)
-            for kq in (2, 4, 8):
-                P = B.plan(0, 0, 0, kq)
-                t = event_time(torch, lambda: spc.spmm(B, X, plan=P), 10, 2)
-                if best is None or t < best[0]:
-                    best = (t, (r, c), kq)
-            del B, X
-            torch.cuda.empty_cache()
-        (r, c), kq = best[1], best[2]
-        B = spc.csr_to_beta(r, c, rp, ci, vals, A.n_cols)
-        P = B.plan(0, 0, 0, kq)
+        # per k: the faster SpMM among two shapes x three chunk counts
+        Bs = {rc: spc.csr_to_beta(rc[0], rc[1], rp, ci, vals, A.n_cols) for rc in ((2, 4), (4, 8))}
         for k in kset:
             Bm = synth.dense_block(A.n_cols, k, 701 + k)
             Bd = torch.from_numpy(Bm).to(dev).to(dt)
             X = torch.from_numpy(synth.dense_block(A.n_cols, k, 702)).to(dev).to(dt)
-            t_spmm = event_time(torch, lambda: spc.spmm(B, X, plan=P), 10, 2)
+            best = None
+            for rc, Bc in Bs.items():
+                for kq in (2, 4, 8):
+                    Pc = Bc.plan(0, 0, 0, kq)
+                    t = event_time(torch, lambda: spc.spmm(Bc, X, plan=Pc), 10, 2)
+                    if best is None or t < best[0]:
+                        best = (t, rc, kq)
+            t_spmm, (r, c), kq = best
+            B = Bs[(r, c)]
+            P = B.plan(0, 0, 0, kq)
             s = torch.cuda.Stream()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -317,7 +312,7 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
                 "spmm_share_of_iteration": round(t_spmm * total / wall, 3) if total else None})
             log(f"cg {out['runs'][-1]}")
             del X, Xs, Bd
-        del B, P, vals
+        del B, P, Bs, vals
         torch.cuda.empty_cache()
     return out
 

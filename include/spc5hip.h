@@ -184,7 +184,11 @@ spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan, const voi
  * ldx, ldy >= k (the k values of one row are contiguous), A's dtype. Each
  * Y entry is the plain definition sum_j a_ij X[j][q], summed in double
  * precision. plan must be a mode-0 plan of A (wavefront tiles); values must
- * be 16-byte aligned and X smaller than 3.75 GiB. Asynchronous. */
+ * be 16-byte aligned and X smaller than 3.75 GiB. When k is a multiple of
+ * 16 / (value size) and X, Y and their leading dimensions keep every such
+ * group of columns 16-byte aligned, groups of columns share one pass (the
+ * results are the same bits). k = 1 with unit leading dimensions runs the
+ * single-vector kernel. Asynchronous. */
 spc_status spc_spmm_beta(const spc_beta_view *A, const spc_plan *plan, int32_t k, const void *X,
                          int64_t ldx, void *Y, int64_t ldy, int32_t accumulate, hipStream_t stream);
 

@@ -19,6 +19,8 @@
 namespace spc {
 spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, int accumulate, hipStream_t stream);
+spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x, void *y, int accumulate,
+                       hipStream_t stream);
 
 namespace {
 
@@ -300,7 +302,7 @@ template <class T>
 spc_status iteration(const spc_beta_view *A, const spc_plan *P, int k, const Work &w, T *X, int64_t ldx,
                      int64_t n, double tol2, hipStream_t st) {
     const unsigned nb = vec_blocks(n, k);
-    spc_status r = spmm_launch(A, P, k, w.P, k, w.Q, k, 0, st);
+    spc_status r = k == 1 ? spmv_launch(A, P, w.P, w.Q, 0, st) : spmm_launch(A, P, k, w.P, k, w.Q, k, 0, st);
     if (r != SPC_OK) return r;
     hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(kT), 0, st, n, k, (const T *)w.P, (const T *)w.Q, w.part);
     hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kT), 0, st, w.part, (int)nb, k, w.s);

@@ -51,8 +51,11 @@ struct SpmmSmem {
     static constexpr int NCW = NWMAX * Sh::BPW;
     static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
+    // G = E columns of products, interleaved, per mask bit of every word
+    static constexpr int NPROD = NWMAX * 64 * E;
+    static constexpr int NALL = NPROD > NBUF + 64 ? NPROD : NBUF + 64;
     int brow[64];              // tile-relative interval pointers
-    T buf[NBUF + 64];          // packed values, then the unpacked products of one column
+    T buf[NALL];               // packed values, then the unpacked products of a column group
 };
 
 // One tile, all k columns. The tile's streams are read once; every lane
@@ -157,83 +160,156 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
 
     // Columns are taken in groups of G = 16 / sizeof(T) when the launch says
-    // every group is one aligned 16-byte piece of an X row (a.wide): one
-    // 128-bit gather per lane and word then serves G columns, so each X line
-    // is fetched once per group instead of once per column.
+    // every group is one aligned 16-byte piece of each X and Y row (a.wide):
+    // one 128-bit gather per lane and word brings the group's G values, the
+    // G products of a mask bit go to LDS together (entry (64 j + l) G + g),
+    // the row sums read them with wide loads and each row's G results are
+    // stored at once. Otherwise the columns are taken one by one.
     constexpr int G = 16 / (int)sizeof(T);
     using V4 = __attribute__((ext_vector_type(4))) unsigned int;
-    const int step = a.wide ? G : 1;
-    for (int q0 = 0; q0 < a.k; q0 += step) {
-        // 3. gathers of the group's columns for all words
-        T xg[NWM][G];
-        const uint32_t qb = (uint32_t)q0 * (uint32_t)sizeof(T);
-        if (a.wide) {
-#pragma unroll
-            for (int j = 0; j < NWM; ++j) {
-                const V4 w = __builtin_amdgcn_raw_buffer_load_b128(
-                    xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb, 0, 0);
-                const T *wv = reinterpret_cast<const T *>(&w);
-#pragma unroll
-                for (int g = 0; g < G; ++g) xg[j][g] = wv[g];
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < NWM; ++j) {
-                xg[j][0] = buf_load<T>(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb);
-#pragma unroll
-                for (int g = 1; g < G; ++g) xg[j][g] = T(0);
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            if (g >= step) break;
-            const int q = q0 + g;
-            // products of column q, unpacked: bit l of word j at entry 64 j + l
-            wave_sync();  // the values (first column) or the previous column's sums are read
-            T *__restrict__ pw = sm.buf + lane;
+    static_assert(SM::NPROD <= SM::NALL, "products must fit the buffer");
+    if (a.wide) {
+        for (int q0 = 0; q0 < a.k; q0 += G) {
+            const uint32_t qb = (uint32_t)q0 * (uint32_t)sizeof(T);
+            V4 xw[NWM];
 #pragma unroll
             for (int j = 0; j < NWM; ++j)
-                if (j < nw) pw[64 * j] = pick(M[j], v[j] * xg[j][g], T(0));
+                xw[j] = __builtin_amdgcn_raw_buffer_load_b128(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb,
+                                                              0, 0);
+            wave_sync();  // the values (first group) or the previous group's sums are read
+#pragma unroll
+            for (int j = 0; j < NWM; ++j) {
+                if (j < nw) {
+                    const T *xg = reinterpret_cast<const T *>(&xw[j]);
+                    T pg[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) pg[g] = pick(M[j], v[j] * xg[g], T(0));
+                    *reinterpret_cast<V4 *>(&sm.buf[(64 * j + lane) * G]) = *reinterpret_cast<const V4 *>(pg);
+                }
+            }
             wave_sync();
-
-            // 4. row sums: L lanes per (interval, block row)
-            double acc = 0.0;
-            const T *__restrict__ pu = sm.buf;
+            double acc[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = 0.0;
             if (pair < npairs) {
                 const int li = pair / Sh::R, rho = pair % Sh::R;
                 const int bs = sm.brow[li], be = sm.brow[li + 1];
                 if (Sh::R == 1) {
+                    // the same two interleaved partial sums as the one-column path
                     const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                    double a0 = 0.0, a1 = 0.0;
+                    double a1[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) a1[g] = 0.0;
                     int k = es + l;
                     for (; k + L < ee; k += 2 * L) {
-                        a0 += (double)pu[k];
-                        a1 += (double)pu[k + L];
+                        const V4 w0 = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
+                        const V4 w1 = *reinterpret_cast<const V4 *>(&sm.buf[(k + L) * G]);
+                        const T *e0 = reinterpret_cast<const T *>(&w0);
+                        const T *e1 = reinterpret_cast<const T *>(&w1);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            acc[g] += (double)e0[g];
+                            a1[g] += (double)e1[g];
+                        }
                     }
-                    if (k < ee) a0 += (double)pu[k];
-                    acc = a0 + a1;
+                    if (k < ee) {
+                        const V4 w0 = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
+                        const T *e0 = reinterpret_cast<const T *>(&w0);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[g] += a1[g];
                 } else {
                     for (int b = bs + l; b < be; b += L) {
-                        const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                        T pr[Sh::C];
+                        const int e0 = (b + lo_slot) * Sh::RC + rho * Sh::C;
+                        V4 w[Sh::C];
 #pragma unroll
-                        for (int t = 0; t < Sh::C; ++t) pr[t] = e[t];
+                        for (int t = 0; t < Sh::C; ++t) w[t] = *reinterpret_cast<const V4 *>(&sm.buf[(e0 + t) * G]);
 #pragma unroll
-                        for (int t = 0; t < Sh::C; ++t) acc += (double)pr[t];
+                        for (int t = 0; t < Sh::C; ++t) {
+                            const T *e = reinterpret_cast<const T *>(&w[t]);
+#pragma unroll
+                            for (int g = 0; g < G; ++g) acc[g] += (double)e[g];
+                        }
                     }
                 }
             }
-            for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int m = L >> 1; m >= 1; m >>= 1) acc[g] += __shfl_xor(acc[g], m, 64);
             if (pair < npairs && l == 0) {
                 const int li = pair / Sh::R, rho = pair % Sh::R;
                 const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
                 if (row < a.n_rows) {
-                    T *yp = Y + row * a.ldy + q;
+                    T *yp = Y + row * a.ldy + q0;
+                    T out[G];
                     if (a.accumulate) {
-                        if (stored) *yp = (T)(acc + (double)*yp);
+                        const V4 old = *reinterpret_cast<const V4 *>(yp);
+                        const T *o = reinterpret_cast<const T *>(&old);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) out[g] = stored ? (T)(acc[g] + (double)o[g]) : o[g];
                     } else {
-                        *yp = (T)acc;
+#pragma unroll
+                        for (int g = 0; g < G; ++g) out[g] = (T)acc[g];
                     }
+                    *reinterpret_cast<V4 *>(yp) = *reinterpret_cast<const V4 *>(out);
+                }
+            }
+        }
+        return;
+    }
+    for (int q = 0; q < a.k; ++q) {
+        // gathers of column q for all words, then its products, unpacked:
+        // bit l of word j at entry 64 j + l (zero where clear)
+        T xv[NWM];
+        const uint32_t qb = (uint32_t)q * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) xv[j] = buf_load<T>(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb);
+        wave_sync();  // the values (first column) or the previous column's sums are read
+        T *__restrict__ pw = sm.buf + lane;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+            if (j < nw) pw[64 * j] = pick(M[j], v[j] * xv[j], T(0));
+        wave_sync();
+
+        // row sums: L lanes per (interval, block row)
+        double acc = 0.0;
+        const T *__restrict__ pu = sm.buf;
+        if (pair < npairs) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int bs = sm.brow[li], be = sm.brow[li + 1];
+            if (Sh::R == 1) {
+                const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+                double a0 = 0.0, a1 = 0.0;
+                int k = es + l;
+                for (; k + L < ee; k += 2 * L) {
+                    a0 += (double)pu[k];
+                    a1 += (double)pu[k + L];
+                }
+                if (k < ee) a0 += (double)pu[k];
+                acc = a0 + a1;
+            } else {
+                for (int b = bs + l; b < be; b += L) {
+                    const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
+                    T pr[Sh::C];
+#pragma unroll
+                    for (int t = 0; t < Sh::C; ++t) pr[t] = e[t];
+#pragma unroll
+                    for (int t = 0; t < Sh::C; ++t) acc += (double)pr[t];
+                }
+            }
+        }
+        for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        if (pair < npairs && l == 0) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+            if (row < a.n_rows) {
+                T *yp = Y + row * a.ldy + q;
+                if (a.accumulate) {
+                    if (stored) *yp = (T)(acc + (double)*yp);
+                } else {
+                    *yp = (T)acc;
                 }
             }
         }
@@ -339,6 +415,9 @@ spc_status launch(int kq, dim3 grid, const SpmmArgs &a, hipStream_t s) {
 
 }  // namespace
 
+spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x, void *y, int accumulate,
+                       hipStream_t stream);
+
 spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, int accumulate, hipStream_t stream) {
     SpmmArgs a;
@@ -359,7 +438,9 @@ spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const v
     {
         // groups of G columns are whole aligned 16-byte pieces of every X row
         const int64_t es = A->dtype == SPC_F64 ? 8 : 4, G = 16 / es;
-        a.wide = (k % G == 0) && ((ldx * es) % 16 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+        // groups of G columns are whole aligned 16-byte pieces of every X and Y row
+        a.wide = (k % G == 0) && ((ldx * es) % 16 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0) &&
+                 ((ldy * es) % 16 == 0) && (reinterpret_cast<uintptr_t>(Y) % 16 == 0);
     }
     a.n_tiles = (int32_t)P->n_tiles;
     a.accumulate = accumulate;
@@ -399,5 +480,7 @@ extern "C" spc_status spc_spmm_beta(const spc_beta_view *A, const spc_plan *plan
                 "spc_spmm_beta needs a 16-byte aligned values array");
     SPC_REQUIRE(reinterpret_cast<uintptr_t>(X) % es == 0 && reinterpret_cast<uintptr_t>(Y) % es == 0,
                 SPC_ERR_INVALID_ARG, "X and Y must be aligned to the element size");
+    // one contiguous right-hand side is a vector: the single-vector kernel
+    if (k == 1 && ldx == 1 && ldy == 1) return spc::spmv_launch(A, plan, X, Y, accumulate, stream);
     return spc::spmm_launch(A, plan, k, X, ldx, Y, ldy, accumulate, stream);
 }
