@@ -23,7 +23,8 @@ Further sections of the same JSON line (each can be switched off):
   batched     64 matrices (rows log-uniform in [10k, 500k], Poisson(16.8)
               uniform columns + Poisson(2.4) dense 3x3 blocks per block row),
               each in the shape the selector picks, as one launch versus 64
-              launches (plain and graph-captured)
+              launches (plain and graph-captured); and the same for 512
+              small matrices (rows log-uniform in [500, 20k])
   cg          CG on the SPD 27-point matrix of a 192^3 grid (7,077,888 rows,
               189,119,224 nonzeros) with k = 1, 4, 8, 16 right-hand sides,
               FP64 to 1e-8 and FP32 to 1e-5, true residuals recomputed by
@@ -129,12 +130,12 @@ def cpu_baseline(A, x, budget_s: float = 10.0):
 # workload generation in worker processes (forked before the GPU is touched)
 
 def _gen_batched(args):
-    i, tmp = args
+    i, tmp, lo, hi = args
     import numpy as np
 
     from paper_1801_01134_amd import synth
-    A = synth.batched_matrix(i)
-    base = os.path.join(tmp, f"b{i}")
+    A = synth.batched_matrix(i, lo, hi)
+    base = os.path.join(tmp, f"b{lo}_{i}")
     np.save(base + "_rp.npy", A.rowptr)
     np.save(base + "_ci.npy", A.colidx)
     np.save(base + "_v.npy", A.values)
@@ -195,9 +196,10 @@ def select_shape(spc, sel, model, feat):
     return sm, si
 
 
-def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, warmup: int):
+def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, warmup: int,
+                    min_rows: int = 10_000, max_rows: int = 500_000):
     dev = torch.device("cuda")
-    results = pool.map(_gen_batched, [(i, tmp) for i in range(n_mat)])
+    results = pool.map(_gen_batched, [(i, tmp, min_rows, max_rows) for i in range(n_mat)])
     Bs, xs, ys, shapes = [], [], [], []
     from paper_1801_01134_amd import synth
     total_nnz = 0
@@ -221,7 +223,8 @@ def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, w
     plans = [B.plan() for B in Bs]
     ab = sum(algorithmic_bytes(B, P.info()["n_tiles"]) for B, P in zip(Bs, plans))
     flops = 2.0 * total_nnz
-    out = {"matrices": n_mat, "nnz_total": total_nnz, "rows_total": sum(B.n_rows for B in Bs),
+    out = {"matrices": n_mat, "rows_range": [min_rows, max_rows], "nnz_total": total_nnz,
+           "rows_total": sum(B.n_rows for B in Bs),
            "shape_share": [shapes.count(k) for k in range(6)], "alg_bytes": ab,
            "n_tiles": batch.info()["n_tiles"]}
 
@@ -509,6 +512,10 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         out["batched"] = batched_section(spc, torch, sel, model, pool, tmp, args.batched_matrices,
                                          max(5, args.steps // 10), 3)
         log(f"batched: {out['batched']}")
+        torch.cuda.empty_cache()
+        out["batched_small"] = batched_section(spc, torch, sel, model, pool, tmp, 512, max(5, args.steps // 10), 3,
+                                               min_rows=500, max_rows=20_000)
+        log(f"batched small: {out['batched_small']}")
         torch.cuda.empty_cache()
     if do_cg:
         out["cg"] = cg_section(spc, torch, pool, tmp, args.cg_grid, (1, 4, 8, 16), (1, 16))

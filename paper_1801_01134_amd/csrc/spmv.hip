@@ -662,13 +662,15 @@ __device__ __forceinline__ void batched_tile(const SpmvArgs &a, const TileDesc &
     }
 }
 
-template <class T, int KQ>
+template <class T, int KQ, bool PERSIST>
 __global__ __launch_bounds__(kThreads) void k_spmv_batched(const BatchMat *__restrict__ mats,
                                                            const TileDesc *__restrict__ tiles, int64_t n_tiles,
                                                            int accumulate) {
     __shared__ BatchSmem<T, KQ> sm[kWaves];
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += (int64_t)gridDim.x * kWaves) {
+    const int64_t t0 = (int64_t)blockIdx.x * kWaves + wid;
+    const int64_t step = PERSIST ? (int64_t)gridDim.x * kWaves : n_tiles;
+    for (int64_t t = t0; t < n_tiles; t += step) {
         const TileDesc d = tiles[t];
         const BatchMat &M = mats[d.reserved];
         SpmvArgs a;
@@ -701,14 +703,17 @@ __global__ __launch_bounds__(kThreads) void k_spmv_batched(const BatchMat *__res
 
 // A batch whose matrices all have shape S: no switch, and only that shape's
 // LDS layout, so occupancy matches the single-matrix kernel.
-template <int S, class T, int KQ>
+// PERSIST = false: one tile per wavefront (the grid covers the list), no loop.
+template <int S, class T, int KQ, bool PERSIST>
 __global__ __launch_bounds__(kThreads) void k_spmv_batched_fixed(const BatchMat *__restrict__ mats,
                                                                  const TileDesc *__restrict__ tiles, int64_t n_tiles,
                                                                  int accumulate) {
     using Sh = Shape<kShapeR[S], kShapeC[S]>;
     __shared__ WaveSmem<Sh, T, KQ> sm[kWaves];
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += (int64_t)gridDim.x * kWaves) {
+    const int64_t t0 = (int64_t)blockIdx.x * kWaves + wid;
+    const int64_t step = PERSIST ? (int64_t)gridDim.x * kWaves : n_tiles;
+    for (int64_t t = t0; t < n_tiles; t += step) {
         const TileDesc d = tiles[t];
         const BatchMat &M = mats[d.reserved];
         SpmvArgs a;
@@ -732,23 +737,30 @@ __global__ __launch_bounds__(kThreads) void k_spmv_batched_fixed(const BatchMat 
     }
 }
 
-template <int S, class T>
-void launch_batched_fixed(int kq, unsigned grid, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
-                          int accumulate, hipStream_t stream) {
+template <int S, class T, bool P>
+void launch_batched_fixed_p(int kq, unsigned grid, const BatchMat *d_mats, const TileDesc *d_tiles,
+                            int64_t n_tiles, int accumulate, hipStream_t stream) {
     switch (kq) {
     case 2:
-        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 2>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
-                           n_tiles, accumulate);
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 2, P>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
+                           d_tiles, n_tiles, accumulate);
         break;
     case 8:
-        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 8>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
-                           n_tiles, accumulate);
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 8, P>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
+                           d_tiles, n_tiles, accumulate);
         break;
     default:
-        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 4>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
-                           n_tiles, accumulate);
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 4, P>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
+                           d_tiles, n_tiles, accumulate);
         break;
     }
+}
+
+template <int S, class T>
+void launch_batched_fixed(int kq, unsigned grid, bool persist, const BatchMat *d_mats, const TileDesc *d_tiles,
+                          int64_t n_tiles, int accumulate, hipStream_t stream) {
+    if (persist) launch_batched_fixed_p<S, T, true>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
+    else launch_batched_fixed_p<S, T, false>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
 }
 
 // Mode 0, pipelined: a persistent grid; each wavefront walks the tiles
@@ -851,30 +863,33 @@ spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileD
     return with_dtype(dtype, [&](auto tv) -> spc_status {
         using T = decltype(tv);
         if (single_shape >= 0) {
+            const bool persist = grid < groups;
             switch (single_shape) {
-            case 0: launch_batched_fixed<0, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
-            case 1: launch_batched_fixed<1, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
-            case 2: launch_batched_fixed<2, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
-            case 3: launch_batched_fixed<3, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
-            case 4: launch_batched_fixed<4, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
-            default: launch_batched_fixed<5, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 0: launch_batched_fixed<0, T>(kq, grid, persist, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 1: launch_batched_fixed<1, T>(kq, grid, persist, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 2: launch_batched_fixed<2, T>(kq, grid, persist, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 3: launch_batched_fixed<3, T>(kq, grid, persist, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            case 4: launch_batched_fixed<4, T>(kq, grid, persist, d_mats, d_tiles, n_tiles, accumulate, stream); break;
+            default: launch_batched_fixed<5, T>(kq, grid, persist, d_mats, d_tiles, n_tiles, accumulate, stream);
+                break;
             }
             SPC_HIP(hipGetLastError());
             return SPC_OK;
         }
+        const bool persist = grid < groups;
+        auto go = [&](auto kq_c) {
+            constexpr int KQ = decltype(kq_c)::value;
+            if (persist)
+                hipLaunchKernelGGL((k_spmv_batched<T, KQ, true>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
+                                   d_tiles, n_tiles, accumulate);
+            else
+                hipLaunchKernelGGL((k_spmv_batched<T, KQ, false>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
+                                   d_tiles, n_tiles, accumulate);
+        };
         switch (kq) {
-        case 2:
-            hipLaunchKernelGGL((k_spmv_batched<T, 2>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
-                               n_tiles, accumulate);
-            break;
-        case 8:
-            hipLaunchKernelGGL((k_spmv_batched<T, 8>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
-                               n_tiles, accumulate);
-            break;
-        default:
-            hipLaunchKernelGGL((k_spmv_batched<T, 4>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
-                               n_tiles, accumulate);
-            break;
+        case 2: go(std::integral_constant<int, 2>{}); break;
+        case 8: go(std::integral_constant<int, 8>{}); break;
+        default: go(std::integral_constant<int, 4>{}); break;
         }
         SPC_HIP(hipGetLastError());
         return SPC_OK;
