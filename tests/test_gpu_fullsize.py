@@ -1,0 +1,125 @@
+"""Parity at the benchmark's full sizes, in the launch configurations the
+benchmark times. The CSR oracle computes every row (it takes milliseconds
+on the host), so these compare all outputs, not a sample:
+
+  * the 27-point stencil of the 128^3 grid (2,097,152 rows, 55,742,968
+    nonzeros) in all six shapes, FP64 and FP32, under every plan the
+    autotuner may pick (the headline launch among them);
+  * the band + uniform matrix (n = 4096, 16 entries per row) in beta(1,8);
+  * CG on the SPD 27-point matrix of the 192^3 grid, k = 4, FP64 to 1e-8,
+    with the true residual recomputed by the oracle;
+  * 8 of the 64 batched matrices (rows log-uniform in [10k, 500k]) in one
+    launch.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import cg as ocg
+import paper_1801_01134_amd as spc
+from paper_1801_01134_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = {torch.float64: 1e-13, torch.float32: 2e-6}
+NP = {torch.float64: np.float64, torch.float32: np.float32}
+
+_big = {}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def stencil128():
+    if "A" not in _big:
+        A = synth.stencil27(128, diag=27.0)
+        x = synth.dense_vector(A.n_cols, 1)
+        _big["A"] = A
+        _big["x"] = x
+        _big["dev"] = (torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colidx).cuda(),
+                       torch.from_numpy(A.values).cuda())
+        _big["ref64"] = oracle.csr_spmv(A, x)
+        A32 = A.astype(np.float32)
+        _big["ref32"] = oracle.csr_spmv(A32, x.astype(np.float32))
+    return _big
+
+
+def check(y, ref, tol, label):
+    y_ref, s = ref
+    err = np.abs(y.astype(np.float64) - y_ref)
+    bad = np.flatnonzero(~(err <= tol * s))
+    assert bad.size == 0, f"{label}: {bad.size} rows off, first {bad[0]}: {y[bad[0]]} vs {y_ref[bad[0]]}"
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_stencil128_all_rows_all_plans(rc, dtype):
+    r, c = rc
+    say(f"[full] stencil 128^3 beta{rc} {dtype}")
+    S = stencil128()
+    A = S["A"]
+    rp, ci, v64 = S["dev"]
+    B = spc.csr_to_beta(r, c, rp, ci, v64.to(dtype), A.n_cols)
+    assert B.n_blocks == int(oracle.beta_count(A, r, c).sum())
+    x = torch.from_numpy(S["x"]).cuda().to(dtype)
+    ref = S["ref64"] if dtype == torch.float64 else S["ref32"]
+    plans = [dict(mode=0, wave_chunks=q, xcd_remap=xr, pipeline=0) for q in (2, 4, 8) for xr in (0, 2)]
+    plans += [dict(mode=0, wave_chunks=q, pipeline=1) for q in (2, 4, 8)]
+    plans += [dict(mode=1, tile_bits=tb, xcd_remap=xr) for tb in (1024, 4032) for xr in (0, 2)]
+    first = None
+    for p in plans:
+        y = spc.spmv(B, x, plan=spc.plan_from(B, p)).cpu().numpy()
+        check(y, ref, TOL[dtype], f"beta{rc} {p}")
+        if first is None:
+            first = y
+    # the default plan (one wavefront per tile, 4 chunks) repeats bit for bit
+    y1 = spc.spmv(B, x).cpu().numpy()
+    y2 = spc.spmv(B, x).cpu().numpy()
+    assert np.array_equal(y1.view(np.uint8), y2.view(np.uint8))
+
+
+def test_band_plus_uniform_beta18():
+    say("[full] band + uniform n=4096 beta(1,8)")
+    A = synth.band_plus_uniform()
+    x = synth.dense_vector(A.n_cols, 2)
+    B = spc.csr_to_beta(1, 8, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols)
+    y = spc.spmv(B, torch.from_numpy(x).cuda()).cpu().numpy()
+    check(y, oracle.csr_spmv(A, x), 1e-13, "band4096")
+    # conversion of this matrix: r = 1 keeps the values in CSR order
+    assert torch.equal(B.values.cpu(), torch.from_numpy(A.values))
+
+
+def test_cg_192_k4():
+    say("[full] CG 192^3 k=4")
+    A = synth.stencil27(192, diag=26.1, offdiag=-1.0)
+    Bm = synth.dense_block(A.n_cols, 4, 705)
+    B = spc.csr_to_beta(2, 4, torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colidx).cuda(),
+                        torch.from_numpy(A.values).cuda(), A.n_cols)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        X, its, res, total = spc.cg(B, torch.from_numpy(Bm).cuda(), rel_tol=1e-8, max_iter=2000, check_every=25)
+    s.synchronize()
+    assert all(0 < i <= total for i in its)
+    true = ocg.true_residual(A, X.cpu().numpy(), Bm) / np.linalg.norm(Bm, axis=0)
+    assert np.all(true <= 2e-8), true
+
+
+def test_batched_config_sample():
+    say("[full] 8 batched matrices, one launch")
+    mats = [synth.batched_matrix(i) for i in range(8)]
+    Bs, xs, ys, refs = [], [], [], []
+    for i, A in enumerate(mats):
+        r, c = spc.SHAPES[i % 6]
+        Bs.append(spc.csr_to_beta(r, c, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols))
+        x = synth.dense_vector(A.n_cols, 400 + i)
+        xs.append(torch.from_numpy(x).cuda())
+        ys.append(torch.empty(A.n_rows, dtype=torch.float64, device="cuda"))
+        refs.append(oracle.csr_spmv(A, x))
+    spc.Batch(Bs).set_vectors(xs, ys).run()
+    torch.cuda.synchronize()
+    for i, (y, ref) in enumerate(zip(ys, refs)):
+        check(y.cpu().numpy(), ref, 1e-13, f"batched {i}")
