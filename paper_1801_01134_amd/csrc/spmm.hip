@@ -54,7 +54,7 @@ struct SpmmSmem {
     // G = E columns of products, interleaved, per mask bit of every word
     static constexpr int NPROD = NWMAX * 64 * E;
     static constexpr int NALL = NPROD > NBUF + 64 ? NPROD : NBUF + 64;
-    int brow[64];              // tile-relative interval pointers
+    int brow[128];             // tile-relative interval pointers (up to 127 intervals)
     T buf[NALL];               // packed values, then the unpacked products of a column group
 };
 
@@ -93,13 +93,15 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     for (int k = 0; k < SM::NCR; ++k)
         colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
     const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
-    const int br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const int br0 = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const int br1 = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
     const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
     V4 ch[KQ];
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
         ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
-    sm.brow[lane] = br - b0;
+    sm.brow[lane] = br0 - b0;
+    sm.brow[lane + 64] = br1 - b0;
 #pragma unroll
     for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = ch[k];
     if (q_tail < nq) {
@@ -133,30 +135,36 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
             vslot += (uint32_t)__popcll(M[j]);
         }
     }
-    // row-sum layout, fixed for all columns
+    // row-sum layout, fixed for all columns: L lanes per (interval, block
+    // row); with more than 64 pairs (up to 128), L = 1 and a lane takes pairs
+    // lane and lane + 64
     const int npairs = nI * Sh::R;
-    // log2 L: the largest L with npairs * L <= 64 (npairs is 1..64)
-    const int lg = npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
+    const int lg = npairs > 64 ? 0 : npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
     const int L = 1 << lg;
-    const int pair = lane >> lg, l = lane & (L - 1);
+    const int l = lane & (L - 1);
+    const int rounds = npairs > 64 ? 2 : 1;
     T *__restrict__ Y = static_cast<T *>(a.Y);
     // whether each row holds an entry (accumulate leaves empty rows alone)
-    bool stored = false;
-    if (pair < npairs) {
-        const int li = pair / Sh::R, rho = pair % Sh::R;
-        const int bs = sm.brow[li], be = sm.brow[li + 1];
-        if (Sh::R == 1) {
-            stored = be > bs;
-        } else if (a.accumulate) {
-            for (int b = bs + l; b < be; b += L) {
-                const unsigned g = (unsigned)(b + lo_slot);
-                const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
-                stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
+    bool stored[2] = {false, false};
+#pragma unroll
+    for (int rd = 0; rd < 2; ++rd) {
+        const int pair = (lane >> lg) + 64 * rd;
+        if (rd < rounds && pair < npairs) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int bs = sm.brow[li], be = sm.brow[li + 1];
+            if (Sh::R == 1) {
+                stored[rd] = be > bs;
+            } else if (a.accumulate) {
+                for (int b = bs + l; b < be; b += L) {
+                    const unsigned g = (unsigned)(b + lo_slot);
+                    const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
+                    stored[rd] = stored[rd] || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
+                }
             }
         }
+        if (Sh::R > 1 && a.accumulate)
+            for (int m = L >> 1; m >= 1; m >>= 1) stored[rd] = __shfl_xor((int)stored[rd], m, 64) || stored[rd];
     }
-    if (Sh::R > 1 && a.accumulate)
-        for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
     static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
 
     // Columns are taken in groups of G = 16 / sizeof(T) when the launch says
@@ -166,7 +174,6 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     // the row sums read them with wide loads and each row's G results are
     // stored at once. Otherwise the columns are taken one by one.
     constexpr int G = 16 / (int)sizeof(T);
-    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     static_assert(SM::NPROD <= SM::NALL, "products must fit the buffer");
     if (a.wide) {
         for (int q0 = 0; q0 < a.k; q0 += G) {
@@ -188,72 +195,78 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                 }
             }
             wave_sync();
-            double acc[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) acc[g] = 0.0;
-            if (pair < npairs) {
-                const int li = pair / Sh::R, rho = pair % Sh::R;
-                const int bs = sm.brow[li], be = sm.brow[li + 1];
-                if (Sh::R == 1) {
-                    // the same two interleaved partial sums as the one-column path
-                    const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                    double a1[G];
+            for (int rd = 0; rd < 2; ++rd) {
+                const int pair = (lane >> lg) + 64 * rd;
+                if (rd >= rounds) break;
+                double acc[G];
 #pragma unroll
-                    for (int g = 0; g < G; ++g) a1[g] = 0.0;
-                    int k = es + l;
-                    for (; k + L < ee; k += 2 * L) {
-                        const V4 w0 = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
-                        const V4 w1 = *reinterpret_cast<const V4 *>(&sm.buf[(k + L) * G]);
-                        const T *e0 = reinterpret_cast<const T *>(&w0);
-                        const T *e1 = reinterpret_cast<const T *>(&w1);
+                for (int g = 0; g < G; ++g) acc[g] = 0.0;
+                if (pair < npairs) {
+                    const int li = pair / Sh::R, rho = pair % Sh::R;
+                    const int bs = sm.brow[li], be = sm.brow[li + 1];
+                    if (Sh::R == 1) {
+                        // the same two interleaved partial sums as the one-column path
+                        const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+                        double a1[G];
 #pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            acc[g] += (double)e0[g];
-                            a1[g] += (double)e1[g];
+                        for (int g = 0; g < G; ++g) a1[g] = 0.0;
+                        int k = es + l;
+                        for (; k + L < ee; k += 2 * L) {
+                            const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
+                            const V4 w1v = *reinterpret_cast<const V4 *>(&sm.buf[(k + L) * G]);
+                            const T *e0 = reinterpret_cast<const T *>(&w0v);
+                            const T *e1 = reinterpret_cast<const T *>(&w1v);
+#pragma unroll
+                            for (int g = 0; g < G; ++g) {
+                                acc[g] += (double)e0[g];
+                                a1[g] += (double)e1[g];
+                            }
                         }
-                    }
-                    if (k < ee) {
-                        const V4 w0 = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
-                        const T *e0 = reinterpret_cast<const T *>(&w0);
+                        if (k < ee) {
+                            const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
+                            const T *e0 = reinterpret_cast<const T *>(&w0v);
 #pragma unroll
-                        for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
-                    }
+                            for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
+                        }
 #pragma unroll
-                    for (int g = 0; g < G; ++g) acc[g] += a1[g];
-                } else {
-                    for (int b = bs + l; b < be; b += L) {
-                        const int e0 = (b + lo_slot) * Sh::RC + rho * Sh::C;
-                        V4 w[Sh::C];
+                        for (int g = 0; g < G; ++g) acc[g] += a1[g];
+                    } else {
+                        for (int b = bs + l; b < be; b += L) {
+                            const int e0 = (b + lo_slot) * Sh::RC + rho * Sh::C;
+                            V4 w[Sh::C];
 #pragma unroll
-                        for (int t = 0; t < Sh::C; ++t) w[t] = *reinterpret_cast<const V4 *>(&sm.buf[(e0 + t) * G]);
+                            for (int t = 0; t < Sh::C; ++t)
+                                w[t] = *reinterpret_cast<const V4 *>(&sm.buf[(e0 + t) * G]);
 #pragma unroll
-                        for (int t = 0; t < Sh::C; ++t) {
-                            const T *e = reinterpret_cast<const T *>(&w[t]);
+                            for (int t = 0; t < Sh::C; ++t) {
+                                const T *e = reinterpret_cast<const T *>(&w[t]);
 #pragma unroll
-                            for (int g = 0; g < G; ++g) acc[g] += (double)e[g];
+                                for (int g = 0; g < G; ++g) acc[g] += (double)e[g];
+                            }
                         }
                     }
                 }
-            }
 #pragma unroll
-            for (int g = 0; g < G; ++g)
-                for (int m = L >> 1; m >= 1; m >>= 1) acc[g] += __shfl_xor(acc[g], m, 64);
-            if (pair < npairs && l == 0) {
-                const int li = pair / Sh::R, rho = pair % Sh::R;
-                const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
-                if (row < a.n_rows) {
-                    T *yp = Y + row * a.ldy + q0;
-                    T out[G];
-                    if (a.accumulate) {
-                        const V4 old = *reinterpret_cast<const V4 *>(yp);
-                        const T *o = reinterpret_cast<const T *>(&old);
+                for (int g = 0; g < G; ++g)
+                    for (int m = L >> 1; m >= 1; m >>= 1) acc[g] += __shfl_xor(acc[g], m, 64);
+                if (pair < npairs && l == 0) {
+                    const int li = pair / Sh::R, rho = pair % Sh::R;
+                    const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+                    if (row < a.n_rows) {
+                        T *yp = Y + row * a.ldy + q0;
+                        T out[G];
+                        if (a.accumulate) {
+                            const V4 old = *reinterpret_cast<const V4 *>(yp);
+                            const T *o = reinterpret_cast<const T *>(&old);
 #pragma unroll
-                        for (int g = 0; g < G; ++g) out[g] = stored ? (T)(acc[g] + (double)o[g]) : o[g];
-                    } else {
+                            for (int g = 0; g < G; ++g) out[g] = stored[rd] ? (T)(acc[g] + (double)o[g]) : o[g];
+                        } else {
 #pragma unroll
-                        for (int g = 0; g < G; ++g) out[g] = (T)acc[g];
+                            for (int g = 0; g < G; ++g) out[g] = (T)acc[g];
+                        }
+                        *reinterpret_cast<V4 *>(yp) = *reinterpret_cast<const V4 *>(out);
                     }
-                    *reinterpret_cast<V4 *>(yp) = *reinterpret_cast<const V4 *>(out);
                 }
             }
         }
@@ -274,42 +287,47 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         wave_sync();
 
         // row sums: L lanes per (interval, block row)
-        double acc = 0.0;
         const T *__restrict__ pu = sm.buf;
-        if (pair < npairs) {
-            const int li = pair / Sh::R, rho = pair % Sh::R;
-            const int bs = sm.brow[li], be = sm.brow[li + 1];
-            if (Sh::R == 1) {
-                const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                double a0 = 0.0, a1 = 0.0;
-                int k = es + l;
-                for (; k + L < ee; k += 2 * L) {
-                    a0 += (double)pu[k];
-                    a1 += (double)pu[k + L];
-                }
-                if (k < ee) a0 += (double)pu[k];
-                acc = a0 + a1;
-            } else {
-                for (int b = bs + l; b < be; b += L) {
-                    const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                    T pr[Sh::C];
 #pragma unroll
-                    for (int t = 0; t < Sh::C; ++t) pr[t] = e[t];
+        for (int rd = 0; rd < 2; ++rd) {
+            const int pair = (lane >> lg) + 64 * rd;
+            if (rd >= rounds) break;
+            double acc = 0.0;
+            if (pair < npairs) {
+                const int li = pair / Sh::R, rho = pair % Sh::R;
+                const int bs = sm.brow[li], be = sm.brow[li + 1];
+                if (Sh::R == 1) {
+                    const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+                    double a0 = 0.0, a1 = 0.0;
+                    int k = es + l;
+                    for (; k + L < ee; k += 2 * L) {
+                        a0 += (double)pu[k];
+                        a1 += (double)pu[k + L];
+                    }
+                    if (k < ee) a0 += (double)pu[k];
+                    acc = a0 + a1;
+                } else {
+                    for (int b = bs + l; b < be; b += L) {
+                        const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
+                        T pr[Sh::C];
 #pragma unroll
-                    for (int t = 0; t < Sh::C; ++t) acc += (double)pr[t];
+                        for (int t = 0; t < Sh::C; ++t) pr[t] = e[t];
+#pragma unroll
+                        for (int t = 0; t < Sh::C; ++t) acc += (double)pr[t];
+                    }
                 }
             }
-        }
-        for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if (pair < npairs && l == 0) {
-            const int li = pair / Sh::R, rho = pair % Sh::R;
-            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
-            if (row < a.n_rows) {
-                T *yp = Y + row * a.ldy + q;
-                if (a.accumulate) {
-                    if (stored) *yp = (T)(acc + (double)*yp);
-                } else {
-                    *yp = (T)acc;
+            for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+            if (pair < npairs && l == 0) {
+                const int li = pair / Sh::R, rho = pair % Sh::R;
+                const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+                if (row < a.n_rows) {
+                    T *yp = Y + row * a.ldy + q;
+                    if (a.accumulate) {
+                        if (stored[rd]) *yp = (T)(acc + (double)*yp);
+                    } else {
+                        *yp = (T)acc;
+                    }
                 }
             }
         }

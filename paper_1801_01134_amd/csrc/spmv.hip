@@ -238,7 +238,7 @@ struct WaveSmem {
     static constexpr int NCW = NWMAX * Sh::BPW;
     static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
-    int brow[64];                                     // tile-relative interval pointers
+    int brow[128];                                    // tile-relative interval pointers
     T buf[NBUF + 64];                                 // packed values, then unpacked products
 };
 
@@ -247,7 +247,7 @@ template <class Sh, class T, int KQ>
 struct TileIn {
     using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     int colr[WaveSmem<Sh, T, KQ>::NCR];
-    int br;
+    int br[2];  // interval pointers lane and lane + 64 (a tile has up to 127 intervals)
     V4 ch[KQ];
 };
 
@@ -278,7 +278,8 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
     for (int k = 0; k < SM::NCR; ++k)
         in.colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
     const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
-    in.br = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    in.br[0] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    in.br[1] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
     const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
@@ -287,7 +288,11 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
 
 // Everything after the stream loads: metadata and values into LDS, the x
 // gathers and products, the row sums and the y stores.
-template <class Sh, class T, int KQ>
+// VFIRST: store the values to LDS before issuing the gathers (the pipelined
+// kernel, whose values were loaded a tile earlier and have arrived), which
+// frees their registers early; otherwise the gathers go first and the values,
+// loaded last, are stored while the gathers are in flight.
+template <class Sh, class T, int KQ, bool VFIRST = false>
 __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in, __amdgpu_buffer_rsrc_t xr,
                          WaveSmem<Sh, T, KQ> &sm) {
     using SM = WaveSmem<Sh, T, KQ>;
@@ -308,7 +313,8 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
     // interval pointers into LDS (lanes past the tile's intervals write what
     // the out-of-range loads returned; nothing reads them)
-    sm.brow[lane] = in.br - b0;
+    sm.brow[lane] = in.br[0] - b0;
+    sm.brow[lane + 64] = in.br[1] - b0;
     wave_sync();
 
     // 2. products, lane = mask bit, words walked on the scalar unit. All of
@@ -320,6 +326,16 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     // The last word keeps the bits of the next tile's blocks; their entries
     // are never read.
     static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
+    if (VFIRST && nw > 0) {
+#pragma unroll
+        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
+        if (q_tail < nq) {
+            if (lane < E) {
+                const int64_t g = abase + (int64_t)q_tail * E + lane;
+                if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+            }
+        }
+    }
     if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
         constexpr int NWM = SM::NWMAX;
         static_assert(NWM <= 64, "the masks array is padded for 64 words read past its end");
@@ -345,12 +361,14 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
             xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
         }
         // the values, now that the gathers are in flight
+        if (!VFIRST) {
 #pragma unroll
-        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
-        if (q_tail < nq) {
-            if (lane < E) {
-                const int64_t g = abase + (int64_t)q_tail * E + lane;
-                if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+            for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
+            if (q_tail < nq) {
+                if (lane < E) {
+                    const int64_t g = abase + (int64_t)q_tail * E + lane;
+                    if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+                }
             }
         }
         wave_sync();
@@ -371,60 +389,66 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     }
     wave_sync();
 
-    // 3. row sums: L lanes per (interval, block row), over the unpacked products
+    // 3. row sums: L lanes per (interval, block row), over the unpacked
+    // products. A tile has up to 128 pairs: with more than 64, L = 1 and a
+    // lane takes pairs lane and lane + 64.
     const int npairs = nI * Sh::R;
-    // log2 L: the largest L with npairs * L <= 64 (npairs is 1..64)
-    const int lg = npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
+    // log2 L: the largest L with npairs * L <= 64
+    const int lg = npairs > 64 ? 0 : npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
     const int L = 1 << lg;
-    const int pair = lane >> lg, l = lane & (L - 1);
-    double acc = 0.0;
-    bool stored = false;  // the row holds at least one entry (accumulate leaves other rows alone)
+    const int l = lane & (L - 1);
     const T *__restrict__ pu = sm.buf;
-    if (pair < npairs) {
-        const int li = pair / Sh::R, rho = pair % Sh::R;
-        const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
-        if (Sh::R == 1) {
-            // the row's entries are contiguous: slots bs .. be-1, C entries each
-            const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-            double a0 = 0.0, a1 = 0.0;
-            int k = es + l;
-            for (; k + L < ee; k += 2 * L) {
-                a0 += (double)pu[k];
-                a1 += (double)pu[k + L];
-            }
-            if (k < ee) a0 += (double)pu[k];
-            acc = a0 + a1;
-            stored = be > bs;  // every block holds at least one entry
-        } else {
-            for (int b = bs + l; b < be; b += L) {
-                const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                T pr[Sh::C];
-#pragma unroll
-                for (int k = 0; k < Sh::C; ++k) pr[k] = e[k];
-#pragma unroll
-                for (int k = 0; k < Sh::C; ++k) acc += (double)pr[k];
-            }
-            if (a.accumulate) {
+    for (int round = 0; round < 2; ++round) {
+        if (round == 1 && npairs <= 64) break;
+        const int pair = (lane >> lg) + 64 * round;
+        double acc = 0.0;
+        bool stored = false;  // the row holds at least one entry (accumulate leaves other rows alone)
+        if (pair < npairs) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
+            if (Sh::R == 1) {
+                // the row's entries are contiguous: slots bs .. be-1, C entries each
+                const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+                double a0 = 0.0, a1 = 0.0;
+                int k = es + l;
+                for (; k + L < ee; k += 2 * L) {
+                    a0 += (double)pu[k];
+                    a1 += (double)pu[k + L];
+                }
+                if (k < ee) a0 += (double)pu[k];
+                acc = a0 + a1;
+                stored = be > bs;  // every block holds at least one entry
+            } else {
                 for (int b = bs + l; b < be; b += L) {
-                    const unsigned g = (unsigned)(b + lo_slot);
-                    const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
-                    stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
+                    const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
+                    T pr[Sh::C];
+#pragma unroll
+                    for (int k = 0; k < Sh::C; ++k) pr[k] = e[k];
+#pragma unroll
+                    for (int k = 0; k < Sh::C; ++k) acc += (double)pr[k];
+                }
+                if (a.accumulate) {
+                    for (int b = bs + l; b < be; b += L) {
+                        const unsigned g = (unsigned)(b + lo_slot);
+                        const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
+                        stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
+                    }
                 }
             }
         }
-    }
-    for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-    if (Sh::R > 1 && a.accumulate)
-        for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
-    if (pair < npairs && l == 0) {
-        const int li = pair / Sh::R, rho = pair % Sh::R;
-        const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
-        if (row < a.n_rows) {
-            T *__restrict__ y = static_cast<T *>(a.y);
-            if (a.accumulate) {
-                if (stored) y[row] = (T)(acc + (double)y[row]);
-            } else {
-                y[row] = (T)acc;
+        for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+        if (Sh::R > 1 && a.accumulate)
+            for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
+        if (pair < npairs && l == 0) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+            if (row < a.n_rows) {
+                T *__restrict__ y = static_cast<T *>(a.y);
+                if (a.accumulate) {
+                    if (stored) y[row] = (T)(acc + (double)y[row]);
+                } else {
+                    y[row] = (T)acc;
+                }
             }
         }
     }
@@ -795,7 +819,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
             if (!lngn) tile_issue<Sh, T, KQ>(a, dn, nxt);
         }
         if (lng) wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
-        else tile_run<Sh, T, KQ>(a, d, cur, xr, sm[wid]);
+        else tile_run<Sh, T, KQ, true>(a, d, cur, xr, sm[wid]);
         if (!more) break;
         wave_sync();  // this tile's LDS reads are done before the next tile writes
         t = tn;
@@ -906,8 +930,9 @@ spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out) {
     });
 }
 
-// Mode 0 loads a tile's interval pointers one per lane, the end pointer included.
-int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? (r == 1 ? 63 : 64 / r) : kThreads / r; }
+// Mode 0 loads a tile's interval pointers two per lane (up to 128, the end pointer
+// included) and takes up to 128 (interval, block row) pairs, two per lane.
+int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? (r == 1 ? 127 : 128 / r) : kThreads / r; }
 
 // Tile capacity in mask bits for a mode and a chunk count (mode 0) or the
 // workgroup tile size (mode 1).

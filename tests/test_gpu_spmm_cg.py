@@ -115,11 +115,17 @@ def test_spmm_grouped_columns_strided(rc, dtype):
     tol = TOL[dtype] * (S_ref + np.abs(Y0[:, 4:4 + k]))
     assert np.all(np.abs(got[:, 4:4 + k] - want[:, 4:4 + k]) <= tol)
     assert np.array_equal(got[:, :4], Y0[:, :4].astype(np.float64))
-    # column by column (k = 1 takes the ungrouped path): the same bits
+    # column by column through the one-column path (a strided view of X, so
+    # not the single-vector kernel, which sums long rows in its own order):
+    # the same bits as the grouped pass
     Yg = spc.spmm(B, X.contiguous())
     for q in range(k):
-        yq = spc.spmm(B, X[:, q:q + 1].contiguous())
+        yq = spc.spmm(B, X[:, q:q + 1])
         assert torch.equal(yq[:, 0], Yg[:, q]), q
+    # a contiguous single column runs the single-vector kernel: same values
+    # within the tolerance
+    y1 = spc.spmm(B, X[:, :1].contiguous())[:, 0].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(y1 - Y_ref[:, 0]) <= TOL[dtype] * S_ref[:, 0])
 
 
 def _spd(m):
