@@ -64,6 +64,11 @@ class CSR:
         return np.diff(self.rowptr)
 
 
+def from_keys_sorted(n_rows: int, n_cols: int, rows, cols, seed: int) -> CSR:
+    """CSR of the given (row, col) pairs (deduplicated and sorted), values U[-1, 1]."""
+    return _from_keys(n_rows, n_cols, np.asarray(rows), np.asarray(cols), rng_for(10, n_rows, seed))
+
+
 def _from_keys(n_rows: int, n_cols: int, rows: np.ndarray, cols: np.ndarray,
                rng: np.random.Generator, low=-1.0, high=1.0) -> CSR:
     """Deduplicate (row, col) pairs, sort them row-major and draw values."""

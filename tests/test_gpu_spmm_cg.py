@@ -39,6 +39,8 @@ CASES = {
     "dense_rows": _dense_rows,
     "fem6": lambda: synth.fem_blocks(200, 6, 5.0, 10, seed=3),
     "tall": lambda: synth.uniform_random(9000, 37, 3.0, seed=9),
+    # one entry per row: tiles at their cap of 127 intervals / 128 pairs
+    "diagonal": lambda: synth.from_keys_sorted(6007, 6007, np.arange(6007), np.arange(6007), 11),
 }
 _cache = {}
 

@@ -67,6 +67,13 @@ CASES = {
     "tiny1x1": lambda: synth.from_dense(np.array([[2.5]])),
     "tiny3x5": lambda: synth.random_small(3, 5, 0.6, seed=10),
     "all_empty": lambda: synth.CSR(10, 10, np.zeros(11, np.int64), np.zeros(0, np.int32), np.zeros(0)),
+    # one entry per row: tiles reach their cap of (interval, block row) pairs
+    # (127 intervals for r = 1, 128 pairs otherwise), so every lane takes two
+    "diagonal": lambda: synth.from_keys_sorted(6007, 6007, np.arange(6007), np.arange(6007), 11),
+    # two entries per row, 8 columns apart: one value per beta(1,8) block
+    "two_per_row": lambda: synth.from_keys_sorted(
+        5003, 5003, np.repeat(np.arange(5003), 2),
+        np.stack([np.arange(5003), (np.arange(5003) + 8) % 5003], axis=1).reshape(-1), 12),
 }
 
 _cache = {}
