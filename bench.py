@@ -284,7 +284,7 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
             X = torch.from_numpy(synth.dense_block(A.n_cols, k, 702)).to(dev).to(dt)
             best = None
             for rc, Bc in Bs.items():
-                for kq in (2, 4, 8):
+                for kq in (2, 4, 6, 8):
                     Pc = Bc.plan(0, 0, 0, kq)
                     t = event_time(torch, lambda: spc.spmm(Bc, X, plan=Pc), 10, 2)
                     if best is None or t < best[0]:

@@ -152,7 +152,7 @@ typedef struct spc_plan_params {
     int32_t tile_bits;
     int32_t xcd_remap;
     int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles */
-    int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4 or 8; 0 = 4 */
+    int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4, 6 or 8; 0 = 4 */
     int32_t pipeline;       /* mode 0: 0 = one wavefront per tile; 1 = persistent wavefronts (as
                                many workgroups as fit on the device) that load their next tile
                                while working on the current one; N > 1 = the same with at most N
@@ -223,7 +223,7 @@ spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k,
  *   on `stream` (microseconds, host *us_out). Synchronizes.
  *
  * spc_autotune: builds a plan for every candidate parameter set (both
- *   modes; mode 0 with 2, 4 and 8 chunks per lane, one wavefront per tile or
+ *   modes; mode 0 with 2, 4, 6 and 8 chunks per lane, one wavefront per tile or
  *   pipelined; mode 1 with 1024, 2048, 3072 and 4032 tile bits; each with
  *   and without XCD remapping where the grid order applies), times it
  *   with spc_time_spmv and returns the fastest set in *best and its time in

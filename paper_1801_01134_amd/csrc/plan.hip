@@ -85,7 +85,8 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     const int pipeline = params ? params->pipeline : 0;
     SPC_REQUIRE(pipeline >= 0, SPC_ERR_INVALID_ARG, "pipeline must be >= 0");
     SPC_REQUIRE(!(pipeline && mode != 0), SPC_ERR_INVALID_ARG, "pipeline applies to mode 0 only");
-    SPC_REQUIRE(kq == 2 || kq == 4 || kq == 8, SPC_ERR_INVALID_ARG, "wave_chunks must be 2, 4 or 8");
+    SPC_REQUIRE(kq == 2 || kq == 4 || kq == 6 || kq == 8, SPC_ERR_INVALID_ARG,
+                "wave_chunks must be 2, 4, 6 or 8");
     SPC_REQUIRE(tile_bits == 1024 || tile_bits == 2048 || tile_bits == 3072 || tile_bits == 4032,
                 SPC_ERR_INVALID_ARG, "tile_bits must be 1024, 2048, 3072 or 4032 (got %d)", tile_bits);
     const int shape = shape_of(A->r, A->c);

@@ -424,6 +424,7 @@ template <int R, int C, class T>
 spc_status launch(int kq, dim3 grid, const SpmmArgs &a, hipStream_t s) {
     switch (kq) {
     case 2: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 2>), grid, dim3(kThreads), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 6>), grid, dim3(kThreads), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 8>), grid, dim3(kThreads), 0, s, a); break;
     default: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 4>), grid, dim3(kThreads), 0, s, a); break;
     }

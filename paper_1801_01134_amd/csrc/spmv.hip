@@ -769,6 +769,10 @@ void launch_batched_fixed_p(int kq, unsigned grid, const BatchMat *d_mats, const
         hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 2, P>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
                            d_tiles, n_tiles, accumulate);
         break;
+    case 6:
+        hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 6, P>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
+                           d_tiles, n_tiles, accumulate);
+        break;
     case 8:
         hipLaunchKernelGGL((k_spmv_batched_fixed<S, T, 8, P>), dim3(grid), dim3(kThreads), 0, stream, d_mats,
                            d_tiles, n_tiles, accumulate);
@@ -845,6 +849,7 @@ template <int R, int C, class T>
 spc_status launch_wave_pipe(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (kq) {
     case 2: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 2>), grid, dim3(kThreads), 0, stream, a); break;
+    case 6: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 6>), grid, dim3(kThreads), 0, stream, a); break;
     case 8: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 8>), grid, dim3(kThreads), 0, stream, a); break;
     default: hipLaunchKernelGGL((k_spmv_wave_pipe<R, C, T, 4>), grid, dim3(kThreads), 0, stream, a); break;
     }
@@ -856,6 +861,7 @@ spc_status launch_wave_pipe(int kq, dim3 grid, const SpmvArgs &a, hipStream_t st
 template <int R, int C, class T>
 spc_status resident_groups(int kq, int *out) {
     const void *f = kq == 2   ? reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 2>)
+                    : kq == 6 ? reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 6>)
                     : kq == 8 ? reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 8>)
                               : reinterpret_cast<const void *>(k_spmv_wave_pipe<R, C, T, 4>);
     int per_cu = 0, dev = 0, cus = 0;
@@ -870,6 +876,7 @@ template <int R, int C, class T>
 spc_status launch_wave(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (kq) {
     case 2: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 2>), grid, dim3(kThreads), 0, stream, a); break;
+    case 6: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 6>), grid, dim3(kThreads), 0, stream, a); break;
     case 8: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 8>), grid, dim3(kThreads), 0, stream, a); break;
     default: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 4>), grid, dim3(kThreads), 0, stream, a); break;
     }
@@ -912,6 +919,7 @@ spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileD
         };
         switch (kq) {
         case 2: go(std::integral_constant<int, 2>{}); break;
+        case 6: go(std::integral_constant<int, 6>{}); break;
         case 8: go(std::integral_constant<int, 8>{}); break;
         default: go(std::integral_constant<int, 4>{}); break;
         }

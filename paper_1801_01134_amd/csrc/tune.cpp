@@ -45,7 +45,7 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
     if (n_records) *n_records = 0;
     std::vector<spc_plan_params> cands;
     for (int remap : {0, 2}) {
-        for (int kq : {2, 4, 8}) {
+        for (int kq : {2, 4, 6, 8}) {
             spc_plan_params p{};
             p.mode = 0;
             p.wave_chunks = kq;

@@ -68,7 +68,7 @@ def build(dtype):
     return Bs, xs, ys, refs
 
 
-@pytest.mark.parametrize("kq", [2, 4, 8])
+@pytest.mark.parametrize("kq", [2, 4, 6, 8])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_batched_matches_oracle_and_single_launches(dtype, kq):
     say(f"[batched] {dtype} kq={kq}")

@@ -67,8 +67,8 @@ def test_stencil128_all_rows_all_plans(rc, dtype):
     assert B.n_blocks == int(oracle.beta_count(A, r, c).sum())
     x = torch.from_numpy(S["x"]).cuda().to(dtype)
     ref = S["ref64"] if dtype == torch.float64 else S["ref32"]
-    plans = [dict(mode=0, wave_chunks=q, xcd_remap=xr, pipeline=0) for q in (2, 4, 8) for xr in (0, 2)]
-    plans += [dict(mode=0, wave_chunks=q, pipeline=1) for q in (2, 4, 8)]
+    plans = [dict(mode=0, wave_chunks=q, xcd_remap=xr, pipeline=0) for q in (2, 4, 6, 8) for xr in (0, 2)]
+    plans += [dict(mode=0, wave_chunks=q, pipeline=1) for q in (2, 4, 6, 8)]
     plans += [dict(mode=1, tile_bits=tb, xcd_remap=xr) for tb in (1024, 4032) for xr in (0, 2)]
     first = None
     for p in plans:

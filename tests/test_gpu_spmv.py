@@ -144,7 +144,7 @@ def test_spmv_parity(name, rc, dtype):
 
 @pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
 @pytest.mark.parametrize("mode,tile_bits,chunks,remap", [
-    (0, 0, 2, 0), (0, 0, 4, 2), (0, 0, 8, 1),
+    (0, 0, 2, 0), (0, 0, 4, 2), (0, 0, 6, 0), (0, 0, 8, 1),
     (1, 1024, 0, 0), (1, 2048, 0, 2), (1, 3072, 0, 0), (1, 4032, 0, 1)])
 @pytest.mark.parametrize("name", ["powerlaw", "stencil13", "fem6", "dense_rows", "empty_rows"])
 def test_plan_variants_and_determinism(rc, mode, tile_bits, chunks, remap, name):
@@ -268,7 +268,7 @@ def test_empty_matrix_with_null_masks_pointer():
 
 @pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("chunks", [2, 4, 8])
+@pytest.mark.parametrize("chunks", [2, 4, 6, 8])
 @pytest.mark.parametrize("grid", [1, 3, 40])
 def test_pipelined_equals_one_tile_per_wave(rc, dtype, chunks, grid):
     """Persistent wavefronts that prefetch their next tile (capped at `grid`
