@@ -242,6 +242,130 @@ struct WaveSmem {
     T buf[NBUF + 64];                                 // packed values, then unpacked products
 };
 
+// Row results of a tile held back for storing later: byte offsets into y
+// (0xffffffff: nothing) and values, one per round of tile_sums.
+template <class T>
+struct YOut {
+    uint32_t off[2];
+    T val[2];
+};
+
+// 3. Row sums of a wavefront tile whose products sit unpacked in s_buf
+// (entry 64 j + l = bit l of the tile's word j) and whose tile-relative
+// interval pointers sit in s_brow. With DEFER (and y = A x), the results go
+// to *out instead of y; the caller stores them.
+template <class Sh, class T, bool DEFER = false>
+__device__ __forceinline__ void tile_sums(const SpmvArgs &a, const TileDesc &d, int lo_slot, int w0,
+                                          const int *s_brow, const T *s_buf, YOut<T> *out = nullptr) {
+    const int lane = threadIdx.x & 63;
+    const int nI = d.i1 - d.i0;
+    // L lanes per (interval, block row) add its unpacked products. A tile
+    // has up to 128 pairs: with more than 64, L = 1 and a lane takes pairs
+    // lane and lane + 64.
+    const int npairs = nI * Sh::R;
+    // log2 L: the largest L with npairs * L <= 64
+    const int lg = npairs > 64 ? 0 : npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
+    const int L = 1 << lg;
+    const int l = lane & (L - 1);
+    const T *__restrict__ pu = s_buf;
+    if (DEFER) out->off[0] = out->off[1] = 0xffffffffu;
+    for (int round = 0; round < 2; ++round) {
+        if (round == 1 && npairs <= 64) break;
+        const int pair = (lane >> lg) + 64 * round;
+        double acc = 0.0;
+        bool stored = false;  // the row holds at least one entry (accumulate leaves other rows alone)
+        if (pair < npairs) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int bs = s_brow[li], be = s_brow[li + 1];   // tile-relative blocks
+            if (Sh::R == 1) {
+                // the row's entries are contiguous: slots bs .. be-1, C entries each
+                const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
+                double a0 = 0.0, a1 = 0.0;
+                int k = es + l;
+                for (; k + L < ee; k += 2 * L) {
+                    a0 += (double)pu[k];
+                    a1 += (double)pu[k + L];
+                }
+                if (k < ee) a0 += (double)pu[k];
+                acc = a0 + a1;
+                stored = be > bs;  // every block holds at least one entry
+            } else {
+                // two blocks per step, so their reads share one LDS round trip
+                double a0 = 0.0, a1 = 0.0;
+                int b = bs + l;
+                for (; b + L < be; b += 2 * L) {
+                    const T *__restrict__ e0 = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
+                    const T *__restrict__ e1 = e0 + L * Sh::RC;
+                    T p0[Sh::C], p1[Sh::C];
+#pragma unroll
+                    for (int k = 0; k < Sh::C; ++k) {
+                        p0[k] = e0[k];
+                        p1[k] = e1[k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < Sh::C; ++k) {
+                        a0 += (double)p0[k];
+                        a1 += (double)p1[k];
+                    }
+                }
+                if (b < be) {
+                    const T *__restrict__ e0 = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
+                    T p0[Sh::C];
+#pragma unroll
+                    for (int k = 0; k < Sh::C; ++k) p0[k] = e0[k];
+#pragma unroll
+                    for (int k = 0; k < Sh::C; ++k) a0 += (double)p0[k];
+                }
+                acc = a0 + a1;
+                if (a.accumulate) {
+                    for (int b = bs + l; b < be; b += L) {
+                        const unsigned g = (unsigned)(b + lo_slot);
+                        const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
+                        stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
+                    }
+                }
+            }
+        }
+        acc = group_sum(acc, lg);
+        if (Sh::R > 1 && a.accumulate)
+            for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
+        if (DEFER && !a.accumulate) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+            const bool mine = pair < npairs && l == 0 && row < a.n_rows;
+            out->off[round] = mine ? (uint32_t)row * (uint32_t)sizeof(T) : 0xffffffffu;
+            out->val[round] = (T)acc;
+        } else if (pair < npairs && l == 0) {
+            const int li = pair / Sh::R, rho = pair % Sh::R;
+            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
+            if (row < a.n_rows) {
+                T *__restrict__ y = static_cast<T *>(a.y);
+                if (a.accumulate) {
+                    if (stored) y[row] = (T)(acc + (double)y[row]);
+                } else {
+                    y[row] = (T)acc;
+                }
+            }
+        }
+    }
+}
+
+// Stores held-back row results: always two buffer stores (an offset past
+// the end stores nothing), so the count of memory operations in flight does
+// not depend on the data.
+template <class T>
+__device__ __forceinline__ void y_flush(__amdgpu_buffer_rsrc_t yr, const YOut<T> &o) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(
+                __builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, (double)o.val[k]), yr, o.off[k], 0,
+                0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, (float)o.val[k]), yr, o.off[k], 0, 0);
+    }
+}
+
 // Registers holding one tile's streams while their loads are in flight.
 template <class Sh, class T, int KQ>
 struct TileIn {
@@ -288,11 +412,7 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
 
 // Everything after the stream loads: metadata and values into LDS, the x
 // gathers and products, the row sums and the y stores.
-// VFIRST: store the values to LDS before issuing the gathers (the pipelined
-// kernel, whose values were loaded a tile earlier and have arrived), which
-// frees their registers early; otherwise the gathers go first and the values,
-// loaded last, are stored while the gathers are in flight.
-template <class Sh, class T, int KQ, bool VFIRST = false>
+template <class Sh, class T, int KQ>
 __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in, __amdgpu_buffer_rsrc_t xr,
                          WaveSmem<Sh, T, KQ> &sm) {
     using SM = WaveSmem<Sh, T, KQ>;
@@ -300,7 +420,7 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
-    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv;
     const int64_t abase = d.vbase & ~(int64_t)(E - 1);
     const int shift = (int)(d.vbase - abase);
     const int nq = (shift + nv + E - 1) / E;          // chunks holding the tile's values
@@ -326,16 +446,6 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     // The last word keeps the bits of the next tile's blocks; their entries
     // are never read.
     static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
-    if (VFIRST && nw > 0) {
-#pragma unroll
-        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
-        if (q_tail < nq) {
-            if (lane < E) {
-                const int64_t g = abase + (int64_t)q_tail * E + lane;
-                if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
-            }
-        }
-    }
     if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
         constexpr int NWM = SM::NWMAX;
         static_assert(NWM <= 64, "the masks array is padded for 64 words read past its end");
@@ -361,14 +471,12 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
             xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
         }
         // the values, now that the gathers are in flight
-        if (!VFIRST) {
 #pragma unroll
-            for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
-            if (q_tail < nq) {
-                if (lane < E) {
-                    const int64_t g = abase + (int64_t)q_tail * E + lane;
-                    if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
-                }
+        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
+        if (q_tail < nq) {
+            if (lane < E) {
+                const int64_t g = abase + (int64_t)q_tail * E + lane;
+                if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
             }
         }
         wave_sync();
@@ -388,70 +496,7 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
             if (j < nw) pu[64 * j] = pick(M[j], pv[j] * xv[j], T(0));
     }
     wave_sync();
-
-    // 3. row sums: L lanes per (interval, block row), over the unpacked
-    // products. A tile has up to 128 pairs: with more than 64, L = 1 and a
-    // lane takes pairs lane and lane + 64.
-    const int npairs = nI * Sh::R;
-    // log2 L: the largest L with npairs * L <= 64
-    const int lg = npairs > 64 ? 0 : npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
-    const int L = 1 << lg;
-    const int l = lane & (L - 1);
-    const T *__restrict__ pu = sm.buf;
-    for (int round = 0; round < 2; ++round) {
-        if (round == 1 && npairs <= 64) break;
-        const int pair = (lane >> lg) + 64 * round;
-        double acc = 0.0;
-        bool stored = false;  // the row holds at least one entry (accumulate leaves other rows alone)
-        if (pair < npairs) {
-            const int li = pair / Sh::R, rho = pair % Sh::R;
-            const int bs = sm.brow[li], be = sm.brow[li + 1];   // tile-relative blocks
-            if (Sh::R == 1) {
-                // the row's entries are contiguous: slots bs .. be-1, C entries each
-                const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                double a0 = 0.0, a1 = 0.0;
-                int k = es + l;
-                for (; k + L < ee; k += 2 * L) {
-                    a0 += (double)pu[k];
-                    a1 += (double)pu[k + L];
-                }
-                if (k < ee) a0 += (double)pu[k];
-                acc = a0 + a1;
-                stored = be > bs;  // every block holds at least one entry
-            } else {
-                for (int b = bs + l; b < be; b += L) {
-                    const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                    T pr[Sh::C];
-#pragma unroll
-                    for (int k = 0; k < Sh::C; ++k) pr[k] = e[k];
-#pragma unroll
-                    for (int k = 0; k < Sh::C; ++k) acc += (double)pr[k];
-                }
-                if (a.accumulate) {
-                    for (int b = bs + l; b < be; b += L) {
-                        const unsigned g = (unsigned)(b + lo_slot);
-                        const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
-                        stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
-                    }
-                }
-            }
-        }
-        for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if (Sh::R > 1 && a.accumulate)
-            for (int m = L >> 1; m >= 1; m >>= 1) stored = __shfl_xor((int)stored, m, 64) || stored;
-        if (pair < npairs && l == 0) {
-            const int li = pair / Sh::R, rho = pair % Sh::R;
-            const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
-            if (row < a.n_rows) {
-                T *__restrict__ y = static_cast<T *>(a.y);
-                if (a.accumulate) {
-                    if (stored) y[row] = (T)(acc + (double)y[row]);
-                } else {
-                    y[row] = (T)acc;
-                }
-            }
-        }
-    }
+    tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, sm.buf);
 }
 
 template <class Sh, class T, int KQ>
@@ -792,44 +837,224 @@ void launch_batched_fixed(int kq, unsigned grid, bool persist, const BatchMat *d
 }
 
 // Mode 0, pipelined: a persistent grid; each wavefront walks the tiles
-// t, t + S, t + 2S, ... (S = 4 x grid) and issues the next tile's stream
-// loads before it works on the current one, so the next tile's memory
-// latency overlaps the current tile's gathers and sums. Vector loads
-// complete in issue order, so waiting for the current tile's data does not
-// wait for the next tile's.
+// t, t + S, t + 2S, ... (S = 4 x grid). The packed values travel from memory
+// straight into LDS (buffer loads with the LDS destination), into one of two
+// buffers per wavefront, so a tile's values can be in flight while the
+// previous tile is computed without holding any registers. Per tile:
+//   wait for everything issued so far (this tile's streams, loaded during
+//   the previous tile); issue this tile's x gathers; issue the next tile's
+//   streams (block columns, interval pointers, mask words, the descriptor
+//   after it) and its values into the other buffer; compute this tile.
+// Vector memory operations complete in issue order, so waiting for the
+// gathers does not wait for the next tile's streams.
+template <class Sh, class T, int KQ>
+struct PipeSmem {
+    static constexpr int NBUF = WaveSmem<Sh, T, KQ>::NBUF;
+    int brow[128];
+    T buf[2][NBUF + 64];
+};
+
+template <class Sh, class T, int KQ>
+struct TileNext {
+    int colr[WaveSmem<Sh, T, KQ>::NCR];
+    int br[2];
+    uint64_t m;  // lane j: the tile's mask word j (0 past the tile's words)
+};
+
+// s_waitcnt with one counter at zero and the others left alone (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8). The builtin
+// lets the compiler's own wait insertion see the wait; the empty asm keeps
+// memory accesses from moving across it.
+__device__ __forceinline__ void wait_vm_all() {
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void wait_lds_all() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    asm volatile("" ::: "memory");
+}
+
+// Lanes 0..7 load the eight dwords of descriptor t.
+__device__ __forceinline__ int desc_lane(const SpmvArgs &a, int t) {
+    const int lane = threadIdx.x & 63;
+    const auto r = rsrc(a.tiles, (uint32_t)a.n_tiles * (uint32_t)sizeof(TileDesc));
+    const uint32_t off = lane < 8 ? (uint32_t)t * (uint32_t)sizeof(TileDesc) + 4u * (uint32_t)lane : 0xffffffffu;
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+__device__ __forceinline__ TileDesc desc_from_lanes(int v) {
+    TileDesc d;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(v, 0), hi = (uint32_t)__builtin_amdgcn_readlane(v, 1);
+    d.vbase = (int64_t)(((uint64_t)hi << 32) | lo);
+    d.i0 = __builtin_amdgcn_readlane(v, 2);
+    d.i1 = __builtin_amdgcn_readlane(v, 3);
+    d.b0 = __builtin_amdgcn_readlane(v, 4);
+    d.b1 = __builtin_amdgcn_readlane(v, 5);
+    d.nv = __builtin_amdgcn_readlane(v, 6);
+    d.reserved = __builtin_amdgcn_readlane(v, 7);
+    return d;
+}
+
+// Issues a tile's streams: registers for the small ones, LDS (s_vals) for
+// the packed values. All loads are unguarded buffer loads. With on = false
+// the same loads are issued with empty ranges (they return zeros and touch no
+// memory), so the number of memory operations in flight does not depend on
+// a branch and the waits for earlier loads stay exact.
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void tile_issue_lds(const SpmvArgs &a, const TileDesc &d, TileNext<Sh, T, KQ> &in,
+                                               T *s_vals, bool on) {
+    using SM = WaveSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    const int cs0 = w0 * Sh::BPW;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
+    const auto cr = rsrc(a.bcol + cs0, on ? (uint32_t)ncs * 4u : 0u);
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k)
+        in.colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, on ? (uint32_t)(nI + 1) * 4u : 0u);
+    in.br[0] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    in.br[1] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
+    const auto mr = rsrc(a.mw + w0, on ? (uint32_t)nw * 8u : 0u);
+    in.m = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mr, (uint32_t)(lane * 8), 0, kNT));
+    const auto vr = rsrc(vals + abase, on ? (uint32_t)q_tail * 16u : 0u);
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            vr, (__attribute__((address_space(3))) void *)(s_vals + 64 * k * E), 16, (uint32_t)(lane * 16), 1024 * k,
+            0, kNT);
+}
+
+// The compute of a tile whose values are in s_vals (chunk order). prefetch()
+// issues the next tile's loads; it runs after this tile's gathers.
+template <class Sh, class T, int KQ, class F>
+__device__ __forceinline__ void tile_run_lds(const SpmvArgs &a, const TileDesc &d, const TileNext<Sh, T, KQ> &in,
+                                             __amdgpu_buffer_rsrc_t xr, int *s_brow, T *s_vals, F &&prefetch,
+                                             YOut<T> *out) {
+    using SM = WaveSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    const int lo_slot = b0 - w0 * Sh::BPW;
+    const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
+    s_brow[lane] = in.br[0] - b0;
+    s_brow[lane + 64] = in.br[1] - b0;
+    // the array's last chunk may reach past nnz: its values are read one by
+    // one (after the chunk loads have landed, which wrote zeros there)
+    if (q_tail < nq && lane < E) {
+        const int64_t g = abase + (int64_t)q_tail * E + lane;
+        if (g < a.nnz) s_vals[q_tail * E + lane] = vals[g];
+    }
+    if (nw > 0) {
+        constexpr int NWM = SM::NWMAX;
+        const int slot = lane / Sh::RC;
+        const int kcol = (lane % Sh::RC) % Sh::C;
+        uint64_t M[NWM];
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            const uint64_t m = readlane64(in.m, j);
+            M[j] = j == 0 ? (m & lo_mask) : m;
+        }
+        T xv[NWM];
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            const int src = ((j * Sh::BPW) % 64 + slot) * 4;
+            const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
+            xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+        }
+        prefetch();
+        wave_sync();
+        const char *__restrict__ bb = reinterpret_cast<const char *>(s_vals);
+        T pv[NWM];
+        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            pv[j] = *reinterpret_cast<const T *>(bb + lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte);
+            vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
+        }
+        wave_sync();  // all values are read before the products overwrite them
+        T *__restrict__ pu = s_vals + lane;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+            if (j < nw) pu[64 * j] = pick(M[j], pv[j] * xv[j], T(0));
+    } else {
+        prefetch();
+    }
+    wave_sync();
+    tile_sums<Sh, T, true>(a, d, lo_slot, w0, s_brow, s_vals, out);
+}
+
 template <int R, int C, class T, int KQ>
 __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
     using Sh = Shape<R, C>;
     using SM = WaveSmem<Sh, T, KQ>;
-    __shared__ SM sm[kWaves];
+    __shared__ PipeSmem<Sh, T, KQ> sm[kWaves];
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int stride = (int)gridDim.x * kWaves;
     int t = (int)blockIdx.x * kWaves + wid;
     if (t >= a.n_tiles) return;
     const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+    PipeSmem<Sh, T, KQ> &S = sm[wid];
     TileDesc d = a.tiles[t];
     bool lng = d.b1 - d.b0 > SM::NB;
-    TileIn<Sh, T, KQ> cur;
-    if (!lng) tile_issue<Sh, T, KQ>(a, d, cur);
+    TileNext<Sh, T, KQ> cur;
+    tile_issue_lds<Sh, T, KQ>(a, d, cur, S.buf[0], !lng);
+    int dn_raw = desc_lane(a, t + stride);   // all lanes 0 past the last tile
+    int p = 0;
+    // A tile's row results are stored after the next tile's loads have been
+    // issued, so that the wait for those loads does not also wait for the
+    // stores (memory operations are counted together, in issue order).
+    const auto yr = rsrc(a.y, (uint32_t)a.n_rows * (uint32_t)sizeof(T));
+    YOut<T> pend;
+    pend.off[0] = pend.off[1] = 0xffffffffu;
+    pend.val[0] = pend.val[1] = T(0);
     while (true) {
+        wait_vm_all();  // this tile's streams and the next descriptor have landed
         const int tn = t + stride;
         const bool more = tn < a.n_tiles;
-        TileDesc dn = d;
-        bool lngn = true;
-        TileIn<Sh, T, KQ> nxt;
-        if (more) {
-            dn = a.tiles[tn];
-            lngn = dn.b1 - dn.b0 > SM::NB;
-            if (!lngn) tile_issue<Sh, T, KQ>(a, dn, nxt);
+        const TileDesc dn = desc_from_lanes(dn_raw);
+        const bool lngn = dn.b1 - dn.b0 > SM::NB;
+        TileNext<Sh, T, KQ> nxt;
+        int dnn_raw = 0;
+        auto prefetch = [&]() {
+            wait_lds_all();  // reads of the other buffer (two tiles back) are complete
+            tile_issue_lds<Sh, T, KQ>(a, dn, nxt, S.buf[p ^ 1], more && !lngn);
+            dnn_raw = desc_lane(a, tn + stride);
+            y_flush(yr, pend);  // the previous tile's rows
+        };
+        if (lng) {
+            wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+            prefetch();
+            pend.off[0] = pend.off[1] = 0xffffffffu;
+        } else {
+            tile_run_lds<Sh, T, KQ>(a, d, cur, xr, S.brow, S.buf[p], prefetch, &pend);
         }
-        if (lng) wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
-        else tile_run<Sh, T, KQ, true>(a, d, cur, xr, sm[wid]);
-        if (!more) break;
+        if (!more) {
+            y_flush(yr, pend);
+            break;
+        }
         wave_sync();  // this tile's LDS reads are done before the next tile writes
         t = tn;
         d = dn;
         lng = lngn;
         cur = nxt;
+        dn_raw = dnn_raw;
+        p ^= 1;
     }
 }
 
@@ -978,7 +1203,10 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     const int64_t groups = wave ? div_up(P->n_tiles, kWaves) : P->n_tiles;
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
     dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)groups);
-    const bool pipe = wave && P->pipeline && P->resident > 0;
+    // the pipelined kernel reads descriptors with 32-bit byte offsets
+    // and addresses y with 32-bit byte offsets
+    const bool pipe = wave && P->pipeline && P->resident > 0 && P->n_tiles < ((int64_t)1 << 27) &&
+                      (uint64_t)A->n_rows * es < 0xf0000000ull;
     if (pipe) grid = dim3((unsigned)(groups < P->resident ? groups : (int64_t)P->resident));
     return with_shape(P->shape, [&](auto sh) {
         using Sh = decltype(sh);

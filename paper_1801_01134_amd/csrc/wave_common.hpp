@@ -47,6 +47,31 @@ __device__ __forceinline__ int wave_scan_dpp(int v) {
     return v;
 }
 
+// A double moved across lanes by a DPP pattern (both halves); every source
+// lane must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over aligned groups of 2^lg lanes (lg uniform, 0..6); every lane of a
+// group gets the group's total. Within a 16-lane row the partners come from
+// DPP patterns (xor 1, xor 2, the mirrored lane in the 8-lane half, the
+// mirrored lane in the row), which stay in the vector unit; wider groups
+// finish with cross-row shuffles. The order of additions is fixed.
+__device__ __forceinline__ double group_sum(double v, int lg) {
+    if (lg >= 1) v += dpp_f64<0xb1>(v);   // quad_perm [1,0,3,2]
+    if (lg >= 2) v += dpp_f64<0x4e>(v);   // quad_perm [2,3,0,1]
+    if (lg >= 3) v += dpp_f64<0x141>(v);  // row_half_mirror
+    if (lg >= 4) v += dpp_f64<0x140>(v);  // row_mirror
+    if (lg >= 5) v += __shfl_xor(v, 16, 64);
+    if (lg >= 6) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
 // Lane-select from a 64-bit uniform mask without touching the exec mask.
 template <class V>
 __device__ __forceinline__ V pick(uint64_t m, V if_set, V if_clear) {
