@@ -366,21 +366,21 @@ __device__ __forceinline__ void y_flush(__amdgpu_buffer_rsrc_t yr, const YOut<T>
     }
 }
 
-// Registers holding one tile's streams while their loads are in flight.
+// Registers holding one tile's small streams while their loads are in
+// flight (the packed values go straight to LDS).
 template <class Sh, class T, int KQ>
 struct TileIn {
-    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     int colr[WaveSmem<Sh, T, KQ>::NCR];
-    int br[2];  // interval pointers lane and lane + 64 (a tile has up to 127 intervals)
-    V4 ch[KQ];
+    int br[2];   // interval pointers lane and lane + 64 (a tile has up to 127 intervals)
+    uint64_t m;  // lane j: the tile's mask word j (0 past the tile's words)
 };
 
-// Issues every stream of a tile as unguarded buffer loads: first the small
-// ones the x gathers depend on (block columns, interval pointers, mask
-// words), then the packed values, which are needed only after the gathers
-// have been issued (loads complete in issue order).
+// Issues every stream of a tile as unguarded buffer loads: the block
+// columns and interval pointers into registers, then the packed values into
+// LDS (s_vals, chunk k of lane l at 16 (64 k + l) bytes).
 template <class Sh, class T, int KQ>
-__device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in) {
+__device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in,
+                                           T *s_vals) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
     const int lane = threadIdx.x & 63;
@@ -404,20 +404,23 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
     const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
     in.br[0] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
     in.br[1] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
+    const auto mr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
+    in.m = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mr, (uint32_t)(lane * 8), 0, kNT));
     const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
-        in.ch[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            vr, (__attribute__((address_space(3))) void *)(s_vals + 64 * k * E), 16, (uint32_t)(lane * 16), 1024 * k,
+            0, kNT);
 }
 
-// Everything after the stream loads: metadata and values into LDS, the x
-// gathers and products, the row sums and the y stores.
+// Everything after the stream loads: the x gathers and products, the row
+// sums and the y stores.
 template <class Sh, class T, int KQ>
 __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in, __amdgpu_buffer_rsrc_t xr,
                          WaveSmem<Sh, T, KQ> &sm) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
-    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
     const int lane = threadIdx.x & 63;
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
     const int b0 = d.b0, b1 = d.b1, nv = d.nv;
@@ -429,71 +432,56 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     const int w0 = b0 / Sh::BPW;
     const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
     const int lo_slot = b0 - w0 * Sh::BPW;                  // slots of word 0 before the tile
-    const int end_bit = (b1 - w0 * Sh::BPW) * Sh::RC;       // first bit after the tile, from word 0
     const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
     // interval pointers into LDS (lanes past the tile's intervals write what
     // the out-of-range loads returned; nothing reads them)
     sm.brow[lane] = in.br[0] - b0;
     sm.brow[lane + 64] = in.br[1] - b0;
+    // the values have landed in LDS (they were loaded last); the chunk
+    // reaching past nnz came back as zeros and is filled value by value
+    wait_vm_all();
+    if (q_tail < nq && lane < E) {
+        const int64_t g = abase + (int64_t)q_tail * E + lane;
+        if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+    }
     wave_sync();
 
-    // 2. products, lane = mask bit, words walked on the scalar unit. All of
-    // the tile's words are loaded at once and all x gathers issued before
-    // the values are stored to LDS. A lane whose bit is clear gathers out of
-    // range (0, no memory access). Products are stored UNPACKED: the product
-    // of bit l of word j goes to entry 64 j + l (zero where the bit is clear),
-    // so block row rho of tile slot g is the C entries from g RC + rho C on.
-    // The last word keeps the bits of the next tile's blocks; their entries
-    // are never read.
+    // 2. products, lane = mask bit, words walked on the scalar unit. Per
+    // word: the lane's value (LDS, at the count of set bits below it plus the
+    // word's running offset; zero where its bit is clear) and its x gather (a
+    // lane whose bit is clear gathers out of range: 0, no memory access).
+    // Each word's mask is used in this pass only. Products are stored
+    // UNPACKED: the product of bit l of word j goes to entry 64 j + l (zero
+    // where the bit is clear), so block row rho of tile slot g is the C
+    // entries from g RC + rho C on. The last word keeps the bits of the next
+    // tile's blocks; their entries are never read.
     static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
     if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
         constexpr int NWM = SM::NWMAX;
-        static_assert(NWM <= 64, "the masks array is padded for 64 words read past its end");
+        static_assert(NWM <= 64, "a tile's mask words fit one per lane");
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
-        char *__restrict__ bb = reinterpret_cast<char *>(sm.buf);
-        // the masks array is readable 512 bytes past its last word
-        const uint64_t *__restrict__ gp = a.mw + w0;
-        uint64_t M[NWM];
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-            uint64_t m = gp[j];                                     // one wide scalar load
-            if (j == 0) m &= lo_mask;
-            M[j] = j < nw ? m : 0ull;
-        }
-        T xv[NWM];
+        const char *__restrict__ bb = reinterpret_cast<const char *>(sm.buf);
+        T xv[NWM], pv[NWM];
+        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
         // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
         // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes)
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
+            uint64_t m = readlane64(in.m, j);
+            if (j == 0) m &= lo_mask;
             const int src = ((j * Sh::BPW) % 64 + slot) * 4;
             const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
-            xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
-        }
-        // the values, now that the gathers are in flight
-#pragma unroll
-        for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4 *>(&sm.buf[(lane + 64 * k) * E]) = in.ch[k];
-        if (q_tail < nq) {
-            if (lane < E) {
-                const int64_t g = abase + (int64_t)q_tail * E + lane;
-                if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
-            }
-        }
-        wave_sync();
-        // each lane reads the value of its bit in every word (the slot is
-        // inside the buffer even where the bit is clear)
-        T pv[NWM];
-        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-            pv[j] = *reinterpret_cast<const T *>(bb + lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte);
-            vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
+            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+            const T v = *reinterpret_cast<const T *>(bb + lane_rank(m) * (uint32_t)sizeof(T) + vbyte);
+            pv[j] = pick(m, v, T(0));
+            vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
         wave_sync();  // all values are read before the products overwrite them
         T *__restrict__ pu = sm.buf + lane;
 #pragma unroll
         for (int j = 0; j < NWM; ++j)
-            if (j < nw) pu[64 * j] = pick(M[j], pv[j] * xv[j], T(0));
+            if (j < nw) pu[64 * j] = pv[j] * xv[j];
     }
     wave_sync();
     tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, sm.buf);
@@ -503,7 +491,7 @@ template <class Sh, class T, int KQ>
 __device__ __forceinline__ void wave_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
                                           WaveSmem<Sh, T, KQ> &sm) {
     TileIn<Sh, T, KQ> in;
-    tile_issue<Sh, T, KQ>(a, d, in);
+    tile_issue<Sh, T, KQ>(a, d, in, sm.buf);
     tile_run<Sh, T, KQ>(a, d, in, xr, sm);
 }
 
@@ -861,18 +849,6 @@ struct TileNext {
     uint64_t m;  // lane j: the tile's mask word j (0 past the tile's words)
 };
 
-// s_waitcnt with one counter at zero and the others left alone (gfx9
-// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8). The builtin
-// lets the compiler's own wait insertion see the wait; the empty asm keeps
-// memory accesses from moving across it.
-__device__ __forceinline__ void wait_vm_all() {
-    __builtin_amdgcn_s_waitcnt(0x0f70);
-    asm volatile("" ::: "memory");
-}
-__device__ __forceinline__ void wait_lds_all() {
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    asm volatile("" ::: "memory");
-}
 
 // Lanes 0..7 load the eight dwords of descriptor t.
 __device__ __forceinline__ int desc_lane(const SpmvArgs &a, int t) {

@@ -32,6 +32,21 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// s_waitcnt with one counter at zero and the others left alone (gfx9
+// encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8). The builtin
+// lets the compiler's own wait insertion see the wait; the empty asm keeps
+// memory accesses from moving across it.
+// Loads with an LDS destination are not tracked by the compiler: data they
+// bring is read only after wait_vm_all.
+__device__ __forceinline__ void wait_vm_all() {
+    __builtin_amdgcn_s_waitcnt(0x0f70);
+    asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void wait_lds_all() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    asm volatile("" ::: "memory");
+}
+
 __device__ __forceinline__ uint64_t low_bits(int n) {
     return n <= 0 ? 0ull : n >= 64 ? ~0ull : ((1ull << n) - 1ull);
 }
