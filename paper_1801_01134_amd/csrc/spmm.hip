@@ -112,8 +112,10 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     }
     wave_sync();
 
-    // 2. per word: this lane's value and X row offset (lane = mask bit)
-    uint64_t M[NWM];
+    // 2. per word: this lane's value and X row offset (lane = mask bit). A
+    // lane whose bit is clear keeps value 0 and an out-of-range offset (its
+    // gathers return 0), so its products are +0 and the masks are not needed
+    // after this pass.
     T v[NWM];
     uint32_t xo[NWM];
     const int slot = lane / Sh::RC;
@@ -126,13 +128,13 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         for (int j = 0; j < NWM; ++j) {
             uint64_t m = nw > 0 ? gp[j] : 0ull;
             if (j == 0) m &= lo_mask;
-            M[j] = j < nw ? m : 0ull;
-            const uint32_t s = lane_rank(M[j]) + vslot;
-            v[j] = sm.buf[s < (uint32_t)(SM::NBUF + 64) ? s : 0u];
+            m = j < nw ? m : 0ull;
+            const uint32_t s = lane_rank(m) + vslot;
+            v[j] = pick(m, sm.buf[s < (uint32_t)(SM::NBUF + 64) ? s : 0u], T(0));
             // the column of slot j BPW + slot: register (j BPW) / 64 of lane (j BPW + slot) mod 64
             const int c = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, colr[(j * Sh::BPW) / 64]);
-            xo[j] = pick(M[j], (uint32_t)(c + kcol) * xrow, 0xffffffffu);
-            vslot += (uint32_t)__popcll(M[j]);
+            xo[j] = pick(m, (uint32_t)(c + kcol) * xrow, 0xffffffffu);
+            vslot += (uint32_t)__popcll(m);
         }
     }
     // row-sum layout, fixed for all columns: L lanes per (interval, block
@@ -184,15 +186,14 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                 xw[j] = __builtin_amdgcn_raw_buffer_load_b128(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb,
                                                               0, 0);
             wave_sync();  // the values (first group) or the previous group's sums are read
+            // words past the tile's last one hold zeros (their entries are never read)
 #pragma unroll
             for (int j = 0; j < NWM; ++j) {
-                if (j < nw) {
-                    const T *xg = reinterpret_cast<const T *>(&xw[j]);
-                    T pg[G];
+                const T *xg = reinterpret_cast<const T *>(&xw[j]);
+                T pg[G];
 #pragma unroll
-                    for (int g = 0; g < G; ++g) pg[g] = pick(M[j], v[j] * xg[g], T(0));
-                    *reinterpret_cast<V4 *>(&sm.buf[(64 * j + lane) * G]) = *reinterpret_cast<const V4 *>(pg);
-                }
+                for (int g = 0; g < G; ++g) pg[g] = v[j] * xg[g];
+                *reinterpret_cast<V4 *>(&sm.buf[(64 * j + lane) * G]) = *reinterpret_cast<const V4 *>(pg);
             }
             wave_sync();
 #pragma unroll
@@ -248,8 +249,7 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                     }
                 }
 #pragma unroll
-                for (int g = 0; g < G; ++g)
-                    for (int m = L >> 1; m >= 1; m >>= 1) acc[g] += __shfl_xor(acc[g], m, 64);
+                for (int g = 0; g < G; ++g) acc[g] = group_sum(acc[g], lg);
                 if (pair < npairs && l == 0) {
                     const int li = pair / Sh::R, rho = pair % Sh::R;
                     const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;
@@ -282,8 +282,7 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         wave_sync();  // the values (first column) or the previous column's sums are read
         T *__restrict__ pw = sm.buf + lane;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j)
-            if (j < nw) pw[64 * j] = pick(M[j], v[j] * xv[j], T(0));
+        for (int j = 0; j < NWM; ++j) pw[64 * j] = v[j] * xv[j];
         wave_sync();
 
         // row sums: L lanes per (interval, block row)
@@ -317,7 +316,7 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                     }
                 }
             }
-            for (int m = L >> 1; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+            acc = group_sum(acc, lg);
             if (pair < npairs && l == 0) {
                 const int li = pair / Sh::R, rho = pair % Sh::R;
                 const int64_t row = (int64_t)(d.i0 + li) * Sh::R + rho;

@@ -478,10 +478,10 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
             vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
         wave_sync();  // all values are read before the products overwrite them
+        // words past the tile's last one are zero (their entries are never read)
         T *__restrict__ pu = sm.buf + lane;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j)
-            if (j < nw) pu[64 * j] = pv[j] * xv[j];
+        for (int j = 0; j < NWM; ++j) pu[64 * j] = pv[j] * xv[j];
     }
     wave_sync();
     tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, sm.buf);
