@@ -940,34 +940,28 @@ __device__ __forceinline__ void tile_run_lds(const SpmvArgs &a, const TileDesc &
         constexpr int NWM = SM::NWMAX;
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
-        uint64_t M[NWM];
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-            const uint64_t m = readlane64(in.m, j);
-            M[j] = j == 0 ? (m & lo_mask) : m;
-        }
-        T xv[NWM];
-#pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-            const int src = ((j * Sh::BPW) % 64 + slot) * 4;
-            const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
-            xv[j] = buf_load<T>(xr, pick(M[j], (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
-        }
-        prefetch();
-        wave_sync();
         const char *__restrict__ bb = reinterpret_cast<const char *>(s_vals);
-        T pv[NWM];
+        wave_sync();  // the tail values are in LDS
+        // per word, in one pass: the x gather and the lane's value (zero where
+        // its bit is clear); words past the tile's last one are zero
+        T xv[NWM], pv[NWM];
         uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
-            pv[j] = *reinterpret_cast<const T *>(bb + lane_rank(M[j]) * (uint32_t)sizeof(T) + vbyte);
-            vbyte += (uint32_t)__popcll(M[j]) * (uint32_t)sizeof(T);
+            uint64_t m = readlane64(in.m, j);
+            if (j == 0) m &= lo_mask;
+            const int src = ((j * Sh::BPW) % 64 + slot) * 4;
+            const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
+            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+            const T v = *reinterpret_cast<const T *>(bb + lane_rank(m) * (uint32_t)sizeof(T) + vbyte);
+            pv[j] = pick(m, v, T(0));
+            vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
+        prefetch();
         wave_sync();  // all values are read before the products overwrite them
         T *__restrict__ pu = s_vals + lane;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j)
-            if (j < nw) pu[64 * j] = pick(M[j], pv[j] * xv[j], T(0));
+        for (int j = 0; j < NWM; ++j) pu[64 * j] = pv[j] * xv[j];
     } else {
         prefetch();
     }
