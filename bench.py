@@ -45,6 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # dense FP32 vector peak of the part
 MODEL_DIR = os.path.join(ROOT, "paper_1801_01134_amd", "records")
 RECORDS = [os.path.join(MODEL_DIR, f) for f in ("selector_records_mi355x.jsonl", "structured_records_mi355x.jsonl")]
 MODEL = os.path.join(MODEL_DIR, "selector_mlp_mi355x.json")
@@ -194,6 +195,80 @@ def select_shape(spc, sel, model, feat):
     si = sel.select(feat, spc.SEL_INTERP)[0]
     sm = sel.select(feat, spc.SEL_MLP)[0] if model else None
     return sm, si
+
+
+def steps_section(spc, torch, A, rp, ci, v64, sel, model, reps: int = 5):
+    """The other steps of the path, each timed on the device against its own
+    bound: conversion (HBM: CSR read once, beta arrays written once),
+    feature extraction (HBM: CSR structure read once), network training and
+    inference (FP32 vector peak) and one selection."""
+    import numpy as np
+    out = {}
+    n, nnz = A.n_rows, A.nnz
+
+    def wall(fn):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts[1:]))
+
+    conv = {}
+    for (r, c) in spc.SHAPES:
+        B = spc.csr_to_beta(r, c, rp, ci, v64, A.n_cols)
+        nb = B.n_blocks
+        del B
+        t = wall(lambda: spc.csr_to_beta(r, c, rp, ci, v64, A.n_cols))
+        ab = (4 * (n + 1) + 4 * nnz + 8 * nnz                     # CSR read
+              + 4 * ((n + r - 1) // r + 1) + 4 * nb + nb * r * c // 8 + 8 * nnz)   # beta written
+        conv[f"b{r}x{c}"] = {"us": round(t * 1e6, 1), "alg_bytes": ab, "alg_GBs": round(ab / t / 1e9, 1),
+                             "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
+    out["conversion_f64"] = {"note": "count pass, scan, host read of the block count, fill pass; the CSR "
+                                     "structure is read twice (count and fill)", "shapes": conv}
+    t = wall(lambda: spc.matrix_features(rp, ci, A.n_cols))
+    ab = 4 * (n + 1) + 4 * nnz
+    out["features"] = {"us": round(t * 1e6, 1), "alg_bytes": ab, "alg_GBs": round(ab / t / 1e9, 1),
+                       "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
+                       "note": "all six block counts and the row statistics in one pass; includes the copy "
+                               "of 16 floats and 6 counts to the host"}
+    if model is not None and os.path.exists(RECORDS[0]):
+        from paper_1801_01134_amd import records as R
+        recs = R.load(*[p for p in RECORDS if os.path.exists(p)])
+        train, test = R.split(recs)
+        Xtr, Ttr, _, _ = R.arrays(train)
+        Xte, _, _, _ = R.arrays(test)
+        dev = torch.device("cuda")
+        Xd = torch.from_numpy(np.ascontiguousarray(Xtr, dtype=np.float32)).to(dev)
+        Td = torch.from_numpy(np.ascontiguousarray(Ttr, dtype=np.float32)).to(dev)
+        mu, sd = spc.mlp_standardizer(Xd)
+        tau = spc.mlp_targets(Td)
+        p = torch.tensor(model["params"], dtype=torch.float32, device=dev)
+        m_ = torch.zeros_like(p)
+        v_ = torch.zeros_like(p)
+        batch = 64
+        steps = Xtr.shape[0] // batch
+        order = np.random.default_rng(0).permutation(Xtr.shape[0])[:steps * batch].astype(np.int32)
+        spc.mlp_train(p, m_, v_, 0, 1e-4, mu, sd, Xd, tau, order, batch)
+        t = wall(lambda: spc.mlp_train(p, m_, v_, 0, 1e-4, mu, sd, Xd, tau, order, batch))
+        layer = 16 * 64 + 64 * 64 + 64 * 6
+        fl = 3 * 2 * layer * batch           # forward, and a backward of twice its cost
+        out["mlp_train"] = {"steps": steps, "batch": batch, "us_per_step": round(t / steps * 1e6, 2),
+                            "flops_per_step": fl, "achieved_TFLOPs": round(fl * steps / t / 1e12, 5),
+                            "peak_TFLOPs_fp32": FP32_PEAK_TFLOPS,
+                            "frac": round(fl * steps / t / 1e12 / FP32_PEAK_TFLOPS, 7),
+                            "bound": "latency: one workgroup per step (the steps depend on each other)"}
+        Xq = torch.from_numpy(np.ascontiguousarray(Xte, dtype=np.float32)).to(dev)
+        t = wall(lambda: spc.mlp_infer(p, mu, sd, Xq))
+        out["mlp_infer"] = {"rows": int(Xte.shape[0]), "us": round(t * 1e6, 1),
+                            "flops": 2 * layer * int(Xte.shape[0])}
+        feat, _ = spc.matrix_features(rp, ci, A.n_cols)
+        t = wall(lambda: sel.select(feat, spc.SEL_MLP))
+        out["select_one_matrix_us"] = {"mlp": round(t * 1e6, 1),
+                                       "interpolation": round(wall(lambda: sel.select(feat, spc.SEL_INTERP)) * 1e6, 1)}
+    return out
 
 
 def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, warmup: int,
@@ -508,6 +583,10 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         "selection": selection,
         "per_kernel": sweep,
     }
+    if do_select:
+        out["steps"] = steps_section(spc, torch, A, rp, ci, v64, sel, model)
+        log(f"steps: {out['steps']}")
+        torch.cuda.empty_cache()
     if do_batched:
         out["batched"] = batched_section(spc, torch, sel, model, pool, tmp, args.batched_matrices,
                                          max(5, args.steps // 10), 3)

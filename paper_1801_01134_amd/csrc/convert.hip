@@ -10,6 +10,7 @@
 // value offsets have to be scanned: with r = 1 the values array is the CSR
 // one, as the paper points out.
 #include "common.hpp"
+#include "wave_common.hpp"
 
 namespace spc {
 namespace {
@@ -31,52 +32,66 @@ __global__ void k_check_ptr(const int32_t *__restrict__ p, int64_t n, int64_t to
     }
 }
 
-// Checks the rows of one interval and counts its blocks.
+// Checks the rows of one interval and counts its blocks. Each entry is read
+// once, through the row's cursor, by the merge that places it in a block;
+// the range and order checks are made on the way.
 template <int R, int C>
 __global__ __launch_bounds__(kConvThreads) void k_count(int64_t n_rows, int64_t n_cols,
                                                         const int32_t *__restrict__ rowptr,
-                                                        const int32_t *__restrict__ colidx,
+                                                        const int32_t *__restrict__ colidx, int64_t nnz,
                                                         int32_t *__restrict__ counts, int *err) {
     const int64_t n_int = (n_rows + R - 1) / R;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_int;
+    // whole wavefronts run the loop (the resource is per wavefront)
+    const int64_t n_iter = (n_int + 63) & ~(int64_t)63;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_iter;
          t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t_first = t - (threadIdx.x & 63);
+        int64_t rel;
+        const auto cr = dev::col_rsrc(colidx, nnz, rowptr[t_first * R], &rel);
+        if (t >= n_int) continue;
         const int64_t row0 = t * R;
         const int nr = (int)min<int64_t>(R, n_rows - row0);
-        int32_t head[R], end[R];
+        dev::ColCursor cur[R];
+        int32_t prev[R];
         int bad = kErrNone;
+#pragma unroll
         for (int i = 0; i < R; ++i) {
-            head[i] = 0;
-            end[i] = 0;
+            int64_t a = 0, e = 0;
             if (i < nr) {
-                head[i] = rowptr[row0 + i];
-                end[i] = rowptr[row0 + i + 1];
-                if (head[i] > end[i] || head[i] < 0) {
+                a = rowptr[row0 + i];
+                e = rowptr[row0 + i + 1];
+                if (e < a || a < 0) {
                     bad = kErrRange;
-                    end[i] = head[i];
-                }
-                // columns strictly increasing inside [0, n_cols)
-                for (int32_t p = head[i]; p < end[i] && !bad; ++p) {
-                    int32_t cc = colidx[p];
-                    if (cc < 0 || cc >= n_cols) bad = kErrRange;
-                    else if (p > head[i] && colidx[p - 1] >= cc) bad = kErrOrder;
+                    e = a;
                 }
             }
-        }
-        if (bad) {
-            atomicOr(err, 1 << bad);
-            counts[t] = 0;
-            continue;
+            cur[i].init(cr, (int32_t)(a + rel), (int32_t)(e + rel));
+            prev[i] = INT32_MIN;
         }
         int32_t nb = 0;
         for (;;) {
-            int32_t s = INT32_MAX;
+            int64_t s = INT64_MAX;
+#pragma unroll
             for (int i = 0; i < R; ++i)
-                if (head[i] < end[i]) s = min(s, colidx[head[i]]);
-            if (s == INT32_MAX) break;
-            const int64_t lim = (int64_t)s + C;
-            for (int i = 0; i < R; ++i)
-                while (head[i] < end[i] && colidx[head[i]] < lim) ++head[i];
+                if (cur[i].live()) s = min(s, (int64_t)cur[i].cur());
+            if (s == INT64_MAX) break;
+            const int64_t lim = s + C;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                while (cur[i].live() && (int64_t)cur[i].cur() < lim) {
+                    // columns strictly increasing inside [0, n_cols)
+                    const int32_t v = cur[i].cur();
+                    if (v < 0 || v >= n_cols) bad = bad ? bad : kErrRange;
+                    else if (v <= prev[i]) bad = bad ? bad : kErrOrder;
+                    prev[i] = v;
+                    cur[i].next(cr);
+                }
+            }
             ++nb;
+        }
+        if (bad) {
+            atomicOr(err, 1 << bad);
+            nb = 0;
         }
         counts[t] = nb;
     }
@@ -94,49 +109,67 @@ template <> struct MaskWord<1> { using T = uint8_t; };
 template <> struct MaskWord<2> { using T = uint16_t; };
 template <> struct MaskWord<4> { using T = uint32_t; };
 
-// Writes the blocks of one interval: column start, mask, values in block
-// order (row-major inside the block). VT is an unsigned integer of the value
-// width, so values move bit for bit.
-template <int R, int C, class VT>
+// Writes the blocks of one interval (column start and mask) and, for each
+// of its entries, the position its value takes in the block-ordered values
+// array (block order, row-major inside a block). The values stay inside the
+// CSR range of the interval's rows, so the move is a local permutation, done
+// afterwards by k_permute with coalesced reads.
+template <int R, int C>
 __global__ __launch_bounds__(kConvThreads) void k_fill(int64_t n_rows, const int32_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ colidx,
-                                                       const VT *__restrict__ vals,
+                                                       const int32_t *__restrict__ colidx, int64_t nnz,
                                                        const int32_t *__restrict__ brow,
                                                        int32_t *__restrict__ bcol, uint8_t *__restrict__ masks,
-                                                       VT *__restrict__ vout) {
+                                                       int32_t *__restrict__ dst) {
     using Sh = Shape<R, C>;
     using MW = typename MaskWord<Sh::MB>::T;
     const int64_t n_int = (n_rows + R - 1) / R;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_int;
+    const int64_t n_iter = (n_int + 63) & ~(int64_t)63;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_iter;
          t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t_first = t - (threadIdx.x & 63);
+        int64_t rel;
+        const auto cr = dev::col_rsrc(colidx, nnz, rowptr[t_first * R], &rel);
+        if (t >= n_int) continue;
         const int64_t row0 = t * R;
         const int nr = (int)min<int64_t>(R, n_rows - row0);
-        int32_t head[R], end[R];
-        for (int i = 0; i < R; ++i) {
-            head[i] = i < nr ? rowptr[row0 + i] : 0;
-            end[i] = i < nr ? rowptr[row0 + i + 1] : 0;
-        }
+        dev::ColCursor cur[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            cur[i].init(cr, i < nr ? (int32_t)(rowptr[row0 + i] + rel) : 0,
+                        i < nr ? (int32_t)(rowptr[row0 + i + 1] + rel) : 0);
         int64_t b = brow[t];
-        int64_t vo = rowptr[row0];
+        int32_t vo = rowptr[row0];
         for (;;) {
-            int32_t s = INT32_MAX;
+            int64_t s = INT64_MAX;
+#pragma unroll
             for (int i = 0; i < R; ++i)
-                if (head[i] < end[i]) s = min(s, colidx[head[i]]);
-            if (s == INT32_MAX) break;
-            const int64_t lim = (int64_t)s + C;
+                if (cur[i].live()) s = min(s, (int64_t)cur[i].cur());
+            if (s == INT64_MAX) break;
+            const int64_t lim = s + C;
             uint32_t m = 0;
+#pragma unroll
             for (int i = 0; i < R; ++i) {
-                while (head[i] < end[i] && colidx[head[i]] < lim) {
-                    m |= 1u << (i * C + (colidx[head[i]] - s));
-                    vout[vo++] = vals[head[i]];
-                    ++head[i];
+                while (cur[i].live() && (int64_t)cur[i].cur() < lim) {
+                    const int32_t v = cur[i].cur();
+                    m |= 1u << (i * C + (int)(v - s));
+                    if (R > 1) dst[(int64_t)cur[i].p - rel] = vo;
+                    ++vo;
+                    cur[i].next(cr);
                 }
             }
-            bcol[b] = s;
+            bcol[b] = (int32_t)s;
             reinterpret_cast<MW *>(masks)[b] = (MW)m;
             ++b;
         }
     }
+}
+
+// vout[dst[p]] = vals[p], bit for bit (VT: unsigned integer of the value width).
+template <class VT>
+__global__ __launch_bounds__(kConvThreads) void k_permute(int64_t nnz, const int32_t *__restrict__ dst,
+                                                          const VT *__restrict__ vals, VT *__restrict__ vout) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        vout[dst[p]] = vals[p];
 }
 
 __global__ void k_zero_bytes(uint8_t *p, int64_t from, int64_t to) {
@@ -236,11 +269,13 @@ extern "C" spc_status spc_beta_count(int32_t r, int32_t c, int64_t n_rows, int64
     SPC_HIP(err.alloc(sizeof(int)));
     SPC_HIP(hipMemsetAsync(err.p, 0, sizeof(int), stream));
     int herr = 0;
+    int32_t nnz = 0;
     if (n_rows > 0) {
         hipLaunchKernelGGL(k_check_ptr, dim3(grid_for(n_rows + 1)), dim3(kConvThreads), 0, stream, rowptr,
                            n_rows, int64_t(-1), err.as<int>());
         SPC_HIP(hipGetLastError());
         SPC_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, stream));
+        SPC_HIP(hipMemcpyAsync(&nnz, rowptr + n_rows, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         SPC_HIP(hipStreamSynchronize(stream));
         SPC_REQUIRE(herr == 0, SPC_ERR_INDEX_RANGE, "CSR row pointers do not start at 0 or decrease");
     }
@@ -248,7 +283,7 @@ extern "C" spc_status spc_beta_count(int32_t r, int32_t c, int64_t n_rows, int64
         with_shape(s, [&](auto sh) {
             using Sh = decltype(sh);
             hipLaunchKernelGGL((k_count<Sh::R, Sh::C>), dim3(grid_for(n_int)), dim3(kConvThreads), 0,
-                               stream, n_rows, n_cols, rowptr, colidx, counts.as<int32_t>(),
+                               stream, n_rows, n_cols, rowptr, colidx, (int64_t)nnz, counts.as<int32_t>(),
                                err.as<int>());
             return 0;
         });
@@ -292,29 +327,44 @@ extern "C" spc_status spc_csr_to_beta(int32_t r, int32_t c, int32_t dtype, int64
                 "null output array");
     SPC_REQUIRE((reinterpret_cast<uintptr_t>(block_masks_out) & 7u) == 0, SPC_ERR_INVALID_ARG,
                 "block_masks_out must be 8-byte aligned");
-    // block total, for zeroing the mask padding
-    int32_t nb = 0;
+    // block total, for zeroing the mask padding, and the entry count
+    int32_t nb = 0, nnz = 0;
     SPC_HIP(hipMemcpyAsync(&nb, block_rowptr + n_int, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    SPC_HIP(hipMemcpyAsync(&nnz, rowptr + n_rows, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     SPC_HIP(hipStreamSynchronize(stream));
+    SPC_REQUIRE(nnz >= 0, SPC_ERR_INDEX_RANGE, "negative entry count in the row pointers");
     const int64_t used = (int64_t)nb * (r * c / 8), padded = spc_mask_bytes(r, c, nb);
     if (padded > used)
         hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(1024), 0, stream,
                            static_cast<uint8_t *>(block_masks_out), used, padded);
+    // value positions (r > 1; with r = 1 the values keep the CSR order)
+    DevBuf dst;
+    if (r > 1 && nnz > 0) SPC_HIP(dst.alloc(sizeof(int32_t) * (size_t)nnz));
     with_shape(s, [&](auto sh) {
         using Sh = decltype(sh);
-        if (dtype == SPC_F64)
-            hipLaunchKernelGGL((k_fill<Sh::R, Sh::C, uint64_t>), dim3(grid_for(n_int)), dim3(kConvThreads), 0,
-                               stream, n_rows, rowptr, colidx, static_cast<const uint64_t *>(values),
-                               block_rowptr, block_colidx_out, static_cast<uint8_t *>(block_masks_out),
-                               static_cast<uint64_t *>(values_out));
-        else
-            hipLaunchKernelGGL((k_fill<Sh::R, Sh::C, uint32_t>), dim3(grid_for(n_int)), dim3(kConvThreads), 0,
-                               stream, n_rows, rowptr, colidx, static_cast<const uint32_t *>(values),
-                               block_rowptr, block_colidx_out, static_cast<uint8_t *>(block_masks_out),
-                               static_cast<uint32_t *>(values_out));
+        hipLaunchKernelGGL((k_fill<Sh::R, Sh::C>), dim3(grid_for(n_int)), dim3(kConvThreads), 0, stream, n_rows,
+                           rowptr, colidx, (int64_t)nnz, block_rowptr, block_colidx_out,
+                           static_cast<uint8_t *>(block_masks_out), dst.as<int32_t>());
         return 0;
     });
     SPC_HIP(hipGetLastError());
+    const size_t es = dtype == SPC_F64 ? 8 : 4;
+    if (nnz > 0) {
+        if (r == 1) {
+            SPC_HIP(hipMemcpyAsync(values_out, values, es * (size_t)nnz, hipMemcpyDeviceToDevice, stream));
+        } else if (dtype == SPC_F64) {
+            hipLaunchKernelGGL(k_permute<uint64_t>, dim3(grid_for(nnz)), dim3(kConvThreads), 0, stream,
+                               (int64_t)nnz, dst.as<int32_t>(), static_cast<const uint64_t *>(values),
+                               static_cast<uint64_t *>(values_out));
+        } else {
+            hipLaunchKernelGGL(k_permute<uint32_t>, dim3(grid_for(nnz)), dim3(kConvThreads), 0, stream,
+                               (int64_t)nnz, dst.as<int32_t>(), static_cast<const uint32_t *>(values),
+                               static_cast<uint32_t *>(values_out));
+        }
+        SPC_HIP(hipGetLastError());
+    }
+    // the position buffer is released on return: finish with it first
+    if (r > 1 && nnz > 0) SPC_HIP(hipStreamSynchronize(stream));
     return SPC_OK;
 }
 

@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "wave_common.hpp"
 
 namespace spc {
 namespace {
@@ -41,28 +42,22 @@ static_assert(sizeof(FeatSums) == 14 * 8, "FeatSums layout");
 
 // Greedy cover of NR consecutive rows (first row F of the group) with blocks
 // c columns wide. lo/hi: the rows' ranges in colidx (hi == lo for rows that
-// do not exist or were refused).
+// do not exist or were refused); rel turns an entry index into a position in
+// the wavefront's column resource cr.
 template <int NR, int F, int C>
-__device__ __forceinline__ int64_t cover(const int32_t *__restrict__ col, const int (&lo)[kGroup],
+__device__ __forceinline__ int64_t cover(__amdgpu_buffer_rsrc_t cr, int64_t rel, const int (&lo)[kGroup],
                                          const int (&hi)[kGroup]) {
-    int p[NR];
-    int64_t h[NR];
+    dev::ColCursor cur[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        p[r] = lo[F + r];
-        h[r] = p[r] < hi[F + r] ? (int64_t)col[p[r]] : INT64_MAX;
-    }
+    for (int r = 0; r < NR; ++r) cur[r].init(cr, (int32_t)(lo[F + r] + rel), (int32_t)(hi[F + r] + rel));
     int64_t count = 0;
     int64_t end = INT64_MIN;  // first column not covered by the last block
     while (true) {
         int64_t s = INT64_MAX;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            while (h[r] < end) {
-                ++p[r];
-                h[r] = p[r] < hi[F + r] ? (int64_t)col[p[r]] : INT64_MAX;
-            }
-            s = h[r] < s ? h[r] : s;
+            while (cur[r].live() && (int64_t)cur[r].cur() < end) cur[r].next(cr);
+            if (cur[r].live()) s = min(s, (int64_t)cur[r].cur());
         }
         if (s == INT64_MAX) break;
         ++count;
@@ -72,12 +67,12 @@ __device__ __forceinline__ int64_t cover(const int32_t *__restrict__ col, const 
 }
 
 template <int NR, int C, int G>
-__device__ __forceinline__ int64_t cover_all(const int32_t *__restrict__ col, const int (&lo)[kGroup],
+__device__ __forceinline__ int64_t cover_all(__amdgpu_buffer_rsrc_t cr, int64_t rel, const int (&lo)[kGroup],
                                              const int (&hi)[kGroup]) {
     if constexpr (G * NR >= kGroup) {
         return 0;
     } else {
-        return cover<NR, G * NR, C>(col, lo, hi) + cover_all<NR, C, G + 1>(col, lo, hi);
+        return cover<NR, G * NR, C>(cr, rel, lo, hi) + cover_all<NR, C, G + 1>(cr, rel, lo, hi);
     }
 }
 
@@ -114,73 +109,86 @@ __global__ __launch_bounds__(kFT) void k_features(int64_t n_rows, int64_t n_cols
     FeatSums v = {};
     const int64_t n_groups = (n_rows + kGroup - 1) / kGroup;
     const int64_t g = (int64_t)blockIdx.x * kFT + threadIdx.x;
-    if (g < n_groups) {
-        int lo[kGroup], hi[kGroup];
-        int bad = kErrNone;
+    const int64_t g_first = g - (threadIdx.x & 63);   // the wavefront's first group
+    if (g_first < n_groups) {
+        // the wavefront's column resource starts at its first row's entries
+        // (clamped into the array, as the row pointers are not checked yet)
+        int64_t first = rowptr[g_first * kGroup];
+        first = first < 0 ? 0 : first > nnz ? nnz : first;
+        int64_t rel;
+        const auto cr = dev::col_rsrc(col, nnz, first, &rel);
+        if (g < n_groups) {
+            int lo[kGroup], hi[kGroup];
+            int bad = kErrNone;
 #pragma unroll
-        for (int r = 0; r < kGroup; ++r) {
-            const int64_t i = g * kGroup + r;
-            lo[r] = hi[r] = 0;
-            if (i >= n_rows) continue;
-            const int64_t a = rowptr[i], b = rowptr[i + 1];
-            if (a < 0 || b < a || b > nnz || (i == 0 && a != 0) || (i == n_rows - 1 && b != nnz)) {
-                bad |= kErrRange;
-                continue;
-            }
-            // row statistics and the CSR check
-            const int len = (int)(b - a);
-            int64_t prev = -1;
-            int64_t dist = 0;
-            bool row_ok = true;
-            for (int64_t p = a; p < b; ++p) {
-                const int64_t j = col[p];
-                if (j < 0 || j >= n_cols) {
+            for (int r = 0; r < kGroup; ++r) {
+                const int64_t i = g * kGroup + r;
+                lo[r] = hi[r] = 0;
+                if (i >= n_rows) continue;
+                const int64_t a = rowptr[i], b = rowptr[i + 1];
+                if (a < 0 || b < a || b > nnz || (i == 0 && a != 0) || (i == n_rows - 1 && b != nnz)) {
                     bad |= kErrRange;
-                    row_ok = false;
-                    break;
+                    continue;
                 }
-                if (j <= prev) {
-                    bad |= kErrOrder;
-                    row_ok = false;
-                    break;
-                }
-                prev = j;
-                dist += j > i ? j - i : i - j;
-            }
-            if (!row_ok) continue;
-            lo[r] = (int)a;
-            hi[r] = (int)b;
-            v.sum_len2 += (int64_t)len * len;
-            v.sum_dist += dist;
-            v.max_len = len > v.max_len ? len : v.max_len;
-            if (len == 0) {
-                ++v.empty_rows;
-            } else {
-                ++v.nonempty_rows;
-                const double span = (double)(col[b - 1] - col[a] + 1);
-                v.sum_log_span += log2(span / (double)len);
-                // beta(1,8) cover of this row, with the values of each block
-                int64_t p = a;
-                while (p < b) {
-                    const int64_t s = col[p];
-                    int n_in = 0;
-                    while (p < b && col[p] < s + 8) {
-                        ++p;
+                // one pass over the row: the CSR check, the row statistics
+                // and its beta(1,8) cover with the values of each block
+                const int len = (int)(b - a);
+                dev::ColCursor c;
+                c.init(cr, (int32_t)(a + rel), (int32_t)(b + rel));
+                int64_t prev = -1, dist = 0, first_col = 0, last_col = 0;
+                int64_t end18 = INT64_MIN;
+                int n_in = 0;
+                bool row_ok = true;
+                for (int64_t k = 0; c.live(); ++k) {
+                    const int64_t j = c.cur();
+                    if (j < 0 || j >= n_cols) {
+                        bad |= kErrRange;
+                        row_ok = false;
+                        break;
+                    }
+                    if (j <= prev) {
+                        bad |= kErrOrder;
+                        row_ok = false;
+                        break;
+                    }
+                    if (k == 0) first_col = j;
+                    last_col = j;
+                    prev = j;
+                    dist += j > i ? j - i : i - j;
+                    if (j >= end18) {
+                        if (n_in == 1) ++v.single18;
+                        ++v.nb[0];
+                        end18 = j + 8;
+                        n_in = 1;
+                    } else {
                         ++n_in;
                     }
-                    ++v.nb[0];
-                    if (n_in == 1) ++v.single18;
+                    c.next(cr);
+                }
+                if (!row_ok) continue;
+                if (n_in == 1) ++v.single18;
+                lo[r] = (int)a;
+                hi[r] = (int)b;
+                v.sum_len2 += (int64_t)len * len;
+                v.sum_dist += dist;
+                v.max_len = len > v.max_len ? len : v.max_len;
+                if (len == 0) {
+                    ++v.empty_rows;
+                } else {
+                    ++v.nonempty_rows;
+                    const double span = (double)(last_col - first_col + 1);
+                    v.sum_log_span += log2(span / (double)len);
                 }
             }
-        }
-        if (bad) {
-            atomicOr(err, bad);
-        } else {
-            v.nb[1] = cover_all<2, 4, 0>(col, lo, hi);
-            v.nb[2] = cover_all<2, 8, 0>(col, lo, hi);
-            v.nb[3] = cover_all<4, 4, 0>(col, lo, hi);
-            v.nb[4] = cover_all<4, 8, 0>(col, lo, hi);
-            v.nb[5] = cover_all<8, 4, 0>(col, lo, hi);
+            if (bad) {
+                atomicOr(err, bad);
+            } else {
+                v.nb[1] = cover_all<2, 4, 0>(cr, rel, lo, hi);
+                v.nb[2] = cover_all<2, 8, 0>(cr, rel, lo, hi);
+                v.nb[3] = cover_all<4, 4, 0>(cr, rel, lo, hi);
+                v.nb[4] = cover_all<4, 8, 0>(cr, rel, lo, hi);
+                v.nb[5] = cover_all<8, 4, 0>(cr, rel, lo, hi);
+            }
         }
     }
     block_reduce(v, sm, part + (int64_t)blockIdx.x * kSumWords);
