@@ -109,17 +109,58 @@ template <> struct MaskWord<1> { using T = uint8_t; };
 template <> struct MaskWord<2> { using T = uint16_t; };
 template <> struct MaskWord<4> { using T = uint32_t; };
 
+// A lane's run of consecutive outputs out[q0], out[q0 + 1], ... of type T:
+// stored N at a time (one store of N elements per N-aligned group; out
+// aligned to N * sizeof(T) bytes), the partial groups at the run's two ends
+// one by one. The runs of a wavefront's 64 lanes lie far apart, so this
+// cuts the memory transactions of its stores by N.
+template <class T, int N>
+struct Run {
+    struct alignas(N * sizeof(T)) Pack {
+        T v[N];
+    };
+    int64_t q0, q;
+    T b[N];  // shift register: the latest element last (static indices only)
+    __device__ __forceinline__ void init(int64_t start) { q0 = q = start; }
+    __device__ __forceinline__ void put(T *__restrict__ out, T v) {
+        if ((q & ~(int64_t)(N - 1)) < q0) {
+            out[q] = v;  // the run's first group is partial
+        } else {
+#pragma unroll
+            for (int j = 0; j + 1 < N; ++j) b[j] = b[j + 1];
+            b[N - 1] = v;
+            if ((q & (N - 1)) == N - 1) {
+                Pack w;
+#pragma unroll
+                for (int j = 0; j < N; ++j) w.v[j] = b[j];
+                *reinterpret_cast<Pack *>(out + (q - (N - 1))) = w;
+            }
+        }
+        ++q;
+    }
+    // the last, partial group: its m elements are the last m of the register
+    __device__ __forceinline__ void flush(T *__restrict__ out) {
+        const int m = (int)(q & (N - 1));
+        if (m != 0 && (q & ~(int64_t)(N - 1)) >= q0) {
+#pragma unroll
+            for (int j = 0; j < N; ++j)
+                if (j >= N - m) out[q - N + j] = b[j];
+        }
+    }
+};
+
 // Writes the blocks of one interval (column start and mask) and, for each
-// of its entries, the position its value takes in the block-ordered values
-// array (block order, row-major inside a block). The values stay inside the
+// position of the block-ordered values array (block order, row-major inside
+// a block), the CSR entry whose value goes there. The values stay inside the
 // CSR range of the interval's rows, so the move is a local permutation, done
-// afterwards by k_permute with coalesced reads.
-template <int R, int C>
+// afterwards by k_permute (coalesced writes). A4: bcol is 16-byte aligned
+// (its run is stored four at a time). The masks array is 8-byte aligned.
+template <int R, int C, bool A4>
 __global__ __launch_bounds__(kConvThreads) void k_fill(int64_t n_rows, const int32_t *__restrict__ rowptr,
                                                        const int32_t *__restrict__ colidx, int64_t nnz,
                                                        const int32_t *__restrict__ brow,
                                                        int32_t *__restrict__ bcol, uint8_t *__restrict__ masks,
-                                                       int32_t *__restrict__ dst) {
+                                                       int32_t *__restrict__ src) {
     using Sh = Shape<R, C>;
     using MW = typename MaskWord<Sh::MB>::T;
     const int64_t n_int = (n_rows + R - 1) / R;
@@ -138,7 +179,13 @@ __global__ __launch_bounds__(kConvThreads) void k_fill(int64_t n_rows, const int
             cur[i].init(cr, i < nr ? (int32_t)(rowptr[row0 + i] + rel) : 0,
                         i < nr ? (int32_t)(rowptr[row0 + i + 1] + rel) : 0);
         int64_t b = brow[t];
-        int32_t vo = rowptr[row0];
+        // masks go up to four at a time (at most 8 bytes: the array is 8-byte aligned)
+        constexpr int NM = sizeof(MW) == 4 ? 2 : 4;
+        Run<int32_t, 4> vrun, brun;
+        Run<MW, NM> mrun;
+        vrun.init(rowptr[row0]);
+        brun.init(b);
+        mrun.init(b);
         for (;;) {
             int64_t s = INT64_MAX;
 #pragma unroll
@@ -152,24 +199,27 @@ __global__ __launch_bounds__(kConvThreads) void k_fill(int64_t n_rows, const int
                 while (cur[i].live() && (int64_t)cur[i].cur() < lim) {
                     const int32_t v = cur[i].cur();
                     m |= 1u << (i * C + (int)(v - s));
-                    if (R > 1) dst[(int64_t)cur[i].p - rel] = vo;
-                    ++vo;
+                    if (R > 1) vrun.put(src, (int32_t)((int64_t)cur[i].p - rel));
                     cur[i].next(cr);
                 }
             }
-            bcol[b] = (int32_t)s;
-            reinterpret_cast<MW *>(masks)[b] = (MW)m;
+            if (A4) brun.put(bcol, (int32_t)s);
+            else bcol[b] = (int32_t)s;
+            mrun.put(reinterpret_cast<MW *>(masks), (MW)m);
             ++b;
         }
+        if (R > 1) vrun.flush(src);
+        if (A4) brun.flush(bcol);
+        mrun.flush(reinterpret_cast<MW *>(masks));
     }
 }
 
-// vout[dst[p]] = vals[p], bit for bit (VT: unsigned integer of the value width).
+// vout[o] = vals[src[o]], bit for bit (VT: unsigned integer of the value width).
 template <class VT>
-__global__ __launch_bounds__(kConvThreads) void k_permute(int64_t nnz, const int32_t *__restrict__ dst,
+__global__ __launch_bounds__(kConvThreads) void k_permute(int64_t nnz, const int32_t *__restrict__ src,
                                                           const VT *__restrict__ vals, VT *__restrict__ vout) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
-        vout[dst[p]] = vals[p];
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < nnz; o += (int64_t)gridDim.x * blockDim.x)
+        vout[o] = vals[src[o]];
 }
 
 __global__ void k_zero_bytes(uint8_t *p, int64_t from, int64_t to) {
@@ -337,14 +387,21 @@ extern "C" spc_status spc_csr_to_beta(int32_t r, int32_t c, int32_t dtype, int64
     if (padded > used)
         hipLaunchKernelGGL(k_zero_bytes, dim3(1), dim3(1024), 0, stream,
                            static_cast<uint8_t *>(block_masks_out), used, padded);
-    // value positions (r > 1; with r = 1 the values keep the CSR order)
-    DevBuf dst;
-    if (r > 1 && nnz > 0) SPC_HIP(dst.alloc(sizeof(int32_t) * (size_t)nnz));
+    // source entry of each value position (r > 1; with r = 1 the values keep
+    // the CSR order)
+    DevBuf srcmap;
+    if (r > 1 && nnz > 0) SPC_HIP(srcmap.alloc(sizeof(int32_t) * (size_t)nnz));
+    const bool a4 = (reinterpret_cast<uintptr_t>(block_colidx_out) & 15u) == 0;
     with_shape(s, [&](auto sh) {
         using Sh = decltype(sh);
-        hipLaunchKernelGGL((k_fill<Sh::R, Sh::C>), dim3(grid_for(n_int)), dim3(kConvThreads), 0, stream, n_rows,
-                           rowptr, colidx, (int64_t)nnz, block_rowptr, block_colidx_out,
-                           static_cast<uint8_t *>(block_masks_out), dst.as<int32_t>());
+        if (a4)
+            hipLaunchKernelGGL((k_fill<Sh::R, Sh::C, true>), dim3(grid_for(n_int)), dim3(kConvThreads), 0, stream,
+                               n_rows, rowptr, colidx, (int64_t)nnz, block_rowptr, block_colidx_out,
+                               static_cast<uint8_t *>(block_masks_out), srcmap.as<int32_t>());
+        else
+            hipLaunchKernelGGL((k_fill<Sh::R, Sh::C, false>), dim3(grid_for(n_int)), dim3(kConvThreads), 0,
+                               stream, n_rows, rowptr, colidx, (int64_t)nnz, block_rowptr, block_colidx_out,
+                               static_cast<uint8_t *>(block_masks_out), srcmap.as<int32_t>());
         return 0;
     });
     SPC_HIP(hipGetLastError());
@@ -354,16 +411,16 @@ extern "C" spc_status spc_csr_to_beta(int32_t r, int32_t c, int32_t dtype, int64
             SPC_HIP(hipMemcpyAsync(values_out, values, es * (size_t)nnz, hipMemcpyDeviceToDevice, stream));
         } else if (dtype == SPC_F64) {
             hipLaunchKernelGGL(k_permute<uint64_t>, dim3(grid_for(nnz)), dim3(kConvThreads), 0, stream,
-                               (int64_t)nnz, dst.as<int32_t>(), static_cast<const uint64_t *>(values),
+                               (int64_t)nnz, srcmap.as<int32_t>(), static_cast<const uint64_t *>(values),
                                static_cast<uint64_t *>(values_out));
         } else {
             hipLaunchKernelGGL(k_permute<uint32_t>, dim3(grid_for(nnz)), dim3(kConvThreads), 0, stream,
-                               (int64_t)nnz, dst.as<int32_t>(), static_cast<const uint32_t *>(values),
+                               (int64_t)nnz, srcmap.as<int32_t>(), static_cast<const uint32_t *>(values),
                                static_cast<uint32_t *>(values_out));
         }
         SPC_HIP(hipGetLastError());
     }
-    // the position buffer is released on return: finish with it first
+    // the source map is released on return: finish with it first
     if (r > 1 && nnz > 0) SPC_HIP(hipStreamSynchronize(stream));
     return SPC_OK;
 }
