@@ -134,13 +134,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t col_rsrc(const int32_t *colidx
     return rsrc(base, (uint32_t)(bytes < 0 ? 0 : bytes > 0xfffffff0ll ? 0xfffffff0ll : bytes));
 }
 
-// PF = false: no window kept in flight (fewer registers, for walks that
-// keep many cursors at once).
-template <bool PF>
-struct ColCursorT {
+struct ColCursor {
     using I4 = __attribute__((ext_vector_type(4))) int;
     int32_t p, end;
-    I4 w, wn;  // the windows at (p & ~3) and the next four entries (PF)
+    I4 w, wn;  // the windows at (p & ~3) and the next four entries
 
     __device__ __forceinline__ static I4 load(__amdgpu_buffer_rsrc_t r, int32_t q) {
         return __builtin_bit_cast(I4, __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)q * 4u, 0, 0));
@@ -150,7 +147,7 @@ struct ColCursorT {
         end = e;
         const int32_t b = p0 & ~3;
         w = load(r, b);
-        if (PF) wn = load(r, b + 4);
+        wn = load(r, b + 4);
     }
     __device__ __forceinline__ bool live() const { return p < end; }
     // the current column (meaningful while live())
@@ -161,16 +158,11 @@ struct ColCursorT {
     __device__ __forceinline__ void next(__amdgpu_buffer_rsrc_t r) {
         ++p;
         if ((p & 3) == 0) {
-            if (PF) {
-                w = wn;
-                wn = load(r, p + 4);
-            } else {
-                w = load(r, p);
-            }
+            w = wn;
+            wn = load(r, p + 4);
         }
     }
 };
-using ColCursor = ColCursorT<true>;
 
 }  // namespace dev
 }  // namespace spc
