@@ -293,3 +293,69 @@ def test_pipelined_equals_one_tile_per_wave(rc, dtype, chunks, grid):
         assert torch.equal(ya, yb), name
     y_ref, s_ref = oracle.csr_spmv(A, x)
     check_rows(y1.cpu().numpy().astype(np.float64), y_ref, s_ref, TOL[dtype], f"pipe beta{rc}")
+
+
+def _oracle_check(B, ref, r, c):
+    assert B.n_blocks == ref.n_blocks
+    assert np.array_equal(B.block_rowptr.cpu().numpy(), ref.block_rowptr)
+    assert np.array_equal(B.block_colidx.cpu().numpy(), ref.block_colidx)
+    assert np.array_equal(B.block_masks.cpu().numpy()[:ref.n_blocks * r * c // 8], ref.mask_bytes())
+    assert np.array_equal(B.values.cpu().numpy().view(np.uint64), ref.values.view(np.uint64))
+
+
+@pytest.mark.parametrize("offset", [1, 2, 3])
+@pytest.mark.parametrize("name", ["powerlaw", "stencil13", "dense_rows", "tiny3x5"])
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_colidx_not_16_byte_aligned(name, rc, offset):
+    """Columns handed over at an address 4, 8 or 12 bytes past a 16-byte
+    boundary: conversion and features read them in 16-byte windows from the
+    boundary below, and give the same results."""
+    r, c = rc
+    A = case(name)
+    say(f"[colidx+{offset}] {name} beta{rc}")
+    big = torch.zeros(A.nnz + 8, dtype=torch.int32, device="cuda")
+    big[offset:offset + A.nnz] = torch.from_numpy(A.colidx).cuda()
+    ci = big[offset:offset + A.nnz]
+    assert ci.data_ptr() % 16 == 4 * offset
+    rp = torch.from_numpy(A.rowptr).cuda()
+    B = spc.csr_to_beta(r, c, rp, ci, torch.from_numpy(A.values), A.n_cols)
+    _oracle_check(B, oracle.csr_to_beta(A, r, c), r, c)
+    f1, nb1 = spc.matrix_features(rp, ci, A.n_cols)
+    f0, nb0 = spc.matrix_features(rp, torch.from_numpy(A.colidx).cuda(), A.n_cols)
+    assert np.array_equal(nb1, nb0) and np.array_equal(f1.view(np.uint32), f0.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", ["powerlaw", "stencil13", "fem6", "two_per_row"])
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_block_columns_not_16_byte_aligned(name, rc):
+    """A caller's block-column array 4 bytes past a 16-byte boundary: the
+    block columns are then stored one by one, with the same result."""
+    import ctypes
+    from paper_1801_01134_amd import _binding as Bd
+    r, c = rc
+    A = case(name)
+    say(f"[bcol+4] {name} beta{rc}")
+    ref = oracle.csr_to_beta(A, r, c)
+    rp = torch.from_numpy(A.rowptr).cuda()
+    ci = torch.from_numpy(A.colidx).cuda()
+    v = torch.from_numpy(A.values).cuda()
+    n_int = (A.n_rows + r - 1) // r
+    brow = torch.empty(n_int + 1, dtype=torch.int32, device="cuda")
+    nb = ctypes.c_int64()
+    L, s = Bd.lib(), Bd.stream_ptr()
+    Bd.check(L.spc_beta_count(r, c, A.n_rows, A.n_cols, Bd._ptr(rp), Bd._ptr(ci), Bd._ptr(brow),
+                              ctypes.byref(nb), s))
+    nb = nb.value
+    bcol_big = torch.full((nb + 8,), -7, dtype=torch.int32, device="cuda")
+    bcol = bcol_big[1:1 + nb]
+    assert bcol.data_ptr() % 16 == 4
+    masks = torch.empty(Bd.mask_bytes(r, c, nb), dtype=torch.uint8, device="cuda")
+    vout = torch.empty_like(v)
+    Bd.check(L.spc_csr_to_beta(r, c, Bd._dtype_code(v.dtype), A.n_rows, A.n_cols, Bd._ptr(rp), Bd._ptr(ci),
+                               Bd._ptr(v), Bd._ptr(brow), Bd._ptr(bcol), Bd._ptr(masks), Bd._ptr(vout), s))
+    torch.cuda.synchronize()
+    assert np.array_equal(bcol.cpu().numpy(), ref.block_colidx)
+    # nothing written outside the caller's range
+    assert int(bcol_big[0]) == -7 and bool((bcol_big[1 + nb:] == -7).all())
+    assert np.array_equal(masks.cpu().numpy()[:nb * r * c // 8], ref.mask_bytes())
+    assert np.array_equal(vout.cpu().numpy().view(np.uint64), ref.values.view(np.uint64))
