@@ -412,6 +412,8 @@ def main(argv=None):
     ap.add_argument("--cg-grid", type=int, default=192)
     ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap[,pipeline]: force "
                     "the headline plan (skips autotuning; used for profiling)")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="run only the other steps (conversion, features, network) and print them")
     ap.add_argument("--copy-ref", action="store_true",
                     help="run only a plain 256 MiB copy (memory-counter calibration)")
     args = ap.parse_args(argv)
@@ -472,6 +474,10 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     v64 = torch.from_numpy(A.values).to(dev)
     flops = 2.0 * A.nnz
     csr_bytes = {8: A.nnz * 12 + (A.n_rows + 1) * 4, 4: A.nnz * 8 + (A.n_rows + 1) * 4}
+    if args.only_steps:
+        sel, model, _ = load_selector(spc)
+        print(json.dumps({"steps": steps_section(spc, torch, A, rp, ci, v64, sel, model)}), flush=True)
+        return 0
 
     sweep = {}
     best_params = {}
