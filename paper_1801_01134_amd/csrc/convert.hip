@@ -10,7 +10,7 @@
 // value offsets have to be scanned: with r = 1 the values array is the CSR
 // one, as the paper points out.
 #include "common.hpp"
-#include "wave_common.hpp"
+#include "cursor.hpp"
 
 namespace spc {
 namespace {

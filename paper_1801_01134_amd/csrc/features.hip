@@ -15,7 +15,7 @@
 #include <cmath>
 
 #include "common.hpp"
-#include "wave_common.hpp"
+#include "cursor.hpp"
 
 namespace spc {
 namespace {
