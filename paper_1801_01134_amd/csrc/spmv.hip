@@ -222,9 +222,10 @@ __device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, in
 //   2. the values go to LDS in packed order; lane = mask bit then walks the
 //      mask words on the scalar unit: the word is the execution mask (an
 //      inverse ballot), the lane's rank among the word's set bits plus the
-//      running popcount is its value's slot, and the product with
-//      x[colidx + k] replaces the value in place;
-//   3. L lanes per (interval, block row) add its products (L as large as the
+//      running popcount is its value's slot, and it multiplies that value by
+//      x[colidx + k]; the C products of each block row are added across
+//      lanes (DPP) and one partial per (block, block row) goes to LDS;
+//   3. L lanes per (interval, block row) add its partials (L as large as the
 //      tile's row count allows) and combine their sums with shuffles.
 template <class Sh, class T, int KQ>
 struct WaveSmem {
@@ -238,8 +239,13 @@ struct WaveSmem {
     static constexpr int NCW = NWMAX * Sh::BPW;
     static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
-    int brow[128];                                    // tile-relative interval pointers
-    T buf[NBUF + 64];                                 // packed values, then unpacked products
+    static constexpr int NPART = NWMAX * (64 / Sh::C);        // (block, block row) partials of the words
+    static_assert(NPART * 8 <= NBUF * (int)sizeof(T), "the partials must fit the value buffer");
+    T buf[NBUF];                                      // packed values, then the partials (double)
+    // tile-relative interval pointers; they follow buf so that the value
+    // reads of the last word's lanes past the tile (at most 63 entries past
+    // buf, never used) stay inside this wavefront's own area
+    int brow[128];
 };
 
 // Row results of a tile held back for storing later: byte offsets into y
@@ -250,24 +256,58 @@ struct YOut {
     T val[2];
 };
 
-// 3. Row sums of a wavefront tile whose products sit unpacked in s_buf
-// (entry 64 j + l = bit l of the tile's word j) and whose tile-relative
-// interval pointers sit in s_brow. With DEFER (and y = A x), the results go
-// to *out instead of y; the caller stores them.
+// Sum over the aligned groups of G lanes (G = 4 or 8, the block width) of a
+// value every lane holds; each lane of a group gets the group's total, added
+// in a fixed order.
+template <int G, class T>
+__device__ __forceinline__ T row_group_sum(T v) {
+    static_assert(G == 4 || G == 8, "block widths are 4 or 8");
+    if constexpr (sizeof(T) == 8) {
+        v += dpp_f64<0xb1>(v);                          // quad_perm [1,0,3,2]
+        v += dpp_f64<0x4e>(v);                          // quad_perm [2,3,0,1]
+        if constexpr (G == 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+    } else {
+        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf,
+                                                                   false));
+        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4e, 0xf, 0xf,
+                                                                   false));
+        if constexpr (G == 8)
+            v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xf,
+                                                                       0xf, false));
+    }
+    return v;
+}
+
+// 2b. Products of one mask word, added over each block row's C lanes; the
+// lane at column 0 of the block row stores the (block, block row) partial at
+// entry j (64 / C) + lane / C, i.e. slot j BPW + slot, block row rho of the
+// tile's words (slots of the next tile's blocks in the last word get entries
+// that are never read). Every lane must be active.
+template <class Sh, class T>
+__device__ __forceinline__ void store_partial(double *part, int j, T prod) {
+    const int lane = threadIdx.x & 63;
+    const T p = row_group_sum<Sh::C>(prod);
+    if ((lane % Sh::C) == 0) part[j * (64 / Sh::C) + lane / Sh::C] = (double)p;
+}
+
+// 3. Row sums of a wavefront tile whose (block, block row) partials sit in
+// s_part (entry g R + rho: slot g of the tile's words, block row rho)
+// and whose tile-relative interval pointers sit in s_brow. With DEFER (and
+// y = A x), the results go to *out instead of y; the caller stores them.
 template <class Sh, class T, bool DEFER = false>
 __device__ __forceinline__ void tile_sums(const SpmvArgs &a, const TileDesc &d, int lo_slot, int w0,
-                                          const int *s_brow, const T *s_buf, YOut<T> *out = nullptr) {
+                                          const int *s_brow, const double *s_part, YOut<T> *out = nullptr) {
     const int lane = threadIdx.x & 63;
     const int nI = d.i1 - d.i0;
-    // L lanes per (interval, block row) add its unpacked products. A tile
-    // has up to 128 pairs: with more than 64, L = 1 and a lane takes pairs
-    // lane and lane + 64.
+    // L lanes per (interval, block row) add its partials. A tile has up to
+    // 128 pairs: with more than 64, L = 1 and a lane takes pairs lane and
+    // lane + 64.
     const int npairs = nI * Sh::R;
     // log2 L: the largest L with npairs * L <= 64
     const int lg = npairs > 64 ? 0 : npairs > 1 ? __builtin_clz((unsigned)(npairs - 1)) - 26 : 6;
     const int L = 1 << lg;
     const int l = lane & (L - 1);
-    const T *__restrict__ pu = s_buf;
+    const double *__restrict__ pp = s_part;
     if (DEFER) out->off[0] = out->off[1] = 0xffffffffu;
     for (int round = 0; round < 2; ++round) {
         if (round == 1 && npairs <= 64) break;
@@ -277,52 +317,22 @@ __device__ __forceinline__ void tile_sums(const SpmvArgs &a, const TileDesc &d, 
         if (pair < npairs) {
             const int li = pair / Sh::R, rho = pair % Sh::R;
             const int bs = s_brow[li], be = s_brow[li + 1];   // tile-relative blocks
+            // two partials per step, so their reads share one LDS round trip
+            double a0 = 0.0, a1 = 0.0;
+            int b = bs + l;
+            for (; b + L < be; b += 2 * L) {
+                a0 += pp[(b + lo_slot) * Sh::R + rho];
+                a1 += pp[(b + L + lo_slot) * Sh::R + rho];
+            }
+            if (b < be) a0 += pp[(b + lo_slot) * Sh::R + rho];
+            acc = a0 + a1;
             if (Sh::R == 1) {
-                // the row's entries are contiguous: slots bs .. be-1, C entries each
-                const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                double a0 = 0.0, a1 = 0.0;
-                int k = es + l;
-                for (; k + L < ee; k += 2 * L) {
-                    a0 += (double)pu[k];
-                    a1 += (double)pu[k + L];
-                }
-                if (k < ee) a0 += (double)pu[k];
-                acc = a0 + a1;
                 stored = be > bs;  // every block holds at least one entry
-            } else {
-                // two blocks per step, so their reads share one LDS round trip
-                double a0 = 0.0, a1 = 0.0;
-                int b = bs + l;
-                for (; b + L < be; b += 2 * L) {
-                    const T *__restrict__ e0 = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                    const T *__restrict__ e1 = e0 + L * Sh::RC;
-                    T p0[Sh::C], p1[Sh::C];
-#pragma unroll
-                    for (int k = 0; k < Sh::C; ++k) {
-                        p0[k] = e0[k];
-                        p1[k] = e1[k];
-                    }
-#pragma unroll
-                    for (int k = 0; k < Sh::C; ++k) {
-                        a0 += (double)p0[k];
-                        a1 += (double)p1[k];
-                    }
-                }
-                if (b < be) {
-                    const T *__restrict__ e0 = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                    T p0[Sh::C];
-#pragma unroll
-                    for (int k = 0; k < Sh::C; ++k) p0[k] = e0[k];
-#pragma unroll
-                    for (int k = 0; k < Sh::C; ++k) a0 += (double)p0[k];
-                }
-                acc = a0 + a1;
-                if (a.accumulate) {
-                    for (int b = bs + l; b < be; b += L) {
-                        const unsigned g = (unsigned)(b + lo_slot);
-                        const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
-                        stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
-                    }
+            } else if (a.accumulate) {
+                for (int b = bs + l; b < be; b += L) {
+                    const unsigned g = (unsigned)(b + lo_slot);
+                    const uint32_t m = (uint32_t)(a.mw[w0 + g / Sh::BPW] >> ((g % Sh::BPW) * Sh::RC));
+                    stored = stored || ((m >> (rho * Sh::C)) & Sh::CMASK) != 0;
                 }
             }
         }
@@ -450,12 +460,11 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     // word: the lane's value (LDS, at the count of set bits below it plus the
     // word's running offset; zero where its bit is clear) and its x gather (a
     // lane whose bit is clear gathers out of range: 0, no memory access).
-    // Each word's mask is used in this pass only. Products are stored
-    // UNPACKED: the product of bit l of word j goes to entry 64 j + l (zero
-    // where the bit is clear), so block row rho of tile slot g is the C
-    // entries from g RC + rho C on. The last word keeps the bits of the next
-    // tile's blocks; their entries are never read.
-    static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
+    // Each word's mask is used in this pass only. Once all values are read,
+    // each word's products are added over each block row's C lanes and one
+    // partial per (block, block row) replaces the values in LDS. The last
+    // word keeps the bits of the next tile's blocks; their partials are never
+    // read.
     if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
         constexpr int NWM = SM::NWMAX;
         static_assert(NWM <= 64, "a tile's mask words fit one per lane");
@@ -477,14 +486,13 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
             pv[j] = pick(m, v, T(0));
             vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
-        wave_sync();  // all values are read before the products overwrite them
-        // words past the tile's last one are zero (their entries are never read)
-        T *__restrict__ pu = sm.buf + lane;
+        wave_sync();  // all values are read before the partials overwrite them
+        double *__restrict__ part = reinterpret_cast<double *>(sm.buf);
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) pu[64 * j] = pv[j] * xv[j];
+        for (int j = 0; j < NWM; ++j) store_partial<Sh, T>(part, j, pv[j] * xv[j]);
     }
     wave_sync();
-    tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, sm.buf);
+    tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, reinterpret_cast<const double *>(sm.buf));
 }
 
 template <class Sh, class T, int KQ>
@@ -826,20 +834,27 @@ void launch_batched_fixed(int kq, unsigned grid, bool persist, const BatchMat *d
 
 // Mode 0, pipelined: a persistent grid; each wavefront walks the tiles
 // t, t + S, t + 2S, ... (S = 4 x grid). The packed values travel from memory
-// straight into LDS (buffer loads with the LDS destination), into one of two
-// buffers per wavefront, so a tile's values can be in flight while the
-// previous tile is computed without holding any registers. Per tile:
+// straight into LDS (buffer loads with the LDS destination), so a tile's
+// values can be in flight while the previous tile is computed without
+// holding any registers. A wavefront has one value buffer: a tile's values
+// leave it for registers (with their x gathers) before the next tile's
+// values are requested into it, and the tile's partials go to an area of
+// their own. Per tile:
 //   wait for everything issued so far (this tile's streams, loaded during
-//   the previous tile); issue this tile's x gathers; issue the next tile's
-//   streams (block columns, interval pointers, mask words, the descriptor
-//   after it) and its values into the other buffer; compute this tile.
+//   the previous tile); read the values and issue the x gathers; issue the
+//   next tile's streams (block columns, interval pointers, mask words, the
+//   descriptor after it) and its values; compute this tile.
 // Vector memory operations complete in issue order, so waiting for the
 // gathers does not wait for the next tile's streams.
 template <class Sh, class T, int KQ>
 struct PipeSmem {
     static constexpr int NBUF = WaveSmem<Sh, T, KQ>::NBUF;
+    T buf[NBUF];
+    // the partials and the interval pointers follow buf, so that the value
+    // reads of the last word's lanes past the tile (at most 63 entries past
+    // buf, never used) stay inside this wavefront's own area
+    double part[WaveSmem<Sh, T, KQ>::NPART];
     int brow[128];
-    T buf[2][NBUF + 64];
 };
 
 template <class Sh, class T, int KQ>
@@ -910,11 +925,13 @@ __device__ __forceinline__ void tile_issue_lds(const SpmvArgs &a, const TileDesc
 }
 
 // The compute of a tile whose values are in s_vals (chunk order). prefetch()
-// issues the next tile's loads; it runs after this tile's gathers.
+// issues the next tile's loads (its values into s_vals once this tile's
+// value reads are complete); it runs after this tile's gathers. The partials
+// go to s_part.
 template <class Sh, class T, int KQ, class F>
 __device__ __forceinline__ void tile_run_lds(const SpmvArgs &a, const TileDesc &d, const TileNext<Sh, T, KQ> &in,
-                                             __amdgpu_buffer_rsrc_t xr, int *s_brow, T *s_vals, F &&prefetch,
-                                             YOut<T> *out) {
+                                             __amdgpu_buffer_rsrc_t xr, int *s_brow, T *s_vals, double *s_part,
+                                             F &&prefetch, YOut<T> *out) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
     const int lane = threadIdx.x & 63;
@@ -958,15 +975,13 @@ __device__ __forceinline__ void tile_run_lds(const SpmvArgs &a, const TileDesc &
             vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
         prefetch();
-        wave_sync();  // all values are read before the products overwrite them
-        T *__restrict__ pu = s_vals + lane;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) pu[64 * j] = pv[j] * xv[j];
+        for (int j = 0; j < NWM; ++j) store_partial<Sh, T>(s_part, j, pv[j] * xv[j]);
     } else {
         prefetch();
     }
     wave_sync();
-    tile_sums<Sh, T, true>(a, d, lo_slot, w0, s_brow, s_vals, out);
+    tile_sums<Sh, T, true>(a, d, lo_slot, w0, s_brow, s_part, out);
 }
 
 template <int R, int C, class T, int KQ>
@@ -983,9 +998,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
     TileDesc d = a.tiles[t];
     bool lng = d.b1 - d.b0 > SM::NB;
     TileNext<Sh, T, KQ> cur;
-    tile_issue_lds<Sh, T, KQ>(a, d, cur, S.buf[0], !lng);
+    tile_issue_lds<Sh, T, KQ>(a, d, cur, S.buf, !lng);
     int dn_raw = desc_lane(a, t + stride);   // all lanes 0 past the last tile
-    int p = 0;
     // A tile's row results are stored after the next tile's loads have been
     // issued, so that the wait for those loads does not also wait for the
     // stores (memory operations are counted together, in issue order).
@@ -1002,8 +1016,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
         TileNext<Sh, T, KQ> nxt;
         int dnn_raw = 0;
         auto prefetch = [&]() {
-            wait_lds_all();  // reads of the other buffer (two tiles back) are complete
-            tile_issue_lds<Sh, T, KQ>(a, dn, nxt, S.buf[p ^ 1], more && !lngn);
+            wait_lds_all();  // this tile's value reads are complete
+            tile_issue_lds<Sh, T, KQ>(a, dn, nxt, S.buf, more && !lngn);
             dnn_raw = desc_lane(a, tn + stride);
             y_flush(yr, pend);  // the previous tile's rows
         };
@@ -1012,7 +1026,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
             prefetch();
             pend.off[0] = pend.off[1] = 0xffffffffu;
         } else {
-            tile_run_lds<Sh, T, KQ>(a, d, cur, xr, S.brow, S.buf[p], prefetch, &pend);
+            tile_run_lds<Sh, T, KQ>(a, d, cur, xr, S.brow, S.buf, S.part, prefetch, &pend);
         }
         if (!more) {
             y_flush(yr, pend);
@@ -1024,7 +1038,6 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
         lng = lngn;
         cur = nxt;
         dn_raw = dnn_raw;
-        p ^= 1;
     }
 }
 
