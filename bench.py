@@ -351,7 +351,8 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
     out = {"grid": m, "n": A.n_rows, "nnz": A.nnz, "runs": []}
     for dt, kset, tol in ((torch.float64, ks, 1e-8), (torch.float32, fp32_ks, 1e-5)):
         vals = torch.from_numpy(A.values).to(dev).to(dt)
-        # per k: the faster SpMM among two shapes x three chunk counts
+        # per k: the fastest SpMM among two shapes x four chunk counts x four
+        # caps on resident workgroups per compute unit
         Bs = {rc: spc.csr_to_beta(rc[0], rc[1], rp, ci, vals, A.n_cols) for rc in ((2, 4), (4, 8))}
         for k in kset:
             Bm = synth.dense_block(A.n_cols, k, 701 + k)
@@ -360,13 +361,14 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
             best = None
             for rc, Bc in Bs.items():
                 for kq in (2, 4, 6, 8):
-                    Pc = Bc.plan(0, 0, 0, kq)
-                    t = event_time(torch, lambda: spc.spmm(Bc, X, plan=Pc), 10, 2)
-                    if best is None or t < best[0]:
-                        best = (t, rc, kq)
-            t_spmm, (r, c), kq = best
+                    for cap in (0, 2, 3, 4):
+                        Pc = Bc.plan(0, 0, 0, kq, 0, cap)
+                        t = event_time(torch, lambda: spc.spmm(Bc, X, plan=Pc), 10, 2)
+                        if best is None or t < best[0]:
+                            best = (t, rc, kq, cap)
+            t_spmm, (r, c), kq, cap = best
             B = Bs[(r, c)]
-            P = B.plan(0, 0, 0, kq)
+            P = B.plan(0, 0, 0, kq, 0, cap)
             s = torch.cuda.Stream()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -380,6 +382,7 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
             ab = algorithmic_bytes(B, P.info()["n_tiles"], k=k)
             out["runs"].append({
                 "dtype": "f64" if dt == torch.float64 else "f32", "k": k, "shape": [r, c], "wave_chunks": kq,
+                "cu_groups": cap,
                 "rel_tol": tol, "iterations": its, "iterations_run": total,
                 "true_rel_residual_max": float(true.max()),
                 "converged": bool(all(i > 0 for i in its) and true.max() <= 10 * tol),

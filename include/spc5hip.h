@@ -157,7 +157,11 @@ typedef struct spc_plan_params {
                                many workgroups as fit on the device) that load their next tile
                                while working on the current one; N > 1 = the same with at most N
                                workgroups */
-    int32_t reserved[3];
+    int32_t cu_groups;      /* mode 0, SpMV launches that are not persistent and SpMM: 0 = as many
+                               workgroups per compute unit as fit; 2..8 = at most that many (the
+                               launch reserves LDS to hold the others off). Fewer resident
+                               wavefronts can keep more of the gathered rows of X in cache. */
+    int32_t reserved[2];
 } spc_plan_params;
 
 spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,
@@ -224,8 +228,9 @@ spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k,
  *
  * spc_autotune: builds a plan for every candidate parameter set (both
  *   modes; mode 0 with 2, 4, 6 and 8 chunks per lane, one wavefront per tile or
- *   pipelined; mode 1 with 1024, 2048, 3072 and 4032 tile bits; each with
- *   and without XCD remapping where the grid order applies), times it
+ *   pipelined, and with 4, 6 and 8 chunks also capped at 2 and 4 resident
+ *   workgroups per compute unit; mode 1 with 1024, 2048, 3072 and 4032 tile
+ *   bits; each with and without XCD remapping where the grid order applies), times it
  *   with spc_time_spmv and returns the fastest set in *best and its time in
  *   *best_us. If records is not NULL, up to max_records timings are written
  *   there (host memory) and *n_records says how many. x and y are scratch

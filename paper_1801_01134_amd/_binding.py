@@ -33,7 +33,8 @@ class BetaView(ctypes.Structure):
 
 class PlanParams(ctypes.Structure):
     _fields_ = [("tile_bits", c_int32), ("xcd_remap", c_int32), ("mode", c_int32),
-                ("wave_chunks", c_int32), ("pipeline", c_int32), ("reserved", c_int32 * 3)]
+                ("wave_chunks", c_int32), ("pipeline", c_int32), ("cu_groups", c_int32),
+                ("reserved", c_int32 * 2)]
 
 
 class TuneRecord(ctypes.Structure):
@@ -164,10 +165,10 @@ class Plan:
     """A tile plan (library-owned) for one BetaMatrix."""
 
     def __init__(self, A: "BetaMatrix", tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0,
-                 wave_chunks: int = 0, pipeline: int = 0):
+                 wave_chunks: int = 0, pipeline: int = 0, cu_groups: int = 0):
         self._A = A
         self._view = A.view()
-        p = PlanParams(tile_bits, xcd_remap, mode, wave_chunks, pipeline)
+        p = PlanParams(tile_bits, xcd_remap, mode, wave_chunks, pipeline, cu_groups)
         h = c_void_p()
         check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
                                     stream_ptr()))
@@ -223,10 +224,10 @@ class BetaMatrix:
                         self.values.data_ptr() if self.nnz else None)
 
     def plan(self, tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0, wave_chunks: int = 0,
-             pipeline: int = 0) -> Plan:
-        key = (tile_bits, xcd_remap, mode, wave_chunks, pipeline)
+             pipeline: int = 0, cu_groups: int = 0) -> Plan:
+        key = (tile_bits, xcd_remap, mode, wave_chunks, pipeline, cu_groups)
         if key not in self._plans:
-            self._plans[key] = Plan(self, tile_bits, xcd_remap, mode, wave_chunks, pipeline)
+            self._plans[key] = Plan(self, tile_bits, xcd_remap, mode, wave_chunks, pipeline, cu_groups)
         return self._plans[key]
 
     def nbytes(self) -> int:
@@ -319,15 +320,18 @@ def autotune(A: BetaMatrix, reps: int = 20, x: torch.Tensor | None = None):
                              stream_ptr()))
 
     def pd(p):
-        return {"mode": p.mode, "tile_bits": p.tile_bits, "wave_chunks": p.wave_chunks,
-                "xcd_remap": p.xcd_remap, "pipeline": p.pipeline}
+        d = {"mode": p.mode, "tile_bits": p.tile_bits, "wave_chunks": p.wave_chunks,
+             "xcd_remap": p.xcd_remap, "pipeline": p.pipeline}
+        if p.cu_groups:
+            d["cu_groups"] = p.cu_groups
+        return d
     records = [dict(pd(recs[i].params), us=recs[i].us, n_tiles=recs[i].n_tiles) for i in range(n.value)]
     return pd(best), best_us.value, records
 
 
 def plan_from(A: BetaMatrix, params: dict) -> Plan:
     return A.plan(params.get("tile_bits", 0), params.get("xcd_remap", 0), params.get("mode", 0),
-                  params.get("wave_chunks", 0), params.get("pipeline", 0))
+                  params.get("wave_chunks", 0), params.get("pipeline", 0), params.get("cu_groups", 0))
 
 
 def spmm(A: BetaMatrix, X: torch.Tensor, Y: torch.Tensor | None = None, accumulate: bool = False,

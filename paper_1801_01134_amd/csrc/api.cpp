@@ -22,6 +22,20 @@ spc_status hip_fail(hipError_t e, const char *what, const char *file, int line) 
     return SPC_ERR_HIP;
 }
 
+size_t lds_reserve_for(size_t static_lds, int cu_groups) {
+    if (cu_groups <= 0) return 0;
+    int dev = 0, per_cu = 0, per_group = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&per_group, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        per_cu <= 0 || per_group <= 0)
+        return 0;
+    // the smallest per-group LDS with floor(per_cu / lds) <= cu_groups
+    size_t want = (size_t)per_cu / (size_t)(cu_groups + 1) + 1;
+    if (want > (size_t)per_group) want = (size_t)per_group;
+    return want > static_lds ? want - static_lds : 0;
+}
+
 spc_status check_view(const spc_beta_view *A) {
     SPC_REQUIRE(A != nullptr, SPC_ERR_INVALID_ARG, "null matrix view");
     SPC_REQUIRE(shape_of(A->r, A->c) >= 0, SPC_ERR_UNSUPPORTED_SHAPE,

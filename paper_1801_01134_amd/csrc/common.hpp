@@ -106,6 +106,26 @@ spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileD
 // Workgroups of the pipelined mode-0 kernel resident at once (occupancy x CUs).
 spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out);
 
+// Dynamic LDS bytes that keep at most cu_groups workgroups of a kernel (whose
+// static LDS is static_lds bytes) resident per compute unit; 0 when
+// cu_groups is 0 or the kernel already holds no more than that.
+size_t lds_reserve_for(size_t static_lds, int cu_groups);
+
+// Launches kernel(args); with cu_groups > 0 it reserves the LDS that keeps at
+// most that many of its workgroups on a compute unit.
+template <class K, class Args>
+spc_status launch_capped(K kernel, int cu_groups, dim3 grid, dim3 block, hipStream_t s, const Args &args) {
+    size_t dyn = 0;
+    if (cu_groups > 0) {
+        hipFuncAttributes fa;
+        SPC_HIP(hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel)));
+        dyn = lds_reserve_for(fa.sharedSizeBytes, cu_groups);
+    }
+    hipLaunchKernelGGL(kernel, grid, block, dyn, s, args);
+    SPC_HIP(hipGetLastError());
+    return SPC_OK;
+}
+
 // Validation of a view on the host.
 spc_status check_view(const spc_beta_view *A);
 
@@ -141,6 +161,7 @@ struct spc_plan {
     int kq;
     int pipeline;  // mode 0: persistent wavefronts that prefetch their next tile
     int resident;  // workgroups of the pipelined kernel resident at once
+    int cu_groups; // 0, or at most this many workgroups per compute unit (non-persistent launches)
     int device;
     int64_t n_tiles;
     int64_t n_long;

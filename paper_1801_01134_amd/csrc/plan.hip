@@ -84,6 +84,10 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     const int kq = params && params->wave_chunks ? params->wave_chunks : 4;
     const int pipeline = params ? params->pipeline : 0;
     SPC_REQUIRE(pipeline >= 0, SPC_ERR_INVALID_ARG, "pipeline must be >= 0");
+    const int cu_groups = params ? params->cu_groups : 0;
+    SPC_REQUIRE(cu_groups == 0 || (cu_groups >= 2 && cu_groups <= 8), SPC_ERR_INVALID_ARG,
+                "cu_groups must be 0 or 2..8 (got %d)", cu_groups);
+    SPC_REQUIRE(!(cu_groups && mode != 0), SPC_ERR_INVALID_ARG, "cu_groups applies to mode 0 only");
     SPC_REQUIRE(!(pipeline && mode != 0), SPC_ERR_INVALID_ARG, "pipeline applies to mode 0 only");
     SPC_REQUIRE(kq == 2 || kq == 4 || kq == 6 || kq == 8, SPC_ERR_INVALID_ARG,
                 "wave_chunks must be 2, 4, 6 or 8");
@@ -141,6 +145,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     P->kq = kq;
     P->pipeline = pipeline > 0;
     P->resident = 0;
+    P->cu_groups = cu_groups;
     if (pipeline) {
         int g = 0;
         spc_status rs = spmv_resident_groups(shape, A->dtype, kq, &g);

@@ -4,10 +4,11 @@
 // The matrix is streamed once for all k columns: a tile's values, columns,
 // masks and interval pointers are read as in the single-vector kernel, and
 // each lane keeps the value of its mask bit for every word of the tile. The
-// k columns are then taken one after the other, each exactly like one
-// single-vector product over the tile (all x gathers of the tile in flight
-// together, products in LDS, L lanes per row). Sums are formed in double
-// precision and written once per row and column.
+// k columns are then taken one after the other, each like one single-vector
+// product over the tile (all x gathers of the tile in flight together, each
+// block row's products added across lanes, one partial per block row in LDS,
+// L lanes per row). Row sums are formed in double precision and written once
+// per row and column.
 //
 // An interval with more blocks than a tile holds is run by one wavefront
 // with lane = mask bit throughout, each lane keeping k running sums.
@@ -51,11 +52,11 @@ struct SpmmSmem {
     static constexpr int NCW = NWMAX * Sh::BPW;
     static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
-    // G = E columns of products, interleaved, per mask bit of every word
-    static constexpr int NPROD = NWMAX * 64 * E;
-    static constexpr int NALL = NPROD > NBUF + 64 ? NPROD : NBUF + 64;
+    // (block, block row) partials of the tile's words, G = E columns each
+    static constexpr int NPART = NWMAX * (64 / Sh::C) * E;
+    static constexpr int NALL = NPART > NBUF ? NPART : NBUF;
     int brow[128];             // tile-relative interval pointers (up to 127 intervals)
-    T buf[NALL];               // packed values, then the unpacked products of a column group
+    T buf[NALL];               // packed values, then the partials of a column group
 };
 
 // One tile, all k columns. The tile's streams are read once; every lane
@@ -81,7 +82,6 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     const int w0 = b0 / Sh::BPW;
     const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
     const int lo_slot = b0 - w0 * Sh::BPW;
-    const int end_bit = (b1 - w0 * Sh::BPW) * Sh::RC;
     const uint64_t lo_mask = ~low_bits(lo_slot * Sh::RC);
     const int cs0 = w0 * Sh::BPW;
     const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
@@ -130,7 +130,9 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
             if (j == 0) m &= lo_mask;
             m = j < nw ? m : 0ull;
             const uint32_t s = lane_rank(m) + vslot;
-            v[j] = pick(m, sm.buf[s < (uint32_t)(SM::NBUF + 64) ? s : 0u], T(0));
+            // lanes past the tile's values (bits of the next tile's blocks in
+            // the last word) may read past the buffer: clamped, never used
+            v[j] = pick(m, sm.buf[s < (uint32_t)SM::NBUF ? s : 0u], T(0));
             // the column of slot j BPW + slot: register (j BPW) / 64 of lane (j BPW + slot) mod 64
             const int c = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, colr[(j * Sh::BPW) / 64]);
             xo[j] = pick(m, (uint32_t)(c + kcol) * xrow, 0xffffffffu);
@@ -167,16 +169,25 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         if (Sh::R > 1 && a.accumulate)
             for (int m = L >> 1; m >= 1; m >>= 1) stored[rd] = __shfl_xor((int)stored[rd], m, 64) || stored[rd];
     }
-    static_assert(SM::NWMAX * 64 <= SM::NBUF + 64, "the unpacked products must fit the value buffer");
-
+    // Per column group, the products of each word are added over each block
+    // row's C lanes (DPP) and the lane at column 0 of the block row stores
+    // the (block, block row) partial at entry j (64 / C) + lane / C, i.e.
+    // slot j BPW + slot, block row rho (entries of the next tile's blocks in
+    // the last word are never read). L lanes per (interval, block row) then
+    // add its partials, in the same order for every column.
+    //
     // Columns are taken in groups of G = 16 / sizeof(T) when the launch says
     // every group is one aligned 16-byte piece of each X and Y row (a.wide):
-    // one 128-bit gather per lane and word brings the group's G values, the
-    // G products of a mask bit go to LDS together (entry (64 j + l) G + g),
-    // the row sums read them with wide loads and each row's G results are
-    // stored at once. Otherwise the columns are taken one by one.
+    // one 128-bit gather per lane and word brings the group's G values, an
+    // entry holds the group's G partials (16 bytes), the row sums read them
+    // with wide loads and each row's G results are stored at once. Otherwise
+    // the columns are taken one by one, one partial per entry. Both give the
+    // same bits for a column.
     constexpr int G = 16 / (int)sizeof(T);
-    static_assert(SM::NPROD <= SM::NALL, "products must fit the buffer");
+    constexpr int PW = 64 / Sh::C;     // partial entries per word
+    static_assert(SM::NWMAX * PW * G <= SM::NALL, "the partials must fit the buffer");
+    const int pe = lane / Sh::C;       // this lane's partial entry within a word
+    const bool keeper = kcol == 0;     // the lane that stores its block row's partial
     if (a.wide) {
         for (int q0 = 0; q0 < a.k; q0 += G) {
             const uint32_t qb = (uint32_t)q0 * (uint32_t)sizeof(T);
@@ -186,67 +197,46 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                 xw[j] = __builtin_amdgcn_raw_buffer_load_b128(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb,
                                                               0, 0);
             wave_sync();  // the values (first group) or the previous group's sums are read
-            // words past the tile's last one hold zeros (their entries are never read)
 #pragma unroll
             for (int j = 0; j < NWM; ++j) {
                 const T *xg = reinterpret_cast<const T *>(&xw[j]);
                 T pg[G];
 #pragma unroll
-                for (int g = 0; g < G; ++g) pg[g] = v[j] * xg[g];
-                *reinterpret_cast<V4 *>(&sm.buf[(64 * j + lane) * G]) = *reinterpret_cast<const V4 *>(pg);
+                for (int g = 0; g < G; ++g) pg[g] = row_group_sum<Sh::C>(v[j] * xg[g]);
+                if (keeper) *reinterpret_cast<V4 *>(&sm.buf[(j * PW + pe) * G]) = *reinterpret_cast<const V4 *>(pg);
             }
             wave_sync();
 #pragma unroll
             for (int rd = 0; rd < 2; ++rd) {
                 const int pair = (lane >> lg) + 64 * rd;
                 if (rd >= rounds) break;
-                double acc[G];
+                double acc[G], a1[G];
 #pragma unroll
-                for (int g = 0; g < G; ++g) acc[g] = 0.0;
+                for (int g = 0; g < G; ++g) acc[g] = a1[g] = 0.0;
                 if (pair < npairs) {
                     const int li = pair / Sh::R, rho = pair % Sh::R;
                     const int bs = sm.brow[li], be = sm.brow[li + 1];
-                    if (Sh::R == 1) {
-                        // the same two interleaved partial sums as the one-column path
-                        const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                        double a1[G];
+                    int b = bs + l;
+                    for (; b + L < be; b += 2 * L) {
+                        const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[((b + lo_slot) * Sh::R + rho) * G]);
+                        const V4 w1v =
+                            *reinterpret_cast<const V4 *>(&sm.buf[((b + L + lo_slot) * Sh::R + rho) * G]);
+                        const T *e0 = reinterpret_cast<const T *>(&w0v);
+                        const T *e1 = reinterpret_cast<const T *>(&w1v);
 #pragma unroll
-                        for (int g = 0; g < G; ++g) a1[g] = 0.0;
-                        int k = es + l;
-                        for (; k + L < ee; k += 2 * L) {
-                            const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
-                            const V4 w1v = *reinterpret_cast<const V4 *>(&sm.buf[(k + L) * G]);
-                            const T *e0 = reinterpret_cast<const T *>(&w0v);
-                            const T *e1 = reinterpret_cast<const T *>(&w1v);
-#pragma unroll
-                            for (int g = 0; g < G; ++g) {
-                                acc[g] += (double)e0[g];
-                                a1[g] += (double)e1[g];
-                            }
-                        }
-                        if (k < ee) {
-                            const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[k * G]);
-                            const T *e0 = reinterpret_cast<const T *>(&w0v);
-#pragma unroll
-                            for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
-                        }
-#pragma unroll
-                        for (int g = 0; g < G; ++g) acc[g] += a1[g];
-                    } else {
-                        for (int b = bs + l; b < be; b += L) {
-                            const int e0 = (b + lo_slot) * Sh::RC + rho * Sh::C;
-                            V4 w[Sh::C];
-#pragma unroll
-                            for (int t = 0; t < Sh::C; ++t)
-                                w[t] = *reinterpret_cast<const V4 *>(&sm.buf[(e0 + t) * G]);
-#pragma unroll
-                            for (int t = 0; t < Sh::C; ++t) {
-                                const T *e = reinterpret_cast<const T *>(&w[t]);
-#pragma unroll
-                                for (int g = 0; g < G; ++g) acc[g] += (double)e[g];
-                            }
+                        for (int g = 0; g < G; ++g) {
+                            acc[g] += (double)e0[g];
+                            a1[g] += (double)e1[g];
                         }
                     }
+                    if (b < be) {
+                        const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[((b + lo_slot) * Sh::R + rho) * G]);
+                        const T *e0 = reinterpret_cast<const T *>(&w0v);
+#pragma unroll
+                        for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[g] += a1[g];
                 }
 #pragma unroll
                 for (int g = 0; g < G; ++g) acc[g] = group_sum(acc[g], lg);
@@ -273,16 +263,17 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         return;
     }
     for (int q = 0; q < a.k; ++q) {
-        // gathers of column q for all words, then its products, unpacked:
-        // bit l of word j at entry 64 j + l (zero where clear)
+        // gathers of column q for all words, then its partials
         T xv[NWM];
         const uint32_t qb = (uint32_t)q * (uint32_t)sizeof(T);
 #pragma unroll
         for (int j = 0; j < NWM; ++j) xv[j] = buf_load<T>(xr, xo[j] == 0xffffffffu ? 0xffffffffu : xo[j] + qb);
         wave_sync();  // the values (first column) or the previous column's sums are read
-        T *__restrict__ pw = sm.buf + lane;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) pw[64 * j] = v[j] * xv[j];
+        for (int j = 0; j < NWM; ++j) {
+            const T p = row_group_sum<Sh::C>(v[j] * xv[j]);
+            if (keeper) sm.buf[j * PW + pe] = p;
+        }
         wave_sync();
 
         // row sums: L lanes per (interval, block row)
@@ -295,26 +286,14 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
             if (pair < npairs) {
                 const int li = pair / Sh::R, rho = pair % Sh::R;
                 const int bs = sm.brow[li], be = sm.brow[li + 1];
-                if (Sh::R == 1) {
-                    const int es = (bs + lo_slot) * Sh::C, ee = (be + lo_slot) * Sh::C;
-                    double a0 = 0.0, a1 = 0.0;
-                    int k = es + l;
-                    for (; k + L < ee; k += 2 * L) {
-                        a0 += (double)pu[k];
-                        a1 += (double)pu[k + L];
-                    }
-                    if (k < ee) a0 += (double)pu[k];
-                    acc = a0 + a1;
-                } else {
-                    for (int b = bs + l; b < be; b += L) {
-                        const T *__restrict__ e = pu + (b + lo_slot) * Sh::RC + rho * Sh::C;
-                        T pr[Sh::C];
-#pragma unroll
-                        for (int t = 0; t < Sh::C; ++t) pr[t] = e[t];
-#pragma unroll
-                        for (int t = 0; t < Sh::C; ++t) acc += (double)pr[t];
-                    }
+                double a0 = 0.0, a1 = 0.0;
+                int b = bs + l;
+                for (; b + L < be; b += 2 * L) {
+                    a0 += (double)pu[(b + lo_slot) * Sh::R + rho];
+                    a1 += (double)pu[(b + L + lo_slot) * Sh::R + rho];
                 }
+                if (b < be) a0 += (double)pu[(b + lo_slot) * Sh::R + rho];
+                acc = a0 + a1;
             }
             acc = group_sum(acc, lg);
             if (pair < npairs && l == 0) {
@@ -420,15 +399,13 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(SpmmArgs a) {
 }
 
 template <int R, int C, class T>
-spc_status launch(int kq, dim3 grid, const SpmmArgs &a, hipStream_t s) {
+spc_status launch(int kq, int cu_groups, dim3 grid, const SpmmArgs &a, hipStream_t s) {
     switch (kq) {
-    case 2: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 2>), grid, dim3(kThreads), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 6>), grid, dim3(kThreads), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 8>), grid, dim3(kThreads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_spmm_wave<R, C, T, 4>), grid, dim3(kThreads), 0, s, a); break;
+    case 2: return launch_capped(k_spmm_wave<R, C, T, 2>, cu_groups, grid, dim3(kThreads), s, a);
+    case 6: return launch_capped(k_spmm_wave<R, C, T, 6>, cu_groups, grid, dim3(kThreads), s, a);
+    case 8: return launch_capped(k_spmm_wave<R, C, T, 8>, cu_groups, grid, dim3(kThreads), s, a);
+    default: return launch_capped(k_spmm_wave<R, C, T, 4>, cu_groups, grid, dim3(kThreads), s, a);
     }
-    SPC_HIP(hipGetLastError());
-    return SPC_OK;
 }
 
 }  // namespace
@@ -470,7 +447,7 @@ spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const v
         using Sh = decltype(sh);
         return with_dtype(A->dtype, [&](auto tv) {
             using T = decltype(tv);
-            return launch<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
+            return launch<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
         });
     });
 }

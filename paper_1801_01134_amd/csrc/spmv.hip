@@ -256,28 +256,6 @@ struct YOut {
     T val[2];
 };
 
-// Sum over the aligned groups of G lanes (G = 4 or 8, the block width) of a
-// value every lane holds; each lane of a group gets the group's total, added
-// in a fixed order.
-template <int G, class T>
-__device__ __forceinline__ T row_group_sum(T v) {
-    static_assert(G == 4 || G == 8, "block widths are 4 or 8");
-    if constexpr (sizeof(T) == 8) {
-        v += dpp_f64<0xb1>(v);                          // quad_perm [1,0,3,2]
-        v += dpp_f64<0x4e>(v);                          // quad_perm [2,3,0,1]
-        if constexpr (G == 8) v += dpp_f64<0x141>(v);   // row_half_mirror
-    } else {
-        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf,
-                                                                   false));
-        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4e, 0xf, 0xf,
-                                                                   false));
-        if constexpr (G == 8)
-            v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xf,
-                                                                       0xf, false));
-    }
-    return v;
-}
-
 // 2b. Products of one mask word, added over each block row's C lanes; the
 // lane at column 0 of the block row stores the (block, block row) partial at
 // entry j (64 / C) + lane / C, i.e. slot j BPW + slot, block row rho of the
@@ -1081,15 +1059,14 @@ spc_status resident_groups(int kq, int *out) {
 }
 
 template <int R, int C, class T>
-spc_status launch_wave(int kq, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+spc_status launch_wave(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    const dim3 blk(kThreads);
     switch (kq) {
-    case 2: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 2>), grid, dim3(kThreads), 0, stream, a); break;
-    case 6: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 6>), grid, dim3(kThreads), 0, stream, a); break;
-    case 8: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 8>), grid, dim3(kThreads), 0, stream, a); break;
-    default: hipLaunchKernelGGL((k_spmv_wave<R, C, T, 4>), grid, dim3(kThreads), 0, stream, a); break;
+    case 2: return launch_capped(k_spmv_wave<R, C, T, 2>, cu_groups, grid, blk, stream, a);
+    case 6: return launch_capped(k_spmv_wave<R, C, T, 6>, cu_groups, grid, blk, stream, a);
+    case 8: return launch_capped(k_spmv_wave<R, C, T, 8>, cu_groups, grid, blk, stream, a);
+    default: return launch_capped(k_spmv_wave<R, C, T, 4>, cu_groups, grid, blk, stream, a);
     }
-    SPC_HIP(hipGetLastError());
-    return SPC_OK;
 }
 
 }  // namespace
@@ -1197,7 +1174,7 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
             using T = decltype(tv);
             if (!wave) return launch_wg<Sh::R, Sh::C, T>(wg_bits, grid, a, stream);
             if (pipe) return launch_wave_pipe<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
-            return launch_wave<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
+            return launch_wave<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
         });
     });
 }

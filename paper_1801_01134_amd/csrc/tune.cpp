@@ -52,6 +52,13 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
             p.xcd_remap = remap;
             cands.push_back(p);
             if (remap == 0) {
+                if (kq >= 4) {
+                    for (int cap : {2, 4}) {  // fewer resident workgroups per compute unit
+                        spc_plan_params q = p;
+                        q.cu_groups = cap;
+                        cands.push_back(q);
+                    }
+                }
                 p.pipeline = 1;  // persistent: the grid order does not apply
                 cands.push_back(p);
             }

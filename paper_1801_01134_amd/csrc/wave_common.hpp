@@ -87,6 +87,28 @@ __device__ __forceinline__ double group_sum(double v, int lg) {
     return v;
 }
 
+// Sum over the aligned groups of G lanes (G = 4 or 8, the block width) of a
+// value every lane holds; each lane of a group gets the group's total, added
+// in a fixed order.
+template <int G, class T>
+__device__ __forceinline__ T row_group_sum(T v) {
+    static_assert(G == 4 || G == 8, "block widths are 4 or 8");
+    if constexpr (sizeof(T) == 8) {
+        v += dpp_f64<0xb1>(v);                          // quad_perm [1,0,3,2]
+        v += dpp_f64<0x4e>(v);                          // quad_perm [2,3,0,1]
+        if constexpr (G == 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+    } else {
+        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf,
+                                                                   false));
+        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4e, 0xf, 0xf,
+                                                                   false));
+        if constexpr (G == 8)
+            v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xf,
+                                                                       0xf, false));
+    }
+    return v;
+}
+
 // Lane-select from a 64-bit uniform mask without touching the exec mask.
 template <class V>
 __device__ __forceinline__ V pick(uint64_t m, V if_set, V if_clear) {

@@ -173,3 +173,39 @@ def test_cg_graph_equals_direct_and_fp32():
     assert all(i > 0 for i in it3)
     true = ocg.true_residual(A32, X3.cpu().numpy().astype(np.float64), Bm.astype(np.float32).astype(np.float64))
     assert np.all(true <= 1e-4 * np.linalg.norm(Bm, axis=0))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("rc", [(1, 8), (2, 4), (4, 8), (8, 4)], ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_resident_group_cap_same_bits(rc, dtype):
+    """A plan's cu_groups cap (LDS reserved at launch so that at most that
+    many workgroups share a compute unit) changes only where tiles run: SpMM
+    and SpMV give the same bits as without it, and match the oracle."""
+    r, c = rc
+    for name in ("powerlaw", "dense_rows", "diagonal"):
+        A = case(name).astype(NP[dtype])
+        say(f"[cap] {name} beta{rc} {dtype}")
+        B = to_beta(A, r, c, dtype)
+        X = synth.dense_block(A.n_cols, 16, 36, dtype=NP[dtype])
+        Xd = torch.from_numpy(X).cuda()
+        Y_ref, S_ref = oracle.csr_spmm(A, X)
+        for kq in (2, 6):
+            Y0 = spc.spmm(B, Xd, plan=B.plan(0, 0, 0, kq))
+            y0 = spc.spmv(B, Xd[:, 0].contiguous(), plan=B.plan(0, 0, 0, kq))
+            for cap in (2, 3, 8):
+                P = B.plan(0, 0, 0, kq, 0, cap)
+                assert torch.equal(spc.spmm(B, Xd, plan=P), Y0), (name, kq, cap)
+                assert torch.equal(spc.spmv(B, Xd[:, 0].contiguous(), plan=P), y0), (name, kq, cap)
+        err = np.abs(Y0.cpu().numpy().astype(np.float64) - Y_ref)
+        assert np.all(err <= TOL[dtype] * S_ref), name
+
+
+def test_resident_group_cap_is_checked():
+    say("[cap] invalid values")
+    A = case("powerlaw")
+    B = to_beta(A, 2, 4, torch.float64)
+    for bad in (1, 9, -1):
+        with pytest.raises(spc.SpcError):
+            B.plan(0, 0, 0, 4, 0, bad)
+    with pytest.raises(spc.SpcError):
+        B.plan(2048, 0, 1, 0, 0, 2)      # mode 1 takes no cap
