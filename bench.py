@@ -79,7 +79,7 @@ def measured_traffic(kname: str, shape, params: dict, m: int):
             rec = json.load(fh)
         if rec.get("kernel") != kname or rec.get("shape") != list(shape):
             continue
-        keys = ("mode", "wave_chunks", "tile_bits", "xcd_remap", "pipeline")
+        keys = ("mode", "wave_chunks", "tile_bits", "xcd_remap", "pipeline", "cu_groups")
         if {k: rec["plan"].get(k, 0) for k in keys} != {k: params.get(k, 0) for k in keys}:
             continue
         h = hashlib.sha256()
@@ -413,7 +413,7 @@ def main(argv=None):
     ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--batched-matrices", type=int, default=64)
     ap.add_argument("--cg-grid", type=int, default=192)
-    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap[,pipeline]: force "
+    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap[,pipeline[,cu_groups]]: force "
                     "the headline plan (skips autotuning; used for profiling)")
     ap.add_argument("--only-steps", action="store_true",
                     help="run only the other steps (conversion, features, network) and print them")
@@ -484,6 +484,7 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
 
     sweep = {}
     best_params = {}
+    top_params = {}
     for dt in (torch.float64, torch.float32):
         if args.only_headline:
             break
@@ -497,6 +498,8 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
             ab = algorithmic_bytes(B, info["n_tiles"])
             key = f"{'f64' if dt == torch.float64 else 'f32'}_b{r}x{c}"
             best_params[key] = params
+            top_params[key] = [{k: v for k, v in rec.items() if k not in ("us", "n_tiles")}
+                               for rec in sorted(records, key=lambda rec: rec["us"])[:3]]
             sweep[key] = {"us": round(us, 2), "gflops": round(flops / t / 1e9, 1),
                           "alg_GBs": round(ab / t / 1e9, 1), "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
                           "alg_bytes": ab, "matrix_bytes": B.nbytes(),
@@ -525,8 +528,16 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         m_, v_, x_ = fields[:3]
         params = {"mode": m_, "wave_chunks": v_ if m_ == 0 else 0, "tile_bits": v_ if m_ == 1 else 0,
                   "xcd_remap": x_, "pipeline": fields[3] if len(fields) > 3 else 0}
+        if len(fields) > 4 and fields[4]:
+            params["cu_groups"] = fields[4]
     else:
         params = best_params.get(f"f64_b{r}x{c}") or spc.autotune(B, reps=args.sweep_steps, x=xd)[0]
+        # the sweep's three fastest plans of this kernel, timed again with more
+        # launches: near-ties between them are decided on a longer sample
+        cands = top_params.get(f"f64_b{r}x{c}", [])
+        if len(cands) > 1:
+            timed = [(spc.time_spmv(B, spc.plan_from(B, p_), reps=100), i) for i, p_ in enumerate(cands)]
+            params = cands[min(timed)[1]]
     P = spc.plan_from(B, params)
     info = P.info()
     kname = (f"k_spmv_wave{'_pipe' if params.get('pipeline') else ''}<{r},{c},double,{params['wave_chunks'] or 4}>"
