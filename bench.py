@@ -108,6 +108,37 @@ def event_time(torch, fn, steps: int, warmup: int, stream=None) -> float:
     return e0.elapsed_time(e1) * 1e-3 / steps
 
 
+def small_case(spc, torch, steps: int = 2000):
+    """The small square matrix (n = 4096, 8 band + 8 uniform columns per row,
+    FP64, beta(1,8)): 0.8 MB, cache-resident, so a product is bound by launch
+    and latency, not by HBM. Reported in microseconds beside the FP64 CSR
+    oracle on the same matrix."""
+    import oracle
+    from paper_1801_01134_amd import synth
+    A = synth.band_plus_uniform(4096, seed=0)
+    x = synth.dense_vector(A.n_cols, 1)
+    dev = torch.device("cuda")
+    B = spc.csr_to_beta(1, 8, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols)
+    xd = torch.from_numpy(x).to(dev)
+    yd = torch.empty(A.n_rows, dtype=torch.float64, device=dev)
+    params, us_tuned, _ = spc.autotune(B, reps=200, x=xd)
+    P = spc.plan_from(B, params)
+    t = event_time(torch, lambda: spc.spmv(B, xd, yd, plan=P), steps, 50)
+    y_ref, s_ref = oracle.csr_spmv(A, x)
+    ok = bool((abs(yd.cpu().numpy() - y_ref) <= 1e-13 * s_ref).all())
+    oracle.csr_spmv(A, x)
+    reps = 2000
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.csr_spmv(A, x)
+    tc = (time.perf_counter() - t0) / reps
+    return {"n": A.n_rows, "nnz": A.nnz, "n_blocks": B.n_blocks, "plan": params,
+            "us_per_product_launched": round(t * 1e6, 2), "us_device_tuned": round(us_tuned, 2),
+            "gflops": round(2.0 * A.nnz / t / 1e9, 2), "matches_oracle": ok,
+            "oracle_us": round(tc * 1e6, 1), "oracle_threads": oracle.threads(),
+            "note": "back-to-back launches from Python; us_device_tuned is the autotuner's device time"}
+
+
 def cpu_baseline(A, x, budget_s: float = 10.0):
     """The FP64 CSR oracle (plain C, OpenMP over rows) on the host cores."""
     import oracle
@@ -619,6 +650,9 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     if do_cg:
         out["cg"] = cg_section(spc, torch, pool, tmp, args.cg_grid, (1, 4, 8, 16), (1, 16))
         torch.cuda.empty_cache()
+    if not args.only_headline:
+        out["small_case"] = small_case(spc, torch)
+        log(f"small case: {out['small_case']}")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, x64)
     print(json.dumps(out), flush=True)
