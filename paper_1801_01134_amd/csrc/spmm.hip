@@ -49,8 +49,6 @@ struct SpmmSmem {
     static constexpr int NB = WB / Sh::RC;
     static constexpr int NWMAX = NB / Sh::BPW + 2;
     static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;
-    static constexpr int NCW = NWMAX * Sh::BPW;
-    static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
     // (block, block row) partials of the tile's words, G = E columns each
     static constexpr int NPART = NWMAX * (64 / Sh::C) * E;

@@ -229,15 +229,12 @@ __device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, in
 //      tile's row count allows) and combine their sums with shuffles.
 template <class Sh, class T, int KQ>
 struct WaveSmem {
-    static constexpr int G = 4;                       // mask words per scalar load
     static constexpr int E = 16 / sizeof(T);          // values per 16-byte chunk
     static constexpr int WB = (64 * KQ - 1) * E;      // bits (so values) a tile may hold
     static constexpr int NB = WB / Sh::RC;            // blocks a tile may hold
     // NB blocks starting anywhere in a word span at most NB / BPW + 2 words
     static constexpr int NWMAX = NB / Sh::BPW + 2;
     static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;   // 64-lane rounds of block columns
-    static constexpr int NCW = NWMAX * Sh::BPW;
-    static constexpr int NCOL = NCR * 64 > NCW ? NCR * 64 : NCW;
     static constexpr int NBUF = 64 * KQ * E;
     static constexpr int NPART = NWMAX * (64 / Sh::C);        // (block, block row) partials of the words
     static_assert(NPART * 8 <= NBUF * (int)sizeof(T), "the partials must fit the value buffer");
@@ -575,7 +572,6 @@ __device__ void tile_long(const SpmvArgs &a, int I, int b0, int b1, int64_t vbas
     const int w0 = b0 / Sh::BPW;
     const int nwt = (b1 - 1) / Sh::BPW - w0 + 1;
     double acc0 = 0.0, acc1 = 0.0;
-    int n_here = 0;  // stored entries this lane saw
     int64_t vrun = vbase;
     for (int k = 0; k < nwt; k += 64) {
         const int nw = min(64, nwt - k);
