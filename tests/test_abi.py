@@ -67,3 +67,18 @@ def test_argument_errors_before_any_launch():
     assert b"aligned" in L.spc_last_error()
     assert L.spc_spmv_beta(None, None, None, None, 0, None) == -1
     assert L.spc_plan_destroy(None) == 0
+
+
+def test_plan_parameters_checked_on_the_host():
+    """Plan parameters are validated before any device call (the pointers of
+    this view are never dereferenced)."""
+    L = B.lib()
+    h = ctypes.c_void_p()
+    v = B.BetaView(2, 4, 1, 0, 8, 8, 16, 4, 4096, 8192, 16384, 32768)
+    for bad in (dict(cu_groups=1), dict(cu_groups=9), dict(cu_groups=-1),
+                dict(mode=1, tile_bits=2048, cu_groups=2), dict(mode=3),
+                dict(wave_chunks=5), dict(mode=1, tile_bits=1000), dict(pipeline=-1),
+                dict(mode=1, tile_bits=2048, pipeline=1), dict(xcd_remap=3)):
+        p = B.PlanParams(**bad)
+        assert L.spc_plan_create(ctypes.byref(v), ctypes.byref(p), ctypes.byref(h), None) == -1, bad
+        assert not h.value
