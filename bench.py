@@ -446,6 +446,9 @@ def main(argv=None):
     ap.add_argument("--cg-grid", type=int, default=192)
     ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap[,pipeline[,cu_groups]]: force "
                     "the headline plan (skips autotuning; used for profiling)")
+    ap.add_argument("--spmm", default="",
+                    help="k,dtype(64|32),wave_chunks,cu_groups: time only Y = A X on the CG matrix (used for "
+                         "profiling the multi-RHS kernel)")
     ap.add_argument("--only-steps", action="store_true",
                     help="run only the other steps (conversion, features, network) and print them")
     ap.add_argument("--copy-ref", action="store_true",
@@ -463,6 +466,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         print(json.dumps({"copy_ref_bytes_read_per_launch": n * 4, "bytes_written_per_launch": n * 4}))
         return 0
+    if args.spmm:
+        return spmm_only(args)
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} refused: this build measures one GPU only "
               "(the multi-GPU sharding is described in DESIGN.md, not run)", file=sys.stderr)
@@ -488,6 +493,32 @@ def main(argv=None):
         for f in os.listdir(tmp):
             os.remove(os.path.join(tmp, f))
         os.rmdir(tmp)
+
+
+def spmm_only(args):
+    """Y = A X on the SPD 27-point matrix of the CG section (beta(2,4)), one
+    plan, `steps` timed launches after `warmup`; one JSON line."""
+    import torch
+
+    import paper_1801_01134_amd as spc
+    from paper_1801_01134_amd import synth
+    k, bits, kq, cap = (int(t) for t in args.spmm.split(","))
+    dt = torch.float64 if bits == 64 else torch.float32
+    dev = torch.device("cuda:0")
+    A = synth.stencil27(args.cg_grid, diag=26.1, offdiag=-1.0)
+    B = spc.csr_to_beta(2, 4, torch.from_numpy(A.rowptr).to(dev), torch.from_numpy(A.colidx).to(dev),
+                        torch.from_numpy(A.values).to(dev).to(dt), A.n_cols)
+    X = torch.from_numpy(synth.dense_block(A.n_cols, k, 702)).to(dev).to(dt)
+    Y = torch.empty(A.n_rows, k, dtype=dt, device=dev)
+    P = B.plan(0, 0, 0, kq, 0, cap)
+    t = event_time(torch, lambda: spc.spmm(B, X, Y, plan=P), args.steps, args.warmup)
+    ab = algorithmic_bytes(B, P.info()["n_tiles"], k=k)
+    print(json.dumps({"workload": f"27-point SPD stencil {args.cg_grid}^3 (n={A.n_rows}, nnz={A.nnz}), "
+                                  f"beta(2,4), Y = A X, k = {k}, FP{bits}",
+                      "plan": {"wave_chunks": kq, "cu_groups": cap}, "us": round(t * 1e6, 1),
+                      "alg_bytes_per_launch": ab, "alg_GBs": round(ab / t / 1e9, 1),
+                      "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
+    return 0
 
 
 def run(args, pool, tmp, do_batched, do_cg, do_select):
