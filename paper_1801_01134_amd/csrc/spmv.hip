@@ -224,7 +224,8 @@ __device__ void tile_short(const SpmvArgs &a, int i0, int i1, int b0, int b1, in
 //      inverse ballot), the lane's rank among the word's set bits plus the
 //      running popcount is its value's slot, and it multiplies that value by
 //      x[colidx + k]; the C products of each block row are added across
-//      lanes (DPP) and one partial per (block, block row) goes to LDS;
+//      lanes (DPP) into one partial per (block, block row), two for FP64,
+//      which go to LDS;
 //   3. L lanes per (interval, block row) add its partials (L as large as the
 //      tile's row count allows) and combine their sums with shuffles.
 template <class Sh, class T, int KQ>
@@ -236,7 +237,11 @@ struct WaveSmem {
     static constexpr int NWMAX = NB / Sh::BPW + 2;
     static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;   // 64-lane rounds of block columns
     static constexpr int NBUF = 64 * KQ * E;
-    static constexpr int NPART = NWMAX * (64 / Sh::C);        // (block, block row) partials of the words
+    // partials per (block, block row): FP64 stops the lane sums at two per
+    // block row (fewer DPP steps, each a pair of moves and an add), FP32
+    // adds all C lanes (one DPP add per step)
+    static constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+    static constexpr int NPART = NWMAX * (64 / Sh::C) * PPR;  // partials of the tile's words
     static_assert(NPART * 8 <= NBUF * (int)sizeof(T), "the partials must fit the value buffer");
     T buf[NBUF];                                      // packed values, then the partials (double)
     // tile-relative interval pointers; they follow buf so that the value
@@ -253,16 +258,26 @@ struct YOut {
     T val[2];
 };
 
-// 2b. Products of one mask word, added over each block row's C lanes; the
-// lane at column 0 of the block row stores the (block, block row) partial at
-// entry j (64 / C) + lane / C, i.e. slot j BPW + slot, block row rho of the
-// tile's words (slots of the next tile's blocks in the last word get entries
-// that are never read). Every lane must be active.
+// 2b. Products of one mask word, added across the lanes of each block row
+// down to PPR partials per (block, block row): all C lanes for FP32 (one
+// partial), C/2 lanes for FP64 (two partials: columns below and from C/2).
+// The lanes at column 0 (and C/2) store them at entry
+// j (64 / C) PPR + lane / (C / PPR), i.e. slot j BPW + slot, block row rho,
+// half h of the tile's words (slots of the next tile's blocks in the last
+// word get entries that are never read). Every lane must be active.
 template <class Sh, class T>
 __device__ __forceinline__ void store_partial(double *part, int j, T prod) {
+    constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+    constexpr int W = Sh::C / PPR;     // lanes added into one partial
     const int lane = threadIdx.x & 63;
-    const T p = row_group_sum<Sh::C>(prod);
-    if ((lane % Sh::C) == 0) part[j * (64 / Sh::C) + lane / Sh::C] = (double)p;
+    T p = prod;
+    if constexpr (sizeof(T) == 8) {
+        p += dpp_f64<0xb1>(p);                          // quad_perm [1,0,3,2]
+        if constexpr (W == 4) p += dpp_f64<0x4e>(p);    // quad_perm [2,3,0,1]
+    } else {
+        p = row_group_sum<Sh::C>(p);
+    }
+    if ((lane % W) == 0) part[j * (64 / Sh::C) * PPR + lane / W] = (double)p;
 }
 
 // 3. Row sums of a wavefront tile whose (block, block row) partials sit in
@@ -295,11 +310,21 @@ __device__ __forceinline__ void tile_sums(const SpmvArgs &a, const TileDesc &d, 
             // two partials per step, so their reads share one LDS round trip
             double a0 = 0.0, a1 = 0.0;
             int b = bs + l;
+            constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
             for (; b + L < be; b += 2 * L) {
-                a0 += pp[(b + lo_slot) * Sh::R + rho];
-                a1 += pp[(b + L + lo_slot) * Sh::R + rho];
+                const double *e0 = pp + ((b + lo_slot) * Sh::R + rho) * PPR;
+                const double *e1 = pp + ((b + L + lo_slot) * Sh::R + rho) * PPR;
+#pragma unroll
+                for (int h = 0; h < PPR; ++h) {
+                    a0 += e0[h];
+                    a1 += e1[h];
+                }
             }
-            if (b < be) a0 += pp[(b + lo_slot) * Sh::R + rho];
+            if (b < be) {
+                const double *e0 = pp + ((b + lo_slot) * Sh::R + rho) * PPR;
+#pragma unroll
+                for (int h = 0; h < PPR; ++h) a0 += e0[h];
+            }
             acc = a0 + a1;
             if (Sh::R == 1) {
                 stored = be > bs;  // every block holds at least one entry
