@@ -6,8 +6,8 @@
 // each lane keeps the value of its mask bit for every word of the tile. The
 // k columns are then taken one after the other, each like one single-vector
 // product over the tile (all x gathers of the tile in flight together, each
-// block row's products added across lanes, one partial per block row in LDS,
-// L lanes per row). Row sums are formed in double precision and written once
+// block row's products added across lanes into one partial, two for FP64, in
+// LDS, L lanes per row). Row sums are formed in double precision and written once
 // per row and column.
 //
 // An interval with more blocks than a tile holds is run by one wavefront
@@ -51,7 +51,8 @@ struct SpmmSmem {
     static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;
     static constexpr int NBUF = 64 * KQ * E;
     // (block, block row) partials of the tile's words, G = E columns each
-    static constexpr int NPART = NWMAX * (64 / Sh::C) * E;
+    static constexpr int PPR = sizeof(T) == 8 ? 2 : 1;   // partials per (block, block row)
+    static constexpr int NPART = NWMAX * (64 / Sh::C) * PPR * E;
     static constexpr int NALL = NPART > NBUF ? NPART : NBUF;
     int brow[128];             // tile-relative interval pointers (up to 127 intervals)
     T buf[NALL];               // packed values, then the partials of a column group
@@ -182,10 +183,23 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     // the columns are taken one by one, one partial per entry. Both give the
     // same bits for a column.
     constexpr int G = 16 / (int)sizeof(T);
-    constexpr int PW = 64 / Sh::C;     // partial entries per word
+    // FP64 stops the lane sums at PPR = 2 partials per (block, block row)
+    // (each 64-bit DPP step is two moves and an add); FP32 adds all C lanes
+    constexpr int PPR = SM::PPR;
+    constexpr int W = Sh::C / PPR;     // lanes added into one partial
+    constexpr int PW = 64 / Sh::C * PPR;   // partial entries per word
     static_assert(SM::NWMAX * PW * G <= SM::NALL, "the partials must fit the buffer");
-    const int pe = lane / Sh::C;       // this lane's partial entry within a word
-    const bool keeper = kcol == 0;     // the lane that stores its block row's partial
+    const int pe = lane / W;           // this lane's partial entry within a word
+    const bool keeper = kcol % W == 0; // the lanes that store their block row's partials
+    auto lane_sum = [](T p) {
+        if constexpr (sizeof(T) == 8) {
+            p += dpp_f64<0xb1>(p);                          // quad_perm [1,0,3,2]
+            if constexpr (W == 4) p += dpp_f64<0x4e>(p);    // quad_perm [2,3,0,1]
+            return p;
+        } else {
+            return row_group_sum<Sh::C>(p);
+        }
+    };
     if (a.wide) {
         for (int q0 = 0; q0 < a.k; q0 += G) {
             const uint32_t qb = (uint32_t)q0 * (uint32_t)sizeof(T);
@@ -200,7 +214,7 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                 const T *xg = reinterpret_cast<const T *>(&xw[j]);
                 T pg[G];
 #pragma unroll
-                for (int g = 0; g < G; ++g) pg[g] = row_group_sum<Sh::C>(v[j] * xg[g]);
+                for (int g = 0; g < G; ++g) pg[g] = lane_sum(v[j] * xg[g]);
                 if (keeper) *reinterpret_cast<V4 *>(&sm.buf[(j * PW + pe) * G]) = *reinterpret_cast<const V4 *>(pg);
             }
             wave_sync();
@@ -216,22 +230,30 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                     const int bs = sm.brow[li], be = sm.brow[li + 1];
                     int b = bs + l;
                     for (; b + L < be; b += 2 * L) {
-                        const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[((b + lo_slot) * Sh::R + rho) * G]);
-                        const V4 w1v =
-                            *reinterpret_cast<const V4 *>(&sm.buf[((b + L + lo_slot) * Sh::R + rho) * G]);
-                        const T *e0 = reinterpret_cast<const T *>(&w0v);
-                        const T *e1 = reinterpret_cast<const T *>(&w1v);
 #pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            acc[g] += (double)e0[g];
-                            a1[g] += (double)e1[g];
+                        for (int h = 0; h < PPR; ++h) {
+                            const V4 w0v = *reinterpret_cast<const V4 *>(
+                                &sm.buf[(((b + lo_slot) * Sh::R + rho) * PPR + h) * G]);
+                            const V4 w1v = *reinterpret_cast<const V4 *>(
+                                &sm.buf[(((b + L + lo_slot) * Sh::R + rho) * PPR + h) * G]);
+                            const T *e0 = reinterpret_cast<const T *>(&w0v);
+                            const T *e1 = reinterpret_cast<const T *>(&w1v);
+#pragma unroll
+                            for (int g = 0; g < G; ++g) {
+                                acc[g] += (double)e0[g];
+                                a1[g] += (double)e1[g];
+                            }
                         }
                     }
                     if (b < be) {
-                        const V4 w0v = *reinterpret_cast<const V4 *>(&sm.buf[((b + lo_slot) * Sh::R + rho) * G]);
-                        const T *e0 = reinterpret_cast<const T *>(&w0v);
 #pragma unroll
-                        for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
+                        for (int h = 0; h < PPR; ++h) {
+                            const V4 w0v = *reinterpret_cast<const V4 *>(
+                                &sm.buf[(((b + lo_slot) * Sh::R + rho) * PPR + h) * G]);
+                            const T *e0 = reinterpret_cast<const T *>(&w0v);
+#pragma unroll
+                            for (int g = 0; g < G; ++g) acc[g] += (double)e0[g];
+                        }
                     }
 #pragma unroll
                     for (int g = 0; g < G; ++g) acc[g] += a1[g];
@@ -269,7 +291,7 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
         wave_sync();  // the values (first column) or the previous column's sums are read
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
-            const T p = row_group_sum<Sh::C>(v[j] * xv[j]);
+            const T p = lane_sum(v[j] * xv[j]);
             if (keeper) sm.buf[j * PW + pe] = p;
         }
         wave_sync();
@@ -287,10 +309,16 @@ __device__ void spmm_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
                 double a0 = 0.0, a1 = 0.0;
                 int b = bs + l;
                 for (; b + L < be; b += 2 * L) {
-                    a0 += (double)pu[(b + lo_slot) * Sh::R + rho];
-                    a1 += (double)pu[(b + L + lo_slot) * Sh::R + rho];
+#pragma unroll
+                    for (int h = 0; h < PPR; ++h) {
+                        a0 += (double)pu[((b + lo_slot) * Sh::R + rho) * PPR + h];
+                        a1 += (double)pu[((b + L + lo_slot) * Sh::R + rho) * PPR + h];
+                    }
                 }
-                if (b < be) a0 += (double)pu[(b + lo_slot) * Sh::R + rho];
+                if (b < be) {
+#pragma unroll
+                    for (int h = 0; h < PPR; ++h) a0 += (double)pu[((b + lo_slot) * Sh::R + rho) * PPR + h];
+                }
                 acc = a0 + a1;
             }
             acc = group_sum(acc, lg);
