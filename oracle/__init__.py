@@ -16,8 +16,9 @@ in double precision, in the order the paper gives them.
 * ``beta_count`` / ``csr_to_beta`` / ``beta_to_csr``: the beta(r,c) storage
   (Design, "Block-based storage without zero padding", Eq. (1)) under the
   greedy leftmost-cover reading of where blocks start.
-* ``alg1_spmv``: Algorithm 1 executed literally on the beta arrays (tiny
-  inputs), with the vexpand placement rule from the Vectorization section.
+* ``vexpand`` / ``expand_to_dense``: what the beta arrays mean, block by
+  block, with the vexpand placement rule from the Vectorization section
+  (tiny inputs).
 * ``occupancy`` and friends: Eqs. (1)-(4).
 * ``features``, ``fit_interpolation``, ``select_interpolation``, ``regret``:
   the record-based kernel selection ("Performance polynomial interpolation").
@@ -211,18 +212,8 @@ def beta_to_csr(beta: BetaRef):
     return rowptr, colidx, np.ascontiguousarray(beta.values)[src]
 
 
-def masks_from_bytes(mask_bytes: np.ndarray, r: int, c: int, n_blocks: int) -> np.ndarray:
-    """Widen a stream of ceil(rc/8)-byte little-endian masks to uint32."""
-    w = (r * c) // 8
-    b = np.asarray(mask_bytes, dtype=np.uint8)[: n_blocks * w].reshape(n_blocks, w)
-    out = np.zeros(n_blocks, dtype=np.uint32)
-    for i in range(w):
-        out |= b[:, i].astype(np.uint32) << np.uint32(8 * i)
-    return out
-
-
 # --------------------------------------------------------------------------
-# Algorithm 1, executed as printed in the paper (scalar inner loop), tiny inputs
+# The format's meaning, block by block (tiny inputs)
 # --------------------------------------------------------------------------
 def vexpand(mask: int, packed, width: int):
     """The vexpandpd rule (Vectorization section): lane k takes the next packed
@@ -237,29 +228,29 @@ def vexpand(mask: int, packed, width: int):
     return out, idx
 
 
-def alg1_spmv(beta: BetaRef, x, y=None):
-    """Algorithm 1: y += A x over beta(r,c), following its loops in order.
+def expand_to_dense(beta: BetaRef) -> np.ndarray:
+    """The dense matrix a beta(r,c) matrix stands for.
 
-    Outer loop over row intervals of height r, inner loop over the interval's
-    blocks (block_rowptr gives the range), for each block row the c-bit slice
-    of the mask, and a running value cursor advanced once per set bit."""
+    Each block is an r x c tile whose upper-left corner is (interval * r,
+    block column). Its packed values are expanded by the vexpand rule over
+    the block's r*c mask bits taken row after row (values are row-major
+    inside a block, and bit i*c + k is row i, column k), so the tile's entry
+    (i, k) is the next packed value when that bit is set and 0 otherwise.
+    Tiles of one interval never overlap, so they are written, not added."""
     r, c = beta.r, beta.c
-    y = np.zeros(beta.n_rows) if y is None else np.array(y, dtype=np.float64)
-    idx_val = 0
+    out = np.zeros((beta.n_rows, beta.n_cols + c), dtype=np.float64)
+    vpos = 0
     for t in range(len(beta.block_rowptr) - 1):
-        sums = [0.0] * r
         for b in range(int(beta.block_rowptr[t]), int(beta.block_rowptr[t + 1])):
+            tile, used = vexpand(int(beta.masks[b]), beta.values[vpos:vpos + r * c], r * c)
+            vpos += used
             col = int(beta.block_colidx[b])
             for i in range(r):
-                row_mask = (int(beta.masks[b]) >> (i * c)) & ((1 << c) - 1)
-                for k in range(c):
-                    if (row_mask >> k) & 1:
-                        sums[i] += float(x[col + k]) * float(beta.values[idx_val])
-                        idx_val += 1
-        for i in range(r):
-            if t * r + i < beta.n_rows:
-                y[t * r + i] += sums[i]
-    return y
+                if t * r + i < beta.n_rows:
+                    out[t * r + i, col:col + c] = tile[i * c:(i + 1) * c]
+    if vpos != beta.values.size:
+        raise ValueError("mask bits do not account for every packed value")
+    return out[:, :beta.n_cols]
 
 
 def min_cover_bruteforce(cols: list[int], c: int) -> int:

@@ -57,15 +57,6 @@ def features(csr) -> np.ndarray:
     return f
 
 
-def avg_per_shape(csr) -> np.ndarray:
-    """Avg(r,c) = NNZ / N_blocks(r,c) for the six shapes (storage section)."""
-    out = np.zeros(len(SHAPES))
-    for k, (r, c) in enumerate(SHAPES):
-        nb = int(beta_count(csr, r, c).sum())
-        out[k] = csr.nnz / nb if nb else 0.0
-    return out
-
-
 class Interpolation:
     """Per-kernel polynomial of speed against Avg(r,c), fitted by least squares
     on recorded runs; a new matrix gets each kernel's predicted speed from its

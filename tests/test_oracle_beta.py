@@ -1,5 +1,5 @@
 """Pins for the beta(r,c) storage oracle (storage section, Eqs. (1)-(4),
-Algorithm 1, the vexpand rule, Table 1)."""
+the vexpand rule, Table 1)."""
 import json
 import os
 
@@ -86,17 +86,52 @@ def test_greedy_count_is_minimum_cover(r, c):
 
 
 @pytest.mark.parametrize("r,c", SHAPES)
-def test_algorithm1_equals_csr_product(r, c):
+def test_expansion_gives_back_the_matrix(r, c):
+    # storage section: a block is an r x c tile, its mask says which slots
+    # hold the next packed values (the vexpand rule, row after row); the tiles
+    # laid out at (interval * r, block column) must be the matrix itself
     for A in _cases():
-        if A.nnz > 20000:
+        if A.n_rows * A.n_cols > 400_000:
             continue
-        Ai = A.astype(np.float64)
-        Ai.values = np.round(A.values * 8)  # small integers: exact sums
-        x = np.round(synth.dense_vector(A.n_cols, 3) * 8)
-        b = oracle.csr_to_beta(Ai, r, c)
-        y0 = np.round(synth.dense_vector(A.n_rows, 4) * 8)
-        # Algorithm 1 accumulates into y
-        assert np.array_equal(oracle.alg1_spmv(b, x, y0), y0 + oracle.csr_spmv(Ai, x)[0])
+        dense = np.zeros((A.n_rows, A.n_cols))
+        for i in range(A.n_rows):
+            for p in range(A.rowptr[i], A.rowptr[i + 1]):
+                dense[i, A.colidx[p]] = A.values[p]
+        b = oracle.csr_to_beta(A, r, c)
+        assert np.array_equal(oracle.expand_to_dense(b), dense)
+
+
+def test_hand_drawn_blocks():
+    # rows 0..2 of a 3 x 12 matrix, entries (row, col) = value:
+    #   (0,2)=1 (0,5)=2 (1,3)=3 (1,4)=4 (1,9)=5 (2,0)=6
+    a = np.zeros((3, 12))
+    for (i, j), v in {(0, 2): 1, (0, 5): 2, (1, 3): 3, (1, 4): 4, (1, 9): 5, (2, 0): 6}.items():
+        a[i, j] = v
+    A = synth.from_dense(a)
+    # beta(2,4): interval 0 holds columns {2,3,4,5,9}. The first block starts
+    # at 2 and covers 2..5: row 0 sets bits 0 (col 2) and 3 (col 5), row 1
+    # bits 4+1 (col 3) and 4+2 (col 4): 1 + 8 + 32 + 64 = 105. The second
+    # starts at 9: row 1, column 0 of the block -> bit 4 = 16. Interval 1
+    # (row 2 only) has one block at column 0 with bit 0.
+    b = oracle.csr_to_beta(A, 2, 4)
+    assert b.block_rowptr.tolist() == [0, 2, 3]
+    assert b.block_colidx.tolist() == [2, 9, 0]
+    assert b.masks.tolist() == [105, 16, 1]
+    assert b.values.tolist() == [1, 2, 3, 4, 5, 6]       # row-major inside each block
+    # beta(1,8): row 0 -> one block at 2 with bits 0, 3 (= 9); row 1 -> one
+    # block at 3 covering 3..10 with bits 0, 1, 6 (= 67); row 2 -> bit 0 at 0
+    b = oracle.csr_to_beta(A, 1, 8)
+    assert b.block_colidx.tolist() == [2, 3, 0]
+    assert b.masks.tolist() == [9, 67, 1]
+    assert b.values.tolist() == [1, 2, 3, 4, 5, 6]
+    # beta(4,4): one interval (rows 0..2, row 3 absent); union of columns
+    # {0,2,3,4,5,9}: blocks at 0 (cols 0..3) -> (0,2) bit 2, (1,3) bit 4+3,
+    # (2,0) bit 8: 4 + 128 + 256 = 388; at 4 (cols 4..7) -> (0,5) bit 1,
+    # (1,4) bit 4: 2 + 16 = 18; at 9 -> (1,9) bit 4 = 16.
+    b = oracle.csr_to_beta(A, 4, 4)
+    assert b.block_colidx.tolist() == [0, 4, 9]
+    assert b.masks.tolist() == [388, 18, 16]
+    assert b.values.tolist() == [1, 3, 6, 2, 4, 5]
 
 
 def test_dense8000_table1_row():

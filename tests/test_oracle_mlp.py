@@ -72,3 +72,19 @@ def test_targets_and_training_reduces_loss():
     order = np.concatenate([rng.permutation(256) for _ in range(30)])
     P2, losses = mlp.train(P, X, tau, order, batch=32, lr=3e-3)
     assert np.mean(losses[-10:]) < 0.3 * np.mean(losses[:10])
+
+
+def test_standardizer_hand_computed():
+    # column 0: 1, 3, 8 -> mean 4, population variance (9 + 1 + 16) / 3 = 26/3
+    # (the sample variance would be 13); column 1 is constant -> spread 0,
+    # replaced by 1; column 2: spread 1e-13 (below 1e-12) -> 1; column 3:
+    # spread 2e-12 (kept)
+    X = np.array([[1.0, 5.0, 1.0 + 1e-13, 2e-12],
+                  [3.0, 5.0, 1.0 - 1e-13, -2e-12],
+                  [8.0, 5.0, 1.0 + 1e-13, 2e-12]])
+    mu, sd = mlp.standardize_stats(X)
+    assert mu[0] == 4.0 and mu[1] == 5.0
+    assert sd[0] == np.sqrt(26.0 / 3.0)
+    assert sd[1] == 1.0
+    assert sd[2] == 1.0                                  # population spread ~0.94e-13
+    assert abs(sd[3] - np.sqrt(32.0 / 9.0) * 1e-12) <= 1e-24   # population spread ~1.89e-12, kept

@@ -55,6 +55,25 @@ def test_single_value_block_share_constructed():
     assert S.features(synth.from_dense(np.ones((3, 16))))[15] == 0.0
 
 
+def test_span_feature_constructed():
+    # feature 15 = mean over non-empty rows of log2((last - first + 1) / length)
+    #   row 0: columns {0, 7}        span 8, length 2 -> log2(4) = 2
+    #   row 1: columns {3, 4, 5, 6}  span 4, length 4 -> 0
+    #   row 2: empty (not counted)
+    #   row 3: column {10}           span 1, length 1 -> 0
+    #   row 4: columns {1, 2, 9, 16} span 16, length 4 -> log2(4) = 2
+    # mean = (2 + 0 + 0 + 2) / 4 = 1; the inverted ratio would give -1, a span
+    # without the + 1 log2(7/2) + log2(3/4) + ... != 1
+    a = np.zeros((5, 20))
+    for i, cols in enumerate([[0, 7], [3, 4, 5, 6], [], [10], [1, 2, 9, 16]]):
+        a[i, cols] = 1.0
+    assert S.features(synth.from_dense(a))[15] == 1.0
+    # one row of length 3 spread over 12 columns: log2(12 / 3) = 2
+    b = np.zeros((1, 12))
+    b[0, [0, 5, 11]] = 1.0
+    assert S.features(synth.from_dense(b))[15] == 2.0
+
+
 def test_interpolation_recovers_known_cubic():
     rng = synth.rng_for(3)
     avgs = rng.uniform(1, 30, size=(40, 6))
