@@ -63,6 +63,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         i64, i32, vp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
         L.oracle_threads.restype = i32
+        L.oracle_set_threads.argtypes = [i32]
         L.oracle_csr_spmv.argtypes = [i64, vp, vp, vp, vp, vp, vp]
         L.oracle_csr_spmm.argtypes = [i64, vp, vp, vp, i32, vp, i64, vp, i64, vp]
         L.oracle_beta_count.argtypes = [i32, i32, i64, vp, vp, vp]
@@ -75,6 +76,11 @@ def lib():
 
 def threads() -> int:
     return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the C oracle's OpenMP loops from now on."""
+    lib().oracle_set_threads(int(n))
 
 
 def _p(a: np.ndarray):
@@ -300,3 +306,4 @@ def breakeven_avg(r: int, c: int, s_int: int = 4) -> float:
 from . import select as select  # noqa: E402  (re-export submodules)
 from . import mlp as mlp  # noqa: E402
 from . import cg as cg  # noqa: E402
+from . import reorder as reorder  # noqa: E402

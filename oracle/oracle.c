@@ -38,6 +38,16 @@ int oracle_threads(void) {
 #endif
 }
 
+/* Threads of the OpenMP loops that follow (the CPU baseline times one and
+ * all host threads); n < 1 leaves the setting alone. */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* y_i = sum_j a_ij x_j, summed left to right in column order, and
  * s_i = sum_j |a_ij x_j|. Rows are independent, so they are spread over
  * threads without changing any row's summation order. */

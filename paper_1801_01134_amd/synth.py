@@ -389,6 +389,27 @@ def grid_stencil(mx: int, my: int, mz: int, kind: str, keep: float = 1.0, seed: 
     return CSR(n, n, rowptr, colidx, rng.uniform(-1.0, 1.0, size=nnz))
 
 
+def grid_scrambled(mx: int, my: int, mz: int, kind: str, seed: int = 0) -> CSR:
+    """The grid operator of grid_stencil(mx, my, mz, kind) with its points
+    numbered in a seeded random order instead of the natural one: point p
+    carries the label lab[p], and every stencil pair (p, q) is the entry
+    (lab[p], lab[q]). Values U[-1, 1]."""
+    n = mx * my * mz
+    rng = rng_for(11, mx, my, mz, seed)
+    lab = rng.permutation(n).astype(np.int64)
+    idx = np.arange(n, dtype=np.int64)
+    x = idx % mx
+    y = (idx // mx) % my
+    z = idx // (mx * my)
+    rows, cols = [], []
+    for (dz, dy, dx) in STENCILS[kind]:
+        ok = (x + dx >= 0) & (x + dx < mx) & (y + dy >= 0) & (y + dy < my) & (z + dz >= 0) & (z + dz < mz)
+        p = idx[ok]
+        rows.append(lab[p])
+        cols.append(lab[p + dz * mx * my + dy * mx + dx])
+    return _from_keys(n, n, np.concatenate(rows), np.concatenate(cols), rng)
+
+
 def structured_matrix(index: int, min_rows: int = 50_000, max_rows: int = 4_000_000) -> tuple[str, CSR]:
     """Matrix `index` of the structured (grid operator) population."""
     rng = rng_for(50, index)
