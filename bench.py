@@ -65,29 +65,32 @@ def algorithmic_bytes(B, n_tiles: int, k: int = 1, accumulate: bool = False) -> 
     return b
 
 
-def measured_traffic(kname: str, shape, params: dict, m: int):
-    """HBM bytes per launch from the committed memory-counter summary of this
-    kernel, if the kernel sources are still the ones that were measured
-    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading); else
-    None."""
+PLAN_KEYS = ("mode", "wave_chunks", "tile_bits", "tile_order", "pipeline", "cu_groups")
+
+
+def committed_profile(kind: str, kname: str, shape, params: dict, m: int):
+    """The committed profile summary (profiles/*.<kind>.json: 'traffic' for
+    the memory counters, 'trace' for the kernel trace) of this kernel and
+    plan on the m^3 stencil, if the kernel sources still hash to the ones
+    that were measured; else None."""
     import glob
     import hashlib
     if m != 128:
         return None
-    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.traffic.json"))):
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", f"*.{kind}.json"))):
         with open(f) as fh:
             rec = json.load(fh)
         if rec.get("kernel") != kname or rec.get("shape") != list(shape):
             continue
-        keys = ("mode", "wave_chunks", "tile_bits", "xcd_remap", "pipeline", "cu_groups")
-        if {k: rec["plan"].get(k, 0) for k in keys} != {k: params.get(k, 0) for k in keys}:
+        if {k: rec["plan"].get(k, 0) for k in PLAN_KEYS} != {k: params.get(k, 0) for k in PLAN_KEYS}:
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
             with open(os.path.join(ROOT, src), "rb") as fh:
                 h.update(fh.read())
         if h.hexdigest() == rec["sha256"]:
-            return {"bytes": rec["traffic_bytes_per_launch"], "source": os.path.relpath(f, ROOT)}
+            rec["source"] = os.path.relpath(f, ROOT)
+            return rec
     return None
 
 
@@ -139,10 +142,48 @@ def small_case(spc, torch, steps: int = 2000):
             "note": "back-to-back launches from Python; us_device_tuned is the autotuner's device time"}
 
 
-def cpu_baseline(A, x, budget_s: float = 10.0):
-    """The FP64 CSR oracle (plain C, OpenMP over rows) on the host cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(A, x, label: str, budget_s: float = 10.0):
+    """The FP64 CSR oracle (plain C, OpenMP over rows) on the host cores.
+
+    value: consecutive full products for budget_s seconds on all host
+    threads. Beside it, the paper's protocol (16 consecutive products, the
+    first one on a matrix not read since it was built; mean and median) on
+    all threads and on one thread."""
+    import numpy as np
+
     import oracle
-    oracle.csr_spmv(A, x)  # first run: page-in
+    n_all = oracle.threads()
+
+    def sixteen(threads):
+        oracle.set_threads(threads)
+        # fresh copies of the arrays: the first product reads them cold
+        from paper_1801_01134_amd import synth
+        Ac = synth.CSR(A.n_rows, A.n_cols, A.rowptr.copy(), A.colidx.copy(), A.values.copy())
+        ts = []
+        for _ in range(16):
+            t0 = time.perf_counter()
+            oracle.csr_spmv(Ac, x)
+            ts.append(time.perf_counter() - t0)
+        ts = np.array(ts)
+        return {"threads": threads, "mean_ms": round(float(ts.mean()) * 1e3, 3),
+                "median_ms": round(float(np.median(ts)) * 1e3, 3), "first_ms": round(float(ts[0]) * 1e3, 3),
+                "gflops_mean": round(2.0 * A.nnz / ts.mean() / 1e9, 3),
+                "gflops_median": round(2.0 * A.nnz / float(np.median(ts)) / 1e9, 3)}
+
+    protocol = {"all_threads": sixteen(n_all), "one_thread": sixteen(1)}
+    oracle.set_threads(n_all)
     t0 = time.perf_counter()
     runs = 0
     while True:
@@ -152,10 +193,12 @@ def cpu_baseline(A, x, budget_s: float = 10.0):
         if el >= budget_s:
             break
     per = el / runs
-    return {"value": round(2.0 * A.nnz / per / 1e9, 3), "unit": "GFlop/s", "cores": oracle.threads(),
+    return {"value": round(2.0 * A.nnz / per / 1e9, 3), "unit": "GFlop/s", "cores": n_all,
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
             "kind": "oracle",
-            "sample": f"{runs} consecutive FP64 CSR products of the full 128^3 27-point matrix "
-                      f"(mean {per * 1e3:.1f} ms each, {el:.1f} s total)"}
+            "sample": f"{runs} consecutive FP64 CSR products of the full {label} on {n_all} "
+                      f"threads (mean {per * 1e3:.1f} ms each, {el:.1f} s total)",
+            "paper_protocol_16_runs": protocol}
 
 
 # ---------------------------------------------------------------------------
@@ -444,7 +487,7 @@ def main(argv=None):
     ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--batched-matrices", type=int, default=64)
     ap.add_argument("--cg-grid", type=int, default=192)
-    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,xcd_remap[,pipeline[,cu_groups]]: force "
+    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,tile_order[,pipeline[,cu_groups]]: force "
                     "the headline plan (skips autotuning; used for profiling)")
     ap.add_argument("--spmm", default="",
                     help="k,dtype(64|32),wave_chunks,cu_groups: time only Y = A X on the CG matrix (used for "
@@ -541,7 +584,7 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     csr_bytes = {8: A.nnz * 12 + (A.n_rows + 1) * 4, 4: A.nnz * 8 + (A.n_rows + 1) * 4}
     if args.only_steps:
         sel, model, _ = load_selector(spc)
-        print(json.dumps({"steps": steps_section(spc, torch, A, rp, ci, v64, sel, model)}), flush=True)
+        print(json.dumps({"step_timings": steps_section(spc, torch, A, rp, ci, v64, sel, model)}), flush=True)
         return 0
 
     sweep = {}
@@ -587,9 +630,9 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     B = spc.csr_to_beta(r, c, rp, ci, v64, A.n_cols)
     if args.plan:
         fields = [int(t) for t in args.plan.split(",")]
-        m_, v_, x_ = fields[:3]
+        m_, v_, o_ = fields[:3]
         params = {"mode": m_, "wave_chunks": v_ if m_ == 0 else 0, "tile_bits": v_ if m_ == 1 else 0,
-                  "xcd_remap": x_, "pipeline": fields[3] if len(fields) > 3 else 0}
+                  "tile_order": o_, "pipeline": fields[3] if len(fields) > 3 else 0}
         if len(fields) > 4 and fields[4]:
             params["cu_groups"] = fields[4]
     else:
@@ -621,7 +664,14 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     ab = algorithmic_bytes(B, info["n_tiles"])
     achieved = ab / t_kernel / 1e9
     value = flops / (wall / args.steps) / 1e9
-    traffic = measured_traffic(kname, (r, c), params, m)
+    traffic = committed_profile("traffic", kname, (r, c), params, m)
+    trace = committed_profile("trace", kname, (r, c), params, m)
+    # the timed launches' result against the FP64 CSR oracle, per row
+    import oracle
+    y_ref, s_ref = oracle.csr_spmv(A, x64)
+    err = abs(yd.cpu().numpy() - y_ref)
+    matches = bool((err <= 1e-13 * s_ref).all())
+    worst = float((err / (1e-13 * s_ref + 1e-300)).max())
     del B, P
 
     # selection: shapes picked from the matrix's features alone
@@ -655,10 +705,16 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
                    "nnz": A.nnz, "tile_bits": info.get("tile_bits"), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic": traffic["traffic_bytes_per_launch"] if traffic else None,
                      "traffic_source": traffic["source"] if traffic else "no counter record for this kernel build",
                      "kernel": kname, "plan": params,
-                     "alg_bytes_per_launch": ab, "kernel_us": round(t_kernel * 1e6, 2)},
+                     "alg_bytes_per_launch": ab, "kernel_us": round(t_kernel * 1e6, 2),
+                     "kernel_us_source": f"HIP events around {args.steps} back-to-back launches on the launch stream",
+                     "kernel_us_trace": trace["avg_ns"] / 1e3 if trace else None,
+                     "frac_trace": round(ab / (trace["avg_ns"] * 1e-9) / 1e9 / HBM_PEAK_GBS, 4) if trace else None,
+                     "trace_source": trace["source"] if trace else "no kernel trace for this kernel build and plan",
+                     "target_frac": 0.70,
+                     "matches_oracle": matches, "max_err_over_bound": round(worst, 4)},
         "selected_vs_best_time_ratio": ratio,
         "headline_selection": "fastest of the six beta kernels on this matrix, each autotuned over its plan "
                               "candidates (records taken in this run)" if args.shape == "auto" else "forced",
@@ -666,8 +722,8 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         "per_kernel": sweep,
     }
     if do_select:
-        out["steps"] = steps_section(spc, torch, A, rp, ci, v64, sel, model)
-        log(f"steps: {out['steps']}")
+        out["step_timings"] = steps_section(spc, torch, A, rp, ci, v64, sel, model)
+        log(f"step timings: {out['step_timings']}")
         torch.cuda.empty_cache()
     if do_batched:
         out["batched"] = batched_section(spc, torch, sel, model, pool, tmp, args.batched_matrices,
@@ -685,7 +741,7 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         out["small_case"] = small_case(spc, torch)
         log(f"small case: {out['small_case']}")
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(A, x64)
+        out["cpu_baseline"] = cpu_baseline(A, x64, f"{m}^3 27-point matrix")
     print(json.dumps(out), flush=True)
     return 0
 

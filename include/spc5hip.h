@@ -129,6 +129,40 @@ spc_status spc_beta_to_csr(const spc_beta_view *A, int32_t *rowptr_out, int32_t 
                            void *values_out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Reordering before conversion (section "Matrix permutation/reordering": a
+ * Cuthill-McKee breadth-first renumbering puts coupled rows and columns side
+ * by side, so that r x c blocks hold more values). For a square matrix.
+ *
+ * spc_rcm_order: reverse Cuthill-McKee order of the pattern of A + A^T
+ *   (diagonal ignored) into perm_out (device int32[n], perm[new] = old).
+ *   The order is fully defined: deg(v) = distinct neighbours of v; the
+ *   search starts at the unnumbered vertex of smallest degree (smallest
+ *   index on ties); each vertex taken off the queue numbers its unnumbered
+ *   neighbours in (degree, index) order; an exhausted queue with vertices
+ *   left restarts from a new start vertex; the final order is reversed. The
+ *   walk runs on the host (the pattern is copied there once). rowptr int32
+ *   [n+1], colidx int32[nnz] (device; rows need not be sorted). Errors:
+ *   SPC_ERR_INDEX_RANGE (bad row pointers or columns), SPC_ERR_OVERFLOW.
+ *   Synchronizes.
+ * spc_csr_permute: B = P A P^T on the device: B[i][j] = A[perm[i]][perm[j]],
+ *   rows of B with sorted columns, values (dtype) moved bit for bit.
+ *   rowptr_out int32[n+1], colidx_out int32[nnz], values_out[nnz] (caller
+ *   allocated). SPC_ERR_INDEX_RANGE if perm is not a permutation of 0..n-1.
+ *   Synchronizes.
+ * spc_permute_vector: scatter = 0: out[i] = in[perm[i]] (x' = P x);
+ *   scatter = 1: out[perm[i]] = in[i] (y = P^T y'). So y = A x is
+ *   spc_permute_vector(scatter 1) of B (spc_permute_vector(scatter 0) of x).
+ *   in and out must not overlap. Asynchronous. */
+spc_status spc_rcm_order(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                         int32_t *perm_out, hipStream_t stream);
+spc_status spc_csr_permute(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                           int32_t dtype, const void *values, const int32_t *perm,
+                           int32_t *rowptr_out, int32_t *colidx_out, void *values_out,
+                           hipStream_t stream);
+spc_status spc_permute_vector(int64_t n, int32_t dtype, const int32_t *perm, const void *in, void *out,
+                              int32_t scatter, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Plans: the row-interval partition the kernels run on (Design,
  * "Parallelization": consecutive intervals grouped so that groups hold about
  * the same number of blocks and no interval is split). A tile is one such
@@ -139,18 +173,25 @@ spc_status spc_beta_to_csr(const spc_beta_view *A, int32_t *rowptr_out, int32_t 
  *              one of 1024, 2048, 3072, 4032. Mode 0 sizes its tiles from
  *              wave_chunks instead: (64 * wave_chunks - 1) * (16 / value size)
  *              bits, so one wavefront's 16-byte loads cover a tile's values
- *   xcd_remap  0 or 1 = give each of the 8 XCDs one contiguous range of
- *              tiles (0 is the default), 2 = hardware round-robin order
+ *   tile_order SPC_ORDER_XCD (0, the default): workgroup g runs on XCD
+ *              g mod 8, so the launch renumbers tiles to give each of the 8
+ *              XCDs one contiguous range of them (the x entries a range
+ *              gathers then stay in that XCD's L2); SPC_ORDER_HW (1): tiles
+ *              in the hardware's round-robin order (neighbouring tiles on
+ *              different XCDs). Persistent (pipelined) launches ignore it.
  *   mode       0 = one wavefront per tile, four independent tiles per
  *              workgroup: all of a tile's streams are requested at once
  *              (values with 16-byte loads), x is gathered one lane per value;
  *              1 = one workgroup per tile, one lane per mask bit loads,
  *              gathers and multiplies (the direct form of the vexpand step)
- * params == NULL (or all zeros) selects the defaults. */
+ * params == NULL selects spc_plan_default_params(A); all zeros select mode 0
+ * with 4 chunks per lane. */
 typedef struct spc_plan spc_plan;
+#define SPC_ORDER_XCD 0   /* tile_order: each XCD walks one contiguous range of tiles (default) */
+#define SPC_ORDER_HW  1   /* tile_order: the hardware's round-robin of workgroups over the XCDs */
 typedef struct spc_plan_params {
     int32_t tile_bits;
-    int32_t xcd_remap;
+    int32_t tile_order;     /* SPC_ORDER_XCD (0) or SPC_ORDER_HW (1) */
     int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles */
     int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4, 6 or 8; 0 = 4 */
     int32_t pipeline;       /* mode 0: 0 = one wavefront per tile; 1 = persistent wavefronts (as
@@ -166,6 +207,12 @@ typedef struct spc_plan_params {
 
 spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,
                            spc_plan **plan_out, hipStream_t stream);
+/* The library's default parameters for a matrix, from its sizes alone (no
+ * device access): mode 0, XCD order, no cap, and 8 chunks per lane from 16M
+ * entries up, 4 from 1M, else 2 (larger tiles cost fewer per-tile steps,
+ * smaller ones give small matrices enough wavefronts). They are not tuned:
+ * spc_autotune picks among measured candidates. */
+spc_status spc_plan_default_params(const spc_beta_view *A, spc_plan_params *params_out);
 spc_status spc_plan_destroy(spc_plan *plan);
 /* n_tiles, tiles taking the long-interval path, tile_bits actually used. */
 spc_status spc_plan_info(const spc_plan *plan, int64_t *n_tiles, int64_t *n_long,
@@ -176,9 +223,16 @@ spc_status spc_plan_info(const spc_plan *plan, int64_t *n_tiles, int64_t *n_long
  * row sums into y). x: n_cols entries, y: n_rows entries, both of A's dtype.
  * Only stored entries touch y (an Inf or NaN in x under an unset mask bit
  * does not reach y). Rows with no entries get +0 when accumulate = 0.
- * Summation is in double precision for both dtypes, in an order fixed by
- * the plan, so repeated calls give identical bits. plan must come from
- * spc_plan_create on this same A. Asynchronous. */
+ * Precision: FP64 forms every product and sum in double precision. FP32
+ * forms each product, and the sum of the (at most c = 8) products of one
+ * block row of one block, in single precision; those block-row sums are
+ * added in double precision and the row is rounded to float once. The order
+ * of additions is fixed by the plan, so repeated calls give identical bits.
+ * plan: from spc_plan_create on this same A; or NULL, in which case the call
+ * builds a plan with spc_plan_default_params(A), runs the product and
+ * releases the plan: it then reads block_rowptr to the host and
+ * synchronizes the stream (a convenience for one-off products; callers that
+ * repeat products keep a plan). Asynchronous when plan is not NULL. */
 spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan, const void *x, void *y,
                          int32_t accumulate, hipStream_t stream);
 
@@ -192,7 +246,9 @@ spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan, const voi
  * 16 / (value size) and X, Y and their leading dimensions keep every such
  * group of columns 16-byte aligned, groups of columns share one pass (the
  * results are the same bits). k = 1 with unit leading dimensions runs the
- * single-vector kernel. Asynchronous. */
+ * single-vector kernel. plan NULL: as for spc_spmv_beta (a default plan is
+ * built and released by the call, which then synchronizes). Asynchronous
+ * when plan is not NULL. */
 spc_status spc_spmm_beta(const spc_beta_view *A, const spc_plan *plan, int32_t k, const void *X,
                          int64_t ldx, void *Y, int64_t ldy, int32_t accumulate, hipStream_t stream);
 
@@ -308,6 +364,7 @@ spc_status spc_spmv_batched(spc_batch *batch, int32_t accumulate, int32_t grid_b
 spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
                                const int32_t *colidx, float *features_out, int64_t *n_blocks_out,
                                hipStream_t stream);
+
 
 /* ---------------------------------------------------------------------------
  * Learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU network in FP32 whose

@@ -9,5 +9,5 @@ from . import synth  # noqa: F401
 from ._binding import (MLP_N_PARAMS, SEL_INTERP, SEL_MLP, Selector, mlp_infer, mlp_loss_grad,  # noqa: F401
                        mlp_standardizer, mlp_targets, mlp_train)
 from ._binding import (SHAPES, Batch, BetaMatrix, Plan, SpcError, autotune, beta_to_csr, cg,  # noqa: F401
-                       csr_to_beta, lib, mask_bytes, matrix_features, plan_from, spmm, spmv,
-                       time_spmv)
+                       csr_permute, csr_to_beta, lib, mask_bytes, matrix_features, permute_vector, plan_from,
+                       rcm_order, spmm, spmv, time_spmv)

@@ -32,7 +32,7 @@ class BetaView(ctypes.Structure):
 
 
 class PlanParams(ctypes.Structure):
-    _fields_ = [("tile_bits", c_int32), ("xcd_remap", c_int32), ("mode", c_int32),
+    _fields_ = [("tile_bits", c_int32), ("tile_order", c_int32), ("mode", c_int32),
                 ("wave_chunks", c_int32), ("pipeline", c_int32), ("cu_groups", c_int32),
                 ("reserved", c_int32 * 2)]
 
@@ -55,8 +55,13 @@ _SIGS = {
     "spc_csr_to_beta": (c_int32, [c_int32, c_int32, c_int32, c_int64, c_int64, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "spc_beta_to_csr": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "spc_rcm_order": (c_int32, [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "spc_csr_permute": (c_int32, [c_int64, c_int64, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
+    "spc_permute_vector": (c_int32, [c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "spc_plan_create": (c_int32, [POINTER(BetaView), POINTER(PlanParams), POINTER(c_void_p), c_void_p]),
     "spc_plan_destroy": (c_int32, [c_void_p]),
+    "spc_plan_default_params": (c_int32, [POINTER(BetaView), POINTER(PlanParams)]),
     "spc_plan_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
     "spc_spmv_beta": (c_int32, [POINTER(BetaView), c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "spc_spmm_beta": (c_int32, [POINTER(BetaView), c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64,
@@ -164,11 +169,11 @@ def mask_bytes(r: int, c: int, n_blocks: int) -> int:
 class Plan:
     """A tile plan (library-owned) for one BetaMatrix."""
 
-    def __init__(self, A: "BetaMatrix", tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0,
+    def __init__(self, A: "BetaMatrix", tile_bits: int = 0, tile_order: int = 0, mode: int = 0,
                  wave_chunks: int = 0, pipeline: int = 0, cu_groups: int = 0):
         self._A = A
         self._view = A.view()
-        p = PlanParams(tile_bits, xcd_remap, mode, wave_chunks, pipeline, cu_groups)
+        p = PlanParams(tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups)
         h = c_void_p()
         check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
                                     stream_ptr()))
@@ -223,12 +228,22 @@ class BetaMatrix:
                         self.block_masks.data_ptr(),
                         self.values.data_ptr() if self.nnz else None)
 
-    def plan(self, tile_bits: int = 0, xcd_remap: int = 0, mode: int = 0, wave_chunks: int = 0,
+    def plan(self, tile_bits: int = 0, tile_order: int = 0, mode: int = 0, wave_chunks: int = 0,
              pipeline: int = 0, cu_groups: int = 0) -> Plan:
-        key = (tile_bits, xcd_remap, mode, wave_chunks, pipeline, cu_groups)
+        key = (tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups)
         if key not in self._plans:
-            self._plans[key] = Plan(self, tile_bits, xcd_remap, mode, wave_chunks, pipeline, cu_groups)
+            self._plans[key] = Plan(self, tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups)
         return self._plans[key]
+
+    def default_params(self) -> dict:
+        """The library's default plan parameters for this matrix (from its sizes)."""
+        v = self.view()
+        p = PlanParams()
+        check(lib().spc_plan_default_params(ctypes.byref(v), ctypes.byref(p)))
+        return _params_dict(p)
+
+    def default_plan(self) -> Plan:
+        return plan_from(self, self.default_params())
 
     def nbytes(self) -> int:
         """Bytes of the four arrays as Eq. (1) counts them (masks unpadded)."""
@@ -265,6 +280,42 @@ def csr_to_beta(r: int, c: int, rowptr, colidx, values, n_cols: int, dtype=None,
     return BetaMatrix(r, c, n_rows, n_cols, brow, bcol, masks, vout)
 
 
+def rcm_order(rowptr, colidx, device="cuda") -> torch.Tensor:
+    """Reverse Cuthill-McKee order (perm[new] = old, int32 device tensor) of
+    a square CSR pattern."""
+    rp = _dev(rowptr, torch.int32, device)
+    ci = _dev(colidx, torch.int32, device)
+    n, nnz = rp.numel() - 1, ci.numel()
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    check(lib().spc_rcm_order(n, nnz, _ptr(rp), _ptr(ci) if nnz else None, _ptr(perm), stream_ptr()))
+    return perm[:n]
+
+
+def csr_permute(rowptr, colidx, values, perm, device="cuda"):
+    """B = P A P^T (rows and columns renumbered by perm[new] = old) as device
+    tensors (rowptr, colidx, values)."""
+    rp = _dev(rowptr, torch.int32, device)
+    ci = _dev(colidx, torch.int32, device)
+    v = _dev(values, None, device)
+    pm = _dev(perm, torch.int32, device)
+    n, nnz = rp.numel() - 1, ci.numel()
+    rp2 = torch.empty(n + 1, dtype=torch.int32, device=device)
+    ci2 = torch.empty(nnz, dtype=torch.int32, device=device)
+    v2 = torch.empty_like(v)
+    check(lib().spc_csr_permute(n, nnz, _ptr(rp), _ptr(ci) if nnz else None, _dtype_code(v.dtype),
+                                _ptr(v) if nnz else None, _ptr(pm) if n else None, _ptr(rp2),
+                                _ptr(ci2) if nnz else None, _ptr(v2) if nnz else None, stream_ptr()))
+    return rp2, ci2, v2
+
+
+def permute_vector(x: torch.Tensor, perm: torch.Tensor, scatter: bool = False) -> torch.Tensor:
+    """scatter False: out[i] = x[perm[i]]; True: out[perm[i]] = x[i]."""
+    out = torch.empty_like(x)
+    check(lib().spc_permute_vector(x.numel(), _dtype_code(x.dtype), _ptr(perm), _ptr(x), _ptr(out),
+                                   int(scatter), stream_ptr()))
+    return out
+
+
 def beta_to_csr(A: BetaMatrix):
     """BetaMatrix -> (rowptr, colidx, values) device tensors."""
     rp = torch.empty(A.n_rows + 1, dtype=torch.int32, device=A.values.device)
@@ -287,7 +338,7 @@ def spmv(A: BetaMatrix, x: torch.Tensor, y: torch.Tensor | None = None, accumula
         y = torch.empty(A.n_rows, dtype=A.dtype, device=x.device)
     elif y.dtype != A.dtype or y.numel() != A.n_rows or not y.is_contiguous():
         raise ValueError("y must be a contiguous vector of n_rows entries of A's dtype")
-    plan = plan or A.plan()
+    plan = plan or A.default_plan()
     view = plan._view
     check(lib().spc_spmv_beta(ctypes.byref(view), plan.handle, _ptr(x), _ptr(y), int(accumulate),
                               stream_ptr()))
@@ -296,7 +347,7 @@ def spmv(A: BetaMatrix, x: torch.Tensor, y: torch.Tensor | None = None, accumula
 
 def time_spmv(A: BetaMatrix, plan: Plan | None = None, reps: int = 20, warmup: int = 3) -> float:
     """Average device time (us) of one y = A x launch under the plan."""
-    plan = plan or A.plan()
+    plan = plan or A.default_plan()
     x = torch.zeros(A.n_cols, dtype=A.dtype, device=A.values.device)
     y = torch.empty(A.n_rows, dtype=A.dtype, device=A.values.device)
     us = ctypes.c_float()
@@ -319,18 +370,20 @@ def autotune(A: BetaMatrix, reps: int = 20, x: torch.Tensor | None = None):
                              ctypes.byref(best_us), ctypes.cast(recs, c_void_p), 64, ctypes.byref(n),
                              stream_ptr()))
 
-    def pd(p):
-        d = {"mode": p.mode, "tile_bits": p.tile_bits, "wave_chunks": p.wave_chunks,
-             "xcd_remap": p.xcd_remap, "pipeline": p.pipeline}
-        if p.cu_groups:
-            d["cu_groups"] = p.cu_groups
-        return d
-    records = [dict(pd(recs[i].params), us=recs[i].us, n_tiles=recs[i].n_tiles) for i in range(n.value)]
-    return pd(best), best_us.value, records
+    records = [dict(_params_dict(recs[i].params), us=recs[i].us, n_tiles=recs[i].n_tiles) for i in range(n.value)]
+    return _params_dict(best), best_us.value, records
+
+
+def _params_dict(p: PlanParams) -> dict:
+    d = {"mode": p.mode, "tile_bits": p.tile_bits, "wave_chunks": p.wave_chunks,
+         "tile_order": p.tile_order, "pipeline": p.pipeline}
+    if p.cu_groups:
+        d["cu_groups"] = p.cu_groups
+    return d
 
 
 def plan_from(A: BetaMatrix, params: dict) -> Plan:
-    return A.plan(params.get("tile_bits", 0), params.get("xcd_remap", 0), params.get("mode", 0),
+    return A.plan(params.get("tile_bits", 0), params.get("tile_order", 0), params.get("mode", 0),
                   params.get("wave_chunks", 0), params.get("pipeline", 0), params.get("cu_groups", 0))
 
 
@@ -346,7 +399,7 @@ def spmm(A: BetaMatrix, X: torch.Tensor, Y: torch.Tensor | None = None, accumula
         Y = torch.empty((A.n_rows, k), dtype=A.dtype, device=X.device)
     elif Y.shape != (A.n_rows, k) or Y.dtype != A.dtype or Y.stride(1) != 1:
         raise ValueError("Y must be n_rows x k, row-major, of A's dtype")
-    plan = plan or A.plan()
+    plan = plan or A.default_plan()
     check(lib().spc_spmm_beta(ctypes.byref(plan._view), plan.handle, k, _ptr(X), X.stride(0), _ptr(Y),
                               Y.stride(0), int(accumulate), stream_ptr()))
     return Y
@@ -370,7 +423,7 @@ def cg(A: BetaMatrix, B: torch.Tensor, rel_tol: float = 1e-8, max_iter: int = 10
     its = (c_int32 * k)()
     res = (ctypes.c_double * k)()
     tot = c_int32()
-    plan = plan or A.plan()
+    plan = plan or A.default_plan()
     check(lib().spc_cg_solve(ctypes.byref(plan._view), plan.handle, k, _ptr(B), B.stride(0), _ptr(X),
                              X.stride(0), rel_tol, max_iter, check_every, int(use_graph), _ptr(ws), nbytes,
                              ctypes.cast(its, POINTER(c_int32)), ctypes.cast(res, POINTER(ctypes.c_double)),

@@ -150,6 +150,22 @@ struct DevBuf {
     T *as() const { return static_cast<T *>(p); }
 };
 
+// A plan that lives for one call: released after the work queued on its
+// stream has finished (its tile descriptors are read by that work).
+struct TempPlan {
+    spc_plan *p = nullptr;
+    hipStream_t s;
+    explicit TempPlan(hipStream_t stream) : s(stream) {}
+    ~TempPlan() {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)spc_plan_destroy(p);
+        }
+    }
+    TempPlan(const TempPlan &) = delete;
+    TempPlan &operator=(const TempPlan &) = delete;
+};
+
 }  // namespace spc
 
 struct spc_plan {

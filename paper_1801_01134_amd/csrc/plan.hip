@@ -76,9 +76,14 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     SPC_REQUIRE(plan_out != nullptr, SPC_ERR_INVALID_ARG, "null plan_out");
     *plan_out = nullptr;
     const int tile_bits = params && params->tile_bits ? params->tile_bits : 2048;
-    const int remap_arg = params ? params->xcd_remap : 0;
-    SPC_REQUIRE(remap_arg >= 0 && remap_arg <= 2, SPC_ERR_INVALID_ARG, "xcd_remap must be 0, 1 or 2");
-    const int xcd_remap = remap_arg != 2;
+    spc_plan_params dflt{};
+    if (!params) {
+        spc_plan_default_params(A, &dflt);
+        params = &dflt;
+    }
+    SPC_REQUIRE(params->tile_order == SPC_ORDER_XCD || params->tile_order == SPC_ORDER_HW, SPC_ERR_INVALID_ARG,
+                "tile_order must be SPC_ORDER_XCD (0) or SPC_ORDER_HW (1)");
+    const int xcd_remap = params->tile_order == SPC_ORDER_XCD;
     const int mode = params ? params->mode : 0;
     SPC_REQUIRE(mode == 0 || mode == 1, SPC_ERR_INVALID_ARG, "mode must be 0 or 1");
     const int kq = params && params->wave_chunks ? params->wave_chunks : 4;
@@ -224,6 +229,16 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     return SPC_OK;
 }
 
+extern "C" spc_status spc_plan_default_params(const spc_beta_view *A, spc_plan_params *params_out) {
+    SPC_REQUIRE(A && params_out, SPC_ERR_INVALID_ARG, "null view or params_out");
+    spc_plan_params p{};
+    p.mode = 0;
+    p.tile_order = SPC_ORDER_XCD;
+    p.wave_chunks = A->nnz >= (int64_t(1) << 24) ? 8 : A->nnz >= (int64_t(1) << 20) ? 4 : 2;
+    *params_out = p;
+    return SPC_OK;
+}
+
 extern "C" spc_status spc_plan_destroy(spc_plan *plan) {
     if (!plan) return SPC_OK;
     if (plan->d_tiles) SPC_HIP(hipFree(plan->d_tiles));
@@ -255,8 +270,8 @@ extern "C" spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan
                                     int32_t accumulate, hipStream_t stream) {
     spc_status st = check_view(A);
     if (st != SPC_OK) return st;
-    SPC_REQUIRE(plan != nullptr, SPC_ERR_INVALID_ARG, "null plan (create one with spc_plan_create)");
-    SPC_REQUIRE(same_view(*A, plan->A), SPC_ERR_INVALID_ARG, "plan was built for a different matrix view");
+    SPC_REQUIRE(plan == nullptr || same_view(*A, plan->A), SPC_ERR_INVALID_ARG,
+                "plan was built for a different matrix view");
     SPC_REQUIRE(accumulate == 0 || accumulate == 1, SPC_ERR_INVALID_ARG, "accumulate must be 0 or 1");
     if (A->n_rows == 0) return SPC_OK;
     SPC_REQUIRE(y != nullptr, SPC_ERR_INVALID_ARG, "null y");
@@ -264,6 +279,13 @@ extern "C" spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan
     const size_t es = A->dtype == SPC_F64 ? 8 : 4;
     SPC_REQUIRE(reinterpret_cast<uintptr_t>(y) % es == 0 && reinterpret_cast<uintptr_t>(x) % es == 0,
                 SPC_ERR_INVALID_ARG, "x and y must be aligned to the element size");
+    if (plan == nullptr) {
+        // one-off product: a default plan that lives for this call only
+        TempPlan tp(stream);
+        if ((st = spc_plan_create(A, nullptr, &tp.p, stream)) != SPC_OK) return st;
+        if (tp.p->n_tiles == 0) return SPC_OK;
+        return spmv_launch(A, tp.p, x, y, accumulate, stream);
+    }
     if (plan->n_tiles == 0) return SPC_OK;
     return spmv_launch(A, plan, x, y, accumulate, stream);
 }

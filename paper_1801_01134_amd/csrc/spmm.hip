@@ -484,7 +484,12 @@ extern "C" spc_status spc_spmm_beta(const spc_beta_view *A, const spc_plan *plan
                                     int64_t ldx, void *Y, int64_t ldy, int32_t accumulate, hipStream_t stream) {
     spc_status st = spc::check_view(A);
     if (st != SPC_OK) return st;
-    SPC_REQUIRE(plan != nullptr, SPC_ERR_INVALID_ARG, "null plan (create one with spc_plan_create)");
+    spc::TempPlan tp(stream);
+    if (plan == nullptr) {
+        // one-off product: a default plan (mode 0) that lives for this call only
+        if ((st = spc_plan_create(A, nullptr, &tp.p, stream)) != SPC_OK) return st;
+        plan = tp.p;
+    }
     SPC_REQUIRE(plan->mode == 0, SPC_ERR_INVALID_ARG, "spc_spmm_beta needs a plan of mode 0 (wavefront tiles)");
     SPC_REQUIRE(plan->A.block_rowptr == A->block_rowptr && plan->A.values == A->values &&
                     plan->A.block_masks == A->block_masks && plan->A.n_rows == A->n_rows,

@@ -44,14 +44,14 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
     SPC_REQUIRE(best && best_us && reps > 0, SPC_ERR_INVALID_ARG, "bad autotune arguments");
     if (n_records) *n_records = 0;
     std::vector<spc_plan_params> cands;
-    for (int remap : {0, 2}) {
+    for (int order : {SPC_ORDER_XCD, SPC_ORDER_HW}) {
         for (int kq : {2, 4, 6, 8}) {
             spc_plan_params p{};
             p.mode = 0;
             p.wave_chunks = kq;
-            p.xcd_remap = remap;
+            p.tile_order = order;
             cands.push_back(p);
-            if (remap == 0) {
+            if (order == SPC_ORDER_XCD) {
                 if (kq >= 4) {
                     for (int cap : {2, 4}) {  // fewer resident workgroups per compute unit
                         spc_plan_params q = p;
@@ -67,7 +67,7 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
             spc_plan_params p{};
             p.mode = 1;
             p.tile_bits = tb;
-            p.xcd_remap = remap;
+            p.tile_order = order;
             cands.push_back(p);
         }
     }

@@ -59,16 +59,27 @@ def _generate(args):
     return index, fam, A.n_rows, A.n_cols, base, time.perf_counter() - t0
 
 
+class _Ready:
+    """A result computed in this process, read like a pool's async result."""
+
+    def __init__(self, value):
+        self.value = value
+
+    def get(self):
+        return self.value
+
+
 def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int = 12,
             min_rows: int = DEFAULT_MIN_ROWS, max_rows: int = DEFAULT_MAX_ROWS, population: str = "selector",
             log=sys.stderr):
     if population not in POPULATIONS:
         raise ValueError(f"population must be one of {POPULATIONS}")
     import multiprocessing as mp
-    # the pool is forked before this process initialises the GPU
+    # the pool is forked before this process initialises the GPU; workers = 0
+    # generates the matrices in this process instead (no fork)
     ctx = mp.get_context("fork")
     tmp = tempfile.mkdtemp(prefix="spc_records_")
-    pool = ctx.Pool(workers)
+    pool = ctx.Pool(workers) if workers > 0 else None
     try:
         import torch
 
@@ -77,13 +88,14 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
         gen = torch.Generator(device=dev)
         pending = []
         todo = list(range(first, first + count))
-        window = 2 * workers
+        window = max(1, 2 * workers)
         t_start = time.perf_counter()
         with open(out_path, "a") as out:
             while todo or pending:
                 while todo and len(pending) < window:
                     i = todo.pop(0)
-                    pending.append(pool.apply_async(_generate, ((i, min_rows, max_rows, tmp, population),)))
+                    job = (i, min_rows, max_rows, tmp, population)
+                    pending.append(pool.apply_async(_generate, (job,)) if pool else _Ready(_generate(job)))
                 index, fam, n_rows, n_cols, base, t_gen = pending.pop(0).get()
                 rp = torch.from_numpy(np.load(base + "_rp.npy")).to(dev)
                 ci = torch.from_numpy(np.load(base + "_ci.npy")).to(dev)
@@ -105,12 +117,12 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
                     us.append(float(t))
                     params.append(p)
                     d = [q["us"] for q in recs if q["mode"] == 0 and q["wave_chunks"] in (0, 4)
-                         and q["xcd_remap"] == 0]
+                         and q["tile_order"] == 0]
                     dflt.append(float(d[0]) if d else float("nan"))
                     ntiles.append(int(next((q["n_tiles"] for q in recs if q["mode"] == p["mode"]
                                             and q["wave_chunks"] == p["wave_chunks"]
                                             and q["tile_bits"] == p["tile_bits"]
-                                            and q["xcd_remap"] == p["xcd_remap"]), -1)))
+                                            and q["tile_order"] == p["tile_order"]), -1)))
                     del B
                 rec = {"population": population, "index": index, "family": fam, "n_rows": n_rows,
                        "n_cols": n_cols, "nnz": nnz,
@@ -125,8 +137,9 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
                       file=log, flush=True)
                 del rp, ci, vals, x
     finally:
-        pool.terminate()
-        pool.join()
+        if pool is not None:
+            pool.terminate()
+            pool.join()
         for f in os.listdir(tmp):
             os.remove(os.path.join(tmp, f))
         os.rmdir(tmp)

@@ -78,7 +78,7 @@ def test_plan_parameters_checked_on_the_host():
     for bad in (dict(cu_groups=1), dict(cu_groups=9), dict(cu_groups=-1),
                 dict(mode=1, tile_bits=2048, cu_groups=2), dict(mode=3),
                 dict(wave_chunks=5), dict(mode=1, tile_bits=1000), dict(pipeline=-1),
-                dict(mode=1, tile_bits=2048, pipeline=1), dict(xcd_remap=3)):
+                dict(mode=1, tile_bits=2048, pipeline=1), dict(tile_order=2), dict(tile_order=-1)):
         p = B.PlanParams(**bad)
         assert L.spc_plan_create(ctypes.byref(v), ctypes.byref(p), ctypes.byref(h), None) == -1, bad
         assert not h.value

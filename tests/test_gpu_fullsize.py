@@ -4,10 +4,16 @@ on the host), so these compare all outputs, not a sample:
 
   * the 27-point stencil of the 128^3 grid (2,097,152 rows, 55,742,968
     nonzeros) in all six shapes, FP64 and FP32, under every plan the
-    autotuner may pick (the headline launch among them);
+    autotuner may pick (the headline launch among them: 8 chunks per lane,
+    capped at 4 resident workgroups per compute unit), and the library's
+    default plan;
+  * Y = A X on the SPD 27-point matrix of the 192^3 grid (7,077,888 rows,
+    189,119,224 nonzeros) with k = 16 in FP64 and FP32 under the plans the
+    CG benchmark tunes to, every entry against the oracle;
   * the band + uniform matrix (n = 4096, 16 entries per row) in beta(1,8);
-  * CG on the SPD 27-point matrix of the 192^3 grid, k = 4, FP64 to 1e-8,
-    with the true residual recomputed by the oracle;
+  * CG on the SPD 27-point matrix of the 192^3 grid, k = 4, FP64 to 1e-8
+    and k = 16, FP32 to 1e-5, with the true residual recomputed by the
+    oracle;
   * 8 of the 64 batched matrices (rows log-uniform in [10k, 500k]) in one
     launch.
 """
@@ -67,16 +73,18 @@ def test_stencil128_all_rows_all_plans(rc, dtype):
     assert B.n_blocks == int(oracle.beta_count(A, r, c).sum())
     x = torch.from_numpy(S["x"]).cuda().to(dtype)
     ref = S["ref64"] if dtype == torch.float64 else S["ref32"]
-    plans = [dict(mode=0, wave_chunks=q, xcd_remap=xr, pipeline=0) for q in (2, 4, 6, 8) for xr in (0, 2)]
+    plans = [dict(mode=0, wave_chunks=q, tile_order=o, pipeline=0) for q in (2, 4, 6, 8) for o in (0, 1)]
+    plans += [dict(mode=0, wave_chunks=q, cu_groups=cap) for q in (4, 6, 8) for cap in (2, 4)]
     plans += [dict(mode=0, wave_chunks=q, pipeline=1) for q in (2, 4, 6, 8)]
-    plans += [dict(mode=1, tile_bits=tb, xcd_remap=xr) for tb in (1024, 4032) for xr in (0, 2)]
+    plans += [dict(mode=1, tile_bits=tb, tile_order=o) for tb in (1024, 4032) for o in (0, 1)]
+    plans += [B.default_params()]
     first = None
     for p in plans:
         y = spc.spmv(B, x, plan=spc.plan_from(B, p)).cpu().numpy()
         check(y, ref, TOL[dtype], f"beta{rc} {p}")
         if first is None:
             first = y
-    # the default plan (one wavefront per tile, 4 chunks) repeats bit for bit
+    # the library's default plan repeats bit for bit
     y1 = spc.spmv(B, x).cpu().numpy()
     y2 = spc.spmv(B, x).cpu().numpy()
     assert np.array_equal(y1.view(np.uint8), y2.view(np.uint8))
@@ -106,6 +114,51 @@ def test_cg_192_k4():
     assert all(0 < i <= total for i in its)
     true = ocg.true_residual(A, X.cpu().numpy(), Bm) / np.linalg.norm(Bm, axis=0)
     assert np.all(true <= 2e-8), true
+
+
+_cg192 = {}
+
+
+def stencil192():
+    if "A" not in _cg192:
+        _cg192["A"] = synth.stencil27(192, diag=26.1, offdiag=-1.0)
+    return _cg192["A"]
+
+
+@pytest.mark.parametrize("dtype,kq,cap", [(torch.float64, 6, 2), (torch.float64, 8, 4), (torch.float32, 4, 3),
+                                          (torch.float32, 8, 0)], ids=["f64-kq6-cap2", "f64-kq8-cap4",
+                                                                       "f32-kq4-cap3", "f32-kq8"])
+def test_spmm_192_k16_every_entry(dtype, kq, cap):
+    say(f"[full] SpMM 192^3 k=16 {dtype} chunks={kq} cap={cap}")
+    A = stencil192().astype(NP[dtype])
+    X = synth.dense_block(A.n_cols, 16, 702, dtype=NP[dtype])
+    B = spc.csr_to_beta(2, 4, torch.from_numpy(A.rowptr).cuda(), torch.from_numpy(A.colidx).cuda(),
+                        torch.from_numpy(A.values).cuda(), A.n_cols)
+    P = B.plan(0, 0, 0, kq, 0, cap)
+    Y = spc.spmm(B, torch.from_numpy(X).cuda(), plan=P).cpu().numpy().astype(np.float64)
+    Y_ref, S_ref = oracle.csr_spmm(A, X)
+    err = np.abs(Y - Y_ref)
+    bad = np.argwhere(~(err <= TOL[dtype] * S_ref))
+    assert bad.size == 0, f"{bad.shape[0]} entries off, first {bad[0]}"
+
+
+def test_cg_192_k16_fp32():
+    say("[full] CG 192^3 k=16 FP32")
+    A = stencil192()
+    A32 = A.astype(np.float32)
+    Bm = synth.dense_block(A.n_cols, 16, 717).astype(np.float32)
+    B = spc.csr_to_beta(2, 4, torch.from_numpy(A32.rowptr).cuda(), torch.from_numpy(A32.colidx).cuda(),
+                        torch.from_numpy(A32.values).cuda(), A32.n_cols)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        X, its, res, total = spc.cg(B, torch.from_numpy(Bm).cuda(), rel_tol=1e-5, max_iter=1000, check_every=25,
+                                    plan=B.plan(0, 0, 0, 4, 0, 3))
+    s.synchronize()
+    assert all(0 < i <= total for i in its)
+    Bh = Bm.astype(np.float64)
+    true = ocg.true_residual(A32, X.cpu().numpy().astype(np.float64), Bh) / np.linalg.norm(Bh, axis=0)
+    # the recurrence stops at 1e-5; the true residual of FP32 iterates stays within a few times that
+    assert np.all(true <= 5e-5), true
 
 
 def test_batched_config_sample():

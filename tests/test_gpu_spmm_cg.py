@@ -189,10 +189,10 @@ def test_resident_group_cap_same_bits(rc, dtype):
         X = synth.dense_block(A.n_cols, 16, 36, dtype=NP[dtype])
         Xd = torch.from_numpy(X).cuda()
         Y_ref, S_ref = oracle.csr_spmm(A, X)
-        for kq in (2, 6):
+        for kq in (2, 6, 8):
             Y0 = spc.spmm(B, Xd, plan=B.plan(0, 0, 0, kq))
             y0 = spc.spmv(B, Xd[:, 0].contiguous(), plan=B.plan(0, 0, 0, kq))
-            for cap in (2, 3, 8):
+            for cap in (2, 3, 4, 8):
                 P = B.plan(0, 0, 0, kq, 0, cap)
                 assert torch.equal(spc.spmm(B, Xd, plan=P), Y0), (name, kq, cap)
                 assert torch.equal(spc.spmv(B, Xd[:, 0].contiguous(), plan=P), y0), (name, kq, cap)

@@ -143,18 +143,18 @@ def test_spmv_parity(name, rc, dtype):
 
 
 @pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
-@pytest.mark.parametrize("mode,tile_bits,chunks,remap", [
-    (0, 0, 2, 0), (0, 0, 4, 2), (0, 0, 6, 0), (0, 0, 8, 1),
-    (1, 1024, 0, 0), (1, 2048, 0, 2), (1, 3072, 0, 0), (1, 4032, 0, 1)])
+@pytest.mark.parametrize("mode,tile_bits,chunks,order", [
+    (0, 0, 2, 0), (0, 0, 4, 1), (0, 0, 6, 0), (0, 0, 8, 1),
+    (1, 1024, 0, 0), (1, 2048, 0, 1), (1, 3072, 0, 0), (1, 4032, 0, 1)])
 @pytest.mark.parametrize("name", ["powerlaw", "stencil13", "fem6", "dense_rows", "empty_rows"])
-def test_plan_variants_and_determinism(rc, mode, tile_bits, chunks, remap, name):
+def test_plan_variants_and_determinism(rc, mode, tile_bits, chunks, order, name):
     r, c = rc
-    say(f"[plan] {name} beta{rc} mode={mode} tile_bits={tile_bits} chunks={chunks} remap={remap}")
+    say(f"[plan] {name} beta{rc} mode={mode} tile_bits={tile_bits} chunks={chunks} order={order}")
     A = case(name)
     x = synth.dense_vector(A.n_cols, 23)
     y_ref, s_ref = oracle.csr_spmv(A, x)
     B = to_beta(A, r, c, torch.float64)
-    P = B.plan(tile_bits, remap, mode, chunks)
+    P = B.plan(tile_bits, order, mode, chunks)
     info = P.info()
     want_bits = tile_bits if mode == 1 else (64 * chunks - 1) * 2
     assert info["tile_bits"] == want_bits and info["n_tiles"] > 0
@@ -359,3 +359,37 @@ def test_block_columns_not_16_byte_aligned(name, rc):
     assert int(bcol_big[0]) == -7 and bool((bcol_big[1 + nb:] == -7).all())
     assert np.array_equal(masks.cpu().numpy()[:nb * r * c // 8], ref.mask_bytes())
     assert np.array_equal(vout.cpu().numpy().view(np.uint64), ref.values.view(np.uint64))
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_null_plan_through_the_abi(rc, dtype):
+    """spc_spmv_beta and spc_spmm_beta with plan = NULL build the library's
+    default plan for the call: same result as that plan passed explicitly,
+    within the oracle's bound, with accumulate too."""
+    import ctypes
+    from paper_1801_01134_amd import _binding as Bd
+    r, c = rc
+    L, s = Bd.lib(), Bd.stream_ptr()
+    for name in ("powerlaw", "empty_rows", "stencil13"):
+        say(f"[null plan] {name} beta{rc} {dtype}")
+        A = case(name).astype(NP[dtype])
+        x = synth.dense_vector(A.n_cols, 71).astype(NP[dtype])
+        y_ref, s_ref = oracle.csr_spmv(A, x)
+        B = to_beta(A, r, c, dtype)
+        v = B.view()
+        xd = torch.from_numpy(x).cuda()
+        y = torch.full((A.n_rows,), 3.0, dtype=dtype, device="cuda")
+        Bd.check(L.spc_spmv_beta(ctypes.byref(v), None, Bd._ptr(xd), Bd._ptr(y), 0, s))
+        check_rows(y.cpu().numpy().astype(np.float64), y_ref, s_ref, TOL[dtype], f"null plan beta{rc}")
+        assert torch.equal(y, spc.spmv(B, xd, plan=B.default_plan()))
+        base = torch.from_numpy(synth.dense_vector(A.n_rows, 72).astype(NP[dtype])).cuda()
+        ya = base.clone()
+        Bd.check(L.spc_spmv_beta(ctypes.byref(v), None, Bd._ptr(xd), Bd._ptr(ya), 1, s))
+        yb = base.clone()
+        spc.spmv(B, xd, yb, accumulate=True, plan=B.default_plan())
+        assert torch.equal(ya, yb)
+        X = torch.from_numpy(synth.dense_block(A.n_cols, 4, 73, dtype=NP[dtype])).cuda()
+        Y = torch.empty((A.n_rows, 4), dtype=dtype, device="cuda")
+        Bd.check(L.spc_spmm_beta(ctypes.byref(v), None, 4, Bd._ptr(X), 4, Bd._ptr(Y), 4, 0, s))
+        assert torch.equal(Y, spc.spmm(B, X, plan=B.default_plan()))
