@@ -91,6 +91,58 @@ def fit_interpolation(avgs: np.ndarray, speeds: np.ndarray, degree: int = 3) -> 
     return Interpolation(coeffs, lo, hi, degree)
 
 
+class Interpolation2D:
+    """Per-kernel polynomial of speed against two inputs (section "Parallel
+    performance estimation": the average values per block and the amount of
+    parallel hardware, here u = log2 of the share of compute units used):
+    sum over i <= da, j <= du of c[i, j] Avg^i u^j, fitted by least squares.
+    A query's Avg and u are clamped to the fitted ranges; the fastest
+    prediction wins (lowest index on ties)."""
+
+    def __init__(self, coeffs, lo, hi, ulo, uhi):
+        self.coeffs = coeffs          # list of 2-D arrays c[i, j]
+        self.lo = np.asarray(lo, dtype=np.float64)
+        self.hi = np.asarray(hi, dtype=np.float64)
+        self.ulo, self.uhi = float(ulo), float(uhi)
+
+    def predict(self, avg, share) -> np.ndarray:
+        a = np.clip(np.asarray(avg, dtype=np.float64), self.lo, self.hi)
+        u = min(max(np.log2(share), self.ulo), self.uhi)
+        out = []
+        for k, c in enumerate(self.coeffs):
+            out.append(sum(c[i, j] * a[k] ** i * u ** j for i in range(c.shape[0]) for j in range(c.shape[1])))
+        return np.array(out)
+
+    def select(self, avg, share) -> int:
+        return int(np.argmax(self.predict(avg, share)))
+
+
+def fit_interpolation_2d(avgs, log2_shares, speeds, deg_avg: int = 3, deg_share: int = 2) -> Interpolation2D:
+    """avgs, speeds: [n, 6]; log2_shares: [n]. Degrees drop when the records
+    hold fewer distinct values than a degree needs, and then (share degree
+    first) while there are more coefficients than records."""
+    avgs = np.asarray(avgs, dtype=np.float64)
+    speeds = np.asarray(speeds, dtype=np.float64)
+    u = np.asarray(log2_shares, dtype=np.float64)
+    n = avgs.shape[0]
+    du0 = min(deg_share, len(np.unique(u)) - 1)
+    coeffs, lo, hi = [], [], []
+    for k in range(avgs.shape[1]):
+        a, s = avgs[:, k], speeds[:, k]
+        da, du = min(deg_avg, max(0, len(np.unique(a)) - 1)), du0
+        while (da + 1) * (du + 1) > n:
+            if du > 0:
+                du -= 1
+            else:
+                da -= 1
+        V = np.stack([a ** i * u ** j for i in range(da + 1) for j in range(du + 1)], axis=1)
+        c, *_ = np.linalg.lstsq(V, s, rcond=None)
+        coeffs.append(c.reshape(da + 1, du + 1))
+        lo.append(a.min())
+        hi.append(a.max())
+    return Interpolation2D(coeffs, lo, hi, u.min(), u.max())
+
+
 def regret(times_row, chosen: int) -> float:
     """t_selected / t_best - 1 (the time form of Table 3's speed difference)."""
     t = np.asarray(times_row, dtype=np.float64)

@@ -98,3 +98,40 @@ def test_select_ties_take_lowest_index_and_regret():
     assert S.best_kernel(t) == 1
     assert S.regret(t, 1) == 0.0 and S.regret(t, 4) == 0.0
     assert S.regret(t, 0) == pytest.approx(1.0)
+
+
+def test_interpolation_2d_recovers_a_known_surface():
+    # speed_k(Avg, u) = sum c_k[i, j] Avg^i u^j exactly, u = log2 share in {-3..0}
+    rng = synth.rng_for(4)
+    n = 200
+    avgs = rng.uniform(1, 30, size=(n, 6))
+    u = rng.choice([-3.0, -2.0, -1.0, 0.0], size=n)
+    true = [rng.normal(size=(4, 3)) * np.array([[1.0], [0.1], [0.01], [0.001]]) for _ in range(6)]
+    speeds = np.stack([sum(true[k][i, j] * avgs[:, k] ** i * u ** j for i in range(4) for j in range(3))
+                       for k in range(6)], axis=1)
+    m = S.fit_interpolation_2d(avgs, u, speeds, 3, 2)
+    for k in range(6):
+        assert np.allclose(m.coeffs[k], true[k], rtol=1e-7, atol=1e-9)
+    q = np.full(6, 7.0)
+    for share in (0.125, 0.5, 1.0):
+        want = [sum(true[k][i, j] * 7.0 ** i * np.log2(share) ** j for i in range(4) for j in range(3))
+                for k in range(6)]
+        assert np.allclose(m.predict(q, share), want)
+        assert m.select(q, share) == int(np.argmax(want))
+    # shares outside the fitted range are held at its edge
+    assert np.allclose(m.predict(q, 1e-3), m.predict(q, 0.125))
+
+
+def test_interpolation_2d_with_one_share_is_the_1d_fit():
+    # records taken at one share only: the share degree drops to 0 and the
+    # fit is the per-kernel polynomial of the sequential method
+    rng = synth.rng_for(5)
+    avgs = rng.uniform(1, 20, size=(60, 6))
+    speeds = rng.uniform(1, 5, size=(60, 6))
+    m2 = S.fit_interpolation_2d(avgs, np.zeros(60), speeds, 3, 2)
+    m1 = S.fit_interpolation(avgs, speeds, 3)
+    for k in range(6):
+        assert m2.coeffs[k].shape == (4, 1)
+        assert np.allclose(m2.coeffs[k][:, 0], m1.coeffs[k][::-1], rtol=1e-8, atol=1e-10)
+    q = rng.uniform(1, 20, size=6)
+    assert np.allclose(m2.predict(q, 1.0), m1.predict(q))
