@@ -365,6 +365,21 @@ spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_t nnz, cons
                                const int32_t *colidx, float *features_out, int64_t *n_blocks_out,
                                hipStream_t stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): spc_matrix_features without any
+ * allocation. Same arguments, checks, results (bit for bit) and
+ * synchronization. Its kernels work in a fixed 1 MiB device array that the
+ * library holds on each GPU it runs on until the process ends, so it takes
+ * at most spc_matrix_features_noalloc_max_rows() rows (about 19 million);
+ * more return SPC_ERR_CAPACITY before any device work. Every call on one GPU
+ * uses that GPU's array: calls that overlap on one GPU (other host threads
+ * or other streams) race and must be serialized by the caller. The array
+ * keeps the last call's contents; each call clears the part it relies on. */
+spc_status spc_matrix_features_noalloc(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
+                                       const int32_t *colidx, float *features_out, int64_t *n_blocks_out,
+                                       hipStream_t stream);
+int64_t spc_matrix_features_noalloc_max_rows(void);
+
 
 /* ---------------------------------------------------------------------------
  * Learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU network in FP32 whose

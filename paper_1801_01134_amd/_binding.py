@@ -76,6 +76,9 @@ _SIGS = {
                                POINTER(ctypes.c_float), c_void_p, c_int32, POINTER(c_int32), c_void_p]),
     "spc_matrix_features": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_void_p, POINTER(ctypes.c_float),
                                       POINTER(c_int64), c_void_p]),
+    "spc_matrix_features_noalloc": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_void_p,
+                                              POINTER(ctypes.c_float), POINTER(c_int64), c_void_p]),
+    "spc_matrix_features_noalloc_max_rows": (c_int64, []),
     "spc_batch_create": (c_int32, [c_int32, POINTER(BetaView), POINTER(PlanParams), POINTER(c_void_p), c_void_p]),
     "spc_batch_destroy": (c_int32, [c_void_p]),
     "spc_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),

@@ -13,9 +13,18 @@
 // does not depend on scheduling.
 #include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "common.hpp"
 #include "cursor.hpp"
+
+// Scratch of the entry point that allocates nothing: the per-block partials,
+// the total and the error flag of one call. Every GPU holds its own copy for
+// the life of the process; host code reaches it only through the address
+// hipGetSymbolAddress gives on that device (the name itself is a host-side
+// stand-in, not a device address).
+static constexpr size_t kScratchBytes = size_t(1) << 20;
+static __device__ __align__(256) int64_t scratch[kScratchBytes / 8];
 
 namespace spc {
 namespace {
@@ -213,28 +222,50 @@ __global__ __launch_bounds__(kFT) void k_features_total(const int64_t *part, int
     block_reduce(v, sm, out);
 }
 
-}  // namespace
-}  // namespace spc
+__global__ void k_zero_int(int *p) { *p = 0; }
 
-using namespace spc;
+// Partial blocks whose sums (plus the total and the flag) fit the scratch.
+constexpr int64_t kScratchBlocks = (int64_t)((kScratchBytes - 256) / sizeof(FeatSums)) - 1;
 
-extern "C" spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
-                                          const int32_t *colidx, float *features_out,
-                                          int64_t *n_blocks_out, hipStream_t stream) {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};   // per device ordinal
+
+spc_status scratch_on_current_device(void **out) {
+    int dev = 0;
+    SPC_HIP(hipGetDevice(&dev));
+    SPC_REQUIRE(dev >= 0 && dev < 64, SPC_ERR_CAPACITY, "device ordinal %d beyond 63", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        SPC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SPC_REQUIRE(p != nullptr, SPC_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPC_OK;
+}
+
+spc_status check_feature_args(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
+                              const int32_t *colidx, const float *features_out) {
     SPC_REQUIRE(n_rows >= 1 && n_cols >= 1 && nnz >= 0, SPC_ERR_INVALID_ARG,
                 "features need n_rows >= 1, n_cols >= 1 and nnz >= 0");
     SPC_REQUIRE(n_rows < (int64_t(1) << 31) && n_cols < (int64_t(1) << 31) && nnz < (int64_t(1) << 31),
                 SPC_ERR_OVERFLOW, "sizes exceed the int32 index range");
     SPC_REQUIRE(rowptr && (colidx || nnz == 0) && features_out, SPC_ERR_INVALID_ARG, "null argument");
-    const int64_t n_groups = (n_rows + kGroup - 1) / kGroup;
-    const int64_t n_blk = div_up(n_groups, kFT);
-    DevBuf buf;
+    return SPC_OK;
+}
+
+// Launches both feature kernels into `buf` (n_blk + 1 FeatSums, then the
+// error flag), reads the total back, checks the flag and forms the 16
+// features. Synchronizes the stream.
+spc_status features_into(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
+                         const int32_t *colidx, int64_t n_blk, char *buf, float *features_out,
+                         int64_t *n_blocks_out, hipStream_t stream) {
     const size_t part_bytes = (size_t)(n_blk + 1) * sizeof(FeatSums);
-    SPC_HIP(buf.alloc(part_bytes + 256));
-    int64_t *part = buf.as<int64_t>();
+    int64_t *part = reinterpret_cast<int64_t *>(buf);
     int64_t *total = part + n_blk * kSumWords;
-    int *err = reinterpret_cast<int *>(buf.as<char>() + part_bytes);
-    SPC_HIP(hipMemsetAsync(err, 0, sizeof(int), stream));
+    int *err = reinterpret_cast<int *>(buf + part_bytes);
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, stream, err);
     hipLaunchKernelGGL(k_features, dim3((unsigned)n_blk), dim3(kFT), 0, stream, n_rows, n_cols, nnz, rowptr,
                        colidx ? colidx : reinterpret_cast<const int32_t *>(rowptr), part, err);
     hipLaunchKernelGGL(k_features_total, dim3(1), dim3(kFT), 0, stream, part, n_blk, total);
@@ -272,4 +303,40 @@ extern "C" spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_
     if (n_blocks_out)
         for (int s = 0; s < SPC_N_SHAPES; ++s) n_blocks_out[s] = t.nb[s];
     return SPC_OK;
+}
+
+}  // namespace
+}  // namespace spc
+
+using namespace spc;
+
+extern "C" spc_status spc_matrix_features(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rowptr,
+                                          const int32_t *colidx, float *features_out,
+                                          int64_t *n_blocks_out, hipStream_t stream) {
+    spc_status st = check_feature_args(n_rows, n_cols, nnz, rowptr, colidx, features_out);
+    if (st != SPC_OK) return st;
+    const int64_t n_blk = div_up(div_up(n_rows, kGroup), kFT);
+    DevBuf buf;
+    SPC_HIP(buf.alloc((size_t)(n_blk + 1) * sizeof(FeatSums) + 256));
+    return features_into(n_rows, n_cols, nnz, rowptr, colidx, n_blk, buf.as<char>(), features_out, n_blocks_out,
+                         stream);
+}
+
+extern "C" int64_t spc_matrix_features_noalloc_max_rows(void) { return kScratchBlocks * kFT * kGroup; }
+
+extern "C" spc_status spc_matrix_features_noalloc(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                                  const int32_t *rowptr, const int32_t *colidx,
+                                                  float *features_out, int64_t *n_blocks_out,
+                                                  hipStream_t stream) {
+    spc_status st = check_feature_args(n_rows, n_cols, nnz, rowptr, colidx, features_out);
+    if (st != SPC_OK) return st;
+    const int64_t n_blk = div_up(div_up(n_rows, kGroup), kFT);
+    SPC_REQUIRE(n_blk <= kScratchBlocks, SPC_ERR_CAPACITY,
+                "spc_matrix_features_noalloc takes at most %lld rows (its fixed scratch holds %lld partial "
+                "blocks); got %lld",
+                (long long)spc_matrix_features_noalloc_max_rows(), (long long)kScratchBlocks, (long long)n_rows);
+    void *p = nullptr;
+    if ((st = scratch_on_current_device(&p)) != SPC_OK) return st;
+    return features_into(n_rows, n_cols, nnz, rowptr, colidx, n_blk, static_cast<char *>(p), features_out,
+                         n_blocks_out, stream);
 }
