@@ -248,6 +248,7 @@ struct WaveSmem {
     // reads of the last word's lanes past the tile (at most 63 entries past
     // buf, never used) stay inside this wavefront's own area
     int brow[128];
+    double zero[2];                                   // read by the lanes of clear mask bits
 };
 
 // Row results of a tile held back for storing later: byte offsets into y
@@ -265,11 +266,12 @@ struct YOut {
 // j (64 / C) PPR + lane / (C / PPR), i.e. slot j BPW + slot, block row rho,
 // half h of the tile's words (slots of the next tile's blocks in the last
 // word get entries that are never read). Every lane must be active.
+// The lane's entry base (part + lane / W) is formed once by the caller; only
+// the word's offset, a constant, is added per word. keeper: lane % W == 0.
 template <class Sh, class T>
-__device__ __forceinline__ void store_partial(double *part, int j, T prod) {
+__device__ __forceinline__ void store_partial_at(double *mine, bool keeper, int j, T prod) {
     constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
-    constexpr int W = Sh::C / PPR;     // lanes added into one partial
-    const int lane = threadIdx.x & 63;
+    constexpr int W = Sh::C / PPR;
     T p = prod;
     if constexpr (sizeof(T) == 8) {
         p += dpp_f64<0xb1>(p);                          // quad_perm [1,0,3,2]
@@ -277,7 +279,7 @@ __device__ __forceinline__ void store_partial(double *part, int j, T prod) {
     } else {
         p = row_group_sum<Sh::C>(p);
     }
-    if ((lane % W) == 0) part[j * (64 / Sh::C) * PPR + lane / W] = (double)p;
+    if (keeper) mine[j * (64 / Sh::C) * PPR] = (double)p;
 }
 
 // 3. Row sums of a wavefront tile whose (block, block row) partials sit in
@@ -447,6 +449,7 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     // the out-of-range loads returned; nothing reads them)
     sm.brow[lane] = in.br[0] - b0;
     sm.brow[lane + 64] = in.br[1] - b0;
+    if (lane < 2) sm.zero[lane] = 0.0;
     // the values have landed in LDS (they were loaded last); the chunk
     // reaching past nnz came back as zeros and is filled value by value
     wait_vm_all();
@@ -467,29 +470,36 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     // read.
     if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
         constexpr int NWM = SM::NWMAX;
+        constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+        constexpr int W = Sh::C / PPR;
         static_assert(NWM <= 64, "a tile's mask words fit one per lane");
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
         const char *__restrict__ bb = reinterpret_cast<const char *>(sm.buf);
+        // lanes of clear bits read a zero from LDS instead of a value
+        const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.zero) - bb);
+        // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
+        // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes); all
+        // of the tile's cross-lane moves are issued before the first is used
+        int colj[NWM];
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+            colj[j] = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, in.colr[(j * Sh::BPW) / 64]);
         T xv[NWM], pv[NWM];
         uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
-        // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
-        // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes)
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
             uint64_t m = readlane64(in.m, j);
             if (j == 0) m &= lo_mask;
-            const int src = ((j * Sh::BPW) % 64 + slot) * 4;
-            const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
-            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
-            const T v = *reinterpret_cast<const T *>(bb + lane_rank(m) * (uint32_t)sizeof(T) + vbyte);
-            pv[j] = pick(m, v, T(0));
+            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(colj[j] + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+            pv[j] = *reinterpret_cast<const T *>(bb + pick(m, lane_rank(m) * (uint32_t)sizeof(T) + vbyte, zbyte));
             vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
         wave_sync();  // all values are read before the partials overwrite them
-        double *__restrict__ part = reinterpret_cast<double *>(sm.buf);
+        double *__restrict__ mine = reinterpret_cast<double *>(sm.buf) + lane / W;
+        const bool keeper = (lane % W) == 0;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) store_partial<Sh, T>(part, j, pv[j] * xv[j]);
+        for (int j = 0; j < NWM; ++j) store_partial_at<Sh, T>(mine, keeper, j, pv[j] * xv[j]);
     }
     wave_sync();
     tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, reinterpret_cast<const double *>(sm.buf));
@@ -854,6 +864,7 @@ struct PipeSmem {
     // buf, never used) stay inside this wavefront's own area
     double part[WaveSmem<Sh, T, KQ>::NPART];
     int brow[128];
+    double zero[2];   // read by the lanes of clear mask bits
 };
 
 template <class Sh, class T, int KQ>
@@ -930,7 +941,7 @@ __device__ __forceinline__ void tile_issue_lds(const SpmvArgs &a, const TileDesc
 template <class Sh, class T, int KQ, class F>
 __device__ __forceinline__ void tile_run_lds(const SpmvArgs &a, const TileDesc &d, const TileNext<Sh, T, KQ> &in,
                                              __amdgpu_buffer_rsrc_t xr, int *s_brow, T *s_vals, double *s_part,
-                                             F &&prefetch, YOut<T> *out) {
+                                             const double *s_zero, F &&prefetch, YOut<T> *out) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
     const int lane = threadIdx.x & 63;
@@ -954,28 +965,34 @@ __device__ __forceinline__ void tile_run_lds(const SpmvArgs &a, const TileDesc &
     }
     if (nw > 0) {
         constexpr int NWM = SM::NWMAX;
+        constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+        constexpr int W = Sh::C / PPR;
         const int slot = lane / Sh::RC;
         const int kcol = (lane % Sh::RC) % Sh::C;
         const char *__restrict__ bb = reinterpret_cast<const char *>(s_vals);
+        const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(s_zero) - bb);
+        int colj[NWM];
+#pragma unroll
+        for (int j = 0; j < NWM; ++j)
+            colj[j] = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, in.colr[(j * Sh::BPW) / 64]);
         wave_sync();  // the tail values are in LDS
-        // per word, in one pass: the x gather and the lane's value (zero where
-        // its bit is clear); words past the tile's last one are zero
+        // per word, in one pass: the x gather and the lane's value (the zero
+        // slot where its bit is clear); words past the tile's last one are zero
         T xv[NWM], pv[NWM];
         uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);
 #pragma unroll
         for (int j = 0; j < NWM; ++j) {
             uint64_t m = readlane64(in.m, j);
             if (j == 0) m &= lo_mask;
-            const int src = ((j * Sh::BPW) % 64 + slot) * 4;
-            const int c = __builtin_amdgcn_ds_bpermute(src, in.colr[(j * Sh::BPW) / 64]);
-            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(c + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
-            const T v = *reinterpret_cast<const T *>(bb + lane_rank(m) * (uint32_t)sizeof(T) + vbyte);
-            pv[j] = pick(m, v, T(0));
+            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(colj[j] + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+            pv[j] = *reinterpret_cast<const T *>(bb + pick(m, lane_rank(m) * (uint32_t)sizeof(T) + vbyte, zbyte));
             vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
         }
         prefetch();
+        double *__restrict__ mine = s_part + lane / W;
+        const bool keeper = (lane % W) == 0;
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) store_partial<Sh, T>(s_part, j, pv[j] * xv[j]);
+        for (int j = 0; j < NWM; ++j) store_partial_at<Sh, T>(mine, keeper, j, pv[j] * xv[j]);
     } else {
         prefetch();
     }
@@ -994,6 +1011,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
     if (t >= a.n_tiles) return;
     const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
     PipeSmem<Sh, T, KQ> &S = sm[wid];
+    if (lane_id() < 2) S.zero[lane_id()] = 0.0;
     TileDesc d = a.tiles[t];
     bool lng = d.b1 - d.b0 > SM::NB;
     TileNext<Sh, T, KQ> cur;
@@ -1025,7 +1043,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
             prefetch();
             pend.off[0] = pend.off[1] = 0xffffffffu;
         } else {
-            tile_run_lds<Sh, T, KQ>(a, d, cur, xr, S.brow, S.buf, S.part, prefetch, &pend);
+            tile_run_lds<Sh, T, KQ>(a, d, cur, xr, S.brow, S.buf, S.part, S.zero, prefetch, &pend);
         }
         if (!more) {
             y_flush(yr, pend);

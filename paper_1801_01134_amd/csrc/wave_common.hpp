@@ -6,6 +6,8 @@
 namespace spc {
 namespace dev {
 
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
     uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -63,13 +65,19 @@ __device__ __forceinline__ int wave_scan_dpp(int v) {
 }
 
 // A double moved across lanes by a DPP pattern (both halves); every source
-// lane must be active.
+// lane must be active. The patterns used here read a lane of the same row,
+// so no lane falls back to the bound value (and the move needs no old value).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 
 // Sum over aligned groups of 2^lg lanes (lg uniform, 0..6); every lane of a
@@ -98,13 +106,9 @@ __device__ __forceinline__ T row_group_sum(T v) {
         v += dpp_f64<0x4e>(v);                          // quad_perm [2,3,0,1]
         if constexpr (G == 8) v += dpp_f64<0x141>(v);   // row_half_mirror
     } else {
-        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xb1, 0xf, 0xf,
-                                                                   false));
-        v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x4e, 0xf, 0xf,
-                                                                   false));
-        if constexpr (G == 8)
-            v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x141, 0xf,
-                                                                       0xf, false));
+        v += dpp_f32<0xb1>(v);                          // quad_perm [1,0,3,2]
+        v += dpp_f32<0x4e>(v);                          // quad_perm [2,3,0,1]
+        if constexpr (G == 8) v += dpp_f32<0x141>(v);   // row_half_mirror
     }
     return v;
 }
