@@ -25,6 +25,13 @@ Further sections of the same JSON line (each can be switched off):
               each in the shape the selector picks, as one launch versus 64
               launches (plain and graph-captured); and the same for 512
               small matrices (rows log-uniform in [500, 20k])
+  reorder     the 27-point stencil with randomly numbered grid points, each
+              shape autotuned before and after the reverse Cuthill-McKee
+              renumbering (values per block, times, cost of the order and
+              of the permutations)
+  parallel_estimation
+              the headline product on 1/8, 1/4, 1/2 and all of the compute
+              units, and the held-out regrets of the 2-D (Avg, share) model
   cg          CG on the SPD 27-point matrix of a 192^3 grid (7,077,888 rows,
               189,119,224 nonzeros) with k = 1, 4, 8, 16 right-hand sides,
               FP64 to 1e-8 and FP32 to 1e-5, true residuals recomputed by
@@ -230,6 +237,19 @@ def _gen_cg(args):
     return m, A.n_rows, A.n_cols, base
 
 
+def _gen_scrambled(args):
+    m, tmp = args
+    import numpy as np
+
+    from paper_1801_01134_amd import synth
+    A = synth.grid_scrambled(m, m, m, "27pt", seed=9)
+    base = os.path.join(tmp, f"scr{m}")
+    np.save(base + "_rp.npy", A.rowptr)
+    np.save(base + "_ci.npy", A.colidx)
+    np.save(base + "_v.npy", A.values)
+    return m, A.n_rows, A.n_cols, base
+
+
 def _load_csr(base, n_rows, n_cols):
     import numpy as np
 
@@ -412,6 +432,87 @@ def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, w
     return out
 
 
+def reorder_section(spc, torch, pool, tmp, m: int):
+    """Reordering before conversion on the 27-point stencil of an m^3 grid
+    whose points are numbered at random: values per block, and the fastest
+    product of each shape (autotuned), before and after the reverse
+    Cuthill-McKee renumbering; the cost of the order (host walk), of the
+    device permutation and of permuting x and y per product."""
+    import numpy as np
+
+    import oracle
+    dev = torch.device("cuda")
+    _, n_rows, n_cols, base = pool.apply(_gen_scrambled, ((m, tmp),))
+    A = _load_csr(base, n_rows, n_cols)
+    rp = torch.from_numpy(A.rowptr).to(dev)
+    ci = torch.from_numpy(A.colidx).to(dev)
+    v = torch.from_numpy(A.values).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    perm = spc.rcm_order(rp, ci)
+    torch.cuda.synchronize()
+    t_order = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rp2, ci2, v2 = spc.csr_permute(rp, ci, v, perm)
+    torch.cuda.synchronize()
+    t_perm = time.perf_counter() - t0
+    from paper_1801_01134_amd import synth
+    x = torch.from_numpy(synth.dense_vector(A.n_cols, 5)).to(dev)
+    out = {"workload": f"27-point stencil {m}^3 with randomly numbered grid points (n={A.n_rows}, nnz={A.nnz})",
+           "rcm_order_ms": round(t_order * 1e3, 1), "csr_permute_ms": round(t_perm * 1e3, 2),
+           "order_on": "host (breadth-first walk); permutation on the device", "shapes": {}}
+    xp = spc.permute_vector(x, perm)
+    t = event_time(torch, lambda: spc.permute_vector(x, perm), 20, 3)
+    out["permute_vector_us"] = round(t * 1e6, 2)
+    best = {}
+    for label, (a_, b_, c_) in (("random_numbering", (rp, ci, v)), ("rcm", (rp2, ci2, v2))):
+        for (r, c) in spc.SHAPES:
+            B = spc.csr_to_beta(r, c, a_, b_, c_, A.n_cols)
+            params, us, _ = spc.autotune(B, reps=10, x=x if label != "rcm" else xp)
+            key = f"b{r}x{c}"
+            out["shapes"].setdefault(key, {})[label] = {"avg_nnz_per_block": round(A.nnz / B.n_blocks, 3),
+                                                        "us": round(us, 2), "plan": params}
+            best[label] = min(best.get(label, 1e30), us)
+            del B
+            torch.cuda.empty_cache()
+    out["best_us"] = {k: round(v_, 2) for k, v_ in best.items()}
+    out["speedup_best_shape"] = round(best["random_numbering"] / best["rcm"], 3)
+    # the fastest reordered product, mapped back, against the oracle on the original matrix
+    fastest = min(out["shapes"], key=lambda k: out["shapes"][k]["rcm"]["us"])
+    r, c = (int(t_) for t_ in fastest[1:].split("x"))
+    out["rcm_fastest_shape"] = [r, c]
+    B = spc.csr_to_beta(r, c, rp2, ci2, v2, A.n_cols)
+    y = spc.permute_vector(spc.spmv(B, xp), perm, scatter=True).cpu().numpy()
+    y_ref, s_ref = oracle.csr_spmv(A, x.cpu().numpy())
+    out["rcm_product_matches_oracle"] = bool((np.abs(y - y_ref) <= 1e-13 * s_ref).all())
+    return out
+
+
+def shares_section(spc, torch, rp, ci, v64, n_cols, nnz, params, r, c):
+    """The headline product on streams restricted to a share of the compute
+    units, and the held-out regrets of the 2-D (Avg, share) model against
+    the sequential per-kernel polynomial, from the committed share records."""
+    out = {}
+    B = spc.csr_to_beta(r, c, rp, ci, v64, n_cols)
+    P = spc.plan_from(B, params)
+    total = spc.device_cu_count()
+    live = {}
+    for n in (total // 8, total // 4, total // 2, total):
+        cs = spc.CUStream(n)
+        with torch.cuda.stream(cs.stream):
+            us = spc.time_spmv(B, P, reps=20, warmup=3)
+        cs.close()
+        live[str(n)] = {"us": round(us, 2), "gflops": round(2.0 * nnz / (us * 1e-6) / 1e9, 1)}
+    out["headline_kernel_by_cu_count"] = live
+    path = os.path.join(MODEL_DIR, "selector_shares_mi355x.jsonl")
+    if os.path.exists(path):
+        from paper_1801_01134_amd import records as R
+        recs = R.load(path)
+        tr, te = R.split(recs)
+        out["held_out"] = R.evaluate_shares(tr, te)
+    return out
+
+
 def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
     import numpy as np
 
@@ -484,6 +585,8 @@ def main(argv=None):
     ap.add_argument("--only-headline", action="store_true", help="skip the sweep and every extra section")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-reorder", action="store_true")
+    ap.add_argument("--no-shares", action="store_true")
     ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--batched-matrices", type=int, default=64)
     ap.add_argument("--cg-grid", type=int, default=192)
@@ -518,12 +621,14 @@ def main(argv=None):
     extras = not args.only_headline
     do_batched = extras and not args.no_batched
     do_cg = extras and not args.no_cg
+    args.do_reorder = extras and not args.no_reorder
+    args.do_shares = extras and not args.no_shares
     do_select = extras and not args.no_select
 
     # worker processes for the CPU-side matrix generation, forked before any GPU call
     pool = None
     tmp = tempfile.mkdtemp(prefix="spc_bench_")
-    if do_batched or do_cg:
+    if do_batched or do_cg or args.do_reorder:
         import multiprocessing as mp
         pool = mp.get_context("fork").Pool(12)
 
@@ -736,6 +841,14 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         torch.cuda.empty_cache()
     if do_cg:
         out["cg"] = cg_section(spc, torch, pool, tmp, args.cg_grid, (1, 4, 8, 16), (1, 16))
+        torch.cuda.empty_cache()
+    if args.do_reorder:
+        out["reorder"] = reorder_section(spc, torch, pool, tmp, m)
+        log(f"reorder: {out['reorder']}")
+        torch.cuda.empty_cache()
+    if args.do_shares:
+        out["parallel_estimation"] = shares_section(spc, torch, rp, ci, v64, A.n_cols, A.nnz, params, r, c)
+        log(f"parallel estimation: {out['parallel_estimation']}")
         torch.cuda.empty_cache()
     if not args.only_headline:
         out["small_case"] = small_case(spc, torch)

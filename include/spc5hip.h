@@ -380,7 +380,6 @@ spc_status spc_matrix_features_noalloc(int64_t n_rows, int64_t n_cols, int64_t n
                                        hipStream_t stream);
 int64_t spc_matrix_features_noalloc_max_rows(void);
 
-
 /* ---------------------------------------------------------------------------
  * Learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU network in FP32 whose
  * forward, backward and Adam steps run in this library's kernels. The paper
@@ -457,6 +456,40 @@ spc_status spc_selector_interp_coeffs(const spc_selector *sel, double *coeffs_ou
 spc_status spc_selector_set_mlp(spc_selector *sel, const float *params, const float *mu, const float *sd);
 spc_status spc_select_kernel(spc_selector *sel, const float *features, int32_t method, int32_t *shape_out,
                              float *scores_out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Parallel performance estimation (section "Parallel performance
+ * estimation": a non-linear regression of performance on two inputs, the
+ * average values per block and the number of threads). On the GPU the
+ * second input is the share of the compute units a product runs on.
+ *
+ * spc_stream_create_cu: a stream whose kernels run on n_cus of the current
+ *   device's compute units (1 <= n_cus <= spc_device_cu_count(); on a
+ *   256-unit device a multiple of 8, the same number on each of its 8 XCDs),
+ *   spread evenly over the XCDs; the stream has the default priority.
+ *   Release it with spc_stream_destroy.
+ * spc_selector_fit_interp2d: per shape, least squares of speed (GFlop/s,
+ *   host n x 6) on the tensor polynomial sum_{i<=deg_avg, j<=deg_share}
+ *   c_ij Avg^i u^j, with u = log2_share[k] (host n) the log2 of the share
+ *   record k ran on (0 = all units). deg_avg <= 3, deg_share <= 2; degrees
+ *   drop when the records hold fewer distinct values, or fewer records than
+ *   coefficients (the share degree first).
+ * spc_selector_interp2d_coeffs: c_ij (host 6 x 4 x 3 doubles, [shape][i][j],
+ *   zero above the degrees), the fitted Avg range per shape (host 6 each,
+ *   may be NULL) and the fitted u range (host 2, may be NULL).
+ * spc_select_kernel_at: the shape of highest predicted speed for a feature
+ *   vector (host float[16]) at a share in (0, 1]; Avg and u are clamped to
+ *   the fitted ranges; scores_out (host float[6], may be NULL) = predicted
+ *   GFlop/s. SPC_ERR_NO_MODEL without a 2-D fit. */
+spc_status spc_stream_create_cu(int32_t n_cus, hipStream_t *stream_out);
+spc_status spc_stream_destroy(hipStream_t stream);
+int32_t spc_device_cu_count(void);
+spc_status spc_selector_fit_interp2d(spc_selector *sel, int32_t n, const double *avg, const double *log2_share,
+                                     const double *speed, int32_t deg_avg, int32_t deg_share);
+spc_status spc_selector_interp2d_coeffs(const spc_selector *sel, double *coeffs_out, double *lo_out,
+                                        double *hi_out, double *share_range_out);
+spc_status spc_select_kernel_at(spc_selector *sel, const float *features, double cu_share, int32_t *shape_out,
+                                float *scores_out);
 
 #ifdef __cplusplus
 }

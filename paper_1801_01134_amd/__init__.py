@@ -8,6 +8,7 @@ generators in ``synth``.
 from . import synth  # noqa: F401
 from ._binding import (MLP_N_PARAMS, SEL_INTERP, SEL_MLP, Selector, mlp_infer, mlp_loss_grad,  # noqa: F401
                        mlp_standardizer, mlp_targets, mlp_train)
+from ._binding import CUStream, device_cu_count  # noqa: F401
 from ._binding import (SHAPES, Batch, BetaMatrix, Plan, SpcError, autotune, beta_to_csr, cg,  # noqa: F401
                        csr_permute, csr_to_beta, lib, mask_bytes, matrix_features, permute_vector, plan_from,
                        rcm_order, spmm, spmv, time_spmv)

@@ -102,6 +102,15 @@ _SIGS = {
                                        POINTER(ctypes.c_float)]),
     "spc_select_kernel": (c_int32, [c_void_p, POINTER(ctypes.c_float), c_int32, POINTER(c_int32),
                                     POINTER(ctypes.c_float), c_void_p]),
+    "spc_stream_create_cu": (c_int32, [c_int32, POINTER(c_void_p)]),
+    "spc_stream_destroy": (c_int32, [c_void_p]),
+    "spc_device_cu_count": (c_int32, []),
+    "spc_selector_fit_interp2d": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_double), POINTER(ctypes.c_double),
+                                            POINTER(ctypes.c_double), c_int32, c_int32]),
+    "spc_selector_interp2d_coeffs": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(ctypes.c_double),
+                                               POINTER(ctypes.c_double), POINTER(ctypes.c_double)]),
+    "spc_select_kernel_at": (c_int32, [c_void_p, POINTER(ctypes.c_float), ctypes.c_double, POINTER(c_int32),
+                                       POINTER(ctypes.c_float)]),
 }
 
 
@@ -577,6 +586,40 @@ class Selector:
                                          s_.ctypes.data_as(fp)))
         return self
 
+    def fit_interp2d(self, avg, log2_share, speed, deg_avg: int = 3, deg_share: int = 2):
+        """2-D fit of speed against (Avg, log2 of the compute-unit share)."""
+        import numpy as np
+        a = np.ascontiguousarray(avg, dtype=np.float64)
+        u = np.ascontiguousarray(log2_share, dtype=np.float64)
+        v = np.ascontiguousarray(speed, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != 6 or v.shape != a.shape or u.shape != (a.shape[0],):
+            raise ValueError("avg and speed must be n x 6, log2_share n")
+        dp = POINTER(ctypes.c_double)
+        check(lib().spc_selector_fit_interp2d(self.handle, a.shape[0], a.ctypes.data_as(dp), u.ctypes.data_as(dp),
+                                              v.ctypes.data_as(dp), deg_avg, deg_share))
+        return self
+
+    def interp2d_coeffs(self):
+        import numpy as np
+        c = np.zeros((6, 4, 3))
+        lo = np.zeros(6)
+        hi = np.zeros(6)
+        ur = np.zeros(2)
+        dp = POINTER(ctypes.c_double)
+        check(lib().spc_selector_interp2d_coeffs(self.handle, c.ctypes.data_as(dp), lo.ctypes.data_as(dp),
+                                                 hi.ctypes.data_as(dp), ur.ctypes.data_as(dp)))
+        return c, lo, hi, ur
+
+    def select_at(self, features, cu_share: float):
+        """(shape index, predicted GFlop/s[6]) at a share of the compute units."""
+        import numpy as np
+        f = np.ascontiguousarray(features, dtype=np.float32)
+        out = c_int32()
+        sc = (ctypes.c_float * 6)()
+        check(lib().spc_select_kernel_at(self.handle, f.ctypes.data_as(POINTER(ctypes.c_float)), float(cu_share),
+                                         ctypes.byref(out), sc))
+        return int(out.value), np.array(list(sc), dtype=np.float32)
+
     def select(self, features, method: int = SEL_MLP):
         """(shape index, scores[6]) for one host feature vector."""
         import numpy as np
@@ -588,6 +631,34 @@ class Selector:
         check(lib().spc_select_kernel(self.handle, f.ctypes.data_as(POINTER(ctypes.c_float)), method,
                                       ctypes.byref(out), sc, stream_ptr() if method == SEL_MLP else None))
         return int(out.value), np.array(list(sc), dtype=np.float32)
+
+
+class CUStream:
+    """A HIP stream restricted to n_cus compute units, usable as a torch
+    stream (torch.cuda.ExternalStream) for this library's calls."""
+
+    def __init__(self, n_cus: int):
+        h = c_void_p()
+        check(lib().spc_stream_create_cu(int(n_cus), ctypes.byref(h)))
+        self.handle = h
+        self.n_cus = int(n_cus)
+        self.stream = torch.cuda.ExternalStream(h.value)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            self.stream.synchronize()
+            check(lib().spc_stream_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def device_cu_count() -> int:
+    return int(lib().spc_device_cu_count())
 
 
 class Batch:

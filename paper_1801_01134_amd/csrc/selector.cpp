@@ -25,18 +25,12 @@ namespace spc {
 namespace {
 
 constexpr int kMaxDeg = 3;
+constexpr int kMaxDegShare = 2;
 
-// Least-squares coefficients (lowest power first) of a degree-d polynomial.
-std::vector<double> polyfit(const std::vector<double> &a, const std::vector<double> &s, int d) {
-    const int n = (int)a.size(), m = d + 1;
-    std::vector<double> V((size_t)n * m), rhs(s);
-    for (int i = 0; i < n; ++i) {
-        double p = 1.0;
-        for (int j = 0; j < m; ++j) {
-            V[(size_t)i * m + j] = p;
-            p *= a[i];
-        }
-    }
+// Least-squares solution of V c = rhs for an n x m design matrix V
+// (row-major, overwritten): columns scaled to unit norm, Householder QR
+// applied to the right-hand side as it goes, back substitution, unscaled.
+std::vector<double> lstsq(std::vector<double> &V, std::vector<double> rhs, int n, int m) {
     std::vector<double> scale(m, 1.0);
     for (int j = 0; j < m; ++j) {
         double q = 0.0;
@@ -79,6 +73,40 @@ std::vector<double> polyfit(const std::vector<double> &a, const std::vector<doub
     return c;
 }
 
+// Least-squares coefficients (lowest power first) of a degree-d polynomial.
+std::vector<double> polyfit(const std::vector<double> &a, const std::vector<double> &s, int d) {
+    const int n = (int)a.size(), m = d + 1;
+    std::vector<double> V((size_t)n * m);
+    for (int i = 0; i < n; ++i) {
+        double p = 1.0;
+        for (int j = 0; j < m; ++j) {
+            V[(size_t)i * m + j] = p;
+            p *= a[i];
+        }
+    }
+    return lstsq(V, s, n, m);
+}
+
+// Least-squares coefficients of the tensor polynomial sum c[i][j] a^i u^j,
+// i <= da, j <= du (c row-major in i, then j).
+std::vector<double> polyfit2(const std::vector<double> &a, const std::vector<double> &u,
+                             const std::vector<double> &s, int da, int du) {
+    const int n = (int)a.size(), m = (da + 1) * (du + 1);
+    std::vector<double> V((size_t)n * m);
+    for (int r = 0; r < n; ++r) {
+        double pa = 1.0;
+        for (int i = 0; i <= da; ++i) {
+            double pu = 1.0;
+            for (int j = 0; j <= du; ++j) {
+                V[(size_t)r * m + i * (du + 1) + j] = pa * pu;
+                pu *= u[r];
+            }
+            pa *= a[r];
+        }
+    }
+    return lstsq(V, s, n, m);
+}
+
 }  // namespace
 }  // namespace spc
 
@@ -87,6 +115,11 @@ struct spc_selector {
     double coef[SPC_N_SHAPES][spc::kMaxDeg + 1] = {};
     int deg[SPC_N_SHAPES] = {};
     double lo[SPC_N_SHAPES] = {}, hi[SPC_N_SHAPES] = {};
+    // 2-D fit: speed against (Avg, log2 of the compute-unit share)
+    bool has_interp2 = false;
+    double coef2[SPC_N_SHAPES][spc::kMaxDeg + 1][spc::kMaxDegShare + 1] = {};
+    int deg2a[SPC_N_SHAPES] = {}, deg2u[SPC_N_SHAPES] = {};
+    double lo2[SPC_N_SHAPES] = {}, hi2[SPC_N_SHAPES] = {}, ulo = 0.0, uhi = 0.0;
     bool has_mlp = false;
     int device = -1;
     float *d_buf = nullptr;  // params | mu | sd | features | scores, then one int32 choice
@@ -138,6 +171,100 @@ extern "C" spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, cons
         sel->hi[s] = *std::max_element(a.begin(), a.end());
     }
     sel->has_interp = true;
+    return SPC_OK;
+}
+
+extern "C" spc_status spc_selector_fit_interp2d(spc_selector *sel, int32_t n, const double *avg,
+                                                const double *log2_share, const double *speed, int32_t deg_avg,
+                                                int32_t deg_share) {
+    SPC_REQUIRE(sel && avg && log2_share && speed, SPC_ERR_INVALID_ARG, "null argument");
+    SPC_REQUIRE(n >= 1, SPC_ERR_INVALID_ARG, "need at least one record");
+    SPC_REQUIRE(deg_avg >= 0 && deg_avg <= kMaxDeg && deg_share >= 0 && deg_share <= kMaxDegShare,
+                SPC_ERR_INVALID_ARG, "degrees must be in 0..%d (Avg) and 0..%d (share)", kMaxDeg, kMaxDegShare);
+    for (int64_t k = 0; k < (int64_t)n * SPC_N_SHAPES; ++k)
+        SPC_REQUIRE(std::isfinite(avg[k]) && std::isfinite(speed[k]), SPC_ERR_INVALID_ARG,
+                    "record %lld is not finite", (long long)(k / SPC_N_SHAPES));
+    std::set<double> us;
+    for (int i = 0; i < n; ++i) {
+        SPC_REQUIRE(std::isfinite(log2_share[i]), SPC_ERR_INVALID_ARG, "share of record %d is not finite", i);
+        us.insert(log2_share[i]);
+    }
+    const int du0 = std::min<int>(deg_share, (int)us.size() - 1);
+    std::vector<double> u(log2_share, log2_share + n);
+    for (int s = 0; s < SPC_N_SHAPES; ++s) {
+        std::vector<double> a(n), v(n);
+        std::set<double> distinct;
+        for (int i = 0; i < n; ++i) {
+            a[i] = avg[(int64_t)i * SPC_N_SHAPES + s];
+            v[i] = speed[(int64_t)i * SPC_N_SHAPES + s];
+            distinct.insert(a[i]);
+        }
+        int da = std::min<int>(deg_avg, std::max<int>(0, (int)distinct.size() - 1)), du = du0;
+        // no more coefficients than records: lower the share degree, then Avg's
+        while ((da + 1) * (du + 1) > n) {
+            if (du > 0) --du;
+            else --da;
+        }
+        const std::vector<double> c = polyfit2(a, u, v, da, du);
+        for (int i = 0; i <= kMaxDeg; ++i)
+            for (int j = 0; j <= kMaxDegShare; ++j)
+                sel->coef2[s][i][j] = (i <= da && j <= du) ? c[(size_t)i * (du + 1) + j] : 0.0;
+        sel->deg2a[s] = da;
+        sel->deg2u[s] = du;
+        sel->lo2[s] = *std::min_element(a.begin(), a.end());
+        sel->hi2[s] = *std::max_element(a.begin(), a.end());
+    }
+    sel->ulo = *us.begin();
+    sel->uhi = *us.rbegin();
+    sel->has_interp2 = true;
+    return SPC_OK;
+}
+
+extern "C" spc_status spc_selector_interp2d_coeffs(const spc_selector *sel, double *coeffs_out, double *lo_out,
+                                                   double *hi_out, double *share_range_out) {
+    SPC_REQUIRE(sel && coeffs_out, SPC_ERR_INVALID_ARG, "null argument");
+    SPC_REQUIRE(sel->has_interp2, SPC_ERR_NO_MODEL, "the selector has no 2-D interpolation fit");
+    constexpr int M = (kMaxDeg + 1) * (kMaxDegShare + 1);
+    for (int s = 0; s < SPC_N_SHAPES; ++s) {
+        for (int i = 0; i <= kMaxDeg; ++i)
+            for (int j = 0; j <= kMaxDegShare; ++j) coeffs_out[s * M + i * (kMaxDegShare + 1) + j] = sel->coef2[s][i][j];
+        if (lo_out) lo_out[s] = sel->lo2[s];
+        if (hi_out) hi_out[s] = sel->hi2[s];
+    }
+    if (share_range_out) {
+        share_range_out[0] = sel->ulo;
+        share_range_out[1] = sel->uhi;
+    }
+    return SPC_OK;
+}
+
+extern "C" spc_status spc_select_kernel_at(spc_selector *sel, const float *features, double cu_share,
+                                           int32_t *shape_out, float *scores_out) {
+    SPC_REQUIRE(sel && features && shape_out, SPC_ERR_INVALID_ARG, "null argument");
+    SPC_REQUIRE(std::isfinite(cu_share) && cu_share > 0.0 && cu_share <= 1.0, SPC_ERR_INVALID_ARG,
+                "cu_share must be in (0, 1]");
+    SPC_REQUIRE(sel->has_interp2, SPC_ERR_NO_MODEL, "the selector has no 2-D interpolation fit");
+    const double u = std::min(std::max(std::log2(cu_share), sel->ulo), sel->uhi);
+    double best = 0.0;
+    int arg = 0;
+    for (int s = 0; s < SPC_N_SHAPES; ++s) {
+        const double a = std::min(std::max((double)features[8 + s], sel->lo2[s]), sel->hi2[s]);
+        double p = 0.0, pa = 1.0;
+        for (int i = 0; i <= sel->deg2a[s]; ++i) {
+            double pu = 1.0;
+            for (int j = 0; j <= sel->deg2u[s]; ++j) {
+                p += sel->coef2[s][i][j] * pa * pu;
+                pu *= u;
+            }
+            pa *= a;
+        }
+        if (scores_out) scores_out[s] = (float)p;
+        if (s == 0 || p > best) {
+            best = p;
+            arg = s;
+        }
+    }
+    *shape_out = arg;
     return SPC_OK;
 }
 

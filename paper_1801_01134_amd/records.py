@@ -145,6 +145,119 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
         os.rmdir(tmp)
 
 
+SHARES = (32, 64, 128, 256)   # compute units a product runs on (of 256)
+
+
+def collect_shares(first: int, count: int, out_path: str, population: str = "selector",
+                   shares=SHARES, reps: int = 5, workers: int = 12, min_rows: int = DEFAULT_MIN_ROWS,
+                   max_rows: int = DEFAULT_MAX_ROWS, log=sys.stderr):
+    """Records for the 2-D model: each matrix of the population in each of
+    the six shapes (library default plan) timed on streams restricted to
+    `shares` compute units. One JSON line per matrix with us[share][shape]."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    tmp = tempfile.mkdtemp(prefix="spc_shares_")
+    pool = ctx.Pool(workers) if workers > 0 else None
+    try:
+        import torch
+
+        from . import _binding as b
+        dev = torch.device("cuda")
+        total = b.device_cu_count()
+        streams = [b.CUStream(min(int(n), total)) for n in shares]
+        gen = torch.Generator(device=dev)
+        todo = list(range(first, first + count))
+        pending = []
+        window = max(1, 2 * workers)
+        t_start = time.perf_counter()
+        with open(out_path, "a") as out:
+            while todo or pending:
+                while todo and len(pending) < window:
+                    i = todo.pop(0)
+                    job = (i, min_rows, max_rows, tmp, population)
+                    pending.append(pool.apply_async(_generate, (job,)) if pool else _Ready(_generate(job)))
+                index, fam, n_rows, n_cols, base, _ = pending.pop(0).get()
+                rp = torch.from_numpy(np.load(base + "_rp.npy")).to(dev)
+                ci = torch.from_numpy(np.load(base + "_ci.npy")).to(dev)
+                os.remove(base + "_rp.npy")
+                os.remove(base + "_ci.npy")
+                nnz = ci.numel()
+                gen.manual_seed(1801 * 100003 + index)
+                vals = torch.empty(max(1, nnz), dtype=torch.float64, device=dev).uniform_(-1.0, 1.0,
+                                                                                        generator=gen)[:nnz]
+                feat, nb = b.matrix_features(rp, ci, n_cols)
+                us = [[0.0] * 6 for _ in shares]
+                for k, (r, c) in enumerate(SHAPES):
+                    B = b.csr_to_beta(r, c, rp, ci, vals, n_cols)
+                    P = B.default_plan()
+                    for q, cs in enumerate(streams):
+                        with torch.cuda.stream(cs.stream):
+                            us[q][k] = float(b.time_spmv(B, P, reps=reps, warmup=2))
+                    del B, P
+                rec = {"population": population, "index": index, "family": fam, "n_rows": n_rows,
+                       "n_cols": n_cols, "nnz": nnz, "features": [float(v) for v in feat],
+                       "n_blocks": [int(v) for v in nb], "cu_counts": [cs.n_cus for cs in streams],
+                       "cu_total": total, "us": us}
+                out.write(json.dumps(rec) + "\n")
+                out.flush()
+                print(f"[shares] {index} {fam} n={n_rows} nnz={nnz} best per share="
+                      f"{[int(np.argmin(u)) for u in us]} ({time.perf_counter() - t_start:.0f}s)", file=log,
+                      flush=True)
+                del rp, ci, vals
+        for cs in streams:
+            cs.close()
+    finally:
+        if pool is not None:
+            pool.terminate()
+            pool.join()
+        for f in os.listdir(tmp):
+            os.remove(os.path.join(tmp, f))
+        os.rmdir(tmp)
+
+
+def share_rows(recs: list[dict]):
+    """Flattened (matrix, share) rows: features [m, 16], log2 share [m],
+    times [m, 6], speeds [m, 6], matrix index [m]."""
+    X, U, T, G, I = [], [], [], [], []
+    for j, r in enumerate(recs):
+        for n, us in zip(r["cu_counts"], r["us"]):
+            X.append(r["features"])
+            U.append(np.log2(n / r["cu_total"]))
+            T.append(us)
+            G.append([2.0 * r["nnz"] / (t * 1e-6) / 1e9 for t in us])
+            I.append(j)
+    return (np.array(X, dtype=np.float32), np.array(U), np.array(T), np.array(G), np.array(I))
+
+
+def evaluate_shares(train: list[dict], test: list[dict]):
+    """Held-out regret per share of the 2-D fit (speed against Avg and the
+    share), of the sequential per-kernel polynomial fitted at the full share
+    only, and of the best fixed shape on the training records."""
+    from . import _binding as b
+    Xtr, Utr, Ttr, Gtr, _ = share_rows(train)
+    Xte, Ute, Tte, Gte, _ = share_rows(test)
+    sel = b.Selector()
+    sel.fit_interp2d(Xtr[:, 8:14].astype(np.float64), Utr, Gtr, 3, 2)
+    full = Utr == 0.0
+    sel.fit_interp(Xtr[full, 8:14].astype(np.float64), Gtr[full], 3)
+    out = {"n_train_matrices": len(train), "n_test_matrices": len(test), "per_share": {}}
+    for u in sorted(set(Ute.tolist())):
+        m = Ute == u
+        share = float(2.0 ** u)
+        ch2 = np.array([sel.select_at(x, share)[0] for x in Xte[m]], dtype=np.int64)
+        ch1 = np.array([sel.select(x, b.SEL_INTERP)[0] for x in Xte[m]], dtype=np.int64)
+        mt = Utr == u
+        fixed = int(np.argmin(np.mean(Ttr[mt] / Ttr[mt].min(axis=1, keepdims=True), axis=0)))
+        out["per_share"][f"{share:g}"] = {
+            "n": int(m.sum()),
+            "interp2d": summary(regrets(Tte[m], ch2)),
+            "interp1d_full_share": summary(regrets(Tte[m], ch1)),
+            f"fixed_best_on_train_{SHAPES[fixed][0]}x{SHAPES[fixed][1]}":
+                summary(regrets(Tte[m], np.full(int(m.sum()), fixed, np.int64))),
+            "best_shape_share": np.bincount(Tte[m].argmin(axis=1), minlength=6).tolist()}
+    return out
+
+
 def load(*paths: str) -> list[dict]:
     recs = []
     for path in paths:
@@ -289,12 +402,26 @@ def main(argv=None):
     t.add_argument("--records", required=True, nargs="+")
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=400)
+    cs = sub.add_parser("collect-shares")
+    cs.add_argument("--first", type=int, default=0)
+    cs.add_argument("--count", type=int, default=320)
+    cs.add_argument("--out", required=True)
+    cs.add_argument("--reps", type=int, default=5)
+    cs.add_argument("--workers", type=int, default=12)
+    cs.add_argument("--population", default="selector", choices=POPULATIONS)
+    es = sub.add_parser("evaluate-shares")
+    es.add_argument("--records", required=True, nargs="+")
     e = sub.add_parser("evaluate")
     e.add_argument("--records", required=True, nargs="+")
     e.add_argument("--model", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
         collect(a.first, a.count, a.out, a.reps, a.workers, a.min_rows, a.max_rows, a.population)
+    elif a.cmd == "collect-shares":
+        collect_shares(a.first, a.count, a.out, a.population, reps=a.reps, workers=a.workers)
+    elif a.cmd == "evaluate-shares":
+        tr, te = split(load(*a.records))
+        print(json.dumps(evaluate_shares(tr, te)))
     elif a.cmd == "train":
         tr, te = split(load(*a.records))
         res, model = evaluate(tr, te, epochs=a.epochs)

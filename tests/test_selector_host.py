@@ -65,3 +65,46 @@ def test_selector_errors():
     assert e.value.code == -1
     with pytest.raises(spc.SpcError):
         sel.fit_interp(np.ones((3, 6)), np.ones((3, 6)), degree=4)
+
+
+@pytest.mark.parametrize("seed,n,da,du,shares", [(0, 300, 3, 2, 4), (1, 40, 3, 2, 2), (2, 9, 3, 2, 4),
+                                                  (3, 120, 2, 1, 4), (4, 50, 3, 2, 1)])
+def test_interp2d_fit_matches_oracle(seed, n, da, du, shares):
+    """The library's 2-D fit (host QR) against the oracle's (numpy least
+    squares): same coefficients, ranges, clamped predictions and choices."""
+    avg, speed = _records(seed, n, noise=2.0)
+    rng = synth.rng_for(79, seed)
+    u = rng.choice(-np.arange(shares, dtype=np.float64), size=n)
+    speed = speed * (1.0 + 0.3 * u[:, None])               # slower on fewer compute units
+    ref = osel.fit_interpolation_2d(avg, u, speed, da, du)
+    sel = spc.Selector().fit_interp2d(avg, u, speed, da, du)
+    c, lo, hi, ur = sel.interp2d_coeffs()
+    assert np.array_equal(lo, avg.min(axis=0)) and np.array_equal(hi, avg.max(axis=0))
+    assert ur[0] == u.min() and ur[1] == u.max()
+    for k in range(6):
+        want = ref.coeffs[k]
+        got = c[k, :want.shape[0], :want.shape[1]]
+        assert np.allclose(got, want, rtol=1e-7, atol=1e-8 * np.abs(want).max())
+        assert np.count_nonzero(c[k]) <= want.size
+    for _ in range(50):
+        q = rng.uniform(0.0, 60.0, size=6)
+        share = float(2.0 ** -rng.uniform(0, 4))
+        f = np.zeros(16, np.float32)
+        f[8:14] = q
+        shape, scores = sel.select_at(f, share)
+        pred = ref.predict(f[8:14].astype(np.float64), share)
+        assert np.allclose(scores, pred.astype(np.float32), rtol=1e-5, atol=1e-4)
+        top = np.sort(pred)[-2:]
+        if top[1] - top[0] > 1e-6 * abs(top[1]):
+            assert shape == int(np.argmax(pred))
+
+
+def test_interp2d_errors():
+    sel = spc.Selector()
+    with pytest.raises(spc.SpcError):
+        sel.select_at(np.zeros(16, np.float32), 0.5)         # no 2-D fit yet
+    avg, speed = _records(5, 20, 1.0)
+    sel.fit_interp2d(avg, np.zeros(20), speed)
+    for bad in (0.0, -0.5, 1.5, float("nan")):
+        with pytest.raises(spc.SpcError):
+            sel.select_at(np.zeros(16, np.float32), bad)
