@@ -72,7 +72,7 @@ def algorithmic_bytes(B, n_tiles: int, k: int = 1, accumulate: bool = False) -> 
     return b
 
 
-PLAN_KEYS = ("mode", "wave_chunks", "tile_bits", "tile_order", "pipeline", "cu_groups")
+PLAN_KEYS = ("mode", "wave_chunks", "tile_bits", "tile_order", "pipeline", "cu_groups", "wave_tiles")
 
 
 def committed_profile(kind: str, kname: str, shape, params: dict, m: int):
@@ -590,7 +590,7 @@ def main(argv=None):
     ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--batched-matrices", type=int, default=64)
     ap.add_argument("--cg-grid", type=int, default=192)
-    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,tile_order[,pipeline[,cu_groups]]: force "
+    ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,tile_order[,pipeline[,cu_groups[,wave_tiles]]]: force "
                     "the headline plan (skips autotuning; used for profiling)")
     ap.add_argument("--spmm", default="",
                     help="k,dtype(64|32),wave_chunks,cu_groups: time only Y = A X on the CG matrix (used for "
@@ -740,6 +740,8 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
                   "tile_order": o_, "pipeline": fields[3] if len(fields) > 3 else 0}
         if len(fields) > 4 and fields[4]:
             params["cu_groups"] = fields[4]
+        if len(fields) > 5 and fields[5]:
+            params["wave_tiles"] = fields[5]
     else:
         params = best_params.get(f"f64_b{r}x{c}") or spc.autotune(B, reps=args.sweep_steps, x=xd)[0]
         # the sweep's three fastest plans of this kernel, timed again with more
@@ -750,8 +752,10 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
             params = cands[min(timed)[1]]
     P = spc.plan_from(B, params)
     info = P.info()
-    kname = (f"k_spmv_wave{'_pipe' if params.get('pipeline') else ''}<{r},{c},double,{params['wave_chunks'] or 4}>"
-             if params["mode"] == 0 else f"k_spmv_wg<{r},{c},double,{info['tile_bits']}>")
+    kname = ({0: f"k_spmv_wave{'_pipe' if params.get('pipeline') else ('2' if params.get('wave_tiles') == 2 else '')}"
+                 f"<{r},{c},double,{params['wave_chunks'] or 4}>",
+              2: f"k_spmv_test<{r},{c},double,{params['wave_chunks'] or 4}>"}.get(
+                 params["mode"], f"k_spmv_wg<{r},{c},double,{info['tile_bits']}>"))
     for _ in range(args.warmup):
         spc.spmv(B, xd, yd, plan=P)
     torch.cuda.synchronize()

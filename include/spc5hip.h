@@ -183,7 +183,16 @@ spc_status spc_permute_vector(int64_t n, int32_t dtype, const int32_t *perm, con
  *              workgroup: all of a tile's streams are requested at once
  *              (values with 16-byte loads), x is gathered one lane per value;
  *              1 = one workgroup per tile, one lane per mask bit loads,
- *              gathers and multiplies (the direct form of the vexpand step)
+ *              gathers and multiplies (the direct form of the vexpand step);
+ *              2 = "test" tiles (Algorithm 2, for beta(1,8) and beta(2,4)
+ *              only, else SPC_ERR_UNSUPPORTED_SHAPE): one wavefront per tile
+ *              as in mode 0, but a block holding a single value takes one
+ *              lane and no expansion (its column from its bit's position),
+ *              and only blocks with several values are expanded, one lane
+ *              per mask bit of a compacted list. A tile holds up to
+ *              248 blocks (fewer with 2 chunks, or 4 chunks and FP64 for
+ *              beta(2,4)), at most 64 of them with several values, and no
+ *              more values than mode 0's tile (planning reads the masks once)
  * params == NULL selects spc_plan_default_params(A); all zeros select mode 0
  * with 4 chunks per lane. */
 typedef struct spc_plan spc_plan;
@@ -192,17 +201,21 @@ typedef struct spc_plan spc_plan;
 typedef struct spc_plan_params {
     int32_t tile_bits;
     int32_t tile_order;     /* SPC_ORDER_XCD (0) or SPC_ORDER_HW (1) */
-    int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles */
+    int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles, 2 = test tiles */
     int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4, 6 or 8; 0 = 4 */
     int32_t pipeline;       /* mode 0: 0 = one wavefront per tile; 1 = persistent wavefronts (as
                                many workgroups as fit on the device) that load their next tile
                                while working on the current one; N > 1 = the same with at most N
                                workgroups */
-    int32_t cu_groups;      /* mode 0, SpMV launches that are not persistent and SpMM: 0 = as many
+    int32_t cu_groups;      /* modes 0 and 2, launches that are not persistent and SpMM: 0 = as many
                                workgroups per compute unit as fit; 2..8 = at most that many (the
                                launch reserves LDS to hold the others off). Fewer resident
                                wavefronts can keep more of the gathered rows of X in cache. */
-    int32_t reserved[2];
+    int32_t wave_tiles;     /* mode 0, not pipelined, single-vector products: 0 or 1 = one tile per
+                               wavefront; 2 = two consecutive tiles per wavefront, the second one's
+                               values held in registers while the first is worked on, so that both
+                               tiles' loads are in flight together (same results, bit for bit) */
+    int32_t reserved;
 } spc_plan_params;
 
 spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,
@@ -282,11 +295,12 @@ spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k,
  *   over `reps` launches after `warmup` launches, measured with HIP events
  *   on `stream` (microseconds, host *us_out). Synchronizes.
  *
- * spc_autotune: builds a plan for every candidate parameter set (both
- *   modes; mode 0 with 2, 4, 6 and 8 chunks per lane, one wavefront per tile or
+ * spc_autotune: builds a plan for every candidate parameter set (mode 0
+ *   with 2, 4, 6 and 8 chunks per lane, one wavefront per tile or
  *   pipelined, and with 4, 6 and 8 chunks also capped at 2 and 4 resident
  *   workgroups per compute unit; mode 1 with 1024, 2048, 3072 and 4032 tile
- *   bits; each with and without XCD remapping where the grid order applies), times it
+ *   bits; each in both tile orders where the grid order applies; for
+ *   beta(1,8) and beta(2,4) also mode 2 with 2, 4, 6 and 8 chunks), times it
  *   with spc_time_spmv and returns the fastest set in *best and its time in
  *   *best_us. If records is not NULL, up to max_records timings are written
  *   there (host memory) and *n_records says how many. x and y are scratch

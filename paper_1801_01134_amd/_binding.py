@@ -34,7 +34,7 @@ class BetaView(ctypes.Structure):
 class PlanParams(ctypes.Structure):
     _fields_ = [("tile_bits", c_int32), ("tile_order", c_int32), ("mode", c_int32),
                 ("wave_chunks", c_int32), ("pipeline", c_int32), ("cu_groups", c_int32),
-                ("reserved", c_int32 * 2)]
+                ("wave_tiles", c_int32), ("reserved", c_int32)]
 
 
 class TuneRecord(ctypes.Structure):
@@ -182,10 +182,10 @@ class Plan:
     """A tile plan (library-owned) for one BetaMatrix."""
 
     def __init__(self, A: "BetaMatrix", tile_bits: int = 0, tile_order: int = 0, mode: int = 0,
-                 wave_chunks: int = 0, pipeline: int = 0, cu_groups: int = 0):
+                 wave_chunks: int = 0, pipeline: int = 0, cu_groups: int = 0, wave_tiles: int = 0):
         self._A = A
         self._view = A.view()
-        p = PlanParams(tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups)
+        p = PlanParams(tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles)
         h = c_void_p()
         check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
                                     stream_ptr()))
@@ -241,10 +241,10 @@ class BetaMatrix:
                         self.values.data_ptr() if self.nnz else None)
 
     def plan(self, tile_bits: int = 0, tile_order: int = 0, mode: int = 0, wave_chunks: int = 0,
-             pipeline: int = 0, cu_groups: int = 0) -> Plan:
-        key = (tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups)
+             pipeline: int = 0, cu_groups: int = 0, wave_tiles: int = 0) -> Plan:
+        key = (tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles)
         if key not in self._plans:
-            self._plans[key] = Plan(self, tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups)
+            self._plans[key] = Plan(self, tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles)
         return self._plans[key]
 
     def default_params(self) -> dict:
@@ -391,12 +391,15 @@ def _params_dict(p: PlanParams) -> dict:
          "tile_order": p.tile_order, "pipeline": p.pipeline}
     if p.cu_groups:
         d["cu_groups"] = p.cu_groups
+    if p.wave_tiles:
+        d["wave_tiles"] = p.wave_tiles
     return d
 
 
 def plan_from(A: BetaMatrix, params: dict) -> Plan:
     return A.plan(params.get("tile_bits", 0), params.get("tile_order", 0), params.get("mode", 0),
-                  params.get("wave_chunks", 0), params.get("pipeline", 0), params.get("cu_groups", 0))
+                  params.get("wave_chunks", 0), params.get("pipeline", 0), params.get("cu_groups", 0),
+                  params.get("wave_tiles", 0))
 
 
 def spmm(A: BetaMatrix, X: torch.Tensor, Y: torch.Tensor | None = None, accumulate: bool = False,

@@ -428,7 +428,10 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
 
 // Everything after the stream loads: the x gathers and products, the row
 // sums and the y stores.
-template <class Sh, class T, int KQ>
+// PEND >= 0: the tile's values were loaded straight into LDS, and PEND
+// vector memory operations issued after them (a next tile's streams) may
+// stay in flight; PEND < 0: the values were written to LDS from registers.
+template <class Sh, class T, int KQ, int PEND = 0>
 __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in, __amdgpu_buffer_rsrc_t xr,
                          WaveSmem<Sh, T, KQ> &sm) {
     using SM = WaveSmem<Sh, T, KQ>;
@@ -452,7 +455,7 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     if (lane < 2) sm.zero[lane] = 0.0;
     // the values have landed in LDS (they were loaded last); the chunk
     // reaching past nnz came back as zeros and is filled value by value
-    wait_vm_all();
+    if constexpr (PEND >= 0) wait_vm_n<PEND>();
     if (q_tail < nq && lane < E) {
         const int64_t g = abase + (int64_t)q_tail * E + lane;
         if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
@@ -511,6 +514,83 @@ __device__ __forceinline__ void wave_tile(const SpmvArgs &a, const TileDesc &d, 
     TileIn<Sh, T, KQ> in;
     tile_issue<Sh, T, KQ>(a, d, in, sm.buf);
     tile_run<Sh, T, KQ>(a, d, in, xr, sm);
+}
+
+// The KQ 16-byte chunks of a wavefront's value range, lane l taking bytes
+// 16 l of each 1 KB, straight into LDS (chunk k at s_vals + 64 k E).
+template <class T, int KQ>
+__device__ __forceinline__ void values_to_lds(__amdgpu_buffer_rsrc_t vr, T *s_vals) {
+    constexpr int E = 16 / sizeof(T);
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            vr, (__attribute__((address_space(3))) void *)(s_vals + 64 * k * E), 16, (uint32_t)(lane * 16), 1024 * k,
+            0, kNT);
+}
+
+using V4u = __attribute__((ext_vector_type(4))) unsigned int;
+
+// The streams of a tile as tile_issue issues them; with TO_LDS = false the
+// packed values go to registers (v[k]: chunk k, lane l's 16 bytes at
+// 1024 k + 16 l), so that while an earlier tile is worked on they hold no
+// LDS. NCR + 3 + KQ loads, all unguarded buffer loads.
+template <class Sh, class T, int KQ, bool TO_LDS>
+__device__ __forceinline__ void tile_issue_regs(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in,
+                                                V4u (&v)[KQ], T *s_vals) {
+    using SM = WaveSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    const int lane = lane_id();
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / Sh::BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / Sh::BPW - w0 + 1) : 0;
+    const int cs0 = w0 * Sh::BPW;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
+    const auto cr = rsrc(a.bcol + cs0, (uint32_t)ncs * 4u);
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k)
+        in.colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
+    in.br[0] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    in.br[1] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
+    const auto mr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
+    in.m = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mr, (uint32_t)(lane * 8), 0, kNT));
+    const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
+    if constexpr (TO_LDS) {
+        values_to_lds<T, KQ>(vr, s_vals);
+    } else {
+#pragma unroll
+        for (int k = 0; k < KQ; ++k)
+            v[k] = __builtin_amdgcn_raw_buffer_load_b128(vr, (uint32_t)(lane * 16), 1024 * k, kNT);
+    }
+}
+
+// Two consecutive tiles on one wavefront: the first tile's values go straight
+// to LDS, the second tile's to registers, and both tiles' streams are in
+// flight together; the first tile is worked on as soon as its own loads have
+// landed, then the second tile's values are written to the same LDS buffer.
+// A wavefront thus keeps two tiles' bytes in flight for one tile's LDS.
+template <class Sh, class T, int KQ>
+__device__ void wave_tile_pair(const SpmvArgs &a, const TileDesc &d0, const TileDesc &d1,
+                               __amdgpu_buffer_rsrc_t xr, WaveSmem<Sh, T, KQ> &sm) {
+    using SM = WaveSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    constexpr int PEND = SM::NCR + 3 + KQ;     // loads of tile_issue_regs
+    TileIn<Sh, T, KQ> in0, in1;
+    V4u v1[KQ];
+    tile_issue_regs<Sh, T, KQ, true>(a, d0, in0, v1, sm.buf);
+    tile_issue_regs<Sh, T, KQ, false>(a, d1, in1, v1, sm.buf);
+    tile_run<Sh, T, KQ, PEND>(a, d0, in0, xr, sm);
+    wave_sync();  // the first tile's LDS reads are done before its buffer is refilled
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) *reinterpret_cast<V4u *>(&sm.buf[(lane + 64 * k) * E]) = v1[k];
+    tile_run<Sh, T, KQ, -1>(a, d1, in1, xr, sm);
 }
 
 // One interval longer than a wavefront tile, run by one wavefront: each lane
@@ -708,6 +788,36 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave(SpmvArgs a) {
     } else {
         const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
         wave_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+    }
+}
+
+// Mode 0 with two consecutive tiles per wavefront (wave_tiles = 2).
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_wave2(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = WaveSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t0 = 2 * (g * kWaves + wid);
+    if (t0 >= a.n_tiles) return;
+    const bool has1 = t0 + 1 < a.n_tiles;
+    const TileDesc d0 = a.tiles[t0];
+    const TileDesc d1 = a.tiles[has1 ? t0 + 1 : t0];
+    const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+    const bool long0 = d0.b1 - d0.b0 > SM::NB, long1 = d1.b1 - d1.b0 > SM::NB;
+    if (has1 && !long0 && !long1) {
+        wave_tile_pair<Sh, T, KQ>(a, d0, d1, xr, sm[wid]);
+        return;
+    }
+    // a long interval on either side: the two tiles one after the other
+    if (long0) wave_long<Sh, T>(a, d0.i0, d0.b0, d0.b1, d0.vbase);
+    else wave_tile<Sh, T, KQ>(a, d0, xr, sm[wid]);
+    if (has1) {
+        wave_sync();
+        if (long1) wave_long<Sh, T>(a, d1.i0, d1.b0, d1.b1, d1.vbase);
+        else wave_tile<Sh, T, KQ>(a, d1, xr, sm[wid]);
     }
 }
 
@@ -1058,6 +1168,214 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave_pipe(SpmvArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mode 2, "test" tiles (Algorithm 2 of the paper, for the shapes whose block
+// mask is one byte, beta(1,8) and beta(2,4)): a block holding a single value
+// needs no expansion, its value goes straight to its row with one multiply,
+// while the other blocks take the expanding path. On a wavefront:
+//   S. lane = block (64 per round): the block's mask byte comes from its
+//      word by a cross-lane move, a prefix count over the blocks gives each
+//      block's first value; a single-value block's lane reads that value,
+//      finds its column from the bit's position and gathers x; every other
+//      block is appended to a compact list in LDS (mask, first value, slot,
+//      column);
+//   M. lane = mask bit of the compacted blocks (8 per 64-lane word, no lane
+//      spent on single-value blocks): the value at the block's first value
+//      plus the bit's rank, the x gather, and the lane sums per block row
+//      into the (block, block row) partials;
+//   then the row sums of the wavefront tiles. A tile holds up to NB2 blocks,
+//   at most NM2 of them with several values, and at most the value buffer.
+template <class Sh, class T, int KQ>
+struct TestSmem {
+    static constexpr int E = 16 / sizeof(T);
+    static constexpr int NBUF = 64 * KQ * E;
+    static constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+    // the partial entries of every slot (up to 7 before the first block)
+    // lie inside the value buffer, and 4 rounds of 64 lanes cover the slots
+    static constexpr int NB2A = NBUF * (int)sizeof(T) / (Sh::R * PPR * 8) - 8;
+    static constexpr int NB2 = NB2A < 248 ? NB2A : 248;
+    static constexpr int NRS = (NB2 + 8 + 63) / 64;   // rounds of lane = block slot
+    static constexpr int NM2 = 64;                    // blocks with several values per tile
+    static constexpr int NWC = NM2 / 8;               // compacted mask words
+    static_assert(Sh::R * Sh::C == 8, "test tiles are for the shapes with one-byte masks");
+    T buf[NBUF];          // packed values, then the partials (double)
+    int brow[128];
+    double zero[2];
+    uint32_t cpk[NM2];    // compacted blocks: mask | first value << 8 | slot << 20
+    int32_t ccol[NM2];    // their columns
+};
+
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_test(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = TestSmem<Sh, T, KQ>;
+    constexpr int E = SM::E;
+    constexpr int PPR = SM::PPR;
+    constexpr int W = C / PPR;            // lanes added into one partial
+    __shared__ SM smem[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    if (d.reserved & 1) {                 // one interval beyond a test tile's limits
+        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+        return;
+    }
+    SM &sm = smem[wid];
+    const int lane = lane_id();
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / 8;
+    const int lo_slot = b0 - w0 * 8;
+    const int hi_slot = lo_slot + (b1 - b0);  // slots [lo_slot, hi_slot) are the tile's blocks
+    const int nw = (b1 > b0) ? ((b1 - 1) / 8 - w0 + 1) : 0;
+    // streams: block columns (slot lane + 64 k), interval pointers and mask
+    // words (lane j: word j) into registers; the packed values into LDS
+    const int cs0 = w0 * 8;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * 8, a.n_blocks) - cs0);
+    const auto cr = rsrc(a.bcol + cs0, (uint32_t)(ncs > 0 ? ncs : 0) * 4u);
+    int colr[SM::NRS];
+#pragma unroll
+    for (int k = 0; k < SM::NRS; ++k)
+        colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
+    const int br0 = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const int br1 = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
+    const auto mr = rsrc(a.mw + w0, (uint32_t)nw * 8u);
+    const uint64_t mword =
+        __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(mr, (uint32_t)(lane * 8), 0, kNT));
+    values_to_lds<T, KQ>(rsrc(vals + abase, (uint32_t)q_tail * 16u), sm.buf);
+    sm.brow[lane] = br0 - b0;
+    sm.brow[lane + 64] = br1 - b0;
+    if (lane < 2) sm.zero[lane] = 0.0;
+    wait_vm_all();
+    if (q_tail < nq && lane < E) {
+        const int64_t gi = abase + (int64_t)q_tail * E + lane;
+        if (gi < a.nnz) sm.buf[q_tail * E + lane] = vals[gi];
+    }
+    wave_sync();
+    const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+    const char *__restrict__ bb = reinterpret_cast<const char *>(sm.buf);
+    const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.zero) - bb);
+    const uint32_t lo32 = (uint32_t)mword, hi32 = (uint32_t)(mword >> 32);
+
+    // S. lane = block slot
+    T xs[SM::NRS], vs[SM::NRS];
+    int srho[SM::NRS];
+    uint64_t single_m[SM::NRS];
+    int vcarry = 0, mcarry = 0;
+#pragma unroll
+    for (int k = 0; k < SM::NRS; ++k) {
+        const int sl = lane + 64 * k;
+        // the word of slot sl is held by lane sl / 8 (lanes 8 k .. 8 k + 7)
+        const int src = (lane / 8 + 8 * k) * 4;
+        const uint32_t wlo = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)lo32);
+        const uint32_t whi = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)hi32);
+        const int sh = (sl % 8) * 8;
+        uint32_t mk = (sh < 32 ? (wlo >> sh) : (whi >> (sh - 32))) & 0xffu;
+        mk = (sl >= lo_slot && sl < hi_slot) ? mk : 0u;
+        const int pc = __popc(mk);
+        const int incl = wave_scan_dpp(pc);
+        const int voff = vcarry + incl - pc;           // the block's first value in the tile
+        vcarry += __builtin_amdgcn_readlane(incl, 63);
+        const int tb = __builtin_ctz(mk | 0x100u);     // position of a single block's bit
+        srho[k] = tb / C;
+        const uint64_t sb = ballot64(pc == 1);
+        single_m[k] = sb;
+        xs[k] = buf_load<T>(xr, pick(sb, (uint32_t)(colr[k] + tb % C) * (uint32_t)sizeof(T), 0xffffffffu));
+        vs[k] = *reinterpret_cast<const T *>(bb + pick(sb, (uint32_t)(shift + voff) * (uint32_t)sizeof(T), zbyte));
+        const uint64_t mb = ballot64(pc >= 2);
+        const int mr_ = mcarry + (int)lane_rank(mb);
+        if (pc >= 2) {
+            sm.cpk[mr_] = mk | ((uint32_t)voff << 8) | ((uint32_t)sl << 20);
+            sm.ccol[mr_] = colr[k];
+        }
+        mcarry += __popcll(mb);
+    }
+    wave_sync();  // the compact list is written
+
+    // M. lane = mask bit of the compacted blocks
+    const int bit = lane % 8;
+    const int kc = bit % C;
+    const uint32_t below = (1u << bit) - 1u;
+    T xm[SM::NWC], vm[SM::NWC];
+#pragma unroll
+    for (int w = 0; w < SM::NWC; ++w) {
+        const int cb = 8 * w + lane / 8;
+        const bool in = cb < mcarry;
+        const uint32_t pk = in ? sm.cpk[cb] : 0u;
+        const int cc = in ? sm.ccol[cb] : 0;
+        const uint64_t sb = ballot64((pk >> bit) & 1u);
+        const uint32_t vpos = (uint32_t)shift + ((pk >> 8) & 0xfffu) + (uint32_t)__popc(pk & 0xffu & below);
+        xm[w] = buf_load<T>(xr, pick(sb, (uint32_t)(cc + kc) * (uint32_t)sizeof(T), 0xffffffffu));
+        vm[w] = *reinterpret_cast<const T *>(bb + pick(sb, vpos * (uint32_t)sizeof(T), zbyte));
+    }
+    wave_sync();  // every value is read before the partials overwrite them
+
+    double *__restrict__ part = reinterpret_cast<double *>(sm.buf);
+    // single-value blocks: the product in its row's first entry, zeros in
+    // the block's other entries
+#pragma unroll
+    for (int k = 0; k < SM::NRS; ++k) {
+        if ((single_m[k] >> lane) & 1ull) {
+            const int sl = lane + 64 * k;
+            const double pr = (double)(vs[k] * xs[k]);
+#pragma unroll
+            for (int e = 0; e < R * PPR; ++e) part[sl * R * PPR + e] = e == srho[k] * PPR ? pr : 0.0;
+        }
+    }
+    // compacted blocks: lane sums over each block row's W lanes
+    const bool keeper = (lane % W) == 0;
+    const int rho = bit / C, h = kc / W;
+#pragma unroll
+    for (int w = 0; w < SM::NWC; ++w) {
+        T p = vm[w] * xm[w];
+        if constexpr (sizeof(T) == 8) {
+            p += dpp_f64<0xb1>(p);                          // quad_perm [1,0,3,2]
+            if constexpr (W == 4) p += dpp_f64<0x4e>(p);    // quad_perm [2,3,0,1]
+        } else {
+            p = row_group_sum<C>(p);
+        }
+        const int cb = 8 * w + lane / 8;
+        if (keeper && cb < mcarry) {
+            const int sl = (int)(sm.cpk[cb] >> 20);
+            part[(sl * R + rho) * PPR + h] = (double)p;
+        }
+    }
+    wave_sync();
+    tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, part);
+}
+
+template <int R, int C, class T>
+spc_status launch_test(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    const dim3 blk(kThreads);
+    switch (kq) {
+    case 2: return launch_capped(k_spmv_test<R, C, T, 2>, cu_groups, grid, blk, stream, a);
+    case 6: return launch_capped(k_spmv_test<R, C, T, 6>, cu_groups, grid, blk, stream, a);
+    case 8: return launch_capped(k_spmv_test<R, C, T, 8>, cu_groups, grid, blk, stream, a);
+    default: return launch_capped(k_spmv_test<R, C, T, 4>, cu_groups, grid, blk, stream, a);
+    }
+}
+
+// Test tiles exist for the two shapes with one-byte masks only.
+spc_status launch_test_shape(int shape, int dtype, int kq, int cu_groups, dim3 grid, const SpmvArgs &a,
+                             hipStream_t stream) {
+    if (shape == 0)
+        return dtype == SPC_F64 ? launch_test<1, 8, double>(kq, cu_groups, grid, a, stream)
+                                : launch_test<1, 8, float>(kq, cu_groups, grid, a, stream);
+    if (shape == 1)
+        return dtype == SPC_F64 ? launch_test<2, 4, double>(kq, cu_groups, grid, a, stream)
+                                : launch_test<2, 4, float>(kq, cu_groups, grid, a, stream);
+    set_error("test tiles are for beta(1,8) and beta(2,4)");
+    return SPC_ERR_UNSUPPORTED_SHAPE;
+}
+
 template <int R, int C, class T>
 spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (tb) {
@@ -1095,6 +1413,17 @@ spc_status resident_groups(int kq, int *out) {
     SPC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     *out = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
     return SPC_OK;
+}
+
+template <int R, int C, class T>
+spc_status launch_wave2(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    const dim3 blk(kThreads);
+    switch (kq) {
+    case 2: return launch_capped(k_spmv_wave2<R, C, T, 2>, cu_groups, grid, blk, stream, a);
+    case 6: return launch_capped(k_spmv_wave2<R, C, T, 6>, cu_groups, grid, blk, stream, a);
+    case 8: return launch_capped(k_spmv_wave2<R, C, T, 8>, cu_groups, grid, blk, stream, a);
+    default: return launch_capped(k_spmv_wave2<R, C, T, 4>, cu_groups, grid, blk, stream, a);
+    }
 }
 
 template <int R, int C, class T>
@@ -1166,6 +1495,24 @@ spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out) {
 // included) and takes up to 128 (interval, block row) pairs, two per lane.
 int spmv_max_intervals_per_tile(int r, int mode) { return mode == 0 ? (r == 1 ? 127 : 128 / r) : kThreads / r; }
 
+// Blocks a test tile (mode 2) may hold, of which at most 64 with several
+// values; 0 for shapes without test tiles.
+int test_tile_blocks(int shape, int dtype, int kq) {
+    auto nb = [&](auto sh, auto tv) -> int {
+        using Sh = decltype(sh);
+        using T = decltype(tv);
+        switch (kq) {
+        case 2: return TestSmem<Sh, T, 2>::NB2;
+        case 6: return TestSmem<Sh, T, 6>::NB2;
+        case 8: return TestSmem<Sh, T, 8>::NB2;
+        default: return TestSmem<Sh, T, 4>::NB2;
+        }
+    };
+    if (shape == 0) return dtype == SPC_F64 ? nb(Shape<1, 8>{}, double{}) : nb(Shape<1, 8>{}, float{});
+    if (shape == 1) return dtype == SPC_F64 ? nb(Shape<2, 4>{}, double{}) : nb(Shape<2, 4>{}, float{});
+    return 0;
+}
+
 // Tile capacity in mask bits for a mode and a chunk count (mode 0) or the
 // workgroup tile size (mode 1).
 int wave_tile_bits(int dtype, int kq) {
@@ -1197,9 +1544,10 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     const bool aligned = (reinterpret_cast<uintptr_t>(A->values) & 15u) == 0;
     const size_t es = A->dtype == SPC_F64 ? 8 : 4;
     const bool x32 = (uint64_t)A->n_cols * es < 0xf0000000ull;    // x addressed with 32-bit offsets
-    const bool wave = P->mode == 0 && aligned && x32;
+    const bool wave = (P->mode == 0 || P->mode == 2) && aligned && x32;
     const int wg_bits = P->mode == 1 ? P->tile_bits : (P->tile_bits <= 1024 ? 1024 : 2048);
-    const int64_t groups = wave ? div_up(P->n_tiles, kWaves) : P->n_tiles;
+    const bool pair = wave && P->mode == 0 && P->wave_tiles == 2 && !P->pipeline;
+    const int64_t groups = wave ? div_up(pair ? div_up(P->n_tiles, 2) : P->n_tiles, kWaves) : P->n_tiles;
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
     dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)groups);
     // the pipelined kernel reads descriptors with 32-bit byte offsets
@@ -1207,12 +1555,14 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     const bool pipe = wave && P->pipeline && P->resident > 0 && P->n_tiles < ((int64_t)1 << 27) &&
                       (uint64_t)A->n_rows * es < 0xf0000000ull;
     if (pipe) grid = dim3((unsigned)(groups < P->resident ? groups : (int64_t)P->resident));
+    if (wave && P->mode == 2) return launch_test_shape(P->shape, A->dtype, P->kq, P->cu_groups, grid, a, stream);
     return with_shape(P->shape, [&](auto sh) {
         using Sh = decltype(sh);
         return with_dtype(A->dtype, [&](auto tv) {
             using T = decltype(tv);
             if (!wave) return launch_wg<Sh::R, Sh::C, T>(wg_bits, grid, a, stream);
             if (pipe) return launch_wave_pipe<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
+            if (pair) return launch_wave2<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
             return launch_wave<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
         });
     });

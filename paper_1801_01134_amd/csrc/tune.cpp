@@ -59,6 +59,15 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
                         cands.push_back(q);
                     }
                 }
+                if (kq >= 4) {  // two tiles per wavefront
+                    spc_plan_params q = p;
+                    q.wave_tiles = 2;
+                    cands.push_back(q);
+                    if (kq == 8) {
+                        q.cu_groups = 4;
+                        cands.push_back(q);
+                    }
+                }
                 p.pipeline = 1;  // persistent: the grid order does not apply
                 cands.push_back(p);
             }
@@ -68,6 +77,14 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
             p.mode = 1;
             p.tile_bits = tb;
             p.tile_order = order;
+            cands.push_back(p);
+        }
+    }
+    if (A->r * A->c == 8) {
+        for (int kq : {2, 4, 6, 8}) {  // test tiles (Algorithm 2)
+            spc_plan_params p{};
+            p.mode = 2;
+            p.wave_chunks = kq;
             cands.push_back(p);
         }
     }

@@ -8,6 +8,9 @@ namespace dev {
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
+// Bit l set iff lane l's predicate holds (lanes of the wavefront's exec mask).
+__device__ __forceinline__ uint64_t ballot64(bool p) { return (uint64_t)__ballot((int)p); }
+
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
     uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
     uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
@@ -42,6 +45,14 @@ __device__ __forceinline__ void wave_sync() {
 // bring is read only after wait_vm_all.
 __device__ __forceinline__ void wait_vm_all() {
     __builtin_amdgcn_s_waitcnt(0x0f70);
+    asm volatile("" ::: "memory");
+}
+// s_waitcnt vmcnt(N): all but the N most recently issued vector memory
+// operations have completed (they complete in issue order).
+template <int N>
+__device__ __forceinline__ void wait_vm_n() {
+    static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+    __builtin_amdgcn_s_waitcnt(0x0f70 | (N & 0xf) | ((N >> 4) << 14));
     asm volatile("" ::: "memory");
 }
 __device__ __forceinline__ void wait_lds_all() {

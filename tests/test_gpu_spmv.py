@@ -393,3 +393,31 @@ def test_null_plan_through_the_abi(rc, dtype):
         Y = torch.empty((A.n_rows, 4), dtype=dtype, device="cuda")
         Bd.check(L.spc_spmm_beta(ctypes.byref(v), None, 4, Bd._ptr(X), 4, Bd._ptr(Y), 4, 0, s))
         assert torch.equal(Y, spc.spmm(B, X, plan=B.default_plan()))
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("chunks", [2, 4, 6, 8])
+def test_two_tiles_per_wavefront_same_bits(rc, dtype, chunks):
+    """wave_tiles = 2 (two consecutive tiles per wavefront, the second staged
+    in registers) runs the same tiles in the same order of operations: the
+    same bits as one tile per wavefront, with accumulate too, and odd tile
+    counts and long intervals among them."""
+    r, c = rc
+    say(f"[pair] beta{rc} {dtype} chunks={chunks}")
+    for name in ("powerlaw", "dense_rows", "empty_rows", "stencil13", "diagonal", "tiny3x5"):
+        A = case(name).astype(NP[dtype])
+        x = synth.dense_vector(A.n_cols, 27).astype(NP[dtype])
+        B = to_beta(A, r, c, dtype)
+        xd = torch.from_numpy(x).cuda()
+        y0 = spc.spmv(B, xd, plan=B.plan(0, 0, 0, chunks))
+        for order in (0, 1):
+            P = B.plan(0, order, 0, chunks, 0, 0, 2)
+            assert torch.equal(spc.spmv(B, xd, plan=P), y0), (name, order)
+        base = torch.from_numpy(synth.dense_vector(A.n_rows, 28).astype(NP[dtype])).cuda()
+        ya, yb = base.clone(), base.clone()
+        spc.spmv(B, xd, ya, accumulate=True, plan=B.plan(0, 0, 0, chunks))
+        spc.spmv(B, xd, yb, accumulate=True, plan=B.plan(0, 0, 0, chunks, 0, 0, 2))
+        assert torch.equal(ya, yb), name
+    y_ref, s_ref = oracle.csr_spmv(A, x)
+    check_rows(y0.cpu().numpy().astype(np.float64), y_ref, s_ref, TOL[dtype], f"pair beta{rc}")
