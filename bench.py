@@ -54,8 +54,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3   # dense FP32 vector peak of the part
 MODEL_DIR = os.path.join(ROOT, "paper_1801_01134_amd", "records")
-RECORDS = [os.path.join(MODEL_DIR, f) for f in ("selector_records_mi355x.jsonl", "structured_records_mi355x.jsonl")]
+RECORDS = [os.path.join(MODEL_DIR, f) for f in ("selector_records_mi355x.jsonl", "structured_records_mi355x.jsonl",
+                                                "large_records_mi355x.jsonl")]
 MODEL = os.path.join(MODEL_DIR, "selector_mlp_mi355x.json")
+MODEL8 = os.path.join(MODEL_DIR, "selector_mlp8_mi355x.json")
 
 
 def log(*a):
@@ -263,27 +265,46 @@ def _load_csr(base, n_rows, n_cols):
 # ---------------------------------------------------------------------------
 # sections
 
-def load_selector(spc):
-    """(Selector with interpolation and, if present, the network; held-out
-    evaluation of both) from the committed records and model."""
+def load_selectors(spc):
+    """{"classes_6": (Selector, model), "classes_8": ...} fitted on the
+    training split of the committed records (interpolation) with the
+    committed network of that class count, and the held-out evaluation of
+    each. The 8-class entry needs records with the test kernels' times."""
     from paper_1801_01134_amd import records as R
     paths = [p for p in RECORDS if os.path.exists(p)]
     if not paths:
-        return None, None, None
+        return {}, {}
     recs = R.load(*paths)
     train, test = R.split(recs)
-    Xtr, Ttr, Atr, Gtr = R.arrays(train)
-    sel = spc.Selector().fit_interp(Atr, Gtr, 3)
-    model = None
-    if os.path.exists(MODEL):
-        with open(MODEL) as f:
-            model = json.load(f)
-        sel.set_mlp(model["params"], model["mu"], model["sd"])
-    held_out, _ = R.evaluate(train, test, model) if model else (None, None)
-    return sel, model, held_out
+    sels, held = {}, {}
+    for k, path in ((6, MODEL), (8, MODEL8)):
+        if k == 8 and not R.has_test(recs):
+            continue
+        _, _, Atr, Gtr = R.arrays(train, k)
+        sel = spc.Selector().fit_interp(Atr, Gtr, 3)
+        model = None
+        if os.path.exists(path):
+            with open(path) as f:
+                model = json.load(f)
+            if int(model.get("n_out", 6)) != k:
+                model = None
+            else:
+                sel.set_mlp(model["params"], model["mu"], model["sd"])
+        sels[f"classes_{k}"] = (sel, model)
+        held[f"classes_{k}"] = R.evaluate(train, test, model, n_classes=k)[0] if model else None
+    return sels, held
 
 
-def select_shape(spc, sel, model, feat):
+def main_selector(sels):
+    """The selector the bench reports: 8 classes when available."""
+    for name in ("classes_8", "classes_6"):
+        if name in sels:
+            return sels[name]
+    return None, None
+
+
+def select_class(spc, sel, model, feat):
+    """(network's class or None, interpolation's class)."""
     if sel is None:
         return None, None
     si = sel.select(feat, spc.SEL_INTERP)[0]
@@ -332,8 +353,9 @@ def steps_section(spc, torch, A, rp, ci, v64, sel, model, reps: int = 5):
         from paper_1801_01134_amd import records as R
         recs = R.load(*[p for p in RECORDS if os.path.exists(p)])
         train, test = R.split(recs)
-        Xtr, Ttr, _, _ = R.arrays(train)
-        Xte, _, _, _ = R.arrays(test)
+        K = int(model.get("n_out", 6))
+        Xtr, Ttr, _, _ = R.arrays(train, K)
+        Xte, _, _, _ = R.arrays(test, K)
         dev = torch.device("cuda")
         Xd = torch.from_numpy(np.ascontiguousarray(Xtr, dtype=np.float32)).to(dev)
         Td = torch.from_numpy(np.ascontiguousarray(Ttr, dtype=np.float32)).to(dev)
@@ -347,7 +369,7 @@ def steps_section(spc, torch, A, rp, ci, v64, sel, model, reps: int = 5):
         order = np.random.default_rng(0).permutation(Xtr.shape[0])[:steps * batch].astype(np.int32)
         spc.mlp_train(p, m_, v_, 0, 1e-4, mu, sd, Xd, tau, order, batch)
         t = wall(lambda: spc.mlp_train(p, m_, v_, 0, 1e-4, mu, sd, Xd, tau, order, batch))
-        layer = 16 * 64 + 64 * 64 + 64 * 6
+        layer = 16 * 64 + 64 * 64 + 64 * K
         fl = 3 * 2 * layer * batch           # forward, and a backward of twice its cost
         out["mlp_train"] = {"steps": steps, "batch": batch, "us_per_step": round(t / steps * 1e6, 2),
                             "flops_per_step": fl, "achieved_TFLOPs": round(fl * steps / t / 1e12, 5),
@@ -365,70 +387,124 @@ def steps_section(spc, torch, A, rp, ci, v64, sel, model, reps: int = 5):
     return out
 
 
-def batched_section(spc, torch, sel, model, pool, tmp, n_mat: int, steps: int, warmup: int,
+def batch_plan(spc, B, mode: int, cache: dict, key) -> dict:
+    """The matrix's fastest plan of the given mode among the autotuner's
+    records that a batch can run (one tile per wavefront, no pipeline)."""
+    if key not in cache:
+        _, _, recs = spc.autotune(B, reps=3)
+        cache[key] = recs
+    ok = [q for q in cache[key] if q["mode"] == mode and not q.get("pipeline") and q.get("wave_tiles", 0) <= 1]
+    best = min(ok, key=lambda q: q["us"])
+    return {"mode": mode, "wave_chunks": best["wave_chunks"]}
+
+
+def batched_section(spc, torch, selectors, pool, tmp, n_mat: int, steps: int, warmup: int,
                     min_rows: int = 10_000, max_rows: int = 500_000):
+    """A batch of n_mat matrices, each in the kernel class a selector picks
+    from its features (the network when trained, else the interpolation),
+    with the chunk count the autotuner finds for that class. For each
+    selector (6 classes: the shapes; 8: the shapes and the test kernels),
+    the grouped batch (one launch per (mode, shape, chunks) group) against
+    one launch per matrix with the same plans, both also as captured graphs."""
+    import numpy as np
     dev = torch.device("cuda")
     results = pool.map(_gen_batched, [(i, tmp, min_rows, max_rows) for i in range(n_mat)])
-    Bs, xs, ys, shapes = [], [], [], []
     from paper_1801_01134_amd import synth
+    mats, feats, xs = [], [], []
     total_nnz = 0
     for i, n_rows, n_cols, base in results:
         A = _load_csr(base, n_rows, n_cols)
         rp = torch.from_numpy(A.rowptr).to(dev)
         ci = torch.from_numpy(A.colidx).to(dev)
         feat, _ = spc.matrix_features(rp, ci, A.n_cols)
-        s = None
-        if sel is not None:
-            s = select_shape(spc, sel, model, feat)[0 if model else 1]
-        s = 0 if s is None else s
-        r, c = spc.SHAPES[s]
-        Bs.append(spc.csr_to_beta(r, c, rp, ci, torch.from_numpy(A.values).to(dev), A.n_cols))
+        mats.append((rp, ci, torch.from_numpy(A.values).to(dev), A.n_cols, A.n_rows))
+        feats.append(feat)
         xs.append(torch.from_numpy(synth.dense_vector(A.n_cols, 400 + i)).to(dev))
-        ys.append(torch.empty(A.n_rows, dtype=torch.float64, device=dev))
-        shapes.append(s)
         total_nnz += A.nnz
-        del rp, ci
-    batch = spc.Batch(Bs).set_vectors(xs, ys)
-    plans = [B.plan() for B in Bs]
-    ab = sum(algorithmic_bytes(B, P.info()["n_tiles"]) for B, P in zip(Bs, plans))
     flops = 2.0 * total_nnz
     out = {"matrices": n_mat, "rows_range": [min_rows, max_rows], "nnz_total": total_nnz,
-           "rows_total": sum(B.n_rows for B in Bs),
-           "shape_share": [shapes.count(k) for k in range(6)], "alg_bytes": ab,
-           "n_tiles": batch.info()["n_tiles"]}
+           "rows_total": sum(m[4] for m in mats)}
+    betas, tune_cache = {}, {}
 
-    def sep():
-        for B, x, y, P in zip(Bs, xs, ys, plans):
-            spc.spmv(B, x, y, plan=P)
+    def beta(i, shape):
+        if (i, shape) not in betas:
+            rp, ci, v, n_cols, _ = mats[i]
+            r, c = spc.SHAPES[shape]
+            betas[(i, shape)] = spc.csr_to_beta(r, c, rp, ci, v, n_cols)
+        return betas[(i, shape)]
 
-    sep()
-    torch.cuda.synchronize()
-    ref = [y.clone() for y in ys]
-    side = torch.cuda.Stream()
-    variants = {"one_launch": (lambda: batch.run(), None),
-                "one_launch_persistent_2048wg": (lambda: batch.run(grid_blocks=2048), None),
-                "one_launch_graph": (lambda: batch.run(use_graph=True), side),
-                "one_launch_shape_switching_kernel": (lambda: batch.run(), None),
-                "separate_launches": (sep, None)}
-    out["single_shape_kernel"] = batch.info()["single_shape"] >= 0
-    for name, (fn, st) in variants.items():
-        batch.set_kernel(name == "one_launch_shape_switching_kernel")
-        t = event_time(torch, fn, steps, warmup, st)
-        out[name] = {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1),
-                     "alg_GBs": round(ab / t / 1e9, 1), "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
-    # 64 launches captured in one graph
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g, stream=side):
+    def timed(fn, stream=None):
+        t = event_time(torch, fn, steps, warmup, stream)
+        return t
+
+    def row(t, ab):
+        return {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1), "alg_GBs": round(ab / t / 1e9, 1),
+                "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+    for name, (sel, model) in selectors.items():
+        if sel is None:
+            continue
+        method = spc.SEL_MLP if model else spc.SEL_INTERP
+        classes = [sel.select(f, method)[0] for f in feats]
+        Bs, params = [], []
+        for i, k in enumerate(classes):
+            shape = spc.class_shape(k)
+            mode = 2 if spc.class_mode(k) == 2 else 0
+            B = beta(i, shape)
+            Bs.append(B)
+            params.append(batch_plan(spc, B, mode, tune_cache, (i, shape)))
+        ys = [torch.empty(m[4], dtype=torch.float64, device=dev) for m in mats]
+        batch = spc.Batch(Bs, params=params).set_vectors(xs, ys)
+        plans = [spc.plan_from(B, p) for B, p in zip(Bs, params)]
+        ab = sum(algorithmic_bytes(B, P.info()["n_tiles"]) for B, P in zip(Bs, plans))
+        info = batch.info()
+        res = {"selector": "mlp" if model else "interpolation", "n_classes": sel.n_classes(method),
+               "class_share": np.bincount(classes, minlength=8).tolist(), "n_groups": info["n_groups"],
+               "n_tiles": info["n_tiles"], "alg_bytes": ab,
+               "chunks_share": {str(q): sum(1 for p in params if p["wave_chunks"] == q) for q in (2, 4, 6, 8)}}
+
+        def sep():
+            for B, x, y, P in zip(Bs, xs, ys, plans):
+                spc.spmv(B, x, y, plan=P)
+
         sep()
-    t = event_time(torch, g.replay, steps, warmup, side)
-    out["separate_launches_graph"] = {"us": round(t * 1e6, 1), "gflops": round(flops / t / 1e9, 1),
-                                      "alg_GBs": round(ab / t / 1e9, 1),
-                                      "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}
-    batch.set_kernel(False)
-    batch.run()
-    torch.cuda.synchronize()
-    out["bitwise_equal_to_separate"] = all(torch.equal(a, b) for a, b in zip(ys, ref))
-    out["speedup_one_launch_vs_separate"] = round(out["separate_launches"]["us"] / out["one_launch"]["us"], 3)
+        torch.cuda.synchronize()
+        ref = [y.clone() for y in ys]
+        side = torch.cuda.Stream()
+        res["grouped"] = row(timed(lambda: batch.run()), ab)
+        res["grouped_persistent_2048wg"] = row(timed(lambda: batch.run(grid_blocks=2048)), ab)
+        res["grouped_graph"] = row(timed(lambda: batch.run(use_graph=True), side), ab)
+        res["separate_launches"] = row(timed(sep), ab)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            sep()
+        res["separate_launches_graph"] = row(timed(g.replay, side), ab)
+        # each matrix alone in its plan, summed: what the batch's tiles cost without any overlap
+        res["sum_of_single_launches_us"] = round(sum(
+            spc.time_spmv(B, P, reps=max(3, steps // 2)) for B, P in zip(Bs, plans)), 1)
+        batch.run()
+        torch.cuda.synchronize()
+        res["bitwise_equal_to_separate"] = all(torch.equal(a, b) for a, b in zip(ys, ref))
+        res["speedup_grouped_vs_separate"] = round(res["separate_launches"]["us"] / res["grouped"]["us"], 3)
+        out[name] = res
+        del batch, plans, g
+    # the earlier single-launch form: every matrix in mode 0 with 4 chunks, one
+    # launch of the shape-switching kernel, shapes as the 6-class selector picks
+    ref_name = "classes_6" if "classes_6" in out else next((k for k in out if k.startswith("classes_")), None)
+    if ref_name is not None:
+        sel, model = selectors[ref_name]
+        method = spc.SEL_MLP if model else spc.SEL_INTERP
+        Bs = [beta(i, spc.class_shape(sel.select(f, method)[0])) for i, f in enumerate(feats)]
+        ys = [torch.empty(m[4], dtype=torch.float64, device=dev) for m in mats]
+        batch = spc.Batch(Bs, wave_chunks=4).set_vectors(xs, ys).set_kernel(True)
+        ab = sum(algorithmic_bytes(B, B.plan(0, 0, 0, 4).info()["n_tiles"]) for B in Bs)
+        out["shape_switching_one_launch_kq4"] = row(timed(lambda: batch.run()), ab)
+    best = out.get("classes_8") or out.get("classes_6")
+    if best is not None:
+        out["speedup_one_launch_vs_separate"] = best["speedup_grouped_vs_separate"]
+    if "classes_8" in out and "classes_6" in out:
+        out["time_8_classes_over_6_classes"] = round(out["classes_8"]["grouped"]["us"]
+                                                     / out["classes_6"]["grouped"]["us"], 4)
     return out
 
 
@@ -688,7 +764,7 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     flops = 2.0 * A.nnz
     csr_bytes = {8: A.nnz * 12 + (A.n_rows + 1) * 4, 4: A.nnz * 8 + (A.n_rows + 1) * 4}
     if args.only_steps:
-        sel, model, _ = load_selector(spc)
+        sel, model = main_selector(load_selectors(spc)[0])
         print(json.dumps({"step_timings": steps_section(spc, torch, A, rp, ci, v64, sel, model)}), flush=True)
         return 0
 
@@ -710,7 +786,11 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
             best_params[key] = params
             top_params[key] = [{k: v for k, v in rec.items() if k not in ("us", "n_tiles")}
                                for rec in sorted(records, key=lambda rec: rec["us"])[:3]]
+            plain = [q["us"] for q in records if q["mode"] != 2]
+            test = [q["us"] for q in records if q["mode"] == 2]
             sweep[key] = {"us": round(us, 2), "gflops": round(flops / t / 1e9, 1),
+                          "us_own_kernels": round(min(plain), 2),
+                          "us_test_kernel": round(min(test), 2) if test else None,
                           "alg_GBs": round(ab / t / 1e9, 1), "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
                           "alg_bytes": ab, "matrix_bytes": B.nbytes(),
                           "matrix_vs_csr": round(B.nbytes() / csr_bytes[B.values.element_size()], 4),
@@ -783,26 +863,38 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     worst = float((err / (1e-13 * s_ref + 1e-300)).max())
     del B, P
 
-    # selection: shapes picked from the matrix's features alone
+    # selection: kernel classes picked from the matrix's features alone; the
+    # time of a class is its shape's own kernels (classes 0-5) or its test
+    # kernel (6, 7), each autotuned in the sweep above
     selection = None
     ratio = None
+    sels = {}
     sel = model = None
     if do_select:
-        sel, model, held_out = load_selector(spc)
+        sels, held_out = load_selectors(spc)
+        sel, model = main_selector(sels)
         feat, nb = spc.matrix_features(rp, ci, A.n_cols)
-        f64_times = {k: v["us"] for k, v in sweep.items() if k.startswith("f64_")}
+        cls_times = []
+        for k in range(spc.N_CLASSES):
+            r_, c_ = spc.SHAPES[spc.class_shape(k)]
+            e = sweep.get(f"f64_b{r_}x{c_}")
+            cls_times.append(None if e is None else (e["us_test_kernel"] if k >= 6 else e["us_own_kernels"]))
         selection = {"features": [round(float(v), 5) for v in feat], "held_out_regret": held_out}
-        if sel is not None and f64_times:
-            sm, si = select_shape(spc, sel, model, feat)
-            t_best = min(f64_times.values())
-            for name, s_ in (("mlp", sm), ("interpolation", si)):
-                if s_ is None:
-                    continue
-                key = f"f64_b{spc.SHAPES[s_][0]}x{spc.SHAPES[s_][1]}"
-                selection[name] = {"shape": list(spc.SHAPES[s_]), "time_ratio": round(f64_times[key] / t_best, 4)}
-            ratio = selection.get("mlp", selection.get("interpolation", {})).get("time_ratio")
-        elif not f64_times:
-            selection["note"] = "no sweep (only-headline): ratios need every shape's time"
+        if sels and all(t is not None for t in cls_times):
+            t_best = min(cls_times)
+            selection["class_times_us"] = cls_times
+            for name, (sel_, model_) in sels.items():
+                sm, si = select_class(spc, sel_, model_, feat)
+                d = {}
+                for meth, k in (("mlp", sm), ("interpolation", si)):
+                    if k is not None:
+                        d[meth] = {"class": k, "shape": list(spc.SHAPES[spc.class_shape(k)]),
+                                   "test_kernel": k >= 6, "time_ratio": round(cls_times[k] / t_best, 4)}
+                selection[name] = d
+            main = selection.get("classes_8", selection.get("classes_6", {}))
+            ratio = main.get("mlp", main.get("interpolation", {})).get("time_ratio")
+        elif not sweep:
+            selection["note"] = "no sweep (only-headline): ratios need every kernel's time"
 
     out = {
         "metric": "SpMV GFlop/s + HBM GB/s % of peak; selected-vs-best kernel time ratio",
@@ -835,11 +927,13 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
         log(f"step timings: {out['step_timings']}")
         torch.cuda.empty_cache()
     if do_batched:
-        out["batched"] = batched_section(spc, torch, sel, model, pool, tmp, args.batched_matrices,
+        if not sels:
+            sels, _ = load_selectors(spc)
+        out["batched"] = batched_section(spc, torch, sels, pool, tmp, args.batched_matrices,
                                          max(5, args.steps // 10), 3)
         log(f"batched: {out['batched']}")
         torch.cuda.empty_cache()
-        out["batched_small"] = batched_section(spc, torch, sel, model, pool, tmp, 512, max(5, args.steps // 10), 3,
+        out["batched_small"] = batched_section(spc, torch, sels, pool, tmp, 512, max(5, args.steps // 10), 3,
                                                min_rows=500, max_rows=20_000)
         log(f"batched small: {out['batched_small']}")
         torch.cuda.empty_cache()

@@ -320,35 +320,43 @@ spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t 
 
 /* ---------------------------------------------------------------------------
  * Batched products: y_i = A_i x_i (or y_i += A_i x_i) for `count` matrices
- * of uneven sizes and any of the six shapes, in ONE kernel launch. Each
- * matrix is partitioned as spc_plan_create would (whole intervals, about
- * equal blocks per tile, section "Parallelization"); the tiles of all
- * matrices form one list that the launch runs, each wavefront switching on
- * its tile's matrix and shape.
+ * of uneven sizes and any of the six shapes. Each matrix is partitioned as
+ * spc_plan_create would (whole intervals, about equal blocks per tile,
+ * section "Parallelization") with its own parameters: mode 0 (wavefront
+ * tiles) or, for beta(1,8) and beta(2,4), mode 2 (the test tiles of
+ * Algorithm 2), and its own wave_chunks. Matrices of one (mode, shape,
+ * chunk count) form a group; a product is one launch per group, of a kernel
+ * built for that group, over the tiles of all its matrices.
  *
  * spc_batch_create: views (host array of count views, all of one dtype,
- *   values 16-byte aligned, x of each under 3.75 GiB); params: NULL or a
- *   mode-0 parameter set (wave_chunks). The batch keeps the views: their
+ *   values 16-byte aligned, x of each under 3.75 GiB, count < 2^29);
+ *   params (host) with n_params = 0 (params unused: each matrix takes
+ *   spc_plan_default_params), 1 (params[0] for every matrix) or count
+ *   (params[i] for matrix i). Each set used must have mode 0 or 2 (2 only
+ *   for the one-byte-mask shapes), pipeline 0 and wave_tiles 0 or 1; its
+ *   tile_order and cu_groups are not used. The batch keeps the views: their
  *   arrays must stay alive and unchanged. Synchronizes.
  * spc_batch_set_vectors: xs, ys = host arrays of count device pointers (x_i
  *   with n_cols_i entries, y_i with n_rows_i entries). Copies them to the
  *   batch's device table with a synchronous copy; do not call it while a
  *   batched launch of this batch is still running.
  * spc_spmv_batched: grid_blocks = 0 launches one wavefront per tile;
- *   grid_blocks > 0 launches that many workgroups that loop over the tile
- *   list (persistent). use_graph = 1 captures the launch once in a HIP graph
- *   (needs a non-NULL stream; recaptured when accumulate or grid_blocks
- *   change) and replays it. Asynchronous.
- * When all matrices share one shape the launch uses a kernel built for that
- * shape (no per-tile shape switch; that shape's registers and LDS only);
- * spc_batch_set_kernel(batch, 1) forces the shape-switching kernel anyway
- * (0 restores the choice). spc_batch_info reports the shared shape index in
- * *single_shape (-1 when shapes differ). */
+ *   grid_blocks > 0 caps each launch at that many workgroups, which loop
+ *   over their group's tiles (persistent). use_graph = 1 captures the
+ *   launches once in a HIP graph (needs a non-NULL stream; recaptured when
+ *   accumulate or grid_blocks change) and replays it. Asynchronous.
+ * spc_batch_set_kernel(batch, 1) runs the whole list instead as ONE launch
+ *   of a kernel that switches on each tile's shape (its LDS is the largest
+ *   shape's); it needs every matrix in mode 0 with one chunk count
+ *   (SPC_ERR_INVALID_ARG otherwise); 0 restores the grouped launches.
+ * spc_batch_info: tile and long-interval counts, the shape index shared by
+ *   all matrices (-1 when shapes differ) and the number of groups. */
 typedef struct spc_batch spc_batch;
 spc_status spc_batch_create(int32_t count, const spc_beta_view *views, const spc_plan_params *params,
-                            spc_batch **out, hipStream_t stream);
+                            int32_t n_params, spc_batch **out, hipStream_t stream);
 spc_status spc_batch_destroy(spc_batch *batch);
-spc_status spc_batch_info(const spc_batch *batch, int64_t *n_tiles, int64_t *n_long, int32_t *single_shape);
+spc_status spc_batch_info(const spc_batch *batch, int64_t *n_tiles, int64_t *n_long, int32_t *single_shape,
+                          int32_t *n_groups);
 spc_status spc_batch_set_kernel(spc_batch *batch, int32_t general);
 spc_status spc_batch_set_vectors(spc_batch *batch, const void *const *xs, void *const *ys);
 spc_status spc_spmv_batched(spc_batch *batch, int32_t accumulate, int32_t grid_blocks, int32_t use_graph,
@@ -395,80 +403,111 @@ spc_status spc_matrix_features_noalloc(int64_t n_rows, int64_t n_cols, int64_t n
 int64_t spc_matrix_features_noalloc_max_rows(void);
 
 /* ---------------------------------------------------------------------------
- * Learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU network in FP32 whose
- * forward, backward and Adam steps run in this library's kernels. The paper
+ * Kernel classes. The selectors choose among SPC_N_CLASSES kernels: classes
+ * 0..5 are the six block shapes in SPC_SHAPE order, each run by its own
+ * kernels (plan modes 0 and 1); class 6 is the beta(1,8) "test" kernel and
+ * class 7 the beta(2,4) "test" kernel (plan mode 2; Algorithm 2, and the
+ * "test" rows of Table 3). A selector fitted on n_classes = 6 records
+ * chooses among the shapes only. The Avg(r,c) of class k is feature
+ * 8 + spc_class_shape(k).
+ * ------------------------------------------------------------------------- */
+#define SPC_N_CLASSES 8
+#define SPC_CLASS_TEST_B1X8 6
+#define SPC_CLASS_TEST_B2X4 7
+/* Shape index (0..5) of class k (0..7), or -1 for any other k. */
+int32_t spc_class_shape(int32_t k);
+/* Plan mode the class runs in: 2 for the test classes, else -1 (the
+ * shape's own modes 0 and 1; the autotuner or the default plan chooses). */
+int32_t spc_class_mode(int32_t k);
+
+/* ---------------------------------------------------------------------------
+ * Learned kernel selector: a 16 -> 64 -> 64 -> K ReLU network in FP32 whose
+ * forward, backward and Adam steps run in this library's kernels, with
+ * K = n_out = 6 (the shapes) or 8 (the kernel classes above). The paper
  * selects kernels from recorded speeds with one polynomial per kernel
  * (section "Performance polynomial interpolation") and names selection from
  * several matrix properties as future work (Conclusions); the network is
  * that extension. Definitions:
  *   x^   = (x - mu) / sd                 (per feature; training statistics)
  *   h1   = relu(W1 x^ + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
- *   tau  = log2(t / min_k t_k)           (time relative to the best shape)
- *   loss = mean over the batch and the 6 outputs of (o - tau)^2
+ *   tau  = log2(t / min_k t_k)           (time relative to the best kernel)
+ *   loss = mean over the batch and the K outputs of (o - tau)^2
  *   choice = argmin_k o_k (lowest index on ties)
  *   Adam: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected, constant lr.
- * params: SPC_MLP_N_PARAMS floats, in this order, row-major [out][in]:
- *   W1[64][16], b1[64], W2[64][64], b2[64], W3[6][64], b3[6].
- * X: n x 16 feature rows (float, row-major); times, tau: n x 6.
+ * params: SPC_MLP_PARAMS(K) floats, in this order, row-major [out][in]:
+ *   W1[64][16], b1[64], W2[64][64], b2[64], W3[K][64], b3[K].
+ * X: n x 16 feature rows (float, row-major); times, tau: n x K.
+ * n_out other than 6 or 8 is SPC_ERR_INVALID_ARG.
  * All arrays are device memory unless marked host. */
 #define SPC_MLP_N_IN 16
 #define SPC_MLP_N_HIDDEN 64
 #define SPC_MLP_N_OUT 6
-#define SPC_MLP_N_PARAMS 5638
+#define SPC_MLP_MAX_OUT 8
+#define SPC_MLP_PARAMS(k) (SPC_MLP_N_HIDDEN * (SPC_MLP_N_IN + 1) + SPC_MLP_N_HIDDEN * (SPC_MLP_N_HIDDEN + 1) + \
+                           (k) * (SPC_MLP_N_HIDDEN + 1))
+#define SPC_MLP_N_PARAMS 5638 /* SPC_MLP_PARAMS(6); SPC_MLP_PARAMS(8) = 5768 */
 #define SPC_MLP_MAX_BATCH 64
 
 /* mu, sd (16 each): mean and population standard deviation of the columns
  * of X (sd < 1e-12 is replaced by 1). Asynchronous. */
 spc_status spc_mlp_standardizer(const float *X, int32_t n, float *mu_out, float *sd_out, hipStream_t stream);
-/* tau = log2(t / row minimum) for n rows of 6 positive times. Asynchronous. */
-spc_status spc_mlp_targets(const float *times, int32_t n, float *tau_out, hipStream_t stream);
-/* Loss and gradient (SPC_MLP_N_PARAMS floats) of one batch: rows (host,
- * batch entries in [0, n)) pick the batch from X and tau; 1 <= batch <= 64.
- * loss_out: one device float. Synchronizes. */
+/* tau = log2(t / row minimum) for n rows of n_out positive times.
+ * Asynchronous. */
+spc_status spc_mlp_targets(const float *times, int32_t n, int32_t n_out, float *tau_out, hipStream_t stream);
+/* Loss and gradient (SPC_MLP_PARAMS(n_out) floats) of one batch: rows
+ * (host, batch entries in [0, n)) pick the batch from X and tau;
+ * 1 <= batch <= 64. loss_out: one device float. Synchronizes. */
 spc_status spc_mlp_loss_grad(const float *params, const float *mu, const float *sd, const float *X,
-                             const float *tau, int32_t n, const int32_t *rows, int32_t batch,
+                             const float *tau, int32_t n, int32_t n_out, const int32_t *rows, int32_t batch,
                              float *grad_out, float *loss_out, hipStream_t stream);
 /* n_steps Adam steps, step s on the rows order[s*batch .. s*batch+batch-1]
  * (host array, entries in [0, n)). params, adam_m, adam_v (each
- * SPC_MLP_N_PARAMS floats) are updated in place; step0 = Adam steps already
- * taken (bias correction continues from there). losses_out[s] = loss of step
- * s before its update. One workgroup runs all steps in one launch.
- * Synchronizes. */
+ * SPC_MLP_PARAMS(n_out) floats) are updated in place; step0 = Adam steps
+ * already taken (bias correction continues from there). losses_out[s] =
+ * loss of step s before its update. One workgroup runs all steps in one
+ * launch. Synchronizes. */
 spc_status spc_mlp_train(float *params, float *adam_m, float *adam_v, int32_t step0, float lr,
                          const float *mu, const float *sd, const float *X, const float *tau, int32_t n,
-                         const int32_t *order, int32_t n_steps, int32_t batch, float *losses_out,
+                         int32_t n_out, const int32_t *order, int32_t n_steps, int32_t batch, float *losses_out,
                          hipStream_t stream);
-/* Scores (n x 6, may be NULL) and choices (n, may be NULL) for n feature
- * rows. Asynchronous. */
+/* Scores (n x n_out, may be NULL) and choices (n, may be NULL) for n
+ * feature rows. Asynchronous. */
 spc_status spc_mlp_infer(const float *params, const float *mu, const float *sd, const float *X, int32_t n,
-                         float *scores_out, int32_t *choice_out, hipStream_t stream);
+                         int32_t n_out, float *scores_out, int32_t *choice_out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
- * Selector object (library-owned). Interpolation: per shape, a least-squares
- * polynomial of speed against Avg(r,c) over n records (avg, speed: host
- * n x 6 doubles, speed in GFlop/s), degree lowered to (distinct Avg values -
- * 1) when records are few; a query's Avg (features 8..13) is clamped to the
- * fitted range and the highest predicted speed wins (lowest index on ties).
- * MLP: spc_selector_set_mlp copies a trained network (host arrays) to the
- * current device; the smallest score wins.
+ * Selector object (library-owned). Interpolation: per kernel class, a
+ * least-squares polynomial of speed against Avg(r,c) over n records (avg,
+ * speed: host n x n_classes doubles, n_classes 6 or 8, speed in GFlop/s),
+ * degree lowered to (distinct Avg values - 1) when records are few; a
+ * query's Avg (feature 8 + spc_class_shape(k)) is clamped to the fitted
+ * range and the highest predicted speed wins (lowest index on ties).
+ * MLP: spc_selector_set_mlp copies a trained network with n_out outputs
+ * (host arrays) to the current device; the smallest score wins.
  * spc_select_kernel: features = host float[16] (spc_matrix_features);
- * method SPC_SEL_INTERP or SPC_SEL_MLP; *shape_out = 0..5; scores_out (host
- * float[6], may be NULL) = predicted GFlop/s (interpolation) or predicted
- * log2 time ratios (MLP). SPC_ERR_NO_MODEL when the method has no model, so
- * the caller can fall back to the other one. Synchronizes (MLP). */
+ * method SPC_SEL_INTERP or SPC_SEL_MLP; *class_out = the chosen class, in
+ * 0..n-1 for a model of n classes; scores_out (host float[SPC_N_CLASSES],
+ * may be NULL; the first n entries are written) = predicted GFlop/s
+ * (interpolation) or predicted log2 time ratios (MLP). SPC_ERR_NO_MODEL
+ * when the method has no model, so the caller can fall back to the other
+ * one. Synchronizes (MLP). */
 #define SPC_SEL_INTERP 0
 #define SPC_SEL_MLP 1
 typedef struct spc_selector spc_selector;
 spc_status spc_selector_create(spc_selector **out);
 spc_status spc_selector_destroy(spc_selector *sel);
-spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, const double *avg, const double *speed,
-                                   int32_t degree);
-/* Coefficients (host 6 x 4 doubles, lowest power first, zero above the
- * degree) and fitted Avg ranges (host 6 doubles each, may be NULL). */
+spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, int32_t n_classes, const double *avg,
+                                   const double *speed, int32_t degree);
+/* Coefficients (host SPC_N_CLASSES x 4 doubles, lowest power first, zero
+ * above the degree) and fitted Avg ranges (host SPC_N_CLASSES doubles each,
+ * may be NULL) of the first *n_classes_out rows. */
 spc_status spc_selector_interp_coeffs(const spc_selector *sel, double *coeffs_out, double *lo_out,
-                                      double *hi_out);
-spc_status spc_selector_set_mlp(spc_selector *sel, const float *params, const float *mu, const float *sd);
-spc_status spc_select_kernel(spc_selector *sel, const float *features, int32_t method, int32_t *shape_out,
+                                      double *hi_out, int32_t *n_classes_out);
+/* Number of classes the method's model chooses among (0 without a model). */
+int32_t spc_selector_n_classes(const spc_selector *sel, int32_t method);
+spc_status spc_selector_set_mlp(spc_selector *sel, int32_t n_out, const float *params, const float *mu,
+                                const float *sd);
+spc_status spc_select_kernel(spc_selector *sel, const float *features, int32_t method, int32_t *class_out,
                              float *scores_out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------

@@ -1,5 +1,7 @@
-"""FP64 oracle of the learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU
-network trained by Adam on recorded kernel times. TEST INFRASTRUCTURE ONLY.
+"""FP64 oracle of the learned kernel selector: a 16 -> 64 -> 64 -> K ReLU
+network trained by Adam on recorded kernel times, K = 6 (the block shapes)
+or 8 (the shapes and the two "test" kernels of Algorithm 2). TEST
+INFRASTRUCTURE ONLY.
 
 The paper selects kernels by per-kernel polynomial interpolation of recorded
 speeds and names selection from several matrix statistics as future work
@@ -9,9 +11,9 @@ here step by step:
   x^   = (x - mu) / sigma            (training-set mean and spread per feature)
   z1   = W1 x^ + b1,  h1 = relu(z1)
   z2   = W2 h1 + b2,  h2 = relu(z2)
-  o    = W3 h2 + b3                  (one score per kernel shape)
+  o    = W3 h2 + b3                  (one score per kernel class)
   tau  = log2(t / min_k t_k)         (target: time relative to the best kernel)
-  L    = mean over batch and shapes of (o - tau)^2
+  L    = mean over batch and classes of (o - tau)^2
   pick = argmin_k o_k
 
 Weights are row-major [out, in]. Gradients come from the chain rule; Adam
@@ -25,19 +27,19 @@ DIMS = (16, 64, 64, 6)
 PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
 
 
-def param_shapes():
-    d0, d1, d2, d3 = DIMS
-    return {"W1": (d1, d0), "b1": (d1,), "W2": (d2, d1), "b2": (d2,), "W3": (d3, d2), "b3": (d3,)}
+def param_shapes(n_out: int = DIMS[3]):
+    d0, d1, d2 = DIMS[:3]
+    return {"W1": (d1, d0), "b1": (d1,), "W2": (d2, d1), "b2": (d2,), "W3": (n_out, d2), "b3": (n_out,)}
 
 
-def n_params() -> int:
-    return int(sum(int(np.prod(s)) for s in param_shapes().values()))
+def n_params(n_out: int = DIMS[3]) -> int:
+    return int(sum(int(np.prod(s)) for s in param_shapes(n_out).values()))
 
 
-def init_params(rng: np.random.Generator) -> dict:
+def init_params(rng: np.random.Generator, n_out: int = DIMS[3]) -> dict:
     """He-uniform weights, zero biases (the random draw is an input to both sides)."""
     P = {}
-    for name, shp in param_shapes().items():
+    for name, shp in param_shapes(n_out).items():
         if name.startswith("W"):
             lim = np.sqrt(6.0 / shp[1])
             P[name] = rng.uniform(-lim, lim, size=shp)

@@ -79,26 +79,31 @@ _SIGS = {
     "spc_matrix_features_noalloc": (c_int32, [c_int64, c_int64, c_int64, c_void_p, c_void_p,
                                               POINTER(ctypes.c_float), POINTER(c_int64), c_void_p]),
     "spc_matrix_features_noalloc_max_rows": (c_int64, []),
-    "spc_batch_create": (c_int32, [c_int32, POINTER(BetaView), POINTER(PlanParams), POINTER(c_void_p), c_void_p]),
+    "spc_batch_create": (c_int32, [c_int32, POINTER(BetaView), POINTER(PlanParams), c_int32, POINTER(c_void_p),
+                                   c_void_p]),
     "spc_batch_destroy": (c_int32, [c_void_p]),
-    "spc_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32)]),
+    "spc_batch_info": (c_int32, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int32)]),
     "spc_batch_set_kernel": (c_int32, [c_void_p, c_int32]),
     "spc_batch_set_vectors": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p)]),
     "spc_spmv_batched": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p]),
     "spc_mlp_standardizer": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
-    "spc_mlp_targets": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
-    "spc_mlp_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, POINTER(c_int32),
-                                    c_int32, c_void_p, c_void_p, c_void_p]),
+    "spc_mlp_targets": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
+    "spc_mlp_loss_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                    POINTER(c_int32), c_int32, c_void_p, c_void_p, c_void_p]),
     "spc_mlp_train": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, ctypes.c_float, c_void_p, c_void_p, c_void_p,
-                                c_void_p, c_int32, POINTER(c_int32), c_int32, c_int32, c_void_p, c_void_p]),
-    "spc_mlp_infer": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+                                c_void_p, c_int32, c_int32, POINTER(c_int32), c_int32, c_int32, c_void_p, c_void_p]),
+    "spc_mlp_infer": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p,
+                                c_void_p]),
+    "spc_class_shape": (c_int32, [c_int32]),
+    "spc_class_mode": (c_int32, [c_int32]),
     "spc_selector_create": (c_int32, [POINTER(c_void_p)]),
     "spc_selector_destroy": (c_int32, [c_void_p]),
-    "spc_selector_fit_interp": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_double), POINTER(ctypes.c_double),
-                                          c_int32]),
+    "spc_selector_fit_interp": (c_int32, [c_void_p, c_int32, c_int32, POINTER(ctypes.c_double),
+                                          POINTER(ctypes.c_double), c_int32]),
     "spc_selector_interp_coeffs": (c_int32, [c_void_p, POINTER(ctypes.c_double), POINTER(ctypes.c_double),
-                                             POINTER(ctypes.c_double)]),
-    "spc_selector_set_mlp": (c_int32, [c_void_p, POINTER(ctypes.c_float), POINTER(ctypes.c_float),
+                                             POINTER(ctypes.c_double), POINTER(c_int32)]),
+    "spc_selector_n_classes": (c_int32, [c_void_p, c_int32]),
+    "spc_selector_set_mlp": (c_int32, [c_void_p, c_int32, POINTER(ctypes.c_float), POINTER(ctypes.c_float),
                                        POINTER(ctypes.c_float)]),
     "spc_select_kernel": (c_int32, [c_void_p, POINTER(ctypes.c_float), c_int32, POINTER(c_int32),
                                     POINTER(ctypes.c_float), c_void_p]),
@@ -469,6 +474,35 @@ def matrix_features(rowptr, colidx, n_cols: int, device="cuda"):
 MLP_N_PARAMS = 5638
 MLP_MAX_BATCH = 64
 SEL_INTERP, SEL_MLP = 0, 1
+# kernel classes: the six shapes (plan modes 0/1), then the test kernels of
+# Algorithm 2 for beta(1,8) and beta(2,4) (plan mode 2)
+N_CLASSES = 8
+CLASS_TEST_B1X8, CLASS_TEST_B2X4 = 6, 7
+
+
+def mlp_n_params(n_out: int = 6) -> int:
+    """Parameter count of the 16 -> 64 -> 64 -> n_out network."""
+    return 64 * 17 + 64 * 65 + n_out * 65
+
+
+def _mlp_out(params) -> int:
+    for k in (6, 8):
+        if params.numel() == mlp_n_params(k):
+            return k
+    raise ValueError(f"params must hold {mlp_n_params(6)} or {mlp_n_params(8)} floats, got {params.numel()}")
+
+
+def class_shape(k: int) -> int:
+    """Shape index (0..5) of kernel class k."""
+    s = lib().spc_class_shape(int(k))
+    if s < 0:
+        raise ValueError(f"no kernel class {k}")
+    return s
+
+
+def class_mode(k: int) -> int:
+    """Plan mode of kernel class k: 2 for the test classes, -1 for a shape's own kernels."""
+    return int(lib().spc_class_mode(int(k)))
 
 
 def _f32_cuda(t, shape=None):
@@ -496,22 +530,25 @@ def mlp_standardizer(X: torch.Tensor):
 
 
 def mlp_targets(times: torch.Tensor) -> torch.Tensor:
+    """tau = log2(t / row minimum) of n x K times (K = 6 or 8)."""
     n = times.shape[0]
-    _f32_cuda(times, (n, 6))
+    k = times.shape[1] if times.dim() == 2 else 0
+    _f32_cuda(times, (n, k))
     tau = torch.empty_like(times)
-    check(lib().spc_mlp_targets(_ptr(times), n, _ptr(tau), stream_ptr()))
+    check(lib().spc_mlp_targets(_ptr(times), n, k, _ptr(tau), stream_ptr()))
     return tau
 
 
 def mlp_loss_grad(params, mu, sd, X, tau, rows):
     """Loss and gradient of one batch (rows: host indices into X/tau)."""
     n = X.shape[0]
-    for t, shp in ((params, (MLP_N_PARAMS,)), (mu, (16,)), (sd, (16,)), (X, (n, 16)), (tau, (n, 6))):
+    k = _mlp_out(params)
+    for t, shp in ((params, (mlp_n_params(k),)), (mu, (16,)), (sd, (16,)), (X, (n, 16)), (tau, (n, k))):
         _f32_cuda(t, shp)
     r, rp = _i32_host(rows)
-    grad = torch.empty(MLP_N_PARAMS, dtype=torch.float32, device=X.device)
+    grad = torch.empty(mlp_n_params(k), dtype=torch.float32, device=X.device)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
-    check(lib().spc_mlp_loss_grad(_ptr(params), _ptr(mu), _ptr(sd), _ptr(X), _ptr(tau), n, rp, r.size,
+    check(lib().spc_mlp_loss_grad(_ptr(params), _ptr(mu), _ptr(sd), _ptr(X), _ptr(tau), n, k, rp, r.size,
                                   _ptr(grad), _ptr(loss), stream_ptr()))
     return float(loss.item()), grad
 
@@ -520,25 +557,29 @@ def mlp_train(params, adam_m, adam_v, step0: int, lr: float, mu, sd, X, tau, ord
     """Adam steps over batches order[s*batch:(s+1)*batch] (host indices);
     params and moments are updated in place. Returns the per-step losses."""
     n = X.shape[0]
-    for t, shp in ((params, (MLP_N_PARAMS,)), (adam_m, (MLP_N_PARAMS,)), (adam_v, (MLP_N_PARAMS,)),
-                   (mu, (16,)), (sd, (16,)), (X, (n, 16)), (tau, (n, 6))):
+    k = _mlp_out(params)
+    npar = mlp_n_params(k)
+    for t, shp in ((params, (npar,)), (adam_m, (npar,)), (adam_v, (npar,)),
+                   (mu, (16,)), (sd, (16,)), (X, (n, 16)), (tau, (n, k))):
         _f32_cuda(t, shp)
     o, op = _i32_host(order)
     steps = o.size // batch
     losses = torch.empty(max(1, steps), dtype=torch.float32, device=X.device)
     check(lib().spc_mlp_train(_ptr(params), _ptr(adam_m), _ptr(adam_v), step0, lr, _ptr(mu), _ptr(sd), _ptr(X),
-                              _ptr(tau), n, op, steps, batch, _ptr(losses), stream_ptr()))
+                              _ptr(tau), n, k, op, steps, batch, _ptr(losses), stream_ptr()))
     return losses[:steps]
 
 
 def mlp_infer(params, mu, sd, X):
-    """(scores n x 6, choice n) of the network for n feature rows."""
+    """(scores n x K, choice n) of the network (K outputs, 6 or 8) for n
+    feature rows."""
     n = X.shape[0]
-    for t, shp in ((params, (MLP_N_PARAMS,)), (mu, (16,)), (sd, (16,)), (X, (n, 16))):
+    k = _mlp_out(params)
+    for t, shp in ((params, (mlp_n_params(k),)), (mu, (16,)), (sd, (16,)), (X, (n, 16))):
         _f32_cuda(t, shp)
-    scores = torch.empty((n, 6), dtype=torch.float32, device=X.device)
+    scores = torch.empty((n, k), dtype=torch.float32, device=X.device)
     choice = torch.empty(n, dtype=torch.int32, device=X.device)
-    check(lib().spc_mlp_infer(_ptr(params), _ptr(mu), _ptr(sd), _ptr(X), n, _ptr(scores), _ptr(choice),
+    check(lib().spc_mlp_infer(_ptr(params), _ptr(mu), _ptr(sd), _ptr(X), n, k, _ptr(scores), _ptr(choice),
                               stream_ptr()))
     return scores, choice
 
@@ -558,24 +599,32 @@ class Selector:
             self.handle = None
 
     def fit_interp(self, avg, speed, degree: int = 3):
+        """Per-class polynomial fit; avg and speed are n x K (K = 6 shapes
+        or 8 kernel classes; the Avg of a test class is its shape's)."""
         import numpy as np
         a = np.ascontiguousarray(avg, dtype=np.float64)
         v = np.ascontiguousarray(speed, dtype=np.float64)
-        if a.ndim != 2 or a.shape[1] != 6 or v.shape != a.shape:
-            raise ValueError("avg and speed must be n x 6")
-        check(lib().spc_selector_fit_interp(self.handle, a.shape[0], a.ctypes.data_as(POINTER(ctypes.c_double)),
+        if a.ndim != 2 or a.shape[1] not in (6, 8) or v.shape != a.shape:
+            raise ValueError("avg and speed must be n x 6 or n x 8")
+        check(lib().spc_selector_fit_interp(self.handle, a.shape[0], a.shape[1],
+                                            a.ctypes.data_as(POINTER(ctypes.c_double)),
                                             v.ctypes.data_as(POINTER(ctypes.c_double)), degree))
         return self
 
     def interp_coeffs(self):
         import numpy as np
-        c = np.zeros((6, 4))
-        lo = np.zeros(6)
-        hi = np.zeros(6)
+        c = np.zeros((N_CLASSES, 4))
+        lo = np.zeros(N_CLASSES)
+        hi = np.zeros(N_CLASSES)
+        k = c_int32()
         dp = POINTER(ctypes.c_double)
         check(lib().spc_selector_interp_coeffs(self.handle, c.ctypes.data_as(dp), lo.ctypes.data_as(dp),
-                                               hi.ctypes.data_as(dp)))
-        return c, lo, hi
+                                               hi.ctypes.data_as(dp), ctypes.byref(k)))
+        k = int(k.value)
+        return c[:k], lo[:k], hi[:k]
+
+    def n_classes(self, method: int = SEL_MLP) -> int:
+        return int(lib().spc_selector_n_classes(self.handle, method))
 
     def set_mlp(self, params, mu, sd):
         import numpy as np
@@ -583,9 +632,10 @@ class Selector:
         p = np.ascontiguousarray(params, dtype=np.float32)
         m = np.ascontiguousarray(mu, dtype=np.float32)
         s_ = np.ascontiguousarray(sd, dtype=np.float32)
-        if p.size != MLP_N_PARAMS or m.size != 16 or s_.size != 16:
-            raise ValueError("params must hold 5638 floats, mu and sd 16 each")
-        check(lib().spc_selector_set_mlp(self.handle, p.ctypes.data_as(fp), m.ctypes.data_as(fp),
+        k = 8 if p.size == mlp_n_params(8) else 6
+        if p.size != mlp_n_params(k) or m.size != 16 or s_.size != 16:
+            raise ValueError(f"params must hold {mlp_n_params(6)} or {mlp_n_params(8)} floats, mu and sd 16 each")
+        check(lib().spc_selector_set_mlp(self.handle, k, p.ctypes.data_as(fp), m.ctypes.data_as(fp),
                                          s_.ctypes.data_as(fp)))
         return self
 
@@ -624,16 +674,18 @@ class Selector:
         return int(out.value), np.array(list(sc), dtype=np.float32)
 
     def select(self, features, method: int = SEL_MLP):
-        """(shape index, scores[6]) for one host feature vector."""
+        """(kernel class, scores[K]) for one host feature vector; K is the
+        model's class count (6: shapes, 8: shapes and the test kernels)."""
         import numpy as np
         f = np.ascontiguousarray(features, dtype=np.float32)
         if f.size != 16:
             raise ValueError("features must hold 16 floats")
         out = c_int32()
-        sc = (ctypes.c_float * 6)()
+        sc = (ctypes.c_float * N_CLASSES)()
         check(lib().spc_select_kernel(self.handle, f.ctypes.data_as(POINTER(ctypes.c_float)), method,
                                       ctypes.byref(out), sc, stream_ptr() if method == SEL_MLP else None))
-        return int(out.value), np.array(list(sc), dtype=np.float32)
+        k = self.n_classes(method)
+        return int(out.value), np.array(list(sc)[:k], dtype=np.float32)
 
 
 class CUStream:
@@ -664,17 +716,37 @@ def device_cu_count() -> int:
     return int(lib().spc_device_cu_count())
 
 
-class Batch:
-    """Many BetaMatrix products in one launch (library-owned batch)."""
+def _plan_params(d: dict) -> PlanParams:
+    return PlanParams(d.get("tile_bits", 0), d.get("tile_order", 0), d.get("mode", 0), d.get("wave_chunks", 0),
+                      d.get("pipeline", 0), d.get("cu_groups", 0), d.get("wave_tiles", 0), 0)
 
-    def __init__(self, mats: list, wave_chunks: int = 0):
+
+class Batch:
+    """Products of many BetaMatrix objects, one launch per group of matrices
+    that share (mode, shape, chunk count) (library-owned batch).
+
+    params: None (each matrix's default parameters), one dict for all
+    matrices, or a list of one dict per matrix (keys as plan_from takes;
+    mode 0 or 2). wave_chunks alone gives every matrix mode 0 with that
+    chunk count."""
+
+    def __init__(self, mats: list, wave_chunks: int | None = None, params=None):
         if not mats:
             raise ValueError("need at least one matrix")
         self.mats = list(mats)
         self._views = (BetaView * len(mats))(*[m.view() for m in mats])
-        p = PlanParams(0, 0, 0, wave_chunks)
+        if params is None and wave_chunks is not None:
+            params = {"mode": 0, "wave_chunks": wave_chunks}
+        if params is None:
+            arr, n = None, 0
+        elif isinstance(params, dict):
+            arr, n = (PlanParams * 1)(_plan_params(params)), 1
+        else:
+            if len(params) != len(mats):
+                raise ValueError("one parameter set per matrix")
+            arr, n = (PlanParams * len(mats))(*[_plan_params(d) for d in params]), len(mats)
         h = c_void_p()
-        check(lib().spc_batch_create(len(mats), self._views, ctypes.byref(p), ctypes.byref(h), stream_ptr()))
+        check(lib().spc_batch_create(len(mats), self._views, arr, n, ctypes.byref(h), stream_ptr()))
         self.handle = h
         self._xs = self._ys = None
 
@@ -685,12 +757,14 @@ class Batch:
             self.handle = None
 
     def info(self) -> dict:
-        nt, nl, ss = c_int64(), c_int64(), c_int32()
-        check(lib().spc_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(nl), ctypes.byref(ss)))
-        return {"n_tiles": nt.value, "n_long": nl.value, "single_shape": ss.value}
+        nt, nl, ss, ng = c_int64(), c_int64(), c_int32(), c_int32()
+        check(lib().spc_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(nl), ctypes.byref(ss),
+                                   ctypes.byref(ng)))
+        return {"n_tiles": nt.value, "n_long": nl.value, "single_shape": ss.value, "n_groups": ng.value}
 
     def set_kernel(self, general: bool):
-        """general=True forces the shape-switching kernel even for one shape."""
+        """general=True runs the whole list as one launch of the
+        shape-switching kernel (every matrix in mode 0, one chunk count)."""
         check(lib().spc_batch_set_kernel(self.handle, int(general)))
         return self
 

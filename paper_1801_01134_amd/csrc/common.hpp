@@ -102,6 +102,10 @@ struct BatchMat {
 // matrices share it (a kernel without the shape switch), else -1.
 spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
                           int accumulate, int grid_blocks, int single_shape, hipStream_t stream);
+// Batched test tiles (mode 2) of one shape (0 or 1): TileDesc::reserved
+// holds (matrix index << 1) | long flag. grid_blocks as above.
+spc_status batched_launch_test(int dtype, int shape, int kq, const BatchMat *d_mats, const TileDesc *d_tiles,
+                               int64_t n_tiles, int accumulate, int grid_blocks, hipStream_t stream);
 
 // Workgroups of the pipelined mode-0 kernel resident at once (occupancy x CUs).
 spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out);

@@ -1,5 +1,7 @@
-// The learned kernel selector: a 16 -> 64 -> 64 -> 6 ReLU network in FP32,
-// trained on the device by hand-written forward, backward and Adam kernels.
+// The learned kernel selector: a 16 -> 64 -> 64 -> K ReLU network in FP32
+// (K kernel classes: the six block shapes, or eight with the two "test"
+// kernels of Algorithm 2), trained on the device by hand-written forward,
+// backward and Adam kernels.
 //
 // The paper picks a kernel from recorded speeds with one polynomial per
 // kernel of its Avg(r,c) (section "Performance polynomial interpolation"),
@@ -22,16 +24,23 @@
 namespace spc {
 namespace {
 
-constexpr int NI = SPC_MLP_N_IN, NH = SPC_MLP_N_HIDDEN, NO = SPC_MLP_N_OUT;
-constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
-              OB3 = OW3 + NO * NH, NP = OB3 + NO;
-static_assert(NP == SPC_MLP_N_PARAMS, "parameter count");
+constexpr int NI = SPC_MLP_N_IN, NH = SPC_MLP_N_HIDDEN;
+constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH;
+// layout of a network with NO outputs: W3[NO][NH] at OW3, then b3[NO]
+template <int NO>
+struct Lay {
+    static_assert(NO >= 1 && NO <= 8, "the output buffers hold 8 scores per row");
+    static constexpr int OB3 = OW3 + NO * NH, NP = OB3 + NO;
+};
+static_assert(Lay<SPC_MLP_N_OUT>::NP == SPC_MLP_N_PARAMS, "parameter count");
+static_assert(Lay<SPC_MLP_MAX_OUT>::NP == SPC_MLP_PARAMS(SPC_MLP_MAX_OUT), "parameter count");
+constexpr int NPMAX = Lay<SPC_MLP_MAX_OUT>::NP;
 constexpr int kMT = 256;                          // threads of the training workgroup
 constexpr int kMaxB = SPC_MLP_MAX_BATCH;
-constexpr int kOwn = (NP + kMT - 1) / kMT;        // parameters per thread
+constexpr int kOwn = (NPMAX + kMT - 1) / kMT;     // parameters per thread
 
 struct MlpSmem {
-    float P[NP + 2];
+    float P[NPMAX + 2];
     float X[kMaxB * NI];
     float H1[kMaxB * NH];
     float H2[kMaxB * NH];
@@ -46,7 +55,9 @@ struct Adam {
 };
 
 // Gradient of parameter p from the batch's activations (B rows).
+template <int NO>
 __device__ __forceinline__ float param_grad(const MlpSmem &s, int p, int B) {
+    constexpr int OB3 = Lay<NO>::OB3;
     float g = 0.f;
     if (p < OB1) {                      // W1[o][i]
         const int o = (p - OW1) / NI, i = (p - OW1) % NI;
@@ -72,9 +83,11 @@ __device__ __forceinline__ float param_grad(const MlpSmem &s, int p, int B) {
 
 // Forward and backward of one batch; leaves dL/do in O, dL/dz2 in D2,
 // dL/dz1 in D1 and returns the batch loss in red[0] (thread 0 reads it).
+template <int NO>
 __device__ void forward_backward(MlpSmem &s, const float *__restrict__ X, const float *__restrict__ tau,
                                  const float *__restrict__ mu, const float *__restrict__ sd,
                                  const int32_t *__restrict__ rows, int B) {
+    constexpr int OB3 = Lay<NO>::OB3;
     const int t = threadIdx.x;
     for (int e = t; e < B * NI; e += kMT) {
         const int b = e / NI, i = e % NI;
@@ -133,19 +146,22 @@ __device__ void forward_backward(MlpSmem &s, const float *__restrict__ X, const 
     __syncthreads();
 }
 
+template <int NO>
 __global__ __launch_bounds__(kMT) void k_mlp_grad(const float *__restrict__ params, const float *__restrict__ mu,
                                                   const float *__restrict__ sd, const float *__restrict__ X,
                                                   const float *__restrict__ tau, const int32_t *__restrict__ rows,
                                                   int B, float *__restrict__ grad, float *__restrict__ loss) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     MlpSmem &s = *reinterpret_cast<MlpSmem *>(smem_raw);
+    constexpr int NP = Lay<NO>::NP;
     for (int p = threadIdx.x; p < NP; p += kMT) s.P[p] = params[p];
     __syncthreads();
-    forward_backward(s, X, tau, mu, sd, rows, B);
+    forward_backward<NO>(s, X, tau, mu, sd, rows, B);
     if (threadIdx.x == 0) loss[0] = s.red[0] / (float)(B * NO);
-    for (int p = threadIdx.x; p < NP; p += kMT) grad[p] = param_grad(s, p, B);
+    for (int p = threadIdx.x; p < NP; p += kMT) grad[p] = param_grad<NO>(s, p, B);
 }
 
+template <int NO>
 __global__ __launch_bounds__(kMT) void k_mlp_train(float *__restrict__ params, float *__restrict__ am,
                                                    float *__restrict__ av, int step0, Adam opt,
                                                    const float *__restrict__ mu, const float *__restrict__ sd,
@@ -154,6 +170,7 @@ __global__ __launch_bounds__(kMT) void k_mlp_train(float *__restrict__ params, f
                                                    float *__restrict__ losses) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     MlpSmem &s = *reinterpret_cast<MlpSmem *>(smem_raw);
+    constexpr int NP = Lay<NO>::NP;
     const int t = threadIdx.x;
     for (int p = t; p < NP; p += kMT) s.P[p] = params[p];
     // this thread's Adam moments stay in registers for the whole run
@@ -166,7 +183,7 @@ __global__ __launch_bounds__(kMT) void k_mlp_train(float *__restrict__ params, f
     }
     __syncthreads();
     for (int st = 0; st < n_steps; ++st) {
-        forward_backward(s, X, tau, mu, sd, order + (int64_t)st * B, B);
+        forward_backward<NO>(s, X, tau, mu, sd, order + (int64_t)st * B, B);
         if (t == 0) losses[st] = s.red[0] / (float)(B * NO);
         const int step = step0 + st + 1;
         const float c1 = (float)(1.0 - pow((double)opt.b1, (double)step));
@@ -175,7 +192,7 @@ __global__ __launch_bounds__(kMT) void k_mlp_train(float *__restrict__ params, f
         for (int q = 0; q < kOwn; ++q) {
             const int p = t + q * kMT;
             if (p < NP) {
-                const float g = param_grad(s, p, B);
+                const float g = param_grad<NO>(s, p, B);
                 m[q] = opt.b1 * m[q] + (1.f - opt.b1) * g;
                 v[q] = opt.b2 * v[q] + (1.f - opt.b2) * g * g;
                 const float mh = m[q] / c1, vh = v[q] / c2;
@@ -195,11 +212,13 @@ __global__ __launch_bounds__(kMT) void k_mlp_train(float *__restrict__ params, f
     }
 }
 
-// One thread per sample: scores and the smallest-score shape (lowest index
+// One thread per sample: scores and the smallest-score class (lowest index
 // on ties).
+template <int NO>
 __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ params, const float *__restrict__ mu,
                                                    const float *__restrict__ sd, const float *__restrict__ X,
                                                    int n, float *__restrict__ scores, int32_t *__restrict__ choice) {
+    constexpr int NP = Lay<NO>::NP, OB3 = Lay<NO>::OB3;
     __shared__ float P[NP + 2];
     for (int p = threadIdx.x; p < NP; p += blockDim.x) P[p] = params[p];
     __syncthreads();
@@ -273,6 +292,7 @@ __global__ __launch_bounds__(256) void k_mlp_standardizer(const float *__restric
 }
 
 // tau[b][k] = log2(t[b][k] / min_j t[b][j]), in double, rounded once.
+template <int NO>
 __global__ void k_mlp_targets(const float *__restrict__ times, int n, float *__restrict__ tau) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n) return;
@@ -285,6 +305,20 @@ __global__ void k_mlp_targets(const float *__restrict__ times, int n, float *__r
 
 constexpr size_t kSmemBytes = sizeof(MlpSmem);
 static_assert(kSmemBytes <= 160 * 1024, "training workgroup must fit in LDS");
+
+spc_status check_out(int32_t n_out) {
+    SPC_REQUIRE(n_out == SPC_MLP_N_OUT || n_out == SPC_MLP_MAX_OUT, SPC_ERR_INVALID_ARG,
+                "n_out must be %d (the six shapes) or %d (with the two test kernels), got %d", SPC_MLP_N_OUT,
+                SPC_MLP_MAX_OUT, n_out);
+    return SPC_OK;
+}
+
+// f(integral_constant<NO>) for the two output counts
+template <class F>
+auto with_out(int n_out, F &&f) {
+    if (n_out == SPC_MLP_MAX_OUT) return f(std::integral_constant<int, SPC_MLP_MAX_OUT>{});
+    return f(std::integral_constant<int, SPC_MLP_N_OUT>{});
+}
 
 spc_status check_rows(const int32_t *rows, int64_t count, int32_t n) {
     SPC_REQUIRE(rows != nullptr, SPC_ERR_INVALID_ARG, "null row index array");
@@ -307,28 +341,42 @@ extern "C" spc_status spc_mlp_standardizer(const float *X, int32_t n, float *mu_
     return SPC_OK;
 }
 
-extern "C" spc_status spc_mlp_targets(const float *times, int32_t n, float *tau_out, hipStream_t stream) {
+extern "C" spc_status spc_mlp_targets(const float *times, int32_t n, int32_t n_out, float *tau_out,
+                                      hipStream_t stream) {
     SPC_REQUIRE(n >= 0 && (n == 0 || (times && tau_out)), SPC_ERR_INVALID_ARG, "bad arguments");
+    spc_status st = check_out(n_out);
+    if (st != SPC_OK) return st;
     if (n == 0) return SPC_OK;
-    hipLaunchKernelGGL(k_mlp_targets, dim3((n + 255) / 256), dim3(256), 0, stream, times, n, tau_out);
+    with_out(n_out, [&](auto no) {
+        hipLaunchKernelGGL(k_mlp_targets<decltype(no)::value>, dim3((n + 255) / 256), dim3(256), 0, stream, times, n,
+                           tau_out);
+        return 0;
+    });
     SPC_HIP(hipGetLastError());
     return SPC_OK;
 }
 
 extern "C" spc_status spc_mlp_loss_grad(const float *params, const float *mu, const float *sd, const float *X,
-                                        const float *tau, int32_t n, const int32_t *rows, int32_t batch,
-                                        float *grad_out, float *loss_out, hipStream_t stream) {
+                                        const float *tau, int32_t n, int32_t n_out, const int32_t *rows,
+                                        int32_t batch, float *grad_out, float *loss_out, hipStream_t stream) {
     SPC_REQUIRE(params && mu && sd && X && tau && grad_out && loss_out, SPC_ERR_INVALID_ARG, "null argument");
     SPC_REQUIRE(batch >= 1 && batch <= kMaxB, SPC_ERR_CAPACITY, "batch must be in 1..%d", kMaxB);
-    spc_status st = check_rows(rows, batch, n);
+    spc_status st = check_out(n_out);
+    if (st != SPC_OK) return st;
+    st = check_rows(rows, batch, n);
     if (st != SPC_OK) return st;
     DevBuf d;
     SPC_HIP(d.alloc(sizeof(int32_t) * batch));
     SPC_HIP(hipMemcpyAsync(d.p, rows, sizeof(int32_t) * batch, hipMemcpyHostToDevice, stream));
-    SPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_grad),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBytes));
-    hipLaunchKernelGGL(k_mlp_grad, dim3(1), dim3(kMT), kSmemBytes, stream, params, mu, sd, X, tau,
-                       d.as<int32_t>(), batch, grad_out, loss_out);
+    st = with_out(n_out, [&](auto no) -> spc_status {
+        auto k = k_mlp_grad<decltype(no)::value>;
+        SPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kSmemBytes));
+        hipLaunchKernelGGL(k, dim3(1), dim3(kMT), kSmemBytes, stream, params, mu, sd, X, tau, d.as<int32_t>(), batch,
+                           grad_out, loss_out);
+        return SPC_OK;
+    });
+    if (st != SPC_OK) return st;
     SPC_HIP(hipGetLastError());
     SPC_HIP(hipStreamSynchronize(stream));  // the row buffer is freed on return
     return SPC_OK;
@@ -336,10 +384,11 @@ extern "C" spc_status spc_mlp_loss_grad(const float *params, const float *mu, co
 
 extern "C" spc_status spc_mlp_train(float *params, float *adam_m, float *adam_v, int32_t step0, float lr,
                                     const float *mu, const float *sd, const float *X, const float *tau, int32_t n,
-                                    const int32_t *order, int32_t n_steps, int32_t batch, float *losses_out,
-                                    hipStream_t stream) {
+                                    int32_t n_out, const int32_t *order, int32_t n_steps, int32_t batch,
+                                    float *losses_out, hipStream_t stream) {
     SPC_REQUIRE(params && adam_m && adam_v && mu && sd && X && tau && losses_out, SPC_ERR_INVALID_ARG,
                 "null argument");
+    if (spc_status so = check_out(n_out); so != SPC_OK) return so;
     SPC_REQUIRE(batch >= 1 && batch <= kMaxB, SPC_ERR_CAPACITY, "batch must be in 1..%d", kMaxB);
     SPC_REQUIRE(n_steps >= 0 && step0 >= 0 && lr > 0.f, SPC_ERR_INVALID_ARG, "bad step count or learning rate");
     if (n_steps == 0) return SPC_OK;
@@ -349,23 +398,33 @@ extern "C" spc_status spc_mlp_train(float *params, float *adam_m, float *adam_v,
     const size_t bytes = sizeof(int32_t) * (size_t)n_steps * batch;
     SPC_HIP(d.alloc(bytes));
     SPC_HIP(hipMemcpyAsync(d.p, order, bytes, hipMemcpyHostToDevice, stream));
-    SPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_train),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBytes));
     const Adam opt{lr, 0.9f, 0.999f, 1e-8f};
-    hipLaunchKernelGGL(k_mlp_train, dim3(1), dim3(kMT), kSmemBytes, stream, params, adam_m, adam_v, step0, opt,
-                       mu, sd, X, tau, d.as<int32_t>(), n_steps, batch, losses_out);
+    st = with_out(n_out, [&](auto no) -> spc_status {
+        auto k = k_mlp_train<decltype(no)::value>;
+        SPC_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kSmemBytes));
+        hipLaunchKernelGGL(k, dim3(1), dim3(kMT), kSmemBytes, stream, params, adam_m, adam_v, step0, opt, mu, sd, X,
+                           tau, d.as<int32_t>(), n_steps, batch, losses_out);
+        return SPC_OK;
+    });
+    if (st != SPC_OK) return st;
     SPC_HIP(hipGetLastError());
     SPC_HIP(hipStreamSynchronize(stream));
     return SPC_OK;
 }
 
 extern "C" spc_status spc_mlp_infer(const float *params, const float *mu, const float *sd, const float *X,
-                                    int32_t n, float *scores_out, int32_t *choice_out, hipStream_t stream) {
+                                    int32_t n, int32_t n_out, float *scores_out, int32_t *choice_out,
+                                    hipStream_t stream) {
     SPC_REQUIRE(params && mu && sd && n >= 0 && (n == 0 || X), SPC_ERR_INVALID_ARG, "null argument");
     SPC_REQUIRE(scores_out || choice_out, SPC_ERR_INVALID_ARG, "need scores_out or choice_out");
+    if (spc_status so = check_out(n_out); so != SPC_OK) return so;
     if (n == 0) return SPC_OK;
-    hipLaunchKernelGGL(k_mlp_infer, dim3((n + 255) / 256), dim3(256), 0, stream, params, mu, sd, X, n, scores_out,
-                       choice_out);
+    with_out(n_out, [&](auto no) {
+        hipLaunchKernelGGL(k_mlp_infer<decltype(no)::value>, dim3((n + 255) / 256), dim3(256), 0, stream, params, mu,
+                           sd, X, n, scores_out, choice_out);
+        return 0;
+    });
     SPC_HIP(hipGetLastError());
     return SPC_OK;
 }

@@ -11,6 +11,10 @@
 //
 // MLP (this library's extension): the trained network's scores, computed by
 // the inference kernel; the smallest predicted log time ratio wins.
+//
+// Both choose among kernel classes: the six shapes, and optionally the two
+// "test" kernels of Algorithm 2 (beta(1,8) and beta(2,4) in plan mode 2),
+// whose Avg is that of their shape.
 #include <algorithm>
 #include <cmath>
 #include <set>
@@ -19,7 +23,8 @@
 #include "common.hpp"
 
 extern "C" spc_status spc_mlp_infer(const float *params, const float *mu, const float *sd, const float *X,
-                                    int32_t n, float *scores_out, int32_t *choice_out, hipStream_t stream);
+                                    int32_t n, int32_t n_out, float *scores_out, int32_t *choice_out,
+                                    hipStream_t stream);
 
 namespace spc {
 namespace {
@@ -112,26 +117,46 @@ std::vector<double> polyfit2(const std::vector<double> &a, const std::vector<dou
 
 struct spc_selector {
     bool has_interp = false;
-    double coef[SPC_N_SHAPES][spc::kMaxDeg + 1] = {};
-    int deg[SPC_N_SHAPES] = {};
-    double lo[SPC_N_SHAPES] = {}, hi[SPC_N_SHAPES] = {};
+    int n_interp = 0;  // classes of the 1-D fit (6 or 8)
+    double coef[SPC_N_CLASSES][spc::kMaxDeg + 1] = {};
+    int deg[SPC_N_CLASSES] = {};
+    double lo[SPC_N_CLASSES] = {}, hi[SPC_N_CLASSES] = {};
     // 2-D fit: speed against (Avg, log2 of the compute-unit share)
     bool has_interp2 = false;
     double coef2[SPC_N_SHAPES][spc::kMaxDeg + 1][spc::kMaxDegShare + 1] = {};
     int deg2a[SPC_N_SHAPES] = {}, deg2u[SPC_N_SHAPES] = {};
     double lo2[SPC_N_SHAPES] = {}, hi2[SPC_N_SHAPES] = {}, ulo = 0.0, uhi = 0.0;
     bool has_mlp = false;
+    int n_mlp = 0;  // network outputs (6 or 8)
     int device = -1;
     float *d_buf = nullptr;  // params | mu | sd | features | scores, then one int32 choice
 };
 
 namespace {
-constexpr size_t kParamsOff = 0, kMuOff = SPC_MLP_N_PARAMS, kSdOff = kMuOff + SPC_MLP_N_IN,
+constexpr size_t kParamsOff = 0, kMuOff = SPC_MLP_PARAMS(SPC_MLP_MAX_OUT), kSdOff = kMuOff + SPC_MLP_N_IN,
                  kFeatOff = kSdOff + SPC_MLP_N_IN, kScoreOff = kFeatOff + SPC_MLP_N_IN,
                  kChoiceOff = kScoreOff + 8, kBufFloats = kChoiceOff + 4;
 }
 
 using namespace spc;
+
+extern "C" int32_t spc_class_shape(int32_t k) {
+    if (k >= 0 && k < SPC_N_SHAPES) return k;
+    if (k == SPC_CLASS_TEST_B1X8) return 0;
+    if (k == SPC_CLASS_TEST_B2X4) return 1;
+    return -1;
+}
+
+extern "C" int32_t spc_class_mode(int32_t k) {
+    return (k == SPC_CLASS_TEST_B1X8 || k == SPC_CLASS_TEST_B2X4) ? 2 : -1;
+}
+
+extern "C" int32_t spc_selector_n_classes(const spc_selector *sel, int32_t method) {
+    if (!sel) return 0;
+    if (method == SPC_SEL_INTERP) return sel->has_interp ? sel->n_interp : 0;
+    if (method == SPC_SEL_MLP) return sel->has_mlp ? sel->n_mlp : 0;
+    return 0;
+}
 
 extern "C" spc_status spc_selector_create(spc_selector **out) {
     SPC_REQUIRE(out != nullptr, SPC_ERR_INVALID_ARG, "null output pointer");
@@ -146,20 +171,23 @@ extern "C" spc_status spc_selector_destroy(spc_selector *sel) {
     return SPC_OK;
 }
 
-extern "C" spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, const double *avg, const double *speed,
-                                              int32_t degree) {
+extern "C" spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, int32_t n_classes, const double *avg,
+                                              const double *speed, int32_t degree) {
     SPC_REQUIRE(sel && avg && speed, SPC_ERR_INVALID_ARG, "null argument");
     SPC_REQUIRE(n >= 1, SPC_ERR_INVALID_ARG, "need at least one record");
+    SPC_REQUIRE(n_classes == SPC_N_SHAPES || n_classes == SPC_N_CLASSES, SPC_ERR_INVALID_ARG,
+                "n_classes must be %d or %d, got %d", SPC_N_SHAPES, SPC_N_CLASSES, n_classes);
     SPC_REQUIRE(degree >= 0 && degree <= kMaxDeg, SPC_ERR_INVALID_ARG, "degree must be in 0..%d", kMaxDeg);
-    for (int64_t k = 0; k < (int64_t)n * SPC_N_SHAPES; ++k)
+    const int K = n_classes;
+    for (int64_t k = 0; k < (int64_t)n * K; ++k)
         SPC_REQUIRE(std::isfinite(avg[k]) && std::isfinite(speed[k]), SPC_ERR_INVALID_ARG,
-                    "record %lld is not finite", (long long)(k / SPC_N_SHAPES));
-    for (int s = 0; s < SPC_N_SHAPES; ++s) {
+                    "record %lld is not finite", (long long)(k / K));
+    for (int s = 0; s < K; ++s) {
         std::vector<double> a(n), v(n);
         std::set<double> distinct;
         for (int i = 0; i < n; ++i) {
-            a[i] = avg[(int64_t)i * SPC_N_SHAPES + s];
-            v[i] = speed[(int64_t)i * SPC_N_SHAPES + s];
+            a[i] = avg[(int64_t)i * K + s];
+            v[i] = speed[(int64_t)i * K + s];
             distinct.insert(a[i]);
         }
         // fewer distinct abscissae than coefficients: lower the degree
@@ -170,6 +198,7 @@ extern "C" spc_status spc_selector_fit_interp(spc_selector *sel, int32_t n, cons
         sel->lo[s] = *std::min_element(a.begin(), a.end());
         sel->hi[s] = *std::max_element(a.begin(), a.end());
     }
+    sel->n_interp = K;
     sel->has_interp = true;
     return SPC_OK;
 }
@@ -269,10 +298,11 @@ extern "C" spc_status spc_select_kernel_at(spc_selector *sel, const float *featu
 }
 
 extern "C" spc_status spc_selector_interp_coeffs(const spc_selector *sel, double *coeffs_out, double *lo_out,
-                                                 double *hi_out) {
+                                                 double *hi_out, int32_t *n_classes_out) {
     SPC_REQUIRE(sel && coeffs_out, SPC_ERR_INVALID_ARG, "null argument");
     SPC_REQUIRE(sel->has_interp, SPC_ERR_NO_MODEL, "the selector has no interpolation fit");
-    for (int s = 0; s < SPC_N_SHAPES; ++s) {
+    if (n_classes_out) *n_classes_out = sel->n_interp;
+    for (int s = 0; s < sel->n_interp; ++s) {
         for (int j = 0; j <= kMaxDeg; ++j) coeffs_out[s * (kMaxDeg + 1) + j] = sel->coef[s][j];
         if (lo_out) lo_out[s] = sel->lo[s];
         if (hi_out) hi_out[s] = sel->hi[s];
@@ -280,9 +310,11 @@ extern "C" spc_status spc_selector_interp_coeffs(const spc_selector *sel, double
     return SPC_OK;
 }
 
-extern "C" spc_status spc_selector_set_mlp(spc_selector *sel, const float *params, const float *mu,
+extern "C" spc_status spc_selector_set_mlp(spc_selector *sel, int32_t n_out, const float *params, const float *mu,
                                            const float *sd) {
     SPC_REQUIRE(sel && params && mu && sd, SPC_ERR_INVALID_ARG, "null argument");
+    SPC_REQUIRE(n_out == SPC_MLP_N_OUT || n_out == SPC_MLP_MAX_OUT, SPC_ERR_INVALID_ARG,
+                "n_out must be %d or %d, got %d", SPC_MLP_N_OUT, SPC_MLP_MAX_OUT, n_out);
     for (int i = 0; i < SPC_MLP_N_IN; ++i)
         SPC_REQUIRE(std::isfinite(mu[i]) && std::isfinite(sd[i]) && sd[i] > 0.f, SPC_ERR_INVALID_ARG,
                     "standardizer entry %d is not finite or not positive", i);
@@ -296,23 +328,24 @@ extern "C" spc_status spc_selector_set_mlp(spc_selector *sel, const float *param
         SPC_HIP(hipMalloc(&sel->d_buf, kBufFloats * sizeof(float)));
         sel->device = dev;
     }
-    SPC_HIP(hipMemcpy(sel->d_buf + kParamsOff, params, SPC_MLP_N_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+    SPC_HIP(hipMemcpy(sel->d_buf + kParamsOff, params, SPC_MLP_PARAMS(n_out) * sizeof(float), hipMemcpyHostToDevice));
     SPC_HIP(hipMemcpy(sel->d_buf + kMuOff, mu, SPC_MLP_N_IN * sizeof(float), hipMemcpyHostToDevice));
     SPC_HIP(hipMemcpy(sel->d_buf + kSdOff, sd, SPC_MLP_N_IN * sizeof(float), hipMemcpyHostToDevice));
+    sel->n_mlp = n_out;
     sel->has_mlp = true;
     return SPC_OK;
 }
 
 extern "C" spc_status spc_select_kernel(spc_selector *sel, const float *features, int32_t method,
-                                        int32_t *shape_out, float *scores_out, hipStream_t stream) {
-    SPC_REQUIRE(sel && features && shape_out, SPC_ERR_INVALID_ARG, "null argument");
+                                        int32_t *class_out, float *scores_out, hipStream_t stream) {
+    SPC_REQUIRE(sel && features && class_out, SPC_ERR_INVALID_ARG, "null argument");
     SPC_REQUIRE(method == SPC_SEL_INTERP || method == SPC_SEL_MLP, SPC_ERR_INVALID_ARG, "unknown method %d", method);
     if (method == SPC_SEL_INTERP) {
         SPC_REQUIRE(sel->has_interp, SPC_ERR_NO_MODEL, "the selector has no interpolation fit");
         double best = 0.0;
         int arg = 0;
-        for (int s = 0; s < SPC_N_SHAPES; ++s) {
-            const double a = std::min(std::max((double)features[8 + s], sel->lo[s]), sel->hi[s]);
+        for (int s = 0; s < sel->n_interp; ++s) {
+            const double a = std::min(std::max((double)features[8 + spc_class_shape(s)], sel->lo[s]), sel->hi[s]);
             double p = 0.0;
             for (int j = sel->deg[s]; j >= 0; --j) p = p * a + sel->coef[s][j];
             if (scores_out) scores_out[s] = (float)p;
@@ -321,7 +354,7 @@ extern "C" spc_status spc_select_kernel(spc_selector *sel, const float *features
                 arg = s;
             }
         }
-        *shape_out = arg;
+        *class_out = arg;
         return SPC_OK;
     }
     SPC_REQUIRE(sel->has_mlp, SPC_ERR_NO_MODEL, "the selector has no trained network");
@@ -331,14 +364,14 @@ extern "C" spc_status spc_select_kernel(spc_selector *sel, const float *features
                 sel->device, dev);
     float *b = sel->d_buf;
     SPC_HIP(hipMemcpyAsync(b + kFeatOff, features, SPC_MLP_N_IN * sizeof(float), hipMemcpyHostToDevice, stream));
-    spc_status st = spc_mlp_infer(b + kParamsOff, b + kMuOff, b + kSdOff, b + kFeatOff, 1, b + kScoreOff,
-                                  reinterpret_cast<int32_t *>(b + kChoiceOff), stream);
+    spc_status st = spc_mlp_infer(b + kParamsOff, b + kMuOff, b + kSdOff, b + kFeatOff, 1, sel->n_mlp,
+                                  b + kScoreOff, reinterpret_cast<int32_t *>(b + kChoiceOff), stream);
     if (st != SPC_OK) return st;
     float host[8 + 4];
     SPC_HIP(hipMemcpyAsync(host, b + kScoreOff, sizeof(host), hipMemcpyDeviceToHost, stream));
     SPC_HIP(hipStreamSynchronize(stream));
     if (scores_out)
-        for (int s = 0; s < SPC_N_SHAPES; ++s) scores_out[s] = host[s];
-    *shape_out = *reinterpret_cast<int32_t *>(&host[8]);
+        for (int s = 0; s < sel->n_mlp; ++s) scores_out[s] = host[s];
+    *class_out = *reinterpret_cast<int32_t *>(&host[8]);
     return SPC_OK;
 }

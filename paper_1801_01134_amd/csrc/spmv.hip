@@ -836,6 +836,27 @@ union BatchSmem {
     WaveSmem<Shape<8, 4>, T, KQ> s5;
 };
 
+// The product arguments of one matrix of a batch.
+__device__ __forceinline__ SpmvArgs batch_args(const BatchMat &M, const TileDesc *tiles, int accumulate) {
+    SpmvArgs a;
+    a.brow = M.brow;
+    a.bcol = M.bcol;
+    a.mw = M.mw;
+    a.vals = M.vals;
+    a.x = M.x;
+    a.y = M.y;
+    a.tiles = tiles;
+    a.n_rows = M.n_rows;
+    a.nnz = M.nnz;
+    a.n_blocks = M.n_blocks;
+    a.n_cols = M.n_cols;
+    a.n_tiles = 0;
+    a.accumulate = accumulate;
+    a.xcd_remap = 0;
+    a.tiles_per_xcd = 0;
+    return a;
+}
+
 template <class Sh, class T, int KQ>
 __device__ __forceinline__ void batched_tile(const SpmvArgs &a, const TileDesc &d, WaveSmem<Sh, T, KQ> &sm) {
     if (d.b1 - d.b0 > WaveSmem<Sh, T, KQ>::NB) {
@@ -857,22 +878,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_batched(const BatchMat *__res
     for (int64_t t = t0; t < n_tiles; t += step) {
         const TileDesc d = tiles[t];
         const BatchMat &M = mats[d.reserved];
-        SpmvArgs a;
-        a.brow = M.brow;
-        a.bcol = M.bcol;
-        a.mw = M.mw;
-        a.vals = M.vals;
-        a.x = M.x;
-        a.y = M.y;
-        a.tiles = tiles;
-        a.n_rows = M.n_rows;
-        a.nnz = M.nnz;
-        a.n_blocks = M.n_blocks;
-        a.n_cols = M.n_cols;
-        a.n_tiles = 0;
-        a.accumulate = accumulate;
-        a.xcd_remap = 0;
-        a.tiles_per_xcd = 0;
+        const SpmvArgs a = batch_args(M, tiles, accumulate);
         wave_sync();  // the previous tile's LDS reads are done before this tile writes
         switch (M.shape) {
         case 0: batched_tile<Shape<1, 8>, T, KQ>(a, d, sm[wid].s0); break;
@@ -899,23 +905,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv_batched_fixed(const BatchMat 
     const int64_t step = PERSIST ? (int64_t)gridDim.x * kWaves : n_tiles;
     for (int64_t t = t0; t < n_tiles; t += step) {
         const TileDesc d = tiles[t];
-        const BatchMat &M = mats[d.reserved];
-        SpmvArgs a;
-        a.brow = M.brow;
-        a.bcol = M.bcol;
-        a.mw = M.mw;
-        a.vals = M.vals;
-        a.x = M.x;
-        a.y = M.y;
-        a.tiles = tiles;
-        a.n_rows = M.n_rows;
-        a.nnz = M.nnz;
-        a.n_blocks = M.n_blocks;
-        a.n_cols = M.n_cols;
-        a.n_tiles = 0;
-        a.accumulate = accumulate;
-        a.xcd_remap = 0;
-        a.tiles_per_xcd = 0;
+        const SpmvArgs a = batch_args(mats[d.reserved], tiles, accumulate);
         wave_sync();
         batched_tile<Sh, T, KQ>(a, d, sm[wid]);
     }
@@ -1205,25 +1195,14 @@ struct TestSmem {
     int32_t ccol[NM2];    // their columns
 };
 
-template <int R, int C, class T, int KQ>
-__global__ __launch_bounds__(kThreads) void k_spmv_test(SpmvArgs a) {
-    using Sh = Shape<R, C>;
+// One test tile on a wavefront (not a long one).
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void test_tile(const SpmvArgs &a, const TileDesc &d, TestSmem<Sh, T, KQ> &sm) {
     using SM = TestSmem<Sh, T, KQ>;
+    constexpr int R = Sh::R, C = Sh::C;
     constexpr int E = SM::E;
     constexpr int PPR = SM::PPR;
     constexpr int W = C / PPR;            // lanes added into one partial
-    __shared__ SM smem[kWaves];
-    int g = blockIdx.x;
-    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = g * kWaves + wid;
-    if (t >= a.n_tiles) return;
-    const TileDesc d = a.tiles[t];
-    if (d.reserved & 1) {                 // one interval beyond a test tile's limits
-        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
-        return;
-    }
-    SM &sm = smem[wid];
     const int lane = lane_id();
     const T *__restrict__ vals = static_cast<const T *>(a.vals);
     const int b0 = d.b0, b1 = d.b1, nv = d.nv, nI = d.i1 - d.i0;
@@ -1352,6 +1331,23 @@ __global__ __launch_bounds__(kThreads) void k_spmv_test(SpmvArgs a) {
     tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, part);
 }
 
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_test(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    __shared__ TestSmem<Sh, T, KQ> smem[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    if (d.reserved & 1) {                 // one interval beyond a test tile's limits
+        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+        return;
+    }
+    test_tile<Sh, T, KQ>(a, d, smem[wid]);
+}
+
 template <int R, int C, class T>
 spc_status launch_test(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     const dim3 blk(kThreads);
@@ -1374,6 +1370,49 @@ spc_status launch_test_shape(int shape, int dtype, int kq, int cu_groups, dim3 g
                                 : launch_test<2, 4, float>(kq, cu_groups, grid, a, stream);
     set_error("test tiles are for beta(1,8) and beta(2,4)");
     return SPC_ERR_UNSUPPORTED_SHAPE;
+}
+
+// Batched test tiles: TileDesc::reserved holds (matrix index << 1) | long
+// flag. A wavefront loops over the tiles t, t + S, ... (S = 4 x grid), so a
+// grid smaller than the list is persistent.
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_batched_test(const BatchMat *__restrict__ mats,
+                                                                const TileDesc *__restrict__ tiles, int64_t n_tiles,
+                                                                int accumulate) {
+    using Sh = Shape<R, C>;
+    __shared__ TestSmem<Sh, T, KQ> smem[kWaves];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t step = (int64_t)gridDim.x * kWaves;
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += step) {
+        const TileDesc d = tiles[t];
+        const SpmvArgs a = batch_args(mats[d.reserved >> 1], tiles, accumulate);
+        wave_sync();  // the previous tile's LDS reads are done before this tile writes
+        if (d.reserved & 1) wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+        else test_tile<Sh, T, KQ>(a, d, smem[wid]);
+    }
+}
+
+template <int R, int C, class T>
+void launch_batched_test(int kq, unsigned grid, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
+                         int accumulate, hipStream_t stream) {
+    switch (kq) {
+    case 2:
+        hipLaunchKernelGGL((k_spmv_batched_test<R, C, T, 2>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    case 6:
+        hipLaunchKernelGGL((k_spmv_batched_test<R, C, T, 6>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    case 8:
+        hipLaunchKernelGGL((k_spmv_batched_test<R, C, T, 8>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    default:
+        hipLaunchKernelGGL((k_spmv_batched_test<R, C, T, 4>), dim3(grid), dim3(kThreads), 0, stream, d_mats, d_tiles,
+                           n_tiles, accumulate);
+        break;
+    }
 }
 
 template <int R, int C, class T>
@@ -1476,6 +1515,21 @@ spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileD
         case 8: go(std::integral_constant<int, 8>{}); break;
         default: go(std::integral_constant<int, 4>{}); break;
         }
+        SPC_HIP(hipGetLastError());
+        return SPC_OK;
+    });
+}
+
+spc_status batched_launch_test(int dtype, int shape, int kq, const BatchMat *d_mats, const TileDesc *d_tiles,
+                               int64_t n_tiles, int accumulate, int grid_blocks, hipStream_t stream) {
+    SPC_REQUIRE(shape == 0 || shape == 1, SPC_ERR_UNSUPPORTED_SHAPE, "test tiles are for beta(1,8) and beta(2,4)");
+    if (n_tiles == 0) return SPC_OK;
+    const int64_t groups = div_up(n_tiles, kWaves);
+    const unsigned grid = (unsigned)(grid_blocks > 0 && grid_blocks < groups ? grid_blocks : groups);
+    return with_dtype(dtype, [&](auto tv) -> spc_status {
+        using T = decltype(tv);
+        if (shape == 0) launch_batched_test<1, 8, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
+        else launch_batched_test<2, 4, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
         SPC_HIP(hipGetLastError());
         return SPC_OK;
     });

@@ -1,24 +1,28 @@
-"""Timing records of the six beta(r,c) kernels and the selectors built on them.
+"""Timing records of the beta(r,c) kernels and the selectors built on them.
 
 The paper chooses a kernel from timings recorded on earlier runs (its
 record-based strategy): one polynomial per kernel of speed against Avg(r,c)
 (section "Performance polynomial interpolation"). This module
 
-  * collects records: for each matrix of the seeded selector population,
-    the 16 device features (spc_matrix_features), and for each of the six
-    shapes the device conversion followed by the autotuner
-    (spc_autotune: every plan candidate timed with HIP events); one JSON line
-    per matrix;
+  * collects records: for each matrix of a seeded population, the 16 device
+    features (spc_matrix_features), and for each of the six shapes the
+    device conversion followed by the autotuner (spc_autotune: every plan
+    candidate timed with HIP events); one JSON line per matrix with the best
+    time of each shape's own kernels (modes 0 and 1) and, for beta(1,8) and
+    beta(2,4), the best time of the test kernel of Algorithm 2 (mode 2);
   * fits the interpolation selector (spc_selector_fit_interp) and trains the
     network on the device (spc_mlp_standardizer / spc_mlp_targets /
-    spc_mlp_train) from a training split of the records;
+    spc_mlp_train) from a training split of the records, over 6 classes
+    (the shapes) or 8 (the shapes and the two test kernels);
   * evaluates both on the held-out split by regret = t_selected / t_best - 1
-    using the recorded times.
+    using the recorded times, against the best of the classes the selector
+    knows and against the best of all eight kernels.
 
 Command line:
   python -m paper_1801_01134_amd.records collect --first 0 --count 2000 --out recs.jsonl
-  python -m paper_1801_01134_amd.records train --records recs.jsonl --out model.json
+  python -m paper_1801_01134_amd.records train --records recs.jsonl --out model.json [--classes 8]
   python -m paper_1801_01134_amd.records evaluate --records recs.jsonl --model model.json
+  python -m paper_1801_01134_amd.records compare-classes --records recs.jsonl
 
 Matrix generation is CPU work (numpy); a pool of worker processes, started
 before this process touches the GPU, keeps the device busy.
@@ -43,16 +47,23 @@ TRAIN_FRACTION = 0.8
 # ---------------------------------------------------------------------------
 # collection
 
-POPULATIONS = ("selector", "structured")
+POPULATIONS = ("selector", "structured", "large")
+LARGE_MIN_ROWS, LARGE_MAX_ROWS = 1_000_000, 4_000_000
+
+
+def generator(population: str):
+    """The seeded matrix generator of a population: (index, min_rows,
+    max_rows) -> (family, CSR)."""
+    from . import synth
+    return {"selector": synth.selector_matrix, "structured": synth.structured_matrix,
+            "large": synth.large_matrix}[population]
 
 
 def _generate(args):
     """Worker: build matrix `index` and park its CSR structure in files."""
     index, min_rows, max_rows, tmp, population = args
-    from . import synth
     t0 = time.perf_counter()
-    gen = synth.selector_matrix if population == "selector" else synth.structured_matrix
-    fam, A = gen(index, min_rows, max_rows)
+    fam, A = generator(population)(index, min_rows, max_rows)
     base = os.path.join(tmp, f"m{index}")
     np.save(base + "_rp.npy", A.rowptr)
     np.save(base + "_ci.npy", A.colidx)
@@ -289,11 +300,28 @@ def split(recs: list[dict], train_fraction: float = TRAIN_FRACTION):
     return train, test
 
 
-def arrays(recs: list[dict]):
+# Avg(r,c) feature of each kernel class: the six shapes, then the test
+# kernels of beta(1,8) and beta(2,4)
+CLASS_FEATURE = (8, 9, 10, 11, 12, 13, 8, 9)
+CLASS_NAMES = [f"{r}x{c}" for r, c in SHAPES] + ["1x8_test", "2x4_test"]
+
+
+def has_test(recs: list[dict]) -> bool:
+    return all(len(r.get("us_test", [])) == 2 for r in recs)
+
+
+def arrays(recs: list[dict], n_classes: int = 6):
+    """Features [n, 16], times [n, K], Avg per class [n, K], speeds [n, K]
+    (GFlop/s) for K = 6 (the shapes) or 8 (with the test kernels)."""
+    if n_classes not in (6, 8):
+        raise ValueError("n_classes must be 6 or 8")
+    if n_classes == 8 and not has_test(recs):
+        raise ValueError("8 classes need records with the test kernels' times (us_test)")
     X = np.array([r["features"] for r in recs], dtype=np.float32)
-    T = np.array([r["us"] for r in recs], dtype=np.float64)
-    avg = X[:, 8:14].astype(np.float64)
-    G = np.array([r["gflops"] for r in recs], dtype=np.float64)
+    T = np.array([r["us"] + (r["us_test"] if n_classes == 8 else []) for r in recs], dtype=np.float64)
+    avg = X[:, list(CLASS_FEATURE[:n_classes])].astype(np.float64)
+    nnz = np.array([r["nnz"] for r in recs], dtype=np.float64)
+    G = 2.0 * nnz[:, None] / (T * 1e-6) / 1e9
     return X, T, avg, G
 
 
@@ -302,9 +330,10 @@ def arrays(recs: list[dict]):
 
 def train_mlp(X: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 64, lr: float = 2e-3,
               seed: int = 0):
-    """Trains the network on the device. Returns (params, mu, sd, losses)
-    as numpy arrays. Learning rate: lr for the first half of the epochs, then
-    lr/4 and lr/16 (Adam's step count continues across the stages)."""
+    """Trains the network (T.shape[1] outputs) on the device. Returns
+    (params, mu, sd, losses) as numpy arrays. Learning rate: lr for the
+    first half of the epochs, then lr/4 and lr/16 (Adam's step count
+    continues across the stages)."""
     import torch
 
     from . import _binding as b
@@ -315,10 +344,11 @@ def train_mlp(X: np.ndarray, T: np.ndarray, epochs: int = 400, batch: int = 64, 
     mu, sd = b.mlp_standardizer(Xd)
     tau = b.mlp_targets(Td)
     rng = synth.rng_for(60, seed)
-    P = np.zeros(b.MLP_N_PARAMS, dtype=np.float32)
+    K = T.shape[1]
+    P = np.zeros(b.mlp_n_params(K), dtype=np.float32)
     # He-uniform weights, zero biases (same recipe as the oracle's init)
     o = 0
-    for (n_out, n_in) in ((64, 16), (64, 64), (6, 64)):
+    for (n_out, n_in) in ((64, 16), (64, 64), (K, 64)):
         lim = np.sqrt(6.0 / n_in)
         P[o:o + n_out * n_in] = rng.uniform(-lim, lim, size=n_out * n_in)
         o += n_out * n_in + n_out
@@ -349,49 +379,99 @@ def summary(reg: np.ndarray) -> dict:
             "within_5pct": float(np.mean(reg <= 0.05)), "exact": float(np.mean(reg == 0.0))}
 
 
-def evaluate(train: list[dict], test: list[dict], model: dict | None = None, epochs: int = 400):
-    """Fits both selectors on `train` (or uses `model`) and reports held-out
-    regrets for the network, the interpolation, and fixed shapes."""
+def _choices(sel, model, Xte, n_classes):
+    """(network choices or None, interpolation choices) for the test rows."""
     import torch
 
     from . import _binding as b
-    Xtr, Ttr, Atr, Gtr = arrays(train)
-    Xte, Tte, Ate, Gte = arrays(test)
+    ch_mlp = None
+    if model is not None:
+        dev = torch.device("cuda")
+        P = torch.tensor(model["params"], dtype=torch.float32, device=dev)
+        mu = torch.tensor(model["mu"], dtype=torch.float32, device=dev)
+        sd = torch.tensor(model["sd"], dtype=torch.float32, device=dev)
+        _, ch = b.mlp_infer(P, mu, sd, torch.from_numpy(Xte).to(dev))
+        ch_mlp = ch.cpu().numpy().astype(np.int64)
+    ch_int = np.array([sel.select(x, b.SEL_INTERP)[0] for x in Xte], dtype=np.int64)
+    return ch_mlp, ch_int
+
+
+def fit(train: list[dict], n_classes: int = 6, epochs: int = 400, with_mlp: bool = True):
+    """(interpolation selector, network model dict or None) fitted on train."""
+    from . import _binding as b
+    Xtr, Ttr, Atr, Gtr = arrays(train, n_classes)
     sel = b.Selector().fit_interp(Atr, Gtr, 3)
-    if model is None:
+    model = None
+    if with_mlp:
         t0 = time.perf_counter()
         P, mu, sd, losses = train_mlp(Xtr, Ttr, epochs=epochs)
-        t_train = time.perf_counter() - t0
-        model = {"params": P.tolist(), "mu": mu.tolist(), "sd": sd.tolist(),
-                 "final_loss": float(losses[-1]) if losses.size else None, "train_s": t_train,
-                 "epochs": epochs, "n_train": len(train)}
-    dev = torch.device("cuda")
-    P = torch.tensor(model["params"], dtype=torch.float32, device=dev)
-    mu = torch.tensor(model["mu"], dtype=torch.float32, device=dev)
-    sd = torch.tensor(model["sd"], dtype=torch.float32, device=dev)
-    _, ch_mlp = b.mlp_infer(P, mu, sd, torch.from_numpy(Xte).to(dev))
-    ch_mlp = ch_mlp.cpu().numpy().astype(np.int64)
-    ch_int = np.array([sel.select(x, b.SEL_INTERP)[0] for x in Xte], dtype=np.int64)
+        model = {"params": P.tolist(), "mu": mu.tolist(), "sd": sd.tolist(), "n_out": n_classes,
+                 "final_loss": float(losses[-1]) if losses.size else None,
+                 "train_s": time.perf_counter() - t0, "epochs": epochs, "n_train": len(train)}
+    return sel, model
+
+
+def evaluate(train: list[dict], test: list[dict], model: dict | None = None, epochs: int = 400,
+             n_classes: int | None = None):
+    """Fits both selectors on `train` (or uses `model` for the network) and
+    reports held-out regrets for the network, the interpolation, and fixed
+    kernels. With records that hold the test kernels' times, regrets are
+    also given against the best of all eight kernels ("vs_all8")."""
+    if n_classes is None:
+        n_classes = int(model.get("n_out", 6)) if model else 6
+    from . import _binding as b
+    Xtr, Ttr, Atr, Gtr = arrays(train, n_classes)
+    Xte, Tte, Ate, Gte = arrays(test, n_classes)
+    sel = b.Selector().fit_interp(Atr, Gtr, 3)
+    if model is None:
+        _, model = fit(train, n_classes, epochs)
+    ch_mlp, ch_int = _choices(sel, model, Xte, n_classes)
+    T8 = arrays(test, 8)[1] if has_test(test) else None
     best_avg = int(np.argmin(np.mean(Ttr / Ttr.min(axis=1, keepdims=True), axis=0)))
     pops = np.array([r["population"] for r in test])
-    by_pop = {}
-    for pop in POPULATIONS:
-        m = pops == pop
-        if m.any():
-            by_pop[pop] = {"n": int(m.sum()), "mlp": summary(regrets(Tte[m], ch_mlp[m])),
-                           "interpolation": summary(regrets(Tte[m], ch_int[m])),
-                           "fixed_b1x8": summary(regrets(Tte[m], np.zeros(int(m.sum()), np.int64)))}
-    out = {"n_train": len(train), "n_test": len(test),
-           "mlp": summary(regrets(Tte, ch_mlp)),
-           "interpolation": summary(regrets(Tte, ch_int)),
-           "fixed_b1x8": summary(regrets(Tte, np.zeros(len(test), np.int64))),
-           f"fixed_best_on_train_{SHAPES[best_avg][0]}x{SHAPES[best_avg][1]}":
-               summary(regrets(Tte, np.full(len(test), best_avg, np.int64))),
-           "best_shape_share": np.bincount(Tte.argmin(axis=1), minlength=6).tolist(),
-           "mlp_choice_share": np.bincount(ch_mlp, minlength=6).tolist(),
-           "interp_choice_share": np.bincount(ch_int, minlength=6).tolist(),
-           "by_population": by_pop}
+
+    def block(m):
+        n = int(m.sum())
+        d = {"n": n, "mlp": summary(regrets(Tte[m], ch_mlp[m])),
+             "interpolation": summary(regrets(Tte[m], ch_int[m])),
+             "fixed_b1x8": summary(regrets(Tte[m], np.zeros(n, np.int64))),
+             f"fixed_best_on_train_{CLASS_NAMES[best_avg]}":
+                 summary(regrets(Tte[m], np.full(n, best_avg, np.int64)))}
+        if T8 is not None:
+            d["vs_all8"] = {"mlp": summary(regrets(T8[m], ch_mlp[m])),
+                            "interpolation": summary(regrets(T8[m], ch_int[m]))}
+        return d
+
+    out = {"n_classes": n_classes, "n_train": len(train), "n_test": len(test)}
+    out.update(block(np.ones(len(test), bool)))
+    out["best_class_share"] = np.bincount(Tte.argmin(axis=1), minlength=n_classes).tolist()
+    out["mlp_choice_share"] = np.bincount(ch_mlp, minlength=n_classes).tolist()
+    out["interp_choice_share"] = np.bincount(ch_int, minlength=n_classes).tolist()
+    out["by_population"] = {pop: block(pops == pop) for pop in POPULATIONS if (pops == pop).any()}
     return out, model
+
+
+def compare_classes(train: list[dict], test: list[dict], epochs: int = 400):
+    """Held-out regret with and without the two test kernels as classes of
+    their own, all against the best of the eight kernels: the 6-class and
+    8-class network and interpolation, trained on the same split. Also the
+    large population with a network that never saw it (trained on the
+    other populations only)."""
+    out = {}
+    for k in (6, 8):
+        res, _ = evaluate(train, test, None, epochs, k)
+        out[f"classes_{k}"] = res
+    tr_small = [r for r in train if r["population"] != "large"]
+    large = [r for r in train + test if r["population"] == "large"]
+    if large and tr_small:
+        out["large_unseen"] = {}
+        for k in (6, 8):
+            res, _ = evaluate(tr_small, large, None, epochs, k)
+            out["large_unseen"][f"classes_{k}"] = {key: res[key] for key in
+                                                  ("n_classes", "n_train", "n_test", "mlp", "interpolation",
+                                                   "vs_all8", "mlp_choice_share", "best_class_share")
+                                                  if key in res}
+    return out
 
 
 def main(argv=None):
@@ -403,13 +483,20 @@ def main(argv=None):
     c.add_argument("--out", required=True)
     c.add_argument("--reps", type=int, default=5)
     c.add_argument("--workers", type=int, default=12)
-    c.add_argument("--min-rows", type=int, default=DEFAULT_MIN_ROWS)
-    c.add_argument("--max-rows", type=int, default=DEFAULT_MAX_ROWS)
+    c.add_argument("--min-rows", type=int, default=None,
+                   help="default: 50k (1M for the large population)")
+    c.add_argument("--max-rows", type=int, default=None,
+                   help="default: 1M (4M for the large population)")
     c.add_argument("--population", default="selector", choices=POPULATIONS)
     t = sub.add_parser("train")
     t.add_argument("--records", required=True, nargs="+")
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=400)
+    t.add_argument("--classes", type=int, default=6, choices=(6, 8))
+    cc = sub.add_parser("compare-classes")
+    cc.add_argument("--records", required=True, nargs="+")
+    cc.add_argument("--epochs", type=int, default=400)
+    cc.add_argument("--out", default=None)
     cs = sub.add_parser("collect-shares")
     cs.add_argument("--first", type=int, default=0)
     cs.add_argument("--count", type=int, default=320)
@@ -424,15 +511,25 @@ def main(argv=None):
     e.add_argument("--model", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
-        collect(a.first, a.count, a.out, a.reps, a.workers, a.min_rows, a.max_rows, a.population)
+        large = a.population == "large"
+        lo = a.min_rows if a.min_rows is not None else (LARGE_MIN_ROWS if large else DEFAULT_MIN_ROWS)
+        hi = a.max_rows if a.max_rows is not None else (LARGE_MAX_ROWS if large else DEFAULT_MAX_ROWS)
+        collect(a.first, a.count, a.out, a.reps, a.workers, lo, hi, a.population)
     elif a.cmd == "collect-shares":
         collect_shares(a.first, a.count, a.out, a.population, reps=a.reps, workers=a.workers)
     elif a.cmd == "evaluate-shares":
         tr, te = split(load(*a.records))
         print(json.dumps(evaluate_shares(tr, te)))
+    elif a.cmd == "compare-classes":
+        tr, te = split(load(*a.records))
+        res = compare_classes(tr, te, a.epochs)
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+        print(json.dumps(res))
     elif a.cmd == "train":
         tr, te = split(load(*a.records))
-        res, model = evaluate(tr, te, epochs=a.epochs)
+        res, model = evaluate(tr, te, epochs=a.epochs, n_classes=a.classes)
         with open(a.out, "w") as f:
             json.dump(model, f)
         print(json.dumps(res))

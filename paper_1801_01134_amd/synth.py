@@ -345,6 +345,33 @@ def selector_matrix(index: int, min_rows: int = 50_000, max_rows: int = 4_000_00
     return fam, uniform_random(n, n, float(rng.uniform(2, 40)), seed=s)
 
 
+LARGE_NNZ_CAP = 1 << 28
+
+
+def large_matrix(index: int, min_rows: int = 1_000_000, max_rows: int = 4_000_000) -> tuple[str, CSR]:
+    """Matrix `index` of the large population: the four selector families
+    with rows log-uniform in [min_rows, max_rows]. Where a family's draw
+    would exceed LARGE_NNZ_CAP entries, the parameter that sets the entries
+    per row (the band width, the blocks per block row, the mean row length)
+    is lowered to meet it."""
+    rng = rng_for(31, index)
+    fam = FAMILIES[index % 4]
+    n = int(np.exp(rng.uniform(np.log(min_rows), np.log(max_rows))))
+    s = int(rng.integers(0, 2**31))
+    per_row = LARGE_NNZ_CAP / n
+    if fam == "powerlaw":  # mean row length about 34: under the cap for n <= 4M
+        return fam, powerlaw(n, n, 1.5, 2000, mean_run=float(rng.uniform(1.0, 8.0)), seed=s)
+    if fam == "fem":
+        b = int(rng.choice([3, 6]))
+        k = min(float(rng.uniform(3, 12)), per_row / b)
+        return fam, fem_blocks(max(1, n // b), b, k, int(np.exp(rng.uniform(0, np.log(2000)))), seed=s)
+    if fam == "banded":
+        d = float(rng.uniform(0.05, 1.0))
+        w = min(int(np.exp(rng.uniform(np.log(8), np.log(512)))), max(8, int(per_row / d)))
+        return fam, banded(n, w, d, seed=s)
+    return fam, uniform_random(n, n, min(float(rng.uniform(2, 40)), per_row), seed=s)
+
+
 # --------------------------------------------------------------------------
 # Structured grid operators: 2-D 5/9-point and 3-D 7/27-point stencils in
 # natural order idx = x + mx (y + my z), truncated at the boundary, with an

@@ -70,10 +70,9 @@ def test_records_collect_writes_complete_lines():
                       log=sys.stdout)
         with open(out) as f:
             lines = [json.loads(s) for s in f if s.strip()]
-    assert len(lines) == 4
+    assert len(lines) == 2 * len(R.POPULATIONS)
     for rec in lines:
-        gen = synth.selector_matrix if rec["population"] == "selector" else synth.structured_matrix
-        fam, A = gen(rec["index"], 3000, 6000)
+        fam, A = R.generator(rec["population"])(rec["index"], 3000, 6000)
         assert rec["family"] == fam and rec["n_rows"] == A.n_rows and rec["nnz"] == A.nnz
         assert len(rec["features"]) == 16 and all(np.isfinite(rec["features"]))
         nb = [int(oracle.beta_count(A, r, c).sum()) for (r, c) in spc.SHAPES]

@@ -1,9 +1,11 @@
-"""Batched products: one launch over the tiles of many matrices of different
-sizes and shapes. Each y_i is checked against the oracle with the per-row
-tolerance; the batched launch runs the same tiles in the same order of
-operations as one launch per matrix with the same plan, so its results are
-also bit-identical to the single-matrix kernel, with or without a persistent
-grid and with or without graph replay."""
+"""Batched products: one launch per group of matrices (same mode, shape and
+chunk count) over the tiles of many matrices of different sizes and shapes,
+or one launch of the shape-switching kernel. Each y_i is checked against the
+oracle with the per-row tolerance; a batched launch runs the same tiles in
+the same order of operations as one launch per matrix with the same plan, so
+its results are also bit-identical to the single-matrix kernels (mode 0
+wavefront tiles and mode 2 test tiles), with or without a persistent grid
+and with or without graph replay."""
 import sys
 
 import numpy as np
@@ -122,6 +124,71 @@ def test_batch_refuses_bad_arguments():
     with pytest.raises(ValueError):
         b.set_vectors([torch.zeros(3, dtype=torch.float64, device="cuda")],
                       [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")])
+    B44 = spc.csr_to_beta(4, 4, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols)
+    for params, mats_ in [({"mode": 1}, [B64]), ({"mode": 2}, [B44]), ({"mode": 0, "pipeline": 1}, [B64]),
+                          ({"mode": 0, "wave_tiles": 2}, [B64])]:
+        with pytest.raises(spc.SpcError):
+            spc.Batch(mats_, params=params)
+    with pytest.raises(ValueError):
+        spc.Batch([B64, B44], params=[{"mode": 0}])
+    # the shape-switching kernel needs one mode-0 chunk count
+    mixed = spc.Batch([B64, B44], params=[{"mode": 2, "wave_chunks": 4}, {"mode": 0, "wave_chunks": 4}])
+    assert mixed.info()["n_groups"] == 2
+    with pytest.raises(spc.SpcError):
+        mixed.set_kernel(True)
+    with pytest.raises(spc.SpcError):
+        spc.Batch([B64, B44], params=[{"mode": 0, "wave_chunks": 2}, {"mode": 0, "wave_chunks": 4}]).set_kernel(True)
+
+
+def _mixed_params(shapes):
+    """Per matrix: test tiles (mode 2) for every other one-byte-mask matrix,
+    wavefront tiles otherwise; chunk counts cycling over 2, 4, 6, 8."""
+    out = []
+    for k, (r, c) in enumerate(shapes):
+        mode = 2 if (r * c == 8 and k % 2 == 0) else 0
+        out.append({"mode": mode, "wave_chunks": (2, 4, 6, 8)[k % 4]})
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_grouped_batch_mixed_modes_and_chunks(dtype):
+    say(f"[batched] grouped, mixed modes {dtype}")
+    mats, _ = pop()
+    # more one-byte-mask matrices than the six-shape cycle gives
+    shapes = [spc.SHAPES[(0, 1, 0, 1, 2, 3, 4, 5, 0, 1, 1, 0)[k]] for k in range(len(mats))]
+    Bs, xs, ys, refs = [], [], [], []
+    for k, (A, (r, c)) in enumerate(zip(mats, shapes)):
+        A = A.astype(NP[dtype])
+        Bs.append(spc.csr_to_beta(r, c, A.rowptr, A.colidx, torch.from_numpy(A.values).to(dtype), A.n_cols))
+        x = synth.dense_vector(A.n_cols, 95 + k).astype(NP[dtype])
+        xs.append(torch.from_numpy(x).cuda())
+        ys.append(torch.full((A.n_rows,), 7.0, dtype=dtype, device="cuda"))
+        refs.append(oracle.csr_spmv(A, x))
+    params = _mixed_params(shapes)
+    assert any(p["mode"] == 2 for p in params)
+    batch = spc.Batch(Bs, params=params).set_vectors(xs, ys)
+    info = batch.info()
+    keys = {(p["mode"], shapes[k], p["wave_chunks"]) for k, p in enumerate(params)}
+    assert info["n_groups"] == len(keys) and info["single_shape"] == -1
+    plans = [spc.plan_from(B, p) for B, p in zip(Bs, params)]
+    assert info["n_tiles"] == sum(P.info()["n_tiles"] for P in plans)
+    batch.run()
+    torch.cuda.synchronize()
+    first = [y.clone() for y in ys]
+    for y, (y_ref, s) in zip(ys, refs):
+        got = y.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - y_ref) <= TOL[dtype] * s)
+    for B, x, y0, P in zip(Bs, xs, first, plans):
+        assert torch.equal(spc.spmv(B, x, plan=P), y0)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for grid, graph in [(5, False), (0, True), (0, True), (2, True), (2, True)]:
+            for y in ys:
+                y.fill_(-1.0)
+            batch.run(grid_blocks=grid, use_graph=graph)
+            s.synchronize()
+            for y, y0 in zip(ys, first):
+                assert torch.equal(y, y0)
 
 
 @pytest.mark.parametrize("shape", [0, 1, 5])
@@ -147,5 +214,5 @@ def test_single_shape_kernel_equals_general_kernel(shape):
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(ys, fixed))
     for B, x, y0 in zip(Bs, xs, fixed):
-        # the batch plans each matrix with 4 chunks per lane
-        assert torch.equal(spc.spmv(B, x, plan=B.plan(0, 0, 0, 4)), y0)
+        # without parameters the batch plans each matrix with its default
+        assert torch.equal(spc.spmv(B, x, plan=B.default_plan()), y0)

@@ -21,8 +21,13 @@ import paper_1801_01134_amd as spc
 from paper_1801_01134_amd import synth
 
 pytestmark = pytest.mark.gpu
-BLOCKS = [("W1", 0, 1024), ("b1", 1024, 1088), ("W2", 1088, 5184), ("b2", 5184, 5248), ("W3", 5248, 5632),
-          ("b3", 5632, 5638)]
+OUTS = pytest.mark.parametrize("k", [6, 8], ids=["6shapes", "8classes"])
+
+
+def blocks(k=6):
+    """(name, start, end) of each parameter block in the flat layout."""
+    return [("W1", 0, 1024), ("b1", 1024, 1088), ("W2", 1088, 5184), ("b2", 5184, 5248),
+            ("W3", 5248, 5248 + 64 * k), ("b3", 5248 + 64 * k, 5248 + 65 * k)]
 
 
 def say(*a):
@@ -31,31 +36,33 @@ def say(*a):
 
 
 def flat(P):
-    return np.concatenate([np.asarray(P[k], np.float64).reshape(-1) for k, _, _ in BLOCKS])
+    k = np.asarray(P["b3"]).size
+    return np.concatenate([np.asarray(P[n], np.float64).reshape(-1) for n, _, _ in blocks(k)])
 
 
 def unflat(v):
-    shapes = M.param_shapes()
-    return {k: np.asarray(v[a:b], np.float64).reshape(shapes[k]) for k, a, b in BLOCKS}
+    k = 8 if v.size == M.n_params(8) else 6
+    shapes = M.param_shapes(k)
+    return {n: np.asarray(v[a:b], np.float64).reshape(shapes[n]) for n, a, b in blocks(k)}
 
 
-def dataset(n, seed):
+def dataset(n, seed, k=6):
     """Feature rows with the spread of real features and times with a
-    feature-dependent best shape (inputs only; no method arithmetic)."""
+    feature-dependent best class (inputs only; no method arithmetic)."""
     rng = synth.rng_for(510, seed)
     X = (rng.standard_normal((n, 16)) * rng.uniform(0.5, 5.0, 16) + rng.uniform(-3, 3, 16)).astype(np.float32)
-    t = np.exp(0.5 * rng.standard_normal((n, 6)) + 0.1 * X[:, :6]).astype(np.float32)
+    t = np.exp(0.5 * rng.standard_normal((n, k)) + 0.1 * X[:, :k]).astype(np.float32)
     return X, t
 
 
-def prepared(n, seed):
+def prepared(n, seed, k=6):
     """Inputs both sides share: FP32 features and times, the oracle's
     standardizer rounded to FP32, targets rounded to FP32, FP32 params."""
-    X, t = dataset(n, seed)
+    X, t = dataset(n, seed, k)
     mu, sd = M.standardize_stats(X.astype(np.float64))
     mu32, sd32 = mu.astype(np.float32), sd.astype(np.float32)
     tau32 = M.targets(t.astype(np.float64)).astype(np.float32)
-    P32 = flat(M.init_params(synth.rng_for(511, seed))).astype(np.float32)
+    P32 = flat(M.init_params(synth.rng_for(511, seed), k)).astype(np.float32)
     Xh = (X.astype(np.float64) - mu32.astype(np.float64)) / sd32.astype(np.float64)
     return X, t, mu32, sd32, tau32, P32, Xh
 
@@ -64,9 +71,10 @@ def cuda(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def test_standardizer_and_targets():
-    say("[mlp] standardizer, targets")
-    X, t = dataset(1000, 1)
+@OUTS
+def test_standardizer_and_targets(k):
+    say(f"[mlp] standardizer, targets K={k}")
+    X, t = dataset(1000, 1, k)
     mu, sd = spc.mlp_standardizer(cuda(X))
     mu_r, sd_r = M.standardize_stats(X.astype(np.float64))
     assert np.allclose(mu.cpu().numpy(), mu_r, rtol=2**-23, atol=1e-6)
@@ -77,25 +85,28 @@ def test_standardizer_and_targets():
     assert np.all(tau.min(axis=1) == 0.0)
 
 
+@OUTS
 @pytest.mark.parametrize("batch", [1, 17, 64])
-def test_loss_grad_matches_oracle(batch):
-    say(f"[mlp] loss/grad batch={batch}")
-    X, t, mu, sd, tau, P, Xh = prepared(300, 2)
+def test_loss_grad_matches_oracle(batch, k):
+    say(f"[mlp] loss/grad batch={batch} K={k}")
+    X, t, mu, sd, tau, P, Xh = prepared(300, 2, k)
     rows = synth.rng_for(512, batch).choice(300, size=batch, replace=False).astype(np.int32)
     loss, g = spc.mlp_loss_grad(cuda(P), cuda(mu), cuda(sd), cuda(X), cuda(tau), rows)
     g = g.cpu().numpy().astype(np.float64)
     L_ref, G_ref = M.loss_and_grad(unflat(P.astype(np.float64)), Xh[rows], tau[rows].astype(np.float64))
+    assert g.size == M.n_params(k)
     assert abs(loss - L_ref) <= 1e-5 * L_ref
-    for k, a, b in BLOCKS:
-        ref = np.asarray(G_ref[k]).reshape(-1)
+    for name, a, b in blocks(k):
+        ref = np.asarray(G_ref[name]).reshape(-1)
         err = np.linalg.norm(g[a:b] - ref) / max(np.linalg.norm(ref), 1e-30)
-        assert err <= 1e-4, (k, err)
+        assert err <= 1e-4, (name, err)
 
 
-def test_train_matches_oracle_and_resumes():
-    say("[mlp] train 40 steps")
+@OUTS
+def test_train_matches_oracle_and_resumes(k):
+    say(f"[mlp] train 40 steps K={k}")
     n, B, S, lr = 256, 64, 40, 1e-3
-    X, t, mu, sd, tau, P, Xh = prepared(n, 3)
+    X, t, mu, sd, tau, P, Xh = prepared(n, 3, k)
     order = synth.rng_for(513).permutation(np.tile(np.arange(n), (S * B) // n + 1))[:S * B].astype(np.int32)
     p = cuda(P)
     m = torch.zeros_like(p)
@@ -116,9 +127,10 @@ def test_train_matches_oracle_and_resumes():
     assert torch.equal(p, p2) and torch.equal(m, m2) and torch.equal(v, v2)
 
 
-def test_infer_and_selector_match_oracle():
-    say("[mlp] inference")
-    X, t, mu, sd, tau, P, Xh = prepared(2000, 4)
+@OUTS
+def test_infer_and_selector_match_oracle(k):
+    say(f"[mlp] inference K={k}")
+    X, t, mu, sd, tau, P, Xh = prepared(2000, 4, k)
     scores, choice = spc.mlp_infer(cuda(P), cuda(mu), cuda(sd), cuda(X))
     scores = scores.cpu().numpy().astype(np.float64)
     choice = choice.cpu().numpy()
@@ -137,6 +149,7 @@ def test_infer_and_selector_match_oracle():
         sel.select(X[0], spc.SEL_MLP)
     assert e.value.code == -7
     sel.set_mlp(P, mu, sd)
+    assert sel.n_classes(spc.SEL_MLP) == k
     for b in range(0, 2000, 199):
         s, sc = sel.select(X[b], spc.SEL_MLP)
         assert s == choice[b] and np.array_equal(sc, scores[b].astype(np.float32))
@@ -154,3 +167,13 @@ def test_argument_checks():
     f = osel.features(synth.band_plus_uniform()).astype(np.float32)
     s, _ = spc.Selector().set_mlp(P, mu, sd).select(f, spc.SEL_MLP)
     assert 0 <= s < 6
+    # an output count other than 6 or 8 is refused
+    from paper_1801_01134_amd import _binding as bb
+    Xd, Pd, mud, sdd = cuda(X), cuda(P), cuda(mu), cuda(sd)
+    ch = torch.empty(X.shape[0], dtype=torch.int32, device="cuda")
+    with pytest.raises(spc.SpcError) as e:
+        bb.check(spc.lib().spc_mlp_infer(bb._ptr(Pd), bb._ptr(mud), bb._ptr(sdd), bb._ptr(Xd), X.shape[0], 7,
+                                         None, bb._ptr(ch), bb.stream_ptr()))
+    assert e.value.code == -1
+    with pytest.raises(ValueError):
+        spc.mlp_infer(cuda(P[:-1]), cuda(mu), cuda(sd), cuda(X))

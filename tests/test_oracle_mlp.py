@@ -1,21 +1,31 @@
 """Pins for the MLP oracle: finite differences, Adam's closed-form first
 step, and the network's affine regime."""
 import numpy as np
+import pytest
 
 from oracle import mlp
 from paper_1801_01134_amd import synth
 
 
-def _setup(B=12, seed=0):
+def _setup(B=12, seed=0, n_out=6):
     rng = synth.rng_for(500, seed)
-    P = mlp.init_params(rng)
+    P = mlp.init_params(rng, n_out)
     X = rng.normal(size=(B, 16))
-    t = np.exp(rng.normal(size=(B, 6)))
+    t = np.exp(rng.normal(size=(B, n_out)))
     return P, X, mlp.targets(t)
 
 
-def test_gradients_match_central_differences():
-    P, X, tau = _setup()
+def test_parameter_counts():
+    # 16*64 + 64 + 64*64 + 64 + K*64 + K: 5638 for the six shapes, 5768 with
+    # the two test kernels
+    assert mlp.n_params() == mlp.n_params(6) == 5638
+    assert mlp.n_params(8) == 5768
+    assert mlp.param_shapes(8)["W3"] == (8, 64) and mlp.param_shapes(8)["b3"] == (8,)
+
+
+@pytest.mark.parametrize("n_out", [6, 8])
+def test_gradients_match_central_differences(n_out):
+    P, X, tau = _setup(n_out=n_out)
     _, G = mlp.loss_and_grad(P, X, tau)
     rng = synth.rng_for(501)
     for name in mlp.PARAM_NAMES:
@@ -46,18 +56,19 @@ def test_adam_first_step_is_lr_times_sign():
         assert np.allclose(step[big], 1e-3 * np.sign(g[big]), rtol=1e-4)
 
 
-def test_affine_regime_equals_matrix_chain():
+@pytest.mark.parametrize("n_out", [6, 8])
+def test_affine_regime_equals_matrix_chain(n_out):
     rng = synth.rng_for(502)
     P = {"W1": rng.uniform(0.1, 1, (64, 16)), "b1": rng.uniform(0.1, 1, 64),
          "W2": rng.uniform(0.1, 1, (64, 64)), "b2": rng.uniform(0.1, 1, 64),
-         "W3": rng.uniform(-1, 1, (6, 64)), "b3": rng.uniform(-1, 1, 6)}
+         "W3": rng.uniform(-1, 1, (n_out, 64)), "b3": rng.uniform(-1, 1, n_out)}
     X = rng.uniform(0.1, 1, (5, 16))  # every pre-activation is positive
     o, _ = mlp.forward(P, X)
-    want = np.zeros((5, 6))
+    want = np.zeros((5, n_out))
     for b in range(5):
         h1 = [sum(P["W1"][i, j] * X[b, j] for j in range(16)) + P["b1"][i] for i in range(64)]
         h2 = [sum(P["W2"][i, j] * h1[j] for j in range(64)) + P["b2"][i] for i in range(64)]
-        want[b] = [sum(P["W3"][i, j] * h2[j] for j in range(64)) + P["b3"][i] for i in range(6)]
+        want[b] = [sum(P["W3"][i, j] * h2[j] for j in range(64)) + P["b3"][i] for i in range(n_out)]
     assert np.allclose(o, want, rtol=1e-12)
 
 

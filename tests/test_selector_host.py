@@ -43,6 +43,42 @@ def test_interp_fit_matches_oracle(seed, n, degree):
             assert shape == ref.select(f[8:14].astype(np.float64))
 
 
+@pytest.mark.parametrize("seed,n,degree", [(5, 80, 3), (6, 9, 2)])
+def test_interp_eight_classes_matches_oracle(seed, n, degree):
+    """Eight kernel classes: the two test kernels take the Avg of beta(1,8)
+    and beta(2,4) (features 8 and 9)."""
+    avg6, speed6 = _records(seed, n, noise=2.0)
+    rng = synth.rng_for(80, seed)
+    avg = np.concatenate([avg6, avg6[:, :2]], axis=1)
+    speed = np.concatenate([speed6, speed6[:, :2] * rng.uniform(0.7, 1.3, size=(1, 2))
+                            + 3.0 * rng.standard_normal((n, 2))], axis=1)
+    ref = osel.fit_interpolation(avg, speed, degree=degree)
+    sel = spc.Selector().fit_interp(avg, speed, degree)
+    assert sel.n_classes(spc.SEL_INTERP) == 8 and sel.n_classes(spc.SEL_MLP) == 0
+    c, lo, hi = sel.interp_coeffs()
+    assert c.shape == (8, 4) and np.array_equal(lo, avg.min(axis=0))
+    for k in range(8):
+        want = ref.coeffs[k][::-1]
+        assert np.allclose(c[k, :want.size], want, rtol=1e-8, atol=1e-9 * np.abs(want).max())
+    assert [spc.class_shape(k) for k in range(8)] == [0, 1, 2, 3, 4, 5, 0, 1]
+    assert [spc.class_mode(k) for k in range(8)] == [-1] * 6 + [2, 2]
+    with pytest.raises(ValueError):
+        spc.class_shape(8)
+    for _ in range(50):
+        f = np.zeros(16, np.float32)
+        f[8:14] = rng.uniform(0.0, 60.0, size=6)
+        k, scores = sel.select(f, spc.SEL_INTERP)
+        q = f[[8, 9, 10, 11, 12, 13, 8, 9]].astype(np.float64)
+        pred = ref.predict(q)
+        assert scores.shape == (8,)
+        assert np.allclose(scores, pred.astype(np.float32), rtol=1e-6, atol=1e-5)
+        top = np.sort(pred)[::-1]
+        if top[0] - top[1] > 1e-6 * abs(top[0]):
+            assert k == ref.select(q)
+    with pytest.raises(ValueError):
+        spc.Selector().fit_interp(avg[:, :7], speed[:, :7])
+
+
 def test_interp_few_distinct_points_lower_the_degree():
     avg = np.tile(np.array([[2.0, 3, 4, 5, 6, 7]]), (5, 1))
     avg[:2] += 1.0  # two distinct values per shape
