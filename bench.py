@@ -603,23 +603,26 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
     for dt, kset, tol in ((torch.float64, ks, 1e-8), (torch.float32, fp32_ks, 1e-5)):
         vals = torch.from_numpy(A.values).to(dev).to(dt)
         # per k: the fastest SpMM among two shapes x four chunk counts x four
-        # caps on resident workgroups per compute unit
+        # caps on resident workgroups per compute unit x the two SpMM kernels
+        # (mask-bit lanes; the row path where the columns come in 16-byte groups)
         Bs = {rc: spc.csr_to_beta(rc[0], rc[1], rp, ci, vals, A.n_cols) for rc in ((2, 4), (4, 8))}
         for k in kset:
             Bm = synth.dense_block(A.n_cols, k, 701 + k)
             Bd = torch.from_numpy(Bm).to(dev).to(dt)
             X = torch.from_numpy(synth.dense_block(A.n_cols, k, 702)).to(dev).to(dt)
             best = None
+            grouped = (k * X.element_size()) % 16 == 0
             for rc, Bc in Bs.items():
                 for kq in (2, 4, 6, 8):
                     for cap in (0, 2, 3, 4):
-                        Pc = Bc.plan(0, 0, 0, kq, 0, cap)
-                        t = event_time(torch, lambda: spc.spmm(Bc, X, plan=Pc), 10, 2)
-                        if best is None or t < best[0]:
-                            best = (t, rc, kq, cap)
-            t_spmm, (r, c), kq, cap = best
+                        for path in ((spc.SPMM_BITS, spc.SPMM_ROWS) if grouped else (spc.SPMM_BITS,)):
+                            Pc = Bc.plan(0, 0, 0, kq, 0, cap, 0, path)
+                            t = event_time(torch, lambda: spc.spmm(Bc, X, plan=Pc), 10, 2)
+                            if best is None or t < best[0]:
+                                best = (t, rc, kq, cap, path)
+            t_spmm, (r, c), kq, cap, path = best
             B = Bs[(r, c)]
-            P = B.plan(0, 0, 0, kq, 0, cap)
+            P = B.plan(0, 0, 0, kq, 0, cap, 0, path)
             s = torch.cuda.Stream()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -633,7 +636,7 @@ def cg_section(spc, torch, pool, tmp, m: int, ks, fp32_ks):
             ab = algorithmic_bytes(B, P.info()["n_tiles"], k=k)
             out["runs"].append({
                 "dtype": "f64" if dt == torch.float64 else "f32", "k": k, "shape": [r, c], "wave_chunks": kq,
-                "cu_groups": cap,
+                "cu_groups": cap, "spmm_path": "rows" if path == spc.SPMM_ROWS else "mask-bit lanes",
                 "rel_tol": tol, "iterations": its, "iterations_run": total,
                 "true_rel_residual_max": float(true.max()),
                 "converged": bool(all(i > 0 for i in its) and true.max() <= 10 * tol),
@@ -669,8 +672,8 @@ def main(argv=None):
     ap.add_argument("--plan", default="", help="mode,wave_chunks_or_tile_bits,tile_order[,pipeline[,cu_groups[,wave_tiles]]]: force "
                     "the headline plan (skips autotuning; used for profiling)")
     ap.add_argument("--spmm", default="",
-                    help="k,dtype(64|32),wave_chunks,cu_groups: time only Y = A X on the CG matrix (used for "
-                         "profiling the multi-RHS kernel)")
+                    help="k,dtype(64|32),wave_chunks,cu_groups[,spmm_path]: time only Y = A X on the CG matrix "
+                         "(used for profiling the multi-RHS kernels; spmm_path 1 = mask-bit lanes, 2 = rows)")
     ap.add_argument("--only-steps", action="store_true",
                     help="run only the other steps (conversion, features, network) and print them")
     ap.add_argument("--copy-ref", action="store_true",
@@ -726,7 +729,9 @@ def spmm_only(args):
 
     import paper_1801_01134_amd as spc
     from paper_1801_01134_amd import synth
-    k, bits, kq, cap = (int(t) for t in args.spmm.split(","))
+    fields = [int(t) for t in args.spmm.split(",")]
+    k, bits, kq, cap = fields[:4]
+    path = fields[4] if len(fields) > 4 else 0
     dt = torch.float64 if bits == 64 else torch.float32
     dev = torch.device("cuda:0")
     A = synth.stencil27(args.cg_grid, diag=26.1, offdiag=-1.0)
@@ -734,12 +739,12 @@ def spmm_only(args):
                         torch.from_numpy(A.values).to(dev).to(dt), A.n_cols)
     X = torch.from_numpy(synth.dense_block(A.n_cols, k, 702)).to(dev).to(dt)
     Y = torch.empty(A.n_rows, k, dtype=dt, device=dev)
-    P = B.plan(0, 0, 0, kq, 0, cap)
+    P = B.plan(0, 0, 0, kq, 0, cap, 0, path)
     t = event_time(torch, lambda: spc.spmm(B, X, Y, plan=P), args.steps, args.warmup)
     ab = algorithmic_bytes(B, P.info()["n_tiles"], k=k)
     print(json.dumps({"workload": f"27-point SPD stencil {args.cg_grid}^3 (n={A.n_rows}, nnz={A.nnz}), "
                                   f"beta(2,4), Y = A X, k = {k}, FP{bits}",
-                      "plan": {"wave_chunks": kq, "cu_groups": cap}, "us": round(t * 1e6, 1),
+                      "plan": {"wave_chunks": kq, "cu_groups": cap, "spmm_path": path}, "us": round(t * 1e6, 1),
                       "alg_bytes_per_launch": ab, "alg_GBs": round(ab / t / 1e9, 1),
                       "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
     return 0

@@ -215,8 +215,12 @@ typedef struct spc_plan_params {
                                wavefront; 2 = two consecutive tiles per wavefront, the second one's
                                values held in registers while the first is worked on, so that both
                                tiles' loads are in flight together (same results, bit for bit) */
-    int32_t reserved;
+    int32_t spmm_path;      /* SpMM kernel: SPC_SPMM_AUTO (0), SPC_SPMM_BITS (1) or SPC_SPMM_ROWS (2);
+                               see spc_spmm_beta */
 } spc_plan_params;
+#define SPC_SPMM_AUTO 0   /* spmm_path: the row path for rows of 64 bytes or more, else mask-bit lanes */
+#define SPC_SPMM_BITS 1   /* spmm_path: lanes on mask bits, column groups taken in turn */
+#define SPC_SPMM_ROWS 2   /* spmm_path: values sorted by row, lanes on rows and column groups */
 
 spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_params *params,
                            spc_plan **plan_out, hipStream_t stream);
@@ -254,11 +258,22 @@ spc_status spc_spmv_beta(const spc_beta_view *A, const spc_plan *plan, const voi
  * X: n_cols x k and Y: n_rows x k, row-major with leading dimensions
  * ldx, ldy >= k (the k values of one row are contiguous), A's dtype. Each
  * Y entry is the plain definition sum_j a_ij X[j][q], summed in double
- * precision. plan must be a mode-0 plan of A (wavefront tiles); values must
- * be 16-byte aligned and X smaller than 3.75 GiB. When k is a multiple of
- * 16 / (value size) and X, Y and their leading dimensions keep every such
- * group of columns 16-byte aligned, groups of columns share one pass (the
- * results are the same bits). k = 1 with unit leading dimensions runs the
+ * precision (FP32: products in FP32, sums in double). plan must be a mode-0
+ * plan of A (wavefront tiles); values must be 16-byte aligned and X smaller
+ * than 3.75 GiB. "Grouped" below means: k is a multiple of 16 / (value
+ * size) and X, Y and their leading dimensions keep every such group of
+ * columns 16-byte aligned. Two kernels, chosen by the plan's spmm_path:
+ *   mask-bit lanes (SPC_SPMM_BITS): a tile's values stay on the lanes of
+ *     their mask bits and the columns are taken in turn (one at a time, or
+ *     one group at a time when grouped, with the same bits);
+ *   row path (SPC_SPMM_ROWS, grouped only, else SPC_ERR_INVALID_ARG): a
+ *     tile's values are sorted by row in LDS, then a row's 16-byte column
+ *     groups go to lanes of their own, which walk the row's values in
+ *     column order; each Y row is written whole, once.
+ *   SPC_SPMM_AUTO takes the row path when grouped with rows of at least 64
+ *   bytes (FP64 k >= 8, FP32 k = 16), else mask-bit lanes.
+ * The two paths add in different orders (results within the same bound;
+ * each path repeats its bits). k = 1 with unit leading dimensions runs the
  * single-vector kernel. plan NULL: as for spc_spmv_beta (a default plan is
  * built and released by the call, which then synchronizes). Asynchronous
  * when plan is not NULL. */

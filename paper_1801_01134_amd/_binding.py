@@ -34,7 +34,7 @@ class BetaView(ctypes.Structure):
 class PlanParams(ctypes.Structure):
     _fields_ = [("tile_bits", c_int32), ("tile_order", c_int32), ("mode", c_int32),
                 ("wave_chunks", c_int32), ("pipeline", c_int32), ("cu_groups", c_int32),
-                ("wave_tiles", c_int32), ("reserved", c_int32)]
+                ("wave_tiles", c_int32), ("spmm_path", c_int32)]
 
 
 class TuneRecord(ctypes.Structure):
@@ -187,10 +187,11 @@ class Plan:
     """A tile plan (library-owned) for one BetaMatrix."""
 
     def __init__(self, A: "BetaMatrix", tile_bits: int = 0, tile_order: int = 0, mode: int = 0,
-                 wave_chunks: int = 0, pipeline: int = 0, cu_groups: int = 0, wave_tiles: int = 0):
+                 wave_chunks: int = 0, pipeline: int = 0, cu_groups: int = 0, wave_tiles: int = 0,
+                 spmm_path: int = 0):
         self._A = A
         self._view = A.view()
-        p = PlanParams(tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles)
+        p = PlanParams(tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles, spmm_path)
         h = c_void_p()
         check(lib().spc_plan_create(ctypes.byref(self._view), ctypes.byref(p), ctypes.byref(h),
                                     stream_ptr()))
@@ -246,10 +247,11 @@ class BetaMatrix:
                         self.values.data_ptr() if self.nnz else None)
 
     def plan(self, tile_bits: int = 0, tile_order: int = 0, mode: int = 0, wave_chunks: int = 0,
-             pipeline: int = 0, cu_groups: int = 0, wave_tiles: int = 0) -> Plan:
-        key = (tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles)
+             pipeline: int = 0, cu_groups: int = 0, wave_tiles: int = 0, spmm_path: int = 0) -> Plan:
+        key = (tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles, spmm_path)
         if key not in self._plans:
-            self._plans[key] = Plan(self, tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles)
+            self._plans[key] = Plan(self, tile_bits, tile_order, mode, wave_chunks, pipeline, cu_groups, wave_tiles,
+                                    spmm_path)
         return self._plans[key]
 
     def default_params(self) -> dict:
@@ -398,13 +400,15 @@ def _params_dict(p: PlanParams) -> dict:
         d["cu_groups"] = p.cu_groups
     if p.wave_tiles:
         d["wave_tiles"] = p.wave_tiles
+    if p.spmm_path:
+        d["spmm_path"] = p.spmm_path
     return d
 
 
 def plan_from(A: BetaMatrix, params: dict) -> Plan:
     return A.plan(params.get("tile_bits", 0), params.get("tile_order", 0), params.get("mode", 0),
                   params.get("wave_chunks", 0), params.get("pipeline", 0), params.get("cu_groups", 0),
-                  params.get("wave_tiles", 0))
+                  params.get("wave_tiles", 0), params.get("spmm_path", 0))
 
 
 def spmm(A: BetaMatrix, X: torch.Tensor, Y: torch.Tensor | None = None, accumulate: bool = False,
@@ -471,6 +475,7 @@ def matrix_features(rowptr, colidx, n_cols: int, device="cuda"):
 # ---------------------------------------------------------------------------
 # Learned selector (MLP) and interpolation selector
 
+SPMM_AUTO, SPMM_BITS, SPMM_ROWS = 0, 1, 2
 MLP_N_PARAMS = 5638
 MLP_MAX_BATCH = 64
 SEL_INTERP, SEL_MLP = 0, 1
@@ -718,7 +723,7 @@ def device_cu_count() -> int:
 
 def _plan_params(d: dict) -> PlanParams:
     return PlanParams(d.get("tile_bits", 0), d.get("tile_order", 0), d.get("mode", 0), d.get("wave_chunks", 0),
-                      d.get("pipeline", 0), d.get("cu_groups", 0), d.get("wave_tiles", 0), 0)
+                      d.get("pipeline", 0), d.get("cu_groups", 0), d.get("wave_tiles", 0), d.get("spmm_path", 0))
 
 
 class Batch:

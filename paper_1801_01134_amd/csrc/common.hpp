@@ -183,6 +183,7 @@ struct spc_plan {
     int resident;  // workgroups of the pipelined kernel resident at once
     int cu_groups; // 0, or at most this many workgroups per compute unit (non-persistent launches)
     int wave_tiles; // mode 0: 1, or 2 consecutive tiles per wavefront (the second staged in registers)
+    int spmm_path;  // SPC_SPMM_AUTO, SPC_SPMM_BITS or SPC_SPMM_ROWS
     int device;
     int64_t n_tiles;
     int64_t n_long;

@@ -114,6 +114,9 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     SPC_REQUIRE(wave_tiles >= 0 && wave_tiles <= 2, SPC_ERR_INVALID_ARG, "wave_tiles must be 0, 1 or 2");
     SPC_REQUIRE(!(wave_tiles == 2 && (mode != 0 || pipeline)), SPC_ERR_INVALID_ARG,
                 "wave_tiles = 2 applies to mode 0 without pipeline");
+    const int spmm_path = params ? params->spmm_path : SPC_SPMM_AUTO;
+    SPC_REQUIRE(spmm_path == SPC_SPMM_AUTO || spmm_path == SPC_SPMM_BITS || spmm_path == SPC_SPMM_ROWS,
+                SPC_ERR_INVALID_ARG, "spmm_path must be 0, 1 or 2");
     SPC_REQUIRE(cu_groups == 0 || (cu_groups >= 2 && cu_groups <= 8), SPC_ERR_INVALID_ARG,
                 "cu_groups must be 0 or 2..8 (got %d)", cu_groups);
     SPC_REQUIRE(!(cu_groups && mode == 1), SPC_ERR_INVALID_ARG, "cu_groups applies to modes 0 and 2 only");
@@ -219,6 +222,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     P->resident = 0;
     P->cu_groups = cu_groups;
     P->wave_tiles = wave_tiles == 2 ? 2 : 1;
+    P->spmm_path = spmm_path;
     if (pipeline) {
         int g = 0;
         spc_status rs = spmv_resident_groups(shape, A->dtype, kq, &g);

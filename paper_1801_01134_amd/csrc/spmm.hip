@@ -12,6 +12,15 @@
 //
 // An interval with more blocks than a tile holds is run by one wavefront
 // with lane = mask bit throughout, each lane keeping k running sums.
+//
+// Row path (wide right-hand sides, k x sizeof(T) >= 64 bytes per row): the
+// tile's values and columns are first sorted by row in LDS (a prefix of
+// each block row's value counts over the tile's blocks gives every value
+// its place), then Q lanes take one row, lane g gathering the 16-byte
+// column group g of each X row the row touches and keeping the group's
+// sums; the Q lanes of a row store the whole Y row with one instruction.
+// Every X row is fetched in full by one instruction and every Y row is
+// written once.
 #include "common.hpp"
 #include "wave_common.hpp"
 
@@ -40,6 +49,7 @@ struct SpmmArgs {
     int32_t accumulate;
     int32_t xcd_remap;
     int32_t tiles_per_xcd;
+    int32_t lgq;         // row path: log2 of the lanes per row
 };
 
 template <class Sh, class T, int KQ>
@@ -406,6 +416,228 @@ __device__ void spmm_long(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_
     }
 }
 
+// LDS of the row path (per wavefront).
+template <class Sh, class T, int KQ>
+struct RowsSmem {
+    static constexpr int E = 16 / sizeof(T);
+    static constexpr int WB = (64 * KQ - 1) * E;      // values a tile may hold
+    static constexpr int NB = WB / Sh::RC;            // blocks a tile may hold
+    static constexpr int NWMAX = NB / Sh::BPW + 2;
+    static constexpr int NCR = (NWMAX * Sh::BPW + 63) / 64;
+    static constexpr int NBR = (NB + 63) / 64;        // 64-lane rounds over the blocks
+    int brow[128];                 // tile-relative interval pointers
+    int pre[(NB + 1) * Sh::R];     // [block][block row]: that row's values in the tile's earlier blocks
+    int rb[NB * Sh::R];            // [block][block row]: sorted place of the block row's first value
+    int col[WB];                   // columns, sorted by row (and by column within a row)
+    T val[WB];                     // values, in the same order
+};
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = max(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// One tile on the row path, all k columns (a.wide: k is a multiple of G).
+template <class Sh, class T, int KQ>
+__device__ void spmm_rows_tile(const SpmmArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
+                               RowsSmem<Sh, T, KQ> &sm) {
+    using SM = RowsSmem<Sh, T, KQ>;
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    constexpr int R = Sh::R, C = Sh::C, RC = Sh::RC, BPW = Sh::BPW;
+    constexpr int NWM = SM::NWMAX;
+    constexpr int G = 16 / (int)sizeof(T);
+    const int lane = threadIdx.x & 63;
+    const int b0 = d.b0, b1 = d.b1, nI = d.i1 - d.i0;
+    const int nb = b1 - b0;
+    const int w0 = b0 / BPW;
+    const int nw = (b1 > b0) ? ((b1 - 1) / BPW - w0 + 1) : 0;
+    const int lo_slot = b0 - w0 * BPW;
+    const int end_bit = (b1 - w0 * BPW) * RC;   // bits of the tile's blocks end here (from word w0)
+    const int cs0 = w0 * BPW;
+    const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * BPW, a.n_blocks) - cs0);
+
+    // streams: block columns (slot lane + 64 k) and interval pointers
+    const auto cr = rsrc(a.bcol + cs0, (uint32_t)(ncs > 0 ? ncs : 0) * 4u);
+    int colr[SM::NCR];
+#pragma unroll
+    for (int k = 0; k < SM::NCR; ++k)
+        colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
+    const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
+    const int br0 = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
+    const int br1 = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 256, 0);
+    // the tile's mask words and values: lane = mask bit, word j
+    const uint64_t *__restrict__ gp = a.mw + w0;   // readable 512 bytes past the last word
+    uint64_t mj[NWM];
+#pragma unroll
+    for (int j = 0; j < NWM; ++j) {
+        uint64_t m = j < nw ? gp[j] : 0ull;
+        if (j == 0) m &= ~low_bits(lo_slot * RC);
+        mj[j] = m & low_bits(end_bit - 64 * j);
+    }
+    const auto vr = rsrc(static_cast<const T *>(a.vals) + d.vbase, (uint32_t)d.nv * (uint32_t)sizeof(T));
+    T v[NWM];
+    {
+        uint32_t vslot = 0;
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            const uint64_t m = mj[j];
+            v[j] = buf_load<T>(vr, pick(m, (vslot + lane_rank(m)) * (uint32_t)sizeof(T), 0xffffffffu));
+            vslot += (uint32_t)__popcll(m);
+        }
+    }
+    sm.brow[lane] = br0 - b0;
+    sm.brow[lane + 64] = br1 - b0;
+
+    // 1. lane = tile block: value counts of each block row, prefix over the tile
+    int carry[R];
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) carry[rho] = 0;
+#pragma unroll
+    for (int k = 0; k < SM::NBR; ++k) {
+        const int tb = lane + 64 * k;
+        uint32_t mk = 0;
+        if (tb < nb) {
+            const int gs = tb + lo_slot;
+            mk = (uint32_t)(gp[gs / BPW] >> ((gs % BPW) * RC)) & Sh::RCMASK;
+        }
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+            const int c = __popc((mk >> (rho * C)) & Sh::CMASK);
+            const int incl = wave_scan_dpp(c);
+            if (tb < nb) sm.pre[tb * R + rho] = carry[rho] + incl - c;
+            carry[rho] += __builtin_amdgcn_readlane(incl, 63);
+        }
+    }
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho)
+        if (lane == rho) sm.pre[nb * R + rho] = carry[rho];
+    wave_sync();
+
+    // 2. lane = interval: the sorted place of each block row's first value.
+    // Rows are in order (interval, block row); within a row, the values in
+    // block order, so in column order.
+    for (int li = lane; li < nI; li += 64) {
+        const int s0 = sm.brow[li], e0 = sm.brow[li + 1];
+        int before = 0;
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) before += sm.pre[s0 * R + rho];
+        int rs[R];
+#pragma unroll
+        for (int rho = 0; rho < R; ++rho) {
+            rs[rho] = before - sm.pre[s0 * R + rho];
+            before += sm.pre[e0 * R + rho] - sm.pre[s0 * R + rho];
+        }
+        for (int tb = s0; tb < e0; ++tb) {
+#pragma unroll
+            for (int rho = 0; rho < R; ++rho) sm.rb[tb * R + rho] = rs[rho] + sm.pre[tb * R + rho];
+        }
+    }
+    wave_sync();
+
+    // 3. lane = mask bit: each value and its column to their sorted place
+    {
+        const int slot = lane / RC;
+        const int rho = (lane % RC) / C;
+        const int kc = (lane % RC) % C;
+        const uint64_t below_row = low_bits(slot * RC + rho * C);   // bits before this block row
+#pragma unroll
+        for (int j = 0; j < NWM; ++j) {
+            const uint64_t m = mj[j];
+            const int c = __builtin_amdgcn_ds_bpermute(((j * BPW) % 64 + slot) * 4, colr[(j * BPW) / 64]);
+            if ((m >> lane) & 1ull) {
+                const int tb = j * BPW + slot - lo_slot;
+                const int rank = (int)lane_rank(m) - __popcll(m & below_row);
+                const int pos = sm.rb[tb * R + rho] + rank;
+                sm.val[pos] = v[j];
+                sm.col[pos] = c + kc;
+            }
+        }
+    }
+    wave_sync();
+
+    // 4. Q lanes per row: lane g of a row sums column group g (G columns)
+    const int lgq = a.lgq;
+    const int Q = 1 << lgq;
+    const int g = lane & (Q - 1);
+    const bool gon = g * G < a.k;
+    const uint32_t xrow = (uint32_t)a.ldx * (uint32_t)sizeof(T);
+    const uint32_t goff = (uint32_t)(g * 16);
+    const int nrows = nI * R;
+    T *__restrict__ Y = static_cast<T *>(a.Y);
+    constexpr int U = 8;   // gathers in flight per lane
+    for (int p0 = 0; p0 < nrows; p0 += (64 >> lgq)) {
+        const int p = p0 + (lane >> lgq);
+        int start = 0, len = 0;
+        if (p < nrows) {
+            const int li = p / R, rho = p % R;
+            const int s0 = sm.brow[li], e0 = sm.brow[li + 1];
+            len = sm.pre[e0 * R + rho] - sm.pre[s0 * R + rho];
+            start = len > 0 ? sm.rb[s0 * R + rho] : 0;   // the row's first place (its first block's)
+        }
+        const int lmax = wave_max(len);
+        double acc[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) acc[q] = 0.0;
+        for (int u = 0; u < lmax; u += U) {
+            V4 xw[U];
+            T vv[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const bool ok = u + t < len;
+                const int idx = ok ? start + u + t : 0;
+                vv[t] = ok ? sm.val[idx] : T(0);
+                const uint32_t off = (ok && gon) ? (uint32_t)sm.col[idx] * xrow + goff : 0xffffffffu;
+                xw[t] = __builtin_amdgcn_raw_buffer_load_b128(xr, off, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const T *xg = reinterpret_cast<const T *>(&xw[t]);
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    if constexpr (sizeof(T) == 8) acc[q] = __builtin_fma(vv[t], xg[q], acc[q]);
+                    else acc[q] += (double)(vv[t] * xg[q]);
+                }
+            }
+        }
+        if (p < nrows && gon) {
+            const int li = p / R, rho = p % R;
+            const int64_t row = (int64_t)(d.i0 + li) * R + rho;
+            if (row < a.n_rows && (len > 0 || !a.accumulate)) {
+                T *yp = Y + row * a.ldy + g * G;
+                T out[G];
+                if (a.accumulate) {
+                    const V4 old = *reinterpret_cast<const V4 *>(yp);
+                    const T *o = reinterpret_cast<const T *>(&old);
+#pragma unroll
+                    for (int q = 0; q < G; ++q) out[q] = (T)(acc[q] + (double)o[q]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < G; ++q) out[q] = (T)acc[q];
+                }
+                *reinterpret_cast<V4 *>(yp) = *reinterpret_cast<const V4 *>(out);
+            }
+        }
+    }
+}
+
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmm_rows(SpmmArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = RowsSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    const int64_t xbytes = a.n_cols > 0 ? ((a.n_cols - 1) * a.ldx + a.k) * (int64_t)sizeof(T) : 0;
+    const auto xr = rsrc(a.X, (uint32_t)xbytes);
+    if (d.b1 - d.b0 > SM::NB) spmm_long<Sh, T>(a, d, xr);
+    else spmm_rows_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+}
+
 template <int R, int C, class T, int KQ>
 __global__ __launch_bounds__(kThreads) void k_spmm_wave(SpmmArgs a) {
     using Sh = Shape<R, C>;
@@ -422,6 +654,16 @@ __global__ __launch_bounds__(kThreads) void k_spmm_wave(SpmmArgs a) {
     const auto xr = rsrc(a.X, (uint32_t)xbytes);
     if (d.b1 - d.b0 > SM::NB) spmm_long<Sh, T>(a, d, xr);
     else spmm_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+}
+
+template <int R, int C, class T>
+spc_status launch_rows(int kq, int cu_groups, dim3 grid, const SpmmArgs &a, hipStream_t s) {
+    switch (kq) {
+    case 2: return launch_capped(k_spmm_rows<R, C, T, 2>, cu_groups, grid, dim3(kThreads), s, a);
+    case 6: return launch_capped(k_spmm_rows<R, C, T, 6>, cu_groups, grid, dim3(kThreads), s, a);
+    case 8: return launch_capped(k_spmm_rows<R, C, T, 8>, cu_groups, grid, dim3(kThreads), s, a);
+    default: return launch_capped(k_spmm_rows<R, C, T, 4>, cu_groups, grid, dim3(kThreads), s, a);
+    }
 }
 
 template <int R, int C, class T>
@@ -469,10 +711,19 @@ spc_status spmm_launch(const spc_beta_view *A, const spc_plan *P, int k, const v
     const int64_t groups = div_up(P->n_tiles, kWaves);
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
     dim3 grid(P->xcd_remap ? (unsigned)(8 * a.tiles_per_xcd) : (unsigned)groups);
+    // the row path: lanes per row Q = the 16-byte groups of a row, rounded up to a power of two
+    const int64_t es = A->dtype == SPC_F64 ? 8 : 4;
+    const int64_t row_bytes = (int64_t)k * es;
+    SPC_REQUIRE(P->spmm_path != SPC_SPMM_ROWS || a.wide, SPC_ERR_INVALID_ARG,
+                "the row path needs k a multiple of %d and 16-byte aligned X and Y rows", (int)(16 / es));
+    const bool rows = a.wide && (P->spmm_path == SPC_SPMM_ROWS || (P->spmm_path == SPC_SPMM_AUTO && row_bytes >= 64));
+    a.lgq = 0;
+    while ((16 << a.lgq) < row_bytes) ++a.lgq;
     return with_shape(P->shape, [&](auto sh) {
         using Sh = decltype(sh);
         return with_dtype(A->dtype, [&](auto tv) {
             using T = decltype(tv);
+            if (rows) return launch_rows<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
             return launch<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
         });
     });

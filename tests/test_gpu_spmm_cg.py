@@ -119,15 +119,62 @@ def test_spmm_grouped_columns_strided(rc, dtype):
     assert np.array_equal(got[:, :4], Y0[:, :4].astype(np.float64))
     # column by column through the one-column path (a strided view of X, so
     # not the single-vector kernel, which sums long rows in its own order):
-    # the same bits as the grouped pass
-    Yg = spc.spmm(B, X.contiguous())
+    # the same bits as the grouped pass of the mask-bit kernel
+    bits = B.plan(0, 0, 0, 0, 0, 0, 0, spc.SPMM_BITS)
+    Yg = spc.spmm(B, X.contiguous(), plan=bits)
     for q in range(k):
-        yq = spc.spmm(B, X[:, q:q + 1])
+        yq = spc.spmm(B, X[:, q:q + 1], plan=bits)
         assert torch.equal(yq[:, 0], Yg[:, q]), q
     # a contiguous single column runs the single-vector kernel: same values
     # within the tolerance
     y1 = spc.spmm(B, X[:, :1].contiguous())[:, 0].cpu().numpy().astype(np.float64)
     assert np.all(np.abs(y1 - Y_ref[:, 0]) <= TOL[dtype] * S_ref[:, 0])
+
+
+@pytest.mark.parametrize("dtype,k", [(torch.float64, 2), (torch.float64, 8), (torch.float64, 12),
+                                     (torch.float64, 16), (torch.float32, 4), (torch.float32, 16)],
+                         ids=["f64k2", "f64k8", "f64k12", "f64k16", "f32k4", "f32k16"])
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_spmm_row_path_matches_oracle_and_bit_lanes(rc, dtype, k):
+    """The row path (values sorted by row in LDS, lanes on rows and 16-byte
+    column groups) forced on, on every case matrix (long intervals, tiles of
+    127 one-entry intervals, empty rows): each entry within the bound of the
+    oracle, repeated calls bit for bit, y += A X leaving empty rows alone,
+    and the mask-bit kernel within the same bound."""
+    r, c = rc
+    for name in CASES:
+        A = case(name).astype(NP[dtype])
+        say(f"[spmm rows] {name} beta{rc} {dtype} k={k}")
+        B = to_beta(A, r, c, dtype)
+        X = torch.from_numpy(synth.dense_block(A.n_cols, k, 37, dtype=NP[dtype])).cuda()
+        Y_ref, S_ref = oracle.csr_spmm(A, X.cpu().numpy())
+        for kq in (2, 4, 8):
+            rows = B.plan(0, 0, 0, kq, 0, 0, 0, spc.SPMM_ROWS)
+            bits = B.plan(0, 0, 0, kq, 0, 0, 0, spc.SPMM_BITS)
+            Yr = spc.spmm(B, X, plan=rows)
+            assert torch.equal(spc.spmm(B, X, plan=rows), Yr)
+            for Y in (Yr, spc.spmm(B, X, plan=bits)):
+                err = np.abs(Y.cpu().numpy().astype(np.float64) - Y_ref)
+                bad = np.argwhere(~(err <= TOL[dtype] * S_ref))
+                assert bad.size == 0, (name, kq, bad[:3])
+            # accumulate: rows without entries keep their value bit for bit
+            Y0 = torch.from_numpy(synth.dense_block(A.n_rows, k, 38, dtype=NP[dtype])).cuda()
+            Ya = Y0.clone()
+            spc.spmm(B, X, Ya, accumulate=True, plan=rows)
+            empty = np.diff(A.rowptr) == 0
+            assert torch.equal(Ya[torch.from_numpy(empty).cuda()], Y0[torch.from_numpy(empty).cuda()])
+            err = np.abs(Ya.cpu().numpy().astype(np.float64) - (Y0.cpu().numpy().astype(np.float64) + Y_ref))
+            assert np.all(err <= TOL[dtype] * (S_ref + np.abs(Y0.cpu().numpy()))), (name, kq)
+
+
+def test_spmm_row_path_needs_grouped_columns():
+    A = case("powerlaw")
+    B = to_beta(A, 2, 4, torch.float64)
+    X = torch.from_numpy(synth.dense_block(A.n_cols, 5, 39)).cuda()
+    with pytest.raises(spc.SpcError):
+        spc.spmm(B, X, plan=B.plan(0, 0, 0, 4, 0, 0, 0, spc.SPMM_ROWS))
+    with pytest.raises(spc.SpcError):
+        B.plan(0, 0, 0, 4, 0, 0, 0, 3)
 
 
 def _spd(m):
