@@ -6,9 +6,13 @@ Both selectors are evaluated here by the CPU oracle, in FP64: the network's
 forward pass on the held-out matrices' features, and the paper's per-kernel
 polynomial interpolation of speed against Avg(r,c) ("Performance polynomial
 interpolation") fitted on the training matrices. The regret of a choice is
-t_selected / t_best - 1 (the time form of Table 3's speed difference), with
-the recorded times of all six kernels. The split is by matrix index, 80% of
-each population for training and the rest held out, as at training time.
+t_selected / t_best - 1 (the time form of Table 3's speed difference). The
+records hold each matrix's time for eight kernel classes: the six shapes
+and the test kernels of Algorithm 2 for beta(1,8) and beta(2,4). A selector
+of six classes is judged against the best of its six and against the best
+of all eight; one of eight against the best of eight. The split is by
+matrix index, 80% of each population for training and the rest held out,
+as at training time.
 """
 import json
 import os
@@ -22,74 +26,103 @@ from paper_1801_01134_amd import records as R
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 REC = os.path.join(HERE, "..", "paper_1801_01134_amd", "records")
-FILES = [os.path.join(REC, f) for f in ("selector_records_mi355x.jsonl", "structured_records_mi355x.jsonl")]
-MODEL = os.path.join(REC, "selector_mlp_mi355x.json")
+FILES = [os.path.join(REC, f) for f in ("selector_records_mi355x.jsonl", "structured_records_mi355x.jsonl",
+                                        "large_records_mi355x.jsonl")]
+# held-out bars of the committed networks (on the device: 98.4% and 99.3%
+# within 5%, mean regrets 0.29% and 0.20%)
+NET_WITHIN_5PCT = {6: 0.97, 8: 0.98}
+NET_MEAN = {6: 0.006, 8: 0.005}
+MODELS = {6: os.path.join(REC, "selector_mlp_mi355x.json"), 8: os.path.join(REC, "selector_mlp8_mi355x.json")}
 
 
 @pytest.fixture(scope="module")
 def held_out():
-    if not all(os.path.exists(f) for f in FILES + [MODEL]):
-        pytest.skip("no committed records or model")
+    if not all(os.path.exists(f) for f in FILES + list(MODELS.values())):
+        pytest.skip("no committed records or models")
     train, test = R.split(R.load(*FILES))
-    with open(MODEL) as f:
-        model = json.load(f)
-    return train, test, model
+    models = {}
+    for k, path in MODELS.items():
+        with open(path) as f:
+            models[k] = json.load(f)
+        assert models[k]["n_out"] == k
+    return train, test, models
 
 
-def _params(flat):
+def _params(flat, k):
     """The device's flat parameter vector (W1, b1, W2, b2, W3, b3, weights
-    row-major [out, in]) as the oracle's dictionary."""
+    row-major [out, in]) as the oracle's dictionary, for k outputs."""
     flat = np.asarray(flat, dtype=np.float64)
     P, o = {}, 0
     for name in M.PARAM_NAMES:
-        shp = M.param_shapes()[name]
+        shp = M.param_shapes(k)[name]
         n = int(np.prod(shp))
         P[name] = flat[o:o + n].reshape(shp)
         o += n
-    assert o == flat.size == M.n_params()
+    assert o == flat.size == M.n_params(k)
     return P
+
+
+def _network_choice(model, X, k):
+    P = _params(model["params"], k)
+    Xh = (X.astype(np.float64) - np.asarray(model["mu"], np.float64)) / np.asarray(model["sd"], np.float64)
+    return M.predict(P, Xh)
 
 
 def _regrets(T, choice):
     return np.array([S.regret(T[i], int(choice[i])) for i in range(T.shape[0])])
 
 
-def test_network_beats_interpolation_on_held_out_matrices(held_out):
-    train, test, model = held_out
-    Xtr, Ttr, Atr, Gtr = R.arrays(train)
-    Xte, Tte, Ate, Gte = R.arrays(test)
-    assert len(test) >= 400 and Tte.shape[1] == 6
+@pytest.mark.parametrize("k", [6, 8])
+def test_network_beats_interpolation_on_held_out_matrices(held_out, k):
+    train, test, models = held_out
+    Xtr, Ttr, Atr, Gtr = R.arrays(train, k)
+    Xte, Tte, Ate, Gte = R.arrays(test, k)
+    assert len(test) >= 500 and Tte.shape[1] == k
 
-    P = _params(model["params"])
-    Xh = (Xte.astype(np.float64) - np.asarray(model["mu"], np.float64)) / np.asarray(model["sd"], np.float64)
-    net = _regrets(Tte, M.predict(P, Xh))
-
+    net = _regrets(Tte, _network_choice(models[k], Xte, k))
     interp = S.fit_interpolation(Atr, Gtr, 3)
     itp = _regrets(Tte, np.array([interp.select(Ate[i]) for i in range(len(test))]))
-
-    # always the single shape that is best on average over the training matrices
+    # always the single class that is best on average over the training matrices
     fixed_k = int(np.argmin(np.mean(Ttr / Ttr.min(axis=1, keepdims=True), axis=0)))
     fixed = _regrets(Tte, np.full(len(test), fixed_k))
 
-    print(f"held-out mean regret: network {net.mean():.4f}, interpolation {itp.mean():.4f}, "
-          f"fixed shape {fixed.mean():.4f}; within 5%: {np.mean(net <= 0.05):.3f}, "
+    print(f"{k} classes, held-out mean regret: network {net.mean():.4f}, interpolation {itp.mean():.4f}, "
+          f"fixed class {fixed.mean():.4f}; within 5%: {np.mean(net <= 0.05):.3f}, "
           f"{np.mean(itp <= 0.05):.3f}, {np.mean(fixed <= 0.05):.3f}")
-    # the network is within 5% of the best kernel where the interpolation is not
-    assert np.mean(net <= 0.05) >= 0.95
+    assert np.mean(net <= 0.05) >= NET_WITHIN_5PCT[k]
     assert np.mean(net <= 0.05) > np.mean(itp <= 0.05)
-    # and its average loss against the best kernel is a fraction of the others'
-    assert net.mean() < 0.01
+    assert net.mean() < NET_MEAN[k]
     assert net.mean() < 0.5 * itp.mean()
     assert net.mean() < 0.5 * fixed.mean()
 
 
-def test_network_picks_are_stable_under_float32_rounding(held_out):
+def test_test_kernel_classes_lower_the_regret(held_out):
+    """Against the best of all eight kernels, the selectors that know the
+    test kernels lose less than those that choose among the shapes only."""
+    train, test, models = held_out
+    T8 = R.arrays(test, 8)[1]
+    out = {}
+    for k in (6, 8):
+        Xtr, Ttr, Atr, Gtr = R.arrays(train, k)
+        Xte, _, Ate, _ = R.arrays(test, k)
+        interp = S.fit_interpolation(Atr, Gtr, 3)
+        out[k] = (_regrets(T8, _network_choice(models[k], Xte, k)),
+                  _regrets(T8, np.array([interp.select(Ate[i]) for i in range(len(test))])))
+    print("mean regret vs the best of 8: network %.4f -> %.4f, interpolation %.4f -> %.4f"
+          % (out[6][0].mean(), out[8][0].mean(), out[6][1].mean(), out[8][1].mean()))
+    assert out[8][0].mean() < 0.5 * out[6][0].mean()
+    assert out[8][1].mean() < out[6][1].mean()
+
+
+@pytest.mark.parametrize("k", [6, 8])
+def test_network_picks_are_stable_under_float32_rounding(held_out, k):
     """The device runs the network in FP32; its picks agree with the FP64
     forward pass except where two kernels' scores nearly tie, and such
     disagreements cost almost nothing."""
-    _, test, model = held_out
-    Xte, Tte, _, _ = R.arrays(test)
-    P = _params(model["params"])
+    _, test, models = held_out
+    model = models[k]
+    Xte, Tte, _, _ = R.arrays(test, k)
+    P = _params(model["params"], k)
     mu = np.asarray(model["mu"], np.float64)
     sd = np.asarray(model["sd"], np.float64)
     o64, _ = M.forward(P, (Xte.astype(np.float64) - mu) / sd)
