@@ -119,6 +119,39 @@ def test_conversion_bit_exact(name, rc):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+def test_conversion_values_aligned_and_not(rc, dtype):
+    """Conversion into a values output on a 16-byte boundary and into one
+    that is not (one element past it): both give the oracle's values bit for
+    bit, and nothing outside the output is written."""
+    from paper_1801_01134_amd import _binding as bb
+    r, c = rc
+    npd = np.float64 if dtype == torch.float64 else np.float32
+    ubits = np.uint64 if dtype == torch.float64 else np.uint32
+    for name in ("powerlaw", "fem6", "empty_rows"):
+        A = case(name).astype(npd)
+        say(f"[conv values] {name} beta{rc} {dtype}")
+        ref = oracle.csr_to_beta(A, r, c)
+        B = to_beta(A, r, c, dtype)                    # aligned output
+        assert np.array_equal(B.values.cpu().numpy().view(ubits), ref.values.view(ubits))
+        # the same conversion into an output one element past a 16-byte boundary
+        rp = torch.from_numpy(A.rowptr).cuda()
+        ci = torch.from_numpy(A.colidx if A.nnz else np.zeros(1, np.int32)).cuda()
+        v = torch.from_numpy(A.values if A.nnz else np.zeros(1, npd)).cuda()
+        store = torch.zeros(max(A.nnz, 1) + 4, dtype=dtype, device="cuda")
+        vout = store[1:1 + max(A.nnz, 1)]
+        bcol = torch.zeros(max(B.n_blocks, 1), dtype=torch.int32, device="cuda")
+        masks = torch.zeros(B.block_masks.numel(), dtype=torch.uint8, device="cuda")
+        bb.check(spc.lib().spc_csr_to_beta(r, c, bb._dtype_code(dtype), A.n_rows, A.n_cols, bb._ptr(rp),
+                                           bb._ptr(ci), bb._ptr(v), bb._ptr(B.block_rowptr), bb._ptr(bcol),
+                                           bb._ptr(masks), bb._ptr(vout), bb.stream_ptr()))
+        torch.cuda.synchronize()
+        assert np.array_equal(vout[:A.nnz].cpu().numpy().view(ubits), ref.values.view(ubits))
+        assert torch.equal(bcol[:B.n_blocks], B.block_colidx) and torch.equal(masks, B.block_masks)
+        assert store[0].item() == 0 and torch.all(store[1 + max(A.nnz, 1):] == 0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
 def test_spmv_parity(name, rc, dtype):
