@@ -178,10 +178,10 @@ __global__ __launch_bounds__(kT) void k_alpha(const double *part, int nblk, int 
     }
 }
 
-// X += alpha P, R -= alpha Q; partial sums of R*R per column.
+// R -= alpha Q; partial sums of R*R per column. (X moves with the
+// direction update, which reads P anyway.)
 template <class T>
-__global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, T *__restrict__ X, int64_t ldx,
-                                               T *__restrict__ R, const T *__restrict__ P,
+__global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, T *__restrict__ R,
                                                const T *__restrict__ Q, double *part) {
     __shared__ double red[kT];
     const Flat f = flat(n, k);
@@ -190,19 +190,16 @@ __global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, 
         const double al = s->alpha[f.q];
         int64_t e = f.t;
         for (; e + (kU - 1) * f.S < f.N; e += kU * f.S) {
-            T x[kU], r[kU], p[kU], qq[kU];
+            T r[kU], qq[kU];
 #pragma unroll
             for (int j = 0; j < kU; ++j) {
                 const int64_t ej = e + j * f.S;
-                x[j] = X[(ej / k) * ldx + f.q];
                 r[j] = R[ej];
-                p[j] = P[ej];
                 qq[j] = Q[ej];
             }
 #pragma unroll
             for (int j = 0; j < kU; ++j) {
                 const int64_t ej = e + j * f.S;
-                X[(ej / k) * ldx + f.q] = (T)((double)x[j] + al * (double)p[j]);
                 const T rn = (T)((double)r[j] - al * (double)qq[j]);
                 R[ej] = rn;
                 if (j & 1) a1 += (double)rn * (double)rn;
@@ -210,7 +207,6 @@ __global__ __launch_bounds__(kT) void k_update(int64_t n, int k, const Scal *s, 
             }
         }
         for (; e < f.N; e += f.S) {
-            X[(e / k) * ldx + f.q] = (T)((double)X[(e / k) * ldx + f.q] + al * (double)P[e]);
             const T rn = (T)((double)R[e] - al * (double)Q[e]);
             R[e] = rn;
             a0 += (double)rn * (double)rn;
@@ -244,26 +240,38 @@ __global__ __launch_bounds__(kT) void k_beta(const double *part, int nblk, int k
     if (threadIdx.x == 0) s->iter = s->iter + 1;
 }
 
-// P = R + beta P. A finished column gets beta = 0 and keeps alpha = 0, so its
-// X and R no longer change.
+// X += alpha P with this iteration's direction, then P = R + beta P. A
+// finished column gets beta = 0 and keeps alpha = 0, so its X and R no
+// longer change.
 template <class T>
-__global__ __launch_bounds__(kT) void k_direction(int64_t n, int k, const Scal *s, const T *__restrict__ R,
-                                                  T *__restrict__ P) {
+__global__ __launch_bounds__(kT) void k_direction(int64_t n, int k, const Scal *s, T *__restrict__ X, int64_t ldx,
+                                                  const T *__restrict__ R, T *__restrict__ P) {
     const Flat f = flat(n, k);
     if (f.t >= f.S) return;
+    const double al = s->alpha[f.q];
     const double be = s->beta[f.q];
     int64_t e = f.t;
     for (; e + (kU - 1) * f.S < f.N; e += kU * f.S) {
-        T r[kU], p[kU];
+        T x[kU], r[kU], p[kU];
 #pragma unroll
         for (int j = 0; j < kU; ++j) {
-            r[j] = R[e + j * f.S];
-            p[j] = P[e + j * f.S];
+            const int64_t ej = e + j * f.S;
+            x[j] = X[(ej / k) * ldx + f.q];
+            r[j] = R[ej];
+            p[j] = P[ej];
         }
 #pragma unroll
-        for (int j = 0; j < kU; ++j) P[e + j * f.S] = (T)((double)r[j] + be * (double)p[j]);
+        for (int j = 0; j < kU; ++j) {
+            const int64_t ej = e + j * f.S;
+            X[(ej / k) * ldx + f.q] = (T)((double)x[j] + al * (double)p[j]);
+            P[ej] = (T)((double)r[j] + be * (double)p[j]);
+        }
     }
-    for (; e < f.N; e += f.S) P[e] = (T)((double)R[e] + be * (double)P[e]);
+    for (; e < f.N; e += f.S) {
+        const T p = P[e];
+        X[(e / k) * ldx + f.q] = (T)((double)X[(e / k) * ldx + f.q] + al * (double)p);
+        P[e] = (T)((double)R[e] + be * (double)p);
+    }
 }
 
 struct Work {
@@ -306,11 +314,11 @@ spc_status iteration(const spc_beta_view *A, const spc_plan *P, int k, const Wor
     if (r != SPC_OK) return r;
     hipLaunchKernelGGL(k_dot<T>, dim3(nb), dim3(kT), 0, st, n, k, (const T *)w.P, (const T *)w.Q, w.part);
     hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kT), 0, st, w.part, (int)nb, k, w.s);
-    hipLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kT), 0, st, n, k, (const Scal *)w.s, X, ldx, (T *)w.R,
-                       (const T *)w.P, (const T *)w.Q, w.part);
+    hipLaunchKernelGGL(k_update<T>, dim3(nb), dim3(kT), 0, st, n, k, (const Scal *)w.s, (T *)w.R,
+                       (const T *)w.Q, w.part);
     hipLaunchKernelGGL(k_beta, dim3(1), dim3(kT), 0, st, w.part, (int)nb, k, w.s, tol2);
-    hipLaunchKernelGGL(k_direction<T>, dim3(nb), dim3(kT), 0, st, n, k, (const Scal *)w.s, (const T *)w.R,
-                       (T *)w.P);
+    hipLaunchKernelGGL(k_direction<T>, dim3(nb), dim3(kT), 0, st, n, k, (const Scal *)w.s, X, ldx,
+                       (const T *)w.R, (T *)w.P);
     SPC_HIP(hipGetLastError());
     return SPC_OK;
 }
