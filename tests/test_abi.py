@@ -82,3 +82,35 @@ def test_plan_parameters_checked_on_the_host():
         p = B.PlanParams(**bad)
         assert L.spc_plan_create(ctypes.byref(v), ctypes.byref(p), ctypes.byref(h), None) == -1, bad
         assert not h.value
+
+
+def test_kernel_classes_and_output_counts_on_the_host():
+    L = B.lib()
+    # classes: the six shapes, then the test kernels of beta(1,8) and beta(2,4)
+    assert [L.spc_class_shape(k) for k in range(8)] == [0, 1, 2, 3, 4, 5, 0, 1]
+    assert L.spc_class_shape(8) == -1 and L.spc_class_shape(-1) == -1
+    assert [L.spc_class_mode(k) for k in range(8)] == [-1] * 6 + [2, 2]
+    assert L.spc_selector_n_classes(None, 0) == 0
+    # the network takes 6 or 8 outputs; any other count is refused before a launch
+    assert L.spc_mlp_targets(None, 0, 7, None, None) == -1
+    assert L.spc_mlp_targets(None, 0, 6, None, None) == 0
+    assert L.spc_mlp_infer(None, None, None, None, 0, 8, None, None, None) == -1   # null parameters
+    sel = ctypes.c_void_p()
+    assert L.spc_selector_create(ctypes.byref(sel)) == 0
+    one = (ctypes.c_double * 7)(*([1.0] * 7))
+    assert L.spc_selector_fit_interp(sel, 1, 7, one, one, 1) == -1     # 7 classes
+    assert L.spc_selector_fit_interp(sel, 1, 8, (ctypes.c_double * 8)(*([2.0] * 8)),
+                                     (ctypes.c_double * 8)(*([3.0] * 8)), 0) == 0
+    assert L.spc_selector_n_classes(sel, 0) == 8 and L.spc_selector_n_classes(sel, 1) == 0
+    assert L.spc_selector_destroy(sel) == 0
+
+
+def test_batch_parameter_counts_on_the_host():
+    L = B.lib()
+    out = ctypes.c_void_p()
+    v = (B.BetaView * 2)()
+    # n_params must be 0, 1 or count; count >= 1
+    assert L.spc_batch_create(2, v, None, 1, ctypes.byref(out), None) == -1
+    assert L.spc_batch_create(0, v, None, 0, ctypes.byref(out), None) == -1
+    p = (B.PlanParams * 2)()
+    assert L.spc_batch_create(2, v, p, 3, ctypes.byref(out), None) == -1
