@@ -42,3 +42,17 @@ def test_populations_have_generators():
         fam, A = R.generator(pop)(1, 2000, 3000)
         assert 2000 <= A.n_rows <= 3000 or pop == "structured"
         _valid_csr(A)
+
+
+def test_selector_records_span_the_papers_ranges():
+    """The generated selector population covers the values per block of the
+    paper's test sets (Table 1: Avg(1,8) from 1 to 7.6, Avg(4,8) from 1 to
+    30), measured by the device features stored in the committed records."""
+    import os
+    rec = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1801_01134_amd",
+                       "records", "selector_records_mi355x.jsonl")
+    if not os.path.exists(rec):
+        pytest.skip("no committed records")
+    X = np.array([r["features"] for r in R.load(rec)])
+    assert X[:, 8].min() <= 1.0 + 1e-6 and X[:, 8].max() >= 7.6
+    assert X[:, 12].min() <= 1.0 + 1e-6 and X[:, 12].max() >= 30.0
