@@ -86,3 +86,44 @@ def test_records_collect_writes_complete_lines():
         # the test kernels (Algorithm 2) of beta(1,8) and beta(2,4) as classes of their own
         assert len(rec["us_test"]) == 2 and all(t > 0 for t in rec["us_test"])
         assert all(p["mode"] == 2 for p in rec["params_test"])
+
+
+def _synthetic_records(n, seed):
+    """Records whose fastest class follows the features: features are
+    random, times depend on them (inputs only; no method arithmetic)."""
+    rng = synth.rng_for(520, seed)
+    recs = []
+    for i in range(n):
+        f = rng.uniform(0.5, 8.0, 16)
+        t = np.exp(0.4 * rng.standard_normal(8) + 0.3 * f[:8] - 0.3 * f[8:16])
+        recs.append({"population": R.POPULATIONS[i % 3], "index": i // 3, "features": f.tolist(),
+                     "us": t[:6].tolist(), "us_test": t[6:].tolist(), "nnz": 1000 + i})
+    return recs
+
+
+@pytest.mark.parametrize("k", [6, 8])
+def test_records_evaluate_classes(k):
+    """records.evaluate on synthetic records: the device-trained network and
+    the interpolation are judged with the recorded times; the regrets it
+    reports equal the oracle's regret of the same choices."""
+    say(f"[records] evaluate {k} classes")
+    recs = _synthetic_records(450, k)
+    train, test = R.split(recs)
+    res, model = R.evaluate(train, test, epochs=30, n_classes=k)
+    assert res["n_classes"] == k and model["n_out"] == k and len(model["params"]) == spc.mlp_n_params(k)
+    assert res["n_test"] == len(test) and sum(res["mlp_choice_share"]) == len(test)
+    assert len(res["best_class_share"]) == k
+    # the reported mean regret of the network is the oracle's regret of its choices
+    Xte, Tte, _, _ = R.arrays(test, k)
+    P = torch.tensor(model["params"], dtype=torch.float32, device="cuda")
+    mu = torch.tensor(model["mu"], dtype=torch.float32, device="cuda")
+    sd = torch.tensor(model["sd"], dtype=torch.float32, device="cuda")
+    _, ch = spc.mlp_infer(P, mu, sd, torch.from_numpy(Xte).cuda())
+    ch = ch.cpu().numpy()
+    from oracle import select as osel
+    reg = np.array([osel.regret(Tte[i], int(ch[i])) for i in range(len(test))])
+    assert res["mlp"]["mean"] == pytest.approx(reg.mean(), rel=1e-12, abs=1e-15)
+    if k == 8:
+        T8 = R.arrays(test, 8)[1]
+        assert res["vs_all8"]["mlp"]["mean"] == pytest.approx(
+            np.mean([osel.regret(T8[i], int(ch[i])) for i in range(len(test))]), rel=1e-12)
