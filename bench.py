@@ -825,7 +825,7 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     if args.plan:
         fields = [int(t) for t in args.plan.split(",")]
         m_, v_, o_ = fields[:3]
-        params = {"mode": m_, "wave_chunks": v_ if m_ == 0 else 0, "tile_bits": v_ if m_ == 1 else 0,
+        params = {"mode": m_, "wave_chunks": v_ if m_ != 1 else 0, "tile_bits": v_ if m_ == 1 else 0,
                   "tile_order": o_, "pipeline": fields[3] if len(fields) > 3 else 0}
         if len(fields) > 4 and fields[4]:
             params["cu_groups"] = fields[4]
@@ -843,7 +843,8 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     info = P.info()
     kname = ({0: f"k_spmv_wave{'_pipe' if params.get('pipeline') else ('2' if params.get('wave_tiles') == 2 else '')}"
                  f"<{r},{c},{tname},{params['wave_chunks'] or 4}>",
-              2: f"k_spmv_test<{r},{c},{tname},{params['wave_chunks'] or 4}>"}.get(
+              2: f"k_spmv_test<{r},{c},{tname},{params['wave_chunks'] or 4}>",
+              3: f"k_spmv_brow<{r},{c},{tname},{params['wave_chunks'] or 4}>"}.get(
                  params["mode"], f"k_spmv_wg<{r},{c},{tname},{info['tile_bits']}>"))
     for _ in range(args.warmup):
         spc.spmv(B, xd, yd, plan=P)

@@ -192,7 +192,12 @@ spc_status spc_permute_vector(int64_t n, int32_t dtype, const int32_t *perm, con
  *              per mask bit of a compacted list. A tile holds up to
  *              248 blocks (fewer with 2 chunks, or 4 chunks and FP64 for
  *              beta(2,4)), at most 64 of them with several values, and no
- *              more values than mode 0's tile (planning reads the masks once)
+ *              more values than mode 0's tile (planning reads the masks once);
+ *              3 = block-row lanes: mode 0's tiles and streams, but lane =
+ *              (block, block row): the lane walks that block row's set bits
+ *              in turn, one x gather per stored value, and its sum is the
+ *              block row's partial (mode 0 spends a lane per mask bit,
+ *              stored or not)
  * params == NULL selects spc_plan_default_params(A); all zeros select mode 0
  * with 4 chunks per lane. */
 typedef struct spc_plan spc_plan;
@@ -201,13 +206,17 @@ typedef struct spc_plan spc_plan;
 typedef struct spc_plan_params {
     int32_t tile_bits;
     int32_t tile_order;     /* SPC_ORDER_XCD (0) or SPC_ORDER_HW (1) */
-    int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles, 2 = test tiles */
-    int32_t wave_chunks;    /* mode 0: 16-byte value chunks per lane, 2, 4, 6 or 8; 0 = 4 */
+    int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles, 2 = test tiles,
+                               3 = block-row lanes: mode 0's tiles, with each lane taking one
+                               block row and walking its set bits (fewer gathers where block
+                               rows hold few entries; same bound on the results, its own order
+                               of additions) */
+    int32_t wave_chunks;    /* modes 0, 2 and 3: 16-byte value chunks per lane, 2, 4, 6 or 8; 0 = 4 */
     int32_t pipeline;       /* mode 0: 0 = one wavefront per tile; 1 = persistent wavefronts (as
                                many workgroups as fit on the device) that load their next tile
                                while working on the current one; N > 1 = the same with at most N
                                workgroups */
-    int32_t cu_groups;      /* modes 0 and 2, launches that are not persistent and SpMM: 0 = as many
+    int32_t cu_groups;      /* modes 0, 2 and 3, launches that are not persistent and SpMM: 0 = as many
                                workgroups per compute unit as fit; 2..8 = at most that many (the
                                launch reserves LDS to hold the others off). Fewer resident
                                wavefronts can keep more of the gathered rows of X in cache. */
@@ -314,8 +323,9 @@ spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k,
  *   with 2, 4, 6 and 8 chunks per lane, one wavefront per tile or
  *   pipelined, and with 4, 6 and 8 chunks also capped at 2 and 4 resident
  *   workgroups per compute unit; mode 1 with 1024, 2048, 3072 and 4032 tile
- *   bits; each in both tile orders where the grid order applies; for
- *   beta(1,8) and beta(2,4) also mode 2 with 2, 4, 6 and 8 chunks), times it
+ *   bits; each in both tile orders where the grid order applies; mode 3
+ *   with 4, 6 and 8 chunks, uncapped and capped at 4; for beta(1,8) and
+ *   beta(2,4) also mode 2 with 2, 4, 6 and 8 chunks), times it
  *   with spc_time_spmv and returns the fastest set in *best and its time in
  *   *best_us. If records is not NULL, up to max_records timings are written
  *   there (host memory) and *n_records says how many. x and y are scratch
@@ -420,7 +430,7 @@ int64_t spc_matrix_features_noalloc_max_rows(void);
 /* ---------------------------------------------------------------------------
  * Kernel classes. The selectors choose among SPC_N_CLASSES kernels: classes
  * 0..5 are the six block shapes in SPC_SHAPE order, each run by its own
- * kernels (plan modes 0 and 1); class 6 is the beta(1,8) "test" kernel and
+ * kernels (plan modes 0, 1 and 3); class 6 is the beta(1,8) "test" kernel and
  * class 7 the beta(2,4) "test" kernel (plan mode 2; Algorithm 2, and the
  * "test" rows of Table 3). A selector fitted on n_classes = 6 records
  * chooses among the shapes only. The Avg(r,c) of class k is feature
@@ -432,7 +442,7 @@ int64_t spc_matrix_features_noalloc_max_rows(void);
 /* Shape index (0..5) of class k (0..7), or -1 for any other k. */
 int32_t spc_class_shape(int32_t k);
 /* Plan mode the class runs in: 2 for the test classes, else -1 (the
- * shape's own modes 0 and 1; the autotuner or the default plan chooses). */
+ * shape's own modes 0, 1 and 3; the autotuner or the default plan chooses). */
 int32_t spc_class_mode(int32_t k);
 
 /* ---------------------------------------------------------------------------

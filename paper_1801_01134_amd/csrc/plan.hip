@@ -19,6 +19,7 @@ namespace spc {
 int spmv_max_intervals_per_tile(int r, int mode);
 int wave_tile_bits(int dtype, int kq);
 int test_tile_blocks(int shape, int dtype, int kq);
+int brow_tile_blocks(int shape, int dtype, int kq);
 
 namespace {
 
@@ -65,16 +66,19 @@ __global__ __launch_bounds__(256) void k_tile_counts(const TileDesc *__restrict_
     }
 }
 
-// Per interval of a one-byte-mask shape: its value count and its blocks
-// holding more than one value (what a test tile is planned on).
+// Per interval: its value count and its blocks holding more than one value
+// (what test tiles and block-row-lane tiles are planned on). MB: mask bytes
+// per block.
+template <int MB>
 __global__ __launch_bounds__(256) void k_interval_stats(const int32_t *__restrict__ brow, int64_t n_int,
                                                         const uint8_t *__restrict__ masks, int32_t *__restrict__ nval,
                                                         int32_t *__restrict__ nmulti) {
+    using MW = typename MaskT<MB>::T;
     const int64_t I = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (I >= n_int) return;
     int v = 0, m = 0;
     for (int b = brow[I]; b < brow[I + 1]; ++b) {
-        const int pc = __popc((uint32_t)masks[b]);
+        const int pc = __popc((uint32_t)reinterpret_cast<const MW *>(masks)[b]);
         v += pc;
         m += pc >= 2;
     }
@@ -103,7 +107,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
                 "tile_order must be SPC_ORDER_XCD (0) or SPC_ORDER_HW (1)");
     const int xcd_remap = params->tile_order == SPC_ORDER_XCD;
     const int mode = params ? params->mode : 0;
-    SPC_REQUIRE(mode == 0 || mode == 1 || mode == 2, SPC_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+    SPC_REQUIRE(mode >= 0 && mode <= 3, SPC_ERR_INVALID_ARG, "mode must be 0, 1, 2 or 3");
     SPC_REQUIRE(mode != 2 || (A->r * A->c == 8), SPC_ERR_UNSUPPORTED_SHAPE,
                 "mode 2 (test tiles) is for beta(1,8) and beta(2,4)");
     const int kq = params && params->wave_chunks ? params->wave_chunks : 4;
@@ -119,7 +123,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
                 SPC_ERR_INVALID_ARG, "spmm_path must be 0, 1 or 2");
     SPC_REQUIRE(cu_groups == 0 || (cu_groups >= 2 && cu_groups <= 8), SPC_ERR_INVALID_ARG,
                 "cu_groups must be 0 or 2..8 (got %d)", cu_groups);
-    SPC_REQUIRE(!(cu_groups && mode == 1), SPC_ERR_INVALID_ARG, "cu_groups applies to modes 0 and 2 only");
+    SPC_REQUIRE(!(cu_groups && mode == 1), SPC_ERR_INVALID_ARG, "cu_groups applies to modes 0, 2 and 3 only");
     SPC_REQUIRE(!(pipeline && mode != 0), SPC_ERR_INVALID_ARG, "pipeline applies to mode 0 only");
     SPC_REQUIRE(kq == 2 || kq == 4 || kq == 6 || kq == 8, SPC_ERR_INVALID_ARG,
                 "wave_chunks must be 2, 4, 6 or 8");
@@ -148,6 +152,31 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     std::vector<TileDesc> tiles;
     tiles.reserve((size_t)(A->n_blocks / (target ? target : 1) + n_int / max_int + 2));
     int64_t n_long = 0;
+    // Test tiles (mode 2) and block-row-lane tiles (mode 3) are planned on
+    // each interval's value count (and count of blocks with several values)
+    std::vector<int32_t> hv, hm;
+    if ((mode == 2 || mode == 3) && n_int > 0) {
+        hv.resize((size_t)n_int);
+        hm.resize((size_t)n_int);
+        DevBuf dv, dm;
+        SPC_HIP(dv.alloc(sizeof(int32_t) * n_int));
+        SPC_HIP(dm.alloc(sizeof(int32_t) * n_int));
+        const dim3 g((unsigned)div_up(n_int, 256)), b(256);
+        const uint8_t *mk = static_cast<const uint8_t *>(A->block_masks);
+        if (rc == 8)
+            hipLaunchKernelGGL(k_interval_stats<1>, g, b, 0, stream, A->block_rowptr, n_int, mk, dv.as<int32_t>(),
+                               dm.as<int32_t>());
+        else if (rc == 16)
+            hipLaunchKernelGGL(k_interval_stats<2>, g, b, 0, stream, A->block_rowptr, n_int, mk, dv.as<int32_t>(),
+                               dm.as<int32_t>());
+        else
+            hipLaunchKernelGGL(k_interval_stats<4>, g, b, 0, stream, A->block_rowptr, n_int, mk, dv.as<int32_t>(),
+                               dm.as<int32_t>());
+        SPC_HIP(hipGetLastError());
+        SPC_HIP(hipMemcpyAsync(hv.data(), dv.p, sizeof(int32_t) * n_int, hipMemcpyDeviceToHost, stream));
+        SPC_HIP(hipMemcpyAsync(hm.data(), dm.p, sizeof(int32_t) * n_int, hipMemcpyDeviceToHost, stream));
+        SPC_HIP(hipStreamSynchronize(stream));
+    }
     if (mode == 2 && n_int > 0) {
         // test tiles: at most NB2 blocks, 64 of them with several values, and
         // no more values than the buffer holds; an interval beyond any limit
@@ -155,19 +184,6 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
         const int64_t nb2 = test_tile_blocks(shape, A->dtype, kq);
         const int64_t vcap = cap_bits;
         constexpr int64_t kMulti = 64;
-        std::vector<int32_t> hv((size_t)n_int), hm((size_t)n_int);
-        {
-            DevBuf dv, dm;
-            SPC_HIP(dv.alloc(sizeof(int32_t) * n_int));
-            SPC_HIP(dm.alloc(sizeof(int32_t) * n_int));
-            hipLaunchKernelGGL(k_interval_stats, dim3((unsigned)div_up(n_int, 256)), dim3(256), 0, stream,
-                               A->block_rowptr, n_int, static_cast<const uint8_t *>(A->block_masks),
-                               dv.as<int32_t>(), dm.as<int32_t>());
-            SPC_HIP(hipGetLastError());
-            SPC_HIP(hipMemcpyAsync(hv.data(), dv.p, sizeof(int32_t) * n_int, hipMemcpyDeviceToHost, stream));
-            SPC_HIP(hipMemcpyAsync(hm.data(), dm.p, sizeof(int32_t) * n_int, hipMemcpyDeviceToHost, stream));
-            SPC_HIP(hipStreamSynchronize(stream));
-        }
         for (int64_t i = 0; i < n_int;) {
             const int64_t nb = brow[i + 1] - brow[i];
             if (nb > nb2 || hm[i] > kMulti || hv[i] > vcap) {
@@ -191,7 +207,33 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
             tiles.push_back({0, (int32_t)start, (int32_t)i, brow[start], brow[i], 0, 0});
         }
     }
-    for (int64_t i = mode == 2 ? n_int : 0; i < n_int;) {
+    if (mode == 3 && n_int > 0) {
+        // block-row-lane tiles: up to the buffer's values and NBX blocks; an
+        // interval beyond either becomes a tile of its own on the long path
+        // (the kernel tells it by the same two counts)
+        const int64_t nbx = brow_tile_blocks(shape, A->dtype, kq);
+        const int64_t vcap = cap_bits;
+        for (int64_t i = 0; i < n_int;) {
+            const int64_t nb = brow[i + 1] - brow[i];
+            if (nb > nbx || hv[i] > vcap) {
+                tiles.push_back({0, (int32_t)i, (int32_t)(i + 1), brow[i], brow[i + 1], 0, 0});
+                ++n_long;
+                ++i;
+                continue;
+            }
+            const int64_t start = i;
+            int64_t blocks = 0, values = 0;
+            while (i < n_int && i - start < max_int) {
+                const int64_t b = brow[i + 1] - brow[i];
+                if (b > nbx || hv[i] > vcap || blocks + b > nbx || values + hv[i] > vcap) break;
+                blocks += b;
+                values += hv[i];
+                ++i;
+            }
+            tiles.push_back({0, (int32_t)start, (int32_t)i, brow[start], brow[i], 0, 0});
+        }
+    }
+    for (int64_t i = (mode == 2 || mode == 3) ? n_int : 0; i < n_int;) {
         const int64_t nb = brow[i + 1] - brow[i];
         if (nb > target) {
             tiles.push_back({0, (int32_t)i, (int32_t)(i + 1), brow[i], brow[i + 1], 0, 0});

@@ -283,10 +283,11 @@ __device__ __forceinline__ void store_partial_at(double *mine, bool keeper, int 
 }
 
 // 3. Row sums of a wavefront tile whose (block, block row) partials sit in
-// s_part (entry g R + rho: slot g of the tile's words, block row rho)
-// and whose tile-relative interval pointers sit in s_brow. With DEFER (and
-// y = A x), the results go to *out instead of y; the caller stores them.
-template <class Sh, class T, bool DEFER = false>
+// s_part (PPR of them at entry (g R + rho) PPR: slot g of the tile's words,
+// block row rho) and whose tile-relative interval pointers sit in s_brow.
+// Only the tile's own slots are read. With DEFER (and y = A x), the results
+// go to *out instead of y; the caller stores them.
+template <class Sh, class T, bool DEFER = false, int PPR = (sizeof(T) == 8 ? 2 : 1)>
 __device__ __forceinline__ void tile_sums(const SpmvArgs &a, const TileDesc &d, int lo_slot, int w0,
                                           const int *s_brow, const double *s_part, YOut<T> *out = nullptr) {
     const int lane = threadIdx.x & 63;
@@ -312,7 +313,6 @@ __device__ __forceinline__ void tile_sums(const SpmvArgs &a, const TileDesc &d, 
             // two partials per step, so their reads share one LDS round trip
             double a0 = 0.0, a1 = 0.0;
             int b = bs + l;
-            constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
             for (; b + L < be; b += 2 * L) {
                 const double *e0 = pp + ((b + lo_slot) * Sh::R + rho) * PPR;
                 const double *e1 = pp + ((b + L + lo_slot) * Sh::R + rho) * PPR;
@@ -380,9 +380,9 @@ __device__ __forceinline__ void y_flush(__amdgpu_buffer_rsrc_t yr, const YOut<T>
 
 // Registers holding one tile's small streams while their loads are in
 // flight (the packed values go straight to LDS).
-template <class Sh, class T, int KQ>
+template <class Sh, class T, int KQ, int NCR = WaveSmem<Sh, T, KQ>::NCR>
 struct TileIn {
-    int colr[WaveSmem<Sh, T, KQ>::NCR];
+    int colr[NCR];   // block columns of the slots of the tile's words, 64 per register
     int br[2];   // interval pointers lane and lane + 64 (a tile has up to 127 intervals)
     uint64_t m;  // lane j: the tile's mask word j (0 past the tile's words)
 };
@@ -390,8 +390,8 @@ struct TileIn {
 // Issues every stream of a tile as unguarded buffer loads: the block
 // columns and interval pointers into registers, then the packed values into
 // LDS (s_vals, chunk k of lane l at 16 (64 k + l) bytes).
-template <class Sh, class T, int KQ>
-__device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ> &in,
+template <class Sh, class T, int KQ, int NCR>
+__device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ, NCR> &in,
                                            T *s_vals) {
     using SM = WaveSmem<Sh, T, KQ>;
     constexpr int E = SM::E;
@@ -411,7 +411,7 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
     const int ncs = (int)(min<int64_t>((int64_t)(w0 + nw) * Sh::BPW, a.n_blocks) - cs0);
     const auto cr = rsrc(a.bcol + cs0, (uint32_t)ncs * 4u);
 #pragma unroll
-    for (int k = 0; k < SM::NCR; ++k)
+    for (int k = 0; k < NCR; ++k)
         in.colr[k] = __builtin_amdgcn_raw_buffer_load_b32(cr, (uint32_t)(lane * 4), 256 * k, kNT);
     const auto brr = rsrc(a.brow + d.i0, (uint32_t)(nI + 1) * 4u);
     in.br[0] = __builtin_amdgcn_raw_buffer_load_b32(brr, (uint32_t)(lane * 4), 0, 0);
@@ -514,6 +514,159 @@ __device__ __forceinline__ void wave_tile(const SpmvArgs &a, const TileDesc &d, 
     TileIn<Sh, T, KQ> in;
     tile_issue<Sh, T, KQ>(a, d, in, sm.buf);
     tile_run<Sh, T, KQ>(a, d, in, xr, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Block-row lanes (mode 3). Lane (s, rho) takes block row rho of slot s of
+// the tile's words and walks that block row's set bits one after another,
+// gathering x at the block's column plus the bit's column; the wavefront
+// takes as many steps as its fullest block row has bits, and the lane's sum
+// is that block row's one partial. Where block rows hold few of their C
+// entries this issues far fewer gathers than one lane per mask bit, so the
+// tiles are sized by values, not by mask bits: up to the (64 KQ - 1) E
+// values the LDS buffer holds, and up to NBX blocks (at most 64 mask words,
+// 4032 mask bits, and partials that fit the buffer). Everything else (the
+// streams, the interval pointers, the row sums) is mode 0's.
+template <class Sh, class T, int KQ>
+struct BrowSmem {
+    using W = WaveSmem<Sh, T, KQ>;
+    static constexpr int NS = 64 * Sh::BPW;              // slots of 64 mask words
+    static constexpr int NSR = NS / 64;                  // 64-lane rounds over the slots
+    static constexpr int NBR = NS * Sh::R / 64;          // 64-lane rounds over the block rows
+    static constexpr int VCAP = (64 * KQ - 1) * W::E;    // values of a tile (any alignment fits the buffer)
+    static constexpr int NPMAX = W::NBUF * (int)sizeof(T) / 8;   // partials the buffer holds
+    static constexpr int NBA = 4032 / Sh::RC;
+    static constexpr int NBB = NPMAX / Sh::R - Sh::BPW + 1;
+    static constexpr int NBX = NBA < NBB ? NBA : NBB;   // blocks of a tile
+    static_assert(NBX + Sh::BPW - 1 <= NS, "a tile's blocks fit 64 mask words");
+    W w;                    // values then partials, interval pointers, zero
+    uint2 slot[NS];         // per slot: mask bits (0 outside the tile's blocks), first value
+};
+
+// One block row's products, T = double: fused multiply-adds in double.
+// T = float: products and their sum in single precision, as mode 0 forms
+// them (no contraction into fused operations).
+template <class T, int C>
+__device__ __forceinline__ double block_row_sum(const T (&v)[C], const T (&xg)[C], int n) {
+    if constexpr (sizeof(T) == 8) {
+        double s = 0.0;
+#pragma unroll
+        for (int it = 0; it < C; ++it) {
+            if (it >= n) break;
+            s = __builtin_fma(v[it], xg[it], s);
+        }
+        return s;
+    } else {
+        float s = 0.f;
+#pragma unroll
+        for (int it = 0; it < C; ++it) {
+            if (it >= n) break;
+            s = __fadd_rn(s, __fmul_rn(v[it], xg[it]));
+        }
+        return (double)s;
+    }
+}
+
+template <class Sh, class T, int KQ>
+__device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ, Sh::BPW> &in,
+                         __amdgpu_buffer_rsrc_t xr, BrowSmem<Sh, T, KQ> &sm) {
+    using SM = BrowSmem<Sh, T, KQ>;
+    constexpr int E = SM::W::E;
+    constexpr int R = Sh::R, C = Sh::C, BPW = Sh::BPW;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / BPW;
+    const int lo_slot = b0 - w0 * BPW;
+    const int hi_slot = lo_slot + (b1 - b0);   // the tile's blocks are slots [lo_slot, hi_slot)
+    sm.w.brow[lane] = in.br[0] - b0;
+    sm.w.brow[lane + 64] = in.br[1] - b0;
+    if (lane < 2) sm.w.zero[lane] = 0.0;
+    wait_vm_all();   // the values have landed in LDS; the chunk past nnz is filled value by value
+    if (q_tail < nq && lane < E) {
+        const int64_t g = abase + (int64_t)q_tail * E + lane;
+        if (g < a.nnz) sm.w.buf[q_tail * E + lane] = vals[g];
+    }
+    if (b1 > b0) {
+        // A. lane = slot: its mask bits (from the lane holding its word) and
+        // its first value (a prefix over the slots' value counts)
+        const int mlo = (int)(uint32_t)in.m, mhi = (int)(uint32_t)(in.m >> 32);
+        int carry = 0;
+#pragma unroll
+        for (int k = 0; k < SM::NSR; ++k) {
+            if (64 * k >= hi_slot) break;
+            const int s = lane + 64 * k;
+            const int src = (s / BPW) * 4;   // word s / BPW < 64
+            const uint64_t w = ((uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(src, mhi) << 32) |
+                               (uint32_t)__builtin_amdgcn_ds_bpermute(src, mlo);
+            const bool mine = s >= lo_slot && s < hi_slot;
+            const uint32_t mk = mine ? (uint32_t)(w >> ((s % BPW) * Sh::RC)) & Sh::RCMASK : 0u;
+            const int pc = __popc(mk);
+            const int incl = wave_scan_dpp(pc);
+            sm.slot[s] = make_uint2(mk, (uint32_t)(carry + incl - pc));
+            carry += __builtin_amdgcn_readlane(incl, 63);
+        }
+        wave_sync();
+        // B. lane = block row: its set bits in turn, every gather issued
+        // before the first product; lanes out of bits gather nothing (an out
+        // of range offset reads 0) and read the zero in LDS. The slots of a
+        // round share one register of block columns (k / R).
+        const char *__restrict__ bb = reinterpret_cast<const char *>(sm.w.buf);
+        const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.w.zero) - bb);
+        const int hi_row = hi_slot * R;
+        double acc[SM::NBR];
+#pragma unroll
+        for (int k = 0; k < SM::NBR; ++k) {
+            if (64 * k >= hi_row) break;
+            const int br = lane + 64 * k;
+            const int s = br / R, rho = br % R;
+            const bool ok = s < hi_slot;
+            const uint2 si = sm.slot[ok ? s : 0];
+            const int col = __builtin_amdgcn_ds_bpermute((s % 64) * 4, in.colr[k / R]);
+            const uint32_t mk = ok ? si.x : 0u;
+            uint32_t rm = (mk >> (rho * C)) & Sh::CMASK;
+            const uint32_t voff = (uint32_t)shift + si.y + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
+            T xg[C], v[C];
+            int n = 0;   // steps taken: the most bits of any lane's block row (uniform)
+#pragma unroll
+            for (int it = 0; it < C; ++it) {
+                if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
+                const bool on = rm != 0u;
+                const int t = __builtin_ctz(rm | (1u << C));
+                xg[it] = buf_load<T>(xr, on ? (uint32_t)(col + t) * (uint32_t)sizeof(T) : 0xffffffffu);
+                v[it] = *reinterpret_cast<const T *>(bb + (on ? (voff + (uint32_t)it) * (uint32_t)sizeof(T) : zbyte));
+                rm &= rm - 1u;
+                n = it + 1;
+            }
+            acc[k] = block_row_sum<T, C>(v, xg, n);
+        }
+        wave_sync();  // all values are read before the partials overwrite them
+        double *__restrict__ part = reinterpret_cast<double *>(sm.w.buf);
+#pragma unroll
+        for (int k = 0; k < SM::NBR; ++k) {
+            if (64 * k >= hi_row) break;
+            const int br = lane + 64 * k;
+            if (br < hi_row) part[br] = acc[k];   // entry s R + rho
+        }
+    }
+    wave_sync();
+    tile_sums<Sh, T, false, 1>(a, d, lo_slot, w0, sm.w.brow, reinterpret_cast<const double *>(sm.w.buf));
+}
+
+// The host pass of this file never emits device code; the body is compiled
+// for the device only.
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void brow_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
+                                          BrowSmem<Sh, T, KQ> &sm) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    TileIn<Sh, T, KQ, Sh::BPW> in;
+    tile_issue<Sh, T, KQ>(a, d, in, sm.w.buf);
+    brow_run<Sh, T, KQ>(a, d, in, xr, sm);
+#endif
 }
 
 // The KQ 16-byte chunks of a wavefront's value range, lane l taking bytes
@@ -788,6 +941,27 @@ __global__ __launch_bounds__(kThreads) void k_spmv_wave(SpmvArgs a) {
     } else {
         const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
         wave_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+    }
+}
+
+// Mode 3: one block-row-lane tile per wavefront; an interval beyond a
+// tile's values or blocks takes mode 0's long path.
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_brow(SpmvArgs a) {
+    using Sh = Shape<R, C>;
+    using SM = BrowSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    if (d.b1 - d.b0 > SM::NBX || d.nv > SM::VCAP) {
+        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+    } else {
+        const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+        brow_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
     }
 }
 
@@ -1476,6 +1650,17 @@ spc_status launch_wave(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipS
     }
 }
 
+template <int R, int C, class T>
+spc_status launch_brow(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    const dim3 blk(kThreads);
+    switch (kq) {
+    case 2: return launch_capped(k_spmv_brow<R, C, T, 2>, cu_groups, grid, blk, stream, a);
+    case 6: return launch_capped(k_spmv_brow<R, C, T, 6>, cu_groups, grid, blk, stream, a);
+    case 8: return launch_capped(k_spmv_brow<R, C, T, 8>, cu_groups, grid, blk, stream, a);
+    default: return launch_capped(k_spmv_brow<R, C, T, 4>, cu_groups, grid, blk, stream, a);
+    }
+}
+
 }  // namespace
 
 spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
@@ -1569,6 +1754,23 @@ int test_tile_blocks(int shape, int dtype, int kq) {
 
 // Tile capacity in mask bits for a mode and a chunk count (mode 0) or the
 // workgroup tile size (mode 1).
+// Blocks a block-row-lane tile (mode 3) may hold.
+int brow_tile_blocks(int shape, int dtype, int kq) {
+    return with_shape(shape, [&](auto sh) {
+        using Sh = decltype(sh);
+        auto nb = [&](auto tv) -> int {
+            using T = decltype(tv);
+            switch (kq) {
+            case 2: return BrowSmem<Sh, T, 2>::NBX;
+            case 6: return BrowSmem<Sh, T, 6>::NBX;
+            case 8: return BrowSmem<Sh, T, 8>::NBX;
+            default: return BrowSmem<Sh, T, 4>::NBX;
+            }
+        };
+        return dtype == SPC_F64 ? nb(0.0) : nb(0.f);
+    });
+}
+
 int wave_tile_bits(int dtype, int kq) {
     const int E = dtype == SPC_F64 ? 2 : 4;
     return (64 * kq - 1) * E;
@@ -1598,8 +1800,8 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     const bool aligned = (reinterpret_cast<uintptr_t>(A->values) & 15u) == 0;
     const size_t es = A->dtype == SPC_F64 ? 8 : 4;
     const bool x32 = (uint64_t)A->n_cols * es < 0xf0000000ull;    // x addressed with 32-bit offsets
-    const bool wave = (P->mode == 0 || P->mode == 2) && aligned && x32;
-    const int wg_bits = P->mode == 1 ? P->tile_bits : (P->tile_bits <= 1024 ? 1024 : 2048);
+    const bool wave = P->mode != 1 && aligned && x32;
+    const int wg_bits = P->mode == 1 ? P->tile_bits : P->mode == 3 ? 4032 : (P->tile_bits <= 1024 ? 1024 : 2048);
     const bool pair = wave && P->mode == 0 && P->wave_tiles == 2 && !P->pipeline;
     const int64_t groups = wave ? div_up(pair ? div_up(P->n_tiles, 2) : P->n_tiles, kWaves) : P->n_tiles;
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
@@ -1615,6 +1817,7 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
         return with_dtype(A->dtype, [&](auto tv) {
             using T = decltype(tv);
             if (!wave) return launch_wg<Sh::R, Sh::C, T>(wg_bits, grid, a, stream);
+            if (P->mode == 3) return launch_brow<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
             if (pipe) return launch_wave_pipe<Sh::R, Sh::C, T>(P->kq, grid, a, stream);
             if (pair) return launch_wave2<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);
             return launch_wave<Sh::R, Sh::C, T>(P->kq, P->cu_groups, grid, a, stream);

@@ -80,6 +80,15 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
             cands.push_back(p);
         }
     }
+    for (int kq : {4, 6, 8}) {  // block-row lanes
+        for (int cap : {0, 4}) {
+            spc_plan_params p{};
+            p.mode = 3;
+            p.wave_chunks = kq;
+            p.cu_groups = cap;
+            cands.push_back(p);
+        }
+    }
     if (A->r * A->c == 8) {
         for (int kq : {2, 4, 6, 8}) {  // test tiles (Algorithm 2)
             spc_plan_params p{};

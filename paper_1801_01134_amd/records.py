@@ -8,7 +8,7 @@ record-based strategy): one polynomial per kernel of speed against Avg(r,c)
     features (spc_matrix_features), and for each of the six shapes the
     device conversion followed by the autotuner (spc_autotune: every plan
     candidate timed with HIP events); one JSON line per matrix with the best
-    time of each shape's own kernels (modes 0 and 1) and, for beta(1,8) and
+    time of each shape's own kernels (modes 0, 1 and 3) and, for beta(1,8) and
     beta(2,4), the best time of the test kernel of Algorithm 2 (mode 2);
   * fits the interpolation selector (spc_selector_fit_interp) and trains the
     network on the device (spc_mlp_standardizer / spc_mlp_targets /
@@ -125,7 +125,7 @@ def collect(first: int, count: int, out_path: str, reps: int = 5, workers: int =
                 for (r, c) in SHAPES:
                     B = b.csr_to_beta(r, c, rp, ci, vals, n_cols)
                     _, _, recs = b.autotune(B, reps=reps, x=x)
-                    # the shape's own kernels (modes 0 and 1) and, for the
+                    # the shape's own kernels (modes 0, 1 and 3) and, for the
                     # one-byte-mask shapes, the test kernel (mode 2: Algorithm 2)
                     # as a class of its own
                     plain = min((q for q in recs if q["mode"] != 2), key=lambda q: q["us"])

@@ -76,7 +76,8 @@ def test_plan_parameters_checked_on_the_host():
     h = ctypes.c_void_p()
     v = B.BetaView(2, 4, 1, 0, 8, 8, 16, 4, 4096, 8192, 16384, 32768)
     for bad in (dict(cu_groups=1), dict(cu_groups=9), dict(cu_groups=-1),
-                dict(mode=1, tile_bits=2048, cu_groups=2), dict(mode=3),
+                dict(mode=1, tile_bits=2048, cu_groups=2), dict(mode=4), dict(mode=-1),
+                dict(mode=3, wave_tiles=2), dict(mode=3, pipeline=1), dict(mode=3, wave_chunks=3),
                 dict(wave_chunks=5), dict(mode=1, tile_bits=1000), dict(pipeline=-1),
                 dict(mode=1, tile_bits=2048, pipeline=1), dict(tile_order=2), dict(tile_order=-1)):
         p = B.PlanParams(**bad)

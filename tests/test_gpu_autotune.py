@@ -44,7 +44,8 @@ def test_autotune_best_is_fastest_record_and_matches_oracle(name, rc, dtype):
     B = spc.csr_to_beta(r, c, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols)
     xd = torch.from_numpy(x).cuda()
     best, best_us, recs = spc.autotune(B, reps=3, x=xd)
-    assert len(recs) >= 26
+    assert len(recs) >= 32
+    assert sum(q["mode"] == 3 for q in recs) == 6
     keys = [_key({k: v for k, v in q.items() if k not in ("us", "n_tiles")}) for q in recs]
     assert len(set(keys)) == len(keys), "a candidate was timed twice"
     # the headline launch's plan is among the candidates
@@ -81,7 +82,7 @@ def test_records_collect_writes_complete_lines():
             assert rec["features"][8 + k] == pytest.approx(A.nnz / nb[k], rel=1e-6)
         assert len(rec["us"]) == 6 and all(t > 0 for t in rec["us"])
         assert rec["gflops"] == pytest.approx([2.0 * A.nnz / (t * 1e-6) / 1e9 for t in rec["us"]])
-        assert len(rec["params"]) == 6 and all(p["mode"] in (0, 1) for p in rec["params"])
+        assert len(rec["params"]) == 6 and all(p["mode"] in (0, 1, 3) for p in rec["params"])
         assert all(n > 0 for n in rec["n_tiles"])
         # the test kernels (Algorithm 2) of beta(1,8) and beta(2,4) as classes of their own
         assert len(rec["us_test"]) == 2 and all(t > 0 for t in rec["us_test"])

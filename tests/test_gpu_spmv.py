@@ -454,3 +454,114 @@ def test_two_tiles_per_wavefront_same_bits(rc, dtype, chunks):
         assert torch.equal(ya, yb), name
     y_ref, s_ref = oracle.csr_spmv(A, x)
     check_rows(y0.cpu().numpy().astype(np.float64), y_ref, s_ref, TOL[dtype], f"pair beta{rc}")
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("chunks", [2, 4, 6, 8])
+def test_block_row_lanes_parity(rc, dtype, chunks):
+    """Mode 3 (lane = block row, walking its set bits) on every case against
+    the oracle, y = A x and y += A x (rows without entries keep y), capped
+    and uncapped launches giving the same bits, and repeated calls
+    reproducing them."""
+    r, c = rc
+    say(f"[brow] beta{rc} {dtype} chunks={chunks}")
+    for name in CASES:
+        A = case(name).astype(NP[dtype])
+        x = synth.dense_vector(A.n_cols, 29, dtype=NP[dtype])
+        y_ref, s_ref = oracle.csr_spmv(A, x)
+        B = to_beta(A, r, c, dtype)
+        xd = torch.from_numpy(x).cuda()
+        P = B.plan(0, 0, 3, chunks)
+        assert P.info()["tile_bits"] == (64 * chunks - 1) * (16 // NP[dtype]().itemsize)
+        y = spc.spmv(B, xd, plan=P)
+        check_rows(y.cpu().numpy(), y_ref, s_ref, TOL[dtype], f"brow {name} beta{rc}")
+        assert torch.equal(spc.spmv(B, xd, plan=P), y), name
+        assert torch.equal(spc.spmv(B, xd, plan=B.plan(0, 1, 3, chunks, 0, 3)), y), name
+        y0 = synth.dense_vector(A.n_rows, 30, dtype=NP[dtype])
+        ya = spc.spmv(B, xd, torch.from_numpy(y0.copy()).cuda(), accumulate=True, plan=P).cpu().numpy()
+        check_rows(ya, y_ref + y0.astype(np.float64), s_ref + np.abs(y0.astype(np.float64)), TOL[dtype],
+                   f"brow {name} beta{rc} accumulate")
+        empty = A.row_lengths() == 0
+        assert np.array_equal(ya[empty], y0[empty])
+        if empty.any():
+            yh = y.cpu().numpy()
+            assert np.all(yh[empty] == 0) and not np.signbit(yh[empty]).any()
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_block_row_lanes_integers_and_nonfinite(rc, dtype):
+    """Mode 3: integer-valued inputs give exact sums; an Inf in x reaches
+    exactly the rows that store an entry in its column."""
+    r, c = rc
+    say(f"[brow-int] beta{rc} {dtype}")
+    A = synth.powerlaw(1500, 1500, seed=11)
+    A.values = np.round(A.values * 16)
+    x = np.round(synth.dense_vector(A.n_cols, 24) * 16)
+    y_ref, _ = oracle.csr_spmv(A, x)
+    B = to_beta(A.astype(NP[dtype]), r, c, dtype)
+    for chunks in (2, 8):
+        y = spc.spmv(B, torch.from_numpy(x.astype(NP[dtype])).cuda(), plan=B.plan(0, 0, 3, chunks))
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), y_ref)
+    S = synth.random_small(64, 64, 0.15, seed=12)
+    j = 9
+    xs = synth.dense_vector(64, 25)
+    xs[j] = np.inf
+    Bs = to_beta(S.astype(NP[dtype]), r, c, dtype)
+    ys = spc.spmv(Bs, torch.from_numpy(xs.astype(NP[dtype])).cuda(), plan=Bs.plan(0, 0, 3, 4)).cpu().numpy()
+    has_j = np.array([j in S.colidx[S.rowptr[i]:S.rowptr[i + 1]] for i in range(S.n_rows)])
+    assert np.all(np.isfinite(ys[~has_j])) and not np.any(np.isfinite(ys[has_j]))
+
+
+def test_block_row_lanes_refusals():
+    """Mode 3 takes neither two tiles per wavefront nor the pipeline; SpMM,
+    CG and batches refuse its plans; mode 4 does not exist."""
+    say("[brow-refuse]")
+    A = case("stencil13")
+    B = to_beta(A, 2, 4, torch.float64)
+    for bad in (dict(mode=3, wave_chunks=4, wave_tiles=2), dict(mode=3, wave_chunks=4, pipeline=1),
+                dict(mode=4, wave_chunks=4)):
+        with pytest.raises(spc.SpcError):
+            spc.plan_from(B, bad)
+    P = B.plan(0, 0, 3, 4)
+    X = torch.from_numpy(synth.dense_block(A.n_cols, 4, 31)).cuda()
+    with pytest.raises(spc.SpcError):
+        spc.spmm(B, X, plan=P)
+    with pytest.raises(spc.SpcError):
+        spc.cg(B, X, rel_tol=1e-6, max_iter=5, check_every=5, plan=P)
+    with pytest.raises(spc.SpcError):
+        spc.Batch([B], params=[dict(mode=3, wave_chunks=4)])
+
+
+@pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_block_row_lanes_tiles_and_unaligned_values(rc, dtype):
+    """Mode 3 tiles hold up to the buffer's values and the shape's block cap
+    (more blocks than a mode 0 tile where blocks are sparse); with values
+    that are not 16-byte aligned the same tiles run as 4032-bit workgroup
+    tiles, still matching the oracle."""
+    r, c = rc
+    say(f"[brow-tiles] beta{rc} {dtype}")
+    esz = NP[dtype]().itemsize
+    for name in ("stencil16", "uniform", "dense_rows", "diagonal"):
+        A = case(name).astype(NP[dtype])
+        x = synth.dense_vector(A.n_cols, 32, dtype=NP[dtype])
+        y_ref, s_ref = oracle.csr_spmv(A, x)
+        B = to_beta(A, r, c, dtype)
+        for chunks in (2, 8):
+            P3, P0 = B.plan(0, 0, 3, chunks), B.plan(0, 0, 0, chunks)
+            vcap = (64 * chunks - 1) * (16 // esz)
+            # value-sized tiles are never more numerous than bit-sized ones
+            assert P3.info()["n_tiles"] <= P0.info()["n_tiles"], name
+            assert P3.info()["tile_bits"] == vcap
+            y = spc.spmv(B, torch.from_numpy(x).cuda(), plan=P3).cpu().numpy()
+            check_rows(y, y_ref, s_ref, TOL[dtype], f"brow {name} chunks={chunks}")
+        buf = torch.empty(B.nnz + 1, dtype=dtype, device="cuda")
+        buf[1:] = B.values
+        Bu = to_beta(A, r, c, dtype)
+        Bu.values = buf[1:]
+        assert Bu.values.data_ptr() % 16 != 0
+        for chunks in (2, 8):
+            y = spc.spmv(Bu, torch.from_numpy(x).cuda(), plan=Bu.plan(0, 0, 3, chunks)).cpu().numpy()
+            check_rows(y, y_ref, s_ref, TOL[dtype], f"brow unaligned {name} chunks={chunks}")
