@@ -844,7 +844,8 @@ def run(args, pool, tmp, do_batched, do_cg, do_select):
     kname = ({0: f"k_spmv_wave{'_pipe' if params.get('pipeline') else ('2' if params.get('wave_tiles') == 2 else '')}"
                  f"<{r},{c},{tname},{params['wave_chunks'] or 4}>",
               2: f"k_spmv_test<{r},{c},{tname},{params['wave_chunks'] or 4}>",
-              3: f"k_spmv_brow<{r},{c},{tname},{params['wave_chunks'] or 4}>"}.get(
+              3: f"k_spmv_brow<{r},{c},{tname},{params['wave_chunks'] or 4}>",
+              4: f"k_spmv_vlane<{tname},{params['wave_chunks'] or 4}>"}.get(
                  params["mode"], f"k_spmv_wg<{r},{c},{tname},{info['tile_bits']}>"))
     for _ in range(args.warmup):
         spc.spmv(B, xd, yd, plan=P)

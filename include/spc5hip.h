@@ -193,11 +193,23 @@ spc_status spc_permute_vector(int64_t n, int32_t dtype, const int32_t *perm, con
  *              248 blocks (fewer with 2 chunks, or 4 chunks and FP64 for
  *              beta(2,4)), at most 64 of them with several values, and no
  *              more values than mode 0's tile (planning reads the masks once);
- *              3 = block-row lanes: mode 0's tiles and streams, but lane =
+ *              3 = block-row lanes: one wavefront per tile, lane =
  *              (block, block row): the lane walks that block row's set bits
  *              in turn, one x gather per stored value, and its sum is the
  *              block row's partial (mode 0 spends a lane per mask bit,
- *              stored or not)
+ *              stored or not). Tiles are sized by values: up to
+ *              (64 * wave_chunks - 1) * (16 / value size) values and at most
+ *              a per-shape block count (64 mask words, 4032 mask bits, and
+ *              partials that fit the tile's LDS buffer); planning reads the
+ *              masks once;
+ *              4 = value lanes (beta(1,8) only, else
+ *              SPC_ERR_UNSUPPORTED_SHAPE): mode 3's tiles; each block's
+ *              columns are written to LDS at its values' ranks, then one
+ *              lane per stored value gathers x and multiplies, and a row's
+ *              products (contiguous, one row per block) are added. FP32:
+ *              each product is rounded to float, the sums are in double.
+ *              Modes 3 and 4 with values that are not 16-byte aligned run
+ *              their tiles as 4032-bit workgroup tiles
  * params == NULL selects spc_plan_default_params(A); all zeros select mode 0
  * with 4 chunks per lane. */
 typedef struct spc_plan spc_plan;
@@ -207,16 +219,15 @@ typedef struct spc_plan_params {
     int32_t tile_bits;
     int32_t tile_order;     /* SPC_ORDER_XCD (0) or SPC_ORDER_HW (1) */
     int32_t mode;           /* 0 = wavefront tiles (default), 1 = workgroup tiles, 2 = test tiles,
-                               3 = block-row lanes: mode 0's tiles, with each lane taking one
-                               block row and walking its set bits (fewer gathers where block
-                               rows hold few entries; same bound on the results, its own order
-                               of additions) */
-    int32_t wave_chunks;    /* modes 0, 2 and 3: 16-byte value chunks per lane, 2, 4, 6 or 8; 0 = 4 */
+                               3 = block-row lanes, 4 = value lanes (beta(1,8)); see the plan
+                               notes above */
+    int32_t wave_chunks;    /* modes 0, 2, 3 and 4: 16-byte value chunks per lane, 2, 4, 6 or 8;
+                               0 = 4 */
     int32_t pipeline;       /* mode 0: 0 = one wavefront per tile; 1 = persistent wavefronts (as
                                many workgroups as fit on the device) that load their next tile
                                while working on the current one; N > 1 = the same with at most N
                                workgroups */
-    int32_t cu_groups;      /* modes 0, 2 and 3, launches that are not persistent and SpMM: 0 = as many
+    int32_t cu_groups;      /* modes 0, 2, 3 and 4, launches that are not persistent and SpMM: 0 = as many
                                workgroups per compute unit as fit; 2..8 = at most that many (the
                                launch reserves LDS to hold the others off). Fewer resident
                                wavefronts can keep more of the gathered rows of X in cache. */
@@ -252,7 +263,8 @@ spc_status spc_plan_info(const spc_plan *plan, int64_t *n_tiles, int64_t *n_long
  * Precision: FP64 forms every product and sum in double precision. FP32
  * forms each product, and the sum of the (at most c = 8) products of one
  * block row of one block, in single precision; those block-row sums are
- * added in double precision and the row is rounded to float once. The order
+ * added in double precision and the row is rounded to float once (plan
+ * mode 4: products in single precision, every sum in double). The order
  * of additions is fixed by the plan, so repeated calls give identical bits.
  * plan: from spc_plan_create on this same A; or NULL, in which case the call
  * builds a plan with spc_plan_default_params(A), runs the product and
@@ -324,8 +336,9 @@ spc_status spc_cg_solve(const spc_beta_view *A, const spc_plan *plan, int32_t k,
  *   pipelined, and with 4, 6 and 8 chunks also capped at 2 and 4 resident
  *   workgroups per compute unit; mode 1 with 1024, 2048, 3072 and 4032 tile
  *   bits; each in both tile orders where the grid order applies; mode 3
- *   with 4, 6 and 8 chunks, uncapped and capped at 4; for beta(1,8) and
- *   beta(2,4) also mode 2 with 2, 4, 6 and 8 chunks), times it
+ *   with 2, 4, 6 and 8 chunks; for beta(1,8) also mode 4 with 2, 4, 6 and
+ *   8 chunks; for beta(1,8) and beta(2,4) also mode 2 with 2, 4, 6 and 8
+ *   chunks), times it
  *   with spc_time_spmv and returns the fastest set in *best and its time in
  *   *best_us. If records is not NULL, up to max_records timings are written
  *   there (host memory) and *n_records says how many. x and y are scratch

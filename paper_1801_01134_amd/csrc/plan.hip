@@ -107,9 +107,11 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
                 "tile_order must be SPC_ORDER_XCD (0) or SPC_ORDER_HW (1)");
     const int xcd_remap = params->tile_order == SPC_ORDER_XCD;
     const int mode = params ? params->mode : 0;
-    SPC_REQUIRE(mode >= 0 && mode <= 3, SPC_ERR_INVALID_ARG, "mode must be 0, 1, 2 or 3");
+    SPC_REQUIRE(mode >= 0 && mode <= 4, SPC_ERR_INVALID_ARG, "mode must be 0, 1, 2, 3 or 4");
     SPC_REQUIRE(mode != 2 || (A->r * A->c == 8), SPC_ERR_UNSUPPORTED_SHAPE,
                 "mode 2 (test tiles) is for beta(1,8) and beta(2,4)");
+    SPC_REQUIRE(mode != 4 || (A->r == 1 && A->c == 8), SPC_ERR_UNSUPPORTED_SHAPE,
+                "mode 4 (value lanes) is for beta(1,8)");
     const int kq = params && params->wave_chunks ? params->wave_chunks : 4;
     const int pipeline = params ? params->pipeline : 0;
     SPC_REQUIRE(pipeline >= 0, SPC_ERR_INVALID_ARG, "pipeline must be >= 0");
@@ -123,7 +125,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
                 SPC_ERR_INVALID_ARG, "spmm_path must be 0, 1 or 2");
     SPC_REQUIRE(cu_groups == 0 || (cu_groups >= 2 && cu_groups <= 8), SPC_ERR_INVALID_ARG,
                 "cu_groups must be 0 or 2..8 (got %d)", cu_groups);
-    SPC_REQUIRE(!(cu_groups && mode == 1), SPC_ERR_INVALID_ARG, "cu_groups applies to modes 0, 2 and 3 only");
+    SPC_REQUIRE(!(cu_groups && mode == 1), SPC_ERR_INVALID_ARG, "cu_groups applies to modes 0, 2, 3 and 4 only");
     SPC_REQUIRE(!(pipeline && mode != 0), SPC_ERR_INVALID_ARG, "pipeline applies to mode 0 only");
     SPC_REQUIRE(kq == 2 || kq == 4 || kq == 6 || kq == 8, SPC_ERR_INVALID_ARG,
                 "wave_chunks must be 2, 4, 6 or 8");
@@ -152,10 +154,10 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
     std::vector<TileDesc> tiles;
     tiles.reserve((size_t)(A->n_blocks / (target ? target : 1) + n_int / max_int + 2));
     int64_t n_long = 0;
-    // Test tiles (mode 2) and block-row-lane tiles (mode 3) are planned on
+    // Test tiles (mode 2), block-row-lane and value-lane tiles (modes 3, 4) are planned on
     // each interval's value count (and count of blocks with several values)
     std::vector<int32_t> hv, hm;
-    if ((mode == 2 || mode == 3) && n_int > 0) {
+    if (mode >= 2 && n_int > 0) {
         hv.resize((size_t)n_int);
         hm.resize((size_t)n_int);
         DevBuf dv, dm;
@@ -207,8 +209,8 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
             tiles.push_back({0, (int32_t)start, (int32_t)i, brow[start], brow[i], 0, 0});
         }
     }
-    if (mode == 3 && n_int > 0) {
-        // block-row-lane tiles: up to the buffer's values and NBX blocks; an
+    if ((mode == 3 || mode == 4) && n_int > 0) {
+        // block-row-lane and value-lane tiles: up to the buffer's values and NBX blocks; an
         // interval beyond either becomes a tile of its own on the long path
         // (the kernel tells it by the same two counts)
         const int64_t nbx = brow_tile_blocks(shape, A->dtype, kq);
@@ -233,7 +235,7 @@ extern "C" spc_status spc_plan_create(const spc_beta_view *A, const spc_plan_par
             tiles.push_back({0, (int32_t)start, (int32_t)i, brow[start], brow[i], 0, 0});
         }
     }
-    for (int64_t i = (mode == 2 || mode == 3) ? n_int : 0; i < n_int;) {
+    for (int64_t i = mode >= 2 ? n_int : 0; i < n_int;) {
         const int64_t nb = brow[i + 1] - brow[i];
         if (nb > target) {
             tiles.push_back({0, (int32_t)i, (int32_t)(i + 1), brow[i], brow[i + 1], 0, 0});

@@ -29,6 +29,8 @@
 // An interval with more blocks than a tile holds gets a tile of its own and
 // the long path: each lane keeps a running sum for its block row over many
 // words, and the sums of lanes of the same block row are combined at the end.
+#include <type_traits>
+
 #include "common.hpp"
 #include "wave_common.hpp"
 
@@ -539,8 +541,28 @@ struct BrowSmem {
     static constexpr int NBB = NPMAX / Sh::R - Sh::BPW + 1;
     static constexpr int NBX = NBA < NBB ? NBA : NBB;   // blocks of a tile
     static_assert(NBX + Sh::BPW - 1 <= NS, "a tile's blocks fit 64 mask words");
+    // per slot: mask bits (0 outside the tile's blocks) and first value, one
+    // word (bits, then first << RC) where the mask has at most 16 bits
+    static constexpr bool PACK = Sh::RC <= 16;
+    static_assert(!PACK || VCAP < (1 << (32 - Sh::RC)), "a first value fits above the mask bits");
+    using SlotT = std::conditional_t<PACK, uint32_t, uint2>;
     W w;                    // values then partials, interval pointers, zero
-    uint2 slot[NS];         // per slot: mask bits (0 outside the tile's blocks), first value
+    SlotT slot[NS];
+    __device__ __forceinline__ void put(int s, uint32_t mk, int first) {
+        if constexpr (PACK) slot[s] = mk | ((uint32_t)first << Sh::RC);
+        else slot[s] = make_uint2(mk, (uint32_t)first);
+    }
+    __device__ __forceinline__ void get(int s, uint32_t &mk, uint32_t &first) const {
+        if constexpr (PACK) {
+            const uint32_t e = slot[s];
+            mk = e & Sh::RCMASK;
+            first = e >> Sh::RC;
+        } else {
+            const uint2 e = slot[s];
+            mk = e.x;
+            first = e.y;
+        }
+    }
 };
 
 // One block row's products, T = double: fused multiply-adds in double.
@@ -607,7 +629,7 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
             const uint32_t mk = mine ? (uint32_t)(w >> ((s % BPW) * Sh::RC)) & Sh::RCMASK : 0u;
             const int pc = __popc(mk);
             const int incl = wave_scan_dpp(pc);
-            sm.slot[s] = make_uint2(mk, (uint32_t)(carry + incl - pc));
+            sm.put(s, mk, carry + incl - pc);
             carry += __builtin_amdgcn_readlane(incl, 63);
         }
         wave_sync();
@@ -625,11 +647,12 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
             const int br = lane + 64 * k;
             const int s = br / R, rho = br % R;
             const bool ok = s < hi_slot;
-            const uint2 si = sm.slot[ok ? s : 0];
+            uint32_t mk, first;
+            sm.get(ok ? s : 0, mk, first);
             const int col = __builtin_amdgcn_ds_bpermute((s % 64) * 4, in.colr[k / R]);
-            const uint32_t mk = ok ? si.x : 0u;
+            mk = ok ? mk : 0u;
             uint32_t rm = (mk >> (rho * C)) & Sh::CMASK;
-            const uint32_t voff = (uint32_t)shift + si.y + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
+            const uint32_t voff = (uint32_t)shift + first + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
             T xg[C], v[C];
             int n = 0;   // steps taken: the most bits of any lane's block row (uniform)
 #pragma unroll
@@ -666,6 +689,156 @@ __device__ __forceinline__ void brow_tile(const SpmvArgs &a, const TileDesc &d, 
     TileIn<Sh, T, KQ, Sh::BPW> in;
     tile_issue<Sh, T, KQ>(a, d, in, sm.w.buf);
     brow_run<Sh, T, KQ>(a, d, in, xr, sm);
+#endif
+}
+
+// ---------------------------------------------------------------------------
+// Value lanes (mode 4, beta(1,8)): the tiles of mode 3, with one lane per
+// stored value. With one row per block, the values of a row are contiguous
+// in the packed array, so the product pass needs only each value's column:
+//   A. lane = slot: its mask byte, its first value (a prefix over the
+//      slots' value counts), then its columns, written to LDS at the ranks
+//      of its values (as many steps as the fullest block has values);
+//   B. lane = value: column and value from LDS, one x gather, the product
+//      replacing the value in LDS (FP32: the product rounded to float);
+//   C. L lanes per row add the row's contiguous products in double and
+//      combine their sums with shuffles.
+// Every lane of the gather pass holds a stored value, and the lanes of one
+// block read neighbouring x entries in the same instruction.
+template <class Sh, class T, int KQ>
+struct VlaneSmem {
+    static_assert(Sh::R == 1, "value lanes need one row per block");
+    using B = BrowSmem<Sh, T, KQ>;
+    static constexpr int NS = B::NS, NSR = B::NSR, VCAP = B::VCAP, NBX = B::NBX;
+    static constexpr int NVR = (VCAP + 63) / 64;   // 64-lane rounds over a tile's values
+    typename B::W w;        // values, then products; interval pointers; zero
+    static_assert(VCAP < 65536, "first values fit 16 bits");
+    uint16_t first[NS];     // first value of each slot (tile-relative)
+    int col[VCAP];          // column of each value
+};
+
+template <class Sh, class T, int KQ>
+__device__ void vlane_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ, Sh::BPW> &in,
+                          __amdgpu_buffer_rsrc_t xr, VlaneSmem<Sh, T, KQ> &sm) {
+    using SM = VlaneSmem<Sh, T, KQ>;
+    constexpr int E = SM::B::W::E;
+    constexpr int BPW = Sh::BPW;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / BPW;
+    const int lo_slot = b0 - w0 * BPW;
+    const int nb = b1 - b0;
+    const int hi_slot = lo_slot + nb;
+    sm.w.brow[lane] = in.br[0] - b0;
+    sm.w.brow[lane + 64] = in.br[1] - b0;
+    wait_vm_all();   // the values have landed in LDS; the chunk past nnz is filled value by value
+    if (q_tail < nq && lane < E) {
+        const int64_t g = abase + (int64_t)q_tail * E + lane;
+        if (g < a.nnz) sm.w.buf[q_tail * E + lane] = vals[g];
+    }
+    if (nb > 0) {
+        // A. lane = slot: mask byte, first value, then its columns by rank
+        const int mlo = (int)(uint32_t)in.m, mhi = (int)(uint32_t)(in.m >> 32);
+        int carry = 0;
+#pragma unroll
+        for (int k = 0; k < SM::NSR; ++k) {
+            if (64 * k >= hi_slot) break;
+            const int s = lane + 64 * k;
+            const int src = (s / BPW) * 4;
+            const uint64_t w = ((uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(src, mhi) << 32) |
+                               (uint32_t)__builtin_amdgcn_ds_bpermute(src, mlo);
+            const bool mine = s >= lo_slot && s < hi_slot;
+            uint32_t rm = mine ? (uint32_t)(w >> ((s % BPW) * Sh::RC)) & Sh::RCMASK : 0u;
+            const int pc = __popc(rm);
+            const int incl = wave_scan_dpp(pc);
+            const int first = carry + incl - pc;
+            sm.first[s] = (uint16_t)first;
+            carry += __builtin_amdgcn_readlane(incl, 63);
+            const int col0 = in.colr[k];
+#pragma unroll
+            for (int it = 0; it < Sh::C; ++it) {
+                if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
+                if (rm != 0u) sm.col[first + it] = col0 + __builtin_ctz(rm);
+                rm &= rm - 1u;
+            }
+        }
+        wave_sync();
+        // B. lane = value, eight rounds of gathers in flight at a time
+        T *__restrict__ vb = sm.w.buf + shift;
+        constexpr int U = 8;
+#pragma unroll
+        for (int q0 = 0; q0 < SM::NVR; q0 += U) {
+            if (64 * q0 >= nv) break;
+            T xg[U], vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int v = lane + 64 * (q0 + u);
+                const bool on = q0 + u < SM::NVR && v < nv;
+                const int c = sm.col[on ? v : 0];
+                xg[u] = buf_load<T>(xr, on ? (uint32_t)c * (uint32_t)sizeof(T) : 0xffffffffu);
+                vv[u] = on ? vb[v] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int v = lane + 64 * (q0 + u);
+                if (q0 + u < SM::NVR && v < nv) vb[v] = vv[u] * xg[u];
+            }
+        }
+        wave_sync();
+    }
+    // C. row sums: L lanes per row (the largest L with rows * L <= 64; with
+    // more than 64 rows a lane takes rows lane and lane + 64)
+    const int nI = d.i1 - d.i0;
+    const int lg = nI > 64 ? 0 : nI > 1 ? __builtin_clz((unsigned)(nI - 1)) - 26 : 6;
+    const int L = 1 << lg;
+    const int l = lane & (L - 1);
+    const T *__restrict__ pb = sm.w.buf + shift;
+    for (int round = 0; round < 2; ++round) {
+        if (round == 1 && nI <= 64) break;
+        const int li = (lane >> lg) + 64 * round;
+        double acc = 0.0;
+        bool stored = false;
+        if (li < nI) {
+            const int bs = sm.w.brow[li], be = sm.w.brow[li + 1];   // tile-relative blocks
+            stored = be > bs;   // every block holds at least one value
+            const int vs = bs < nb ? sm.first[bs + lo_slot] : nv;
+            const int ve = be < nb ? sm.first[be + lo_slot] : nv;
+            double a0 = 0.0, a1 = 0.0;
+            int v = vs + l;
+            for (; v + L < ve; v += 2 * L) {
+                a0 += (double)pb[v];
+                a1 += (double)pb[v + L];
+            }
+            if (v < ve) a0 += (double)pb[v];
+            acc = a0 + a1;
+        }
+        acc = group_sum(acc, lg);
+        if (li < nI && l == 0) {
+            const int64_t row = (int64_t)d.i0 + li;
+            if (row < a.n_rows) {
+                T *__restrict__ y = static_cast<T *>(a.y);
+                if (a.accumulate) {
+                    if (stored) y[row] = (T)(acc + (double)y[row]);
+                } else {
+                    y[row] = (T)acc;
+                }
+            }
+        }
+    }
+}
+
+template <class Sh, class T, int KQ>
+__device__ __forceinline__ void vlane_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
+                                           VlaneSmem<Sh, T, KQ> &sm) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    TileIn<Sh, T, KQ, Sh::BPW> in;
+    tile_issue<Sh, T, KQ>(a, d, in, sm.w.buf);
+    vlane_run<Sh, T, KQ>(a, d, in, xr, sm);
 #endif
 }
 
@@ -962,6 +1135,27 @@ __global__ __launch_bounds__(kThreads) void k_spmv_brow(SpmvArgs a) {
     } else {
         const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
         brow_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
+    }
+}
+
+// Mode 4: one value-lane tile per wavefront (beta(1,8)); an interval beyond
+// a tile's values or blocks takes mode 0's long path.
+template <class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_vlane(SpmvArgs a) {
+    using Sh = Shape<1, 8>;
+    using SM = VlaneSmem<Sh, T, KQ>;
+    __shared__ SM sm[kWaves];
+    int g = blockIdx.x;
+    if (a.xcd_remap) g = (int)(blockIdx.x & 7u) * a.tiles_per_xcd + (int)(blockIdx.x >> 3);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = g * kWaves + wid;
+    if (t >= a.n_tiles) return;
+    const TileDesc d = a.tiles[t];
+    if (d.b1 - d.b0 > SM::NBX || d.nv > SM::VCAP) {
+        wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+    } else {
+        const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+        vlane_tile<Sh, T, KQ>(a, d, xr, sm[wid]);
     }
 }
 
@@ -1661,6 +1855,17 @@ spc_status launch_brow(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipS
     }
 }
 
+template <class T>
+spc_status launch_vlane(int kq, int cu_groups, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
+    const dim3 blk(kThreads);
+    switch (kq) {
+    case 2: return launch_capped(k_spmv_vlane<T, 2>, cu_groups, grid, blk, stream, a);
+    case 6: return launch_capped(k_spmv_vlane<T, 6>, cu_groups, grid, blk, stream, a);
+    case 8: return launch_capped(k_spmv_vlane<T, 8>, cu_groups, grid, blk, stream, a);
+    default: return launch_capped(k_spmv_vlane<T, 4>, cu_groups, grid, blk, stream, a);
+    }
+}
+
 }  // namespace
 
 spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
@@ -1801,7 +2006,9 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
     const size_t es = A->dtype == SPC_F64 ? 8 : 4;
     const bool x32 = (uint64_t)A->n_cols * es < 0xf0000000ull;    // x addressed with 32-bit offsets
     const bool wave = P->mode != 1 && aligned && x32;
-    const int wg_bits = P->mode == 1 ? P->tile_bits : P->mode == 3 ? 4032 : (P->tile_bits <= 1024 ? 1024 : 2048);
+    const int wg_bits = P->mode == 1                   ? P->tile_bits
+                        : (P->mode == 3 || P->mode == 4) ? 4032
+                                                         : (P->tile_bits <= 1024 ? 1024 : 2048);
     const bool pair = wave && P->mode == 0 && P->wave_tiles == 2 && !P->pipeline;
     const int64_t groups = wave ? div_up(pair ? div_up(P->n_tiles, 2) : P->n_tiles, kWaves) : P->n_tiles;
     a.tiles_per_xcd = (int32_t)div_up(groups, 8);
@@ -1812,6 +2019,9 @@ spc_status spmv_launch(const spc_beta_view *A, const spc_plan *P, const void *x,
                       (uint64_t)A->n_rows * es < 0xf0000000ull;
     if (pipe) grid = dim3((unsigned)(groups < P->resident ? groups : (int64_t)P->resident));
     if (wave && P->mode == 2) return launch_test_shape(P->shape, A->dtype, P->kq, P->cu_groups, grid, a, stream);
+    if (wave && P->mode == 4)
+        return A->dtype == SPC_F64 ? launch_vlane<double>(P->kq, P->cu_groups, grid, a, stream)
+                                   : launch_vlane<float>(P->kq, P->cu_groups, grid, a, stream);
     return with_shape(P->shape, [&](auto sh) {
         using Sh = decltype(sh);
         return with_dtype(A->dtype, [&](auto tv) {

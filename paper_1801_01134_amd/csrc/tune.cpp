@@ -80,12 +80,14 @@ extern "C" spc_status spc_autotune(const spc_beta_view *A, const void *x, void *
             cands.push_back(p);
         }
     }
-    for (int kq : {4, 6, 8}) {  // block-row lanes
-        for (int cap : {0, 4}) {
+    // block-row lanes, and for beta(1,8) value lanes: their tiles are sized
+    // by values, so small chunk counts already fill them
+    for (int mode : {3, 4}) {
+        if (mode == 4 && !(A->r == 1 && A->c == 8)) continue;
+        for (int kq : {2, 4, 6, 8}) {
             spc_plan_params p{};
-            p.mode = 3;
+            p.mode = mode;
             p.wave_chunks = kq;
-            p.cu_groups = cap;
             cands.push_back(p);
         }
     }

@@ -76,13 +76,17 @@ def test_plan_parameters_checked_on_the_host():
     h = ctypes.c_void_p()
     v = B.BetaView(2, 4, 1, 0, 8, 8, 16, 4, 4096, 8192, 16384, 32768)
     for bad in (dict(cu_groups=1), dict(cu_groups=9), dict(cu_groups=-1),
-                dict(mode=1, tile_bits=2048, cu_groups=2), dict(mode=4), dict(mode=-1),
+                dict(mode=1, tile_bits=2048, cu_groups=2), dict(mode=5), dict(mode=-1),
                 dict(mode=3, wave_tiles=2), dict(mode=3, pipeline=1), dict(mode=3, wave_chunks=3),
                 dict(wave_chunks=5), dict(mode=1, tile_bits=1000), dict(pipeline=-1),
                 dict(mode=1, tile_bits=2048, pipeline=1), dict(tile_order=2), dict(tile_order=-1)):
         p = B.PlanParams(**bad)
         assert L.spc_plan_create(ctypes.byref(v), ctypes.byref(p), ctypes.byref(h), None) == -1, bad
         assert not h.value
+    # value lanes exist for beta(1,8) only
+    p = B.PlanParams(mode=4)
+    assert L.spc_plan_create(ctypes.byref(v), ctypes.byref(p), ctypes.byref(h), None) == -2
+    assert not h.value
 
 
 def test_kernel_classes_and_output_counts_on_the_host():

@@ -44,8 +44,9 @@ def test_autotune_best_is_fastest_record_and_matches_oracle(name, rc, dtype):
     B = spc.csr_to_beta(r, c, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols)
     xd = torch.from_numpy(x).cuda()
     best, best_us, recs = spc.autotune(B, reps=3, x=xd)
-    assert len(recs) >= 32
-    assert sum(q["mode"] == 3 for q in recs) == 6
+    assert len(recs) >= 30
+    assert sum(q["mode"] == 3 for q in recs) == 4
+    assert sum(q["mode"] == 4 for q in recs) == (4 if rc == (1, 8) else 0)
     keys = [_key({k: v for k, v in q.items() if k not in ("us", "n_tiles")}) for q in recs]
     assert len(set(keys)) == len(keys), "a candidate was timed twice"
     # the headline launch's plan is among the candidates

@@ -5,7 +5,8 @@ on the host), so these compare all outputs, not a sample:
   * the 27-point stencil of the 128^3 grid (2,097,152 rows, 55,742,968
     nonzeros) in all six shapes, FP64 and FP32, under every plan the
     autotuner may pick (the headline launch among them: 8 chunks per lane,
-    capped at 4 resident workgroups per compute unit; block-row lanes too),
+    capped at 4 resident workgroups per compute unit; block-row and value
+    lanes too),
     and the library's default plan;
   * Y = A X on the SPD 27-point matrix of the 192^3 grid (7,077,888 rows,
     189,119,224 nonzeros) with k = 16 in FP64 and FP32 under the plans the
@@ -80,6 +81,8 @@ def test_stencil128_all_rows_all_plans(rc, dtype):
     if rc in ((1, 8), (2, 4)):
         plans += [dict(mode=2, wave_chunks=q) for q in (4, 8)]
     plans += [dict(mode=3, wave_chunks=q, cu_groups=cap) for q in (4, 6, 8) for cap in (0, 4)]
+    if rc == (1, 8):
+        plans += [dict(mode=4, wave_chunks=q, cu_groups=cap) for q in (4, 6, 8) for cap in (0, 4)]
     plans += [dict(mode=0, wave_chunks=q, pipeline=1) for q in (2, 4, 6, 8)]
     plans += [dict(mode=1, tile_bits=tb, tile_order=o) for tb in (1024, 4032) for o in (0, 1)]
     plans += [B.default_params()]

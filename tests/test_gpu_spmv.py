@@ -565,3 +565,71 @@ def test_block_row_lanes_tiles_and_unaligned_values(rc, dtype):
         for chunks in (2, 8):
             y = spc.spmv(Bu, torch.from_numpy(x).cuda(), plan=Bu.plan(0, 0, 3, chunks)).cpu().numpy()
             check_rows(y, y_ref, s_ref, TOL[dtype], f"brow unaligned {name} chunks={chunks}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("chunks", [2, 4, 6, 8])
+def test_value_lanes_parity(dtype, chunks):
+    """Mode 4 (beta(1,8), one lane per stored value) on every case against
+    the oracle: y = A x and y += A x (rows without entries keep y), capped
+    launches, repeated calls giving the same bits, the same tiles as mode 3,
+    and values that are not 16-byte aligned (4032-bit workgroup tiles)."""
+    say(f"[vlane] {dtype} chunks={chunks}")
+    for name in CASES:
+        A = case(name).astype(NP[dtype])
+        x = synth.dense_vector(A.n_cols, 33, dtype=NP[dtype])
+        y_ref, s_ref = oracle.csr_spmv(A, x)
+        B = to_beta(A, 1, 8, dtype)
+        xd = torch.from_numpy(x).cuda()
+        P = B.plan(0, 0, 4, chunks)
+        assert P.info()["n_tiles"] == B.plan(0, 0, 3, chunks).info()["n_tiles"]
+        y = spc.spmv(B, xd, plan=P)
+        check_rows(y.cpu().numpy(), y_ref, s_ref, TOL[dtype], f"vlane {name}")
+        assert torch.equal(spc.spmv(B, xd, plan=P), y), name
+        assert torch.equal(spc.spmv(B, xd, plan=B.plan(0, 1, 4, chunks, 0, 3)), y), name
+        y0 = synth.dense_vector(A.n_rows, 34, dtype=NP[dtype])
+        ya = spc.spmv(B, xd, torch.from_numpy(y0.copy()).cuda(), accumulate=True, plan=P).cpu().numpy()
+        check_rows(ya, y_ref + y0.astype(np.float64), s_ref + np.abs(y0.astype(np.float64)), TOL[dtype],
+                   f"vlane {name} accumulate")
+        empty = A.row_lengths() == 0
+        assert np.array_equal(ya[empty], y0[empty])
+        if empty.any():
+            yh = y.cpu().numpy()
+            assert np.all(yh[empty] == 0) and not np.signbit(yh[empty]).any()
+        if name in ("stencil16", "dense_rows", "powerlaw"):
+            buf = torch.empty(B.nnz + 1, dtype=dtype, device="cuda")
+            buf[1:] = B.values
+            Bu = to_beta(A, 1, 8, dtype)
+            Bu.values = buf[1:]
+            yu = spc.spmv(Bu, xd, plan=Bu.plan(0, 0, 4, chunks)).cpu().numpy()
+            check_rows(yu, y_ref, s_ref, TOL[dtype], f"vlane unaligned {name}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_value_lanes_integers_nonfinite_and_shapes(dtype):
+    """Mode 4: integer-valued inputs give exact sums; an Inf in x reaches
+    exactly the rows that store an entry in its column; shapes other than
+    beta(1,8) are refused."""
+    say(f"[vlane-int] {dtype}")
+    A = synth.powerlaw(1500, 1500, seed=11)
+    A.values = np.round(A.values * 16)
+    x = np.round(synth.dense_vector(A.n_cols, 24) * 16)
+    y_ref, _ = oracle.csr_spmv(A, x)
+    B = to_beta(A.astype(NP[dtype]), 1, 8, dtype)
+    for chunks in (2, 8):
+        y = spc.spmv(B, torch.from_numpy(x.astype(NP[dtype])).cuda(), plan=B.plan(0, 0, 4, chunks))
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), y_ref)
+    S = synth.random_small(64, 64, 0.15, seed=12)
+    j = 9
+    xs = synth.dense_vector(64, 25)
+    xs[j] = np.inf
+    Bs = to_beta(S.astype(NP[dtype]), 1, 8, dtype)
+    ys = spc.spmv(Bs, torch.from_numpy(xs.astype(NP[dtype])).cuda(), plan=Bs.plan(0, 0, 4, 4)).cpu().numpy()
+    has_j = np.array([j in S.colidx[S.rowptr[i]:S.rowptr[i + 1]] for i in range(S.n_rows)])
+    assert np.all(np.isfinite(ys[~has_j])) and not np.any(np.isfinite(ys[has_j]))
+    for (r, c) in spc.SHAPES[1:]:
+        Bo = to_beta(S.astype(NP[dtype]), r, c, dtype)
+        with pytest.raises(spc.SpcError):
+            Bo.plan(0, 0, 4, 4)
+    with pytest.raises(spc.SpcError):
+        spc.plan_from(Bs, dict(mode=4, wave_chunks=4, wave_tiles=2))
