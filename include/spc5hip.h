@@ -361,8 +361,9 @@ spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t 
  * of uneven sizes and any of the six shapes. Each matrix is partitioned as
  * spc_plan_create would (whole intervals, about equal blocks per tile,
  * section "Parallelization") with its own parameters: mode 0 (wavefront
- * tiles) or, for beta(1,8) and beta(2,4), mode 2 (the test tiles of
- * Algorithm 2), and its own wave_chunks. Matrices of one (mode, shape,
+ * tiles), mode 3 (block-row lanes), for beta(1,8) mode 4 (value lanes), or
+ * for beta(1,8) and beta(2,4) mode 2 (the test tiles of Algorithm 2), and
+ * its own wave_chunks. Matrices of one (mode, shape,
  * chunk count) form a group; a product is one launch per group, of a kernel
  * built for that group, over the tiles of all its matrices.
  *
@@ -370,8 +371,9 @@ spc_status spc_autotune(const spc_beta_view *A, const void *x, void *y, int32_t 
  *   values 16-byte aligned, x of each under 3.75 GiB, count < 2^29);
  *   params (host) with n_params = 0 (params unused: each matrix takes
  *   spc_plan_default_params), 1 (params[0] for every matrix) or count
- *   (params[i] for matrix i). Each set used must have mode 0 or 2 (2 only
- *   for the one-byte-mask shapes), pipeline 0 and wave_tiles 0 or 1; its
+ *   (params[i] for matrix i). Each set used must have mode 0, 2, 3 or 4
+ *   (2 only for the one-byte-mask shapes, 4 only for beta(1,8)), pipeline 0
+ *   and wave_tiles 0 or 1; its
  *   tile_order and cu_groups are not used. The batch keeps the views: their
  *   arrays must stay alive and unchanged. Synchronizes.
  * spc_batch_set_vectors: xs, ys = host arrays of count device pointers (x_i

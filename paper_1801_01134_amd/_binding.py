@@ -732,8 +732,8 @@ class Batch:
 
     params: None (each matrix's default parameters), one dict for all
     matrices, or a list of one dict per matrix (keys as plan_from takes;
-    mode 0 or 2). wave_chunks alone gives every matrix mode 0 with that
-    chunk count."""
+    mode 0, 2, 3 or 4). wave_chunks alone gives every matrix mode 0 with
+    that chunk count."""
 
     def __init__(self, mats: list, wave_chunks: int | None = None, params=None):
         if not mats:

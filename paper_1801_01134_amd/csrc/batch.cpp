@@ -1,8 +1,9 @@
 // Batches: y_i = A_i x_i for many beta(r,c) matrices of uneven size and
 // different shapes. Each matrix gets its own plan (the partition of the
 // section "Parallelization": whole intervals, about equal blocks per tile),
-// in mode 0 (wavefront tiles) or, for beta(1,8) and beta(2,4), mode 2 (the
-// test tiles of Algorithm 2), with its own chunk count. The matrices are
+// in mode 0 (wavefront tiles), mode 3 (block-row lanes), for beta(1,8) mode
+// 4 (value lanes), or for beta(1,8) and beta(2,4) mode 2 (the test tiles of
+// Algorithm 2), with its own chunk count. The matrices are
 // grouped by (shape, mode, chunks); the tiles of a group are concatenated,
 // each tagged with its matrix, and one kernel built for that group runs the
 // group's whole list. A batch is therefore one launch per group present
@@ -63,10 +64,12 @@ void release(spc_batch *b) {
 }
 
 spc_status check_batch_params(const spc_plan_params &p, const spc_beta_view &v, int i) {
-    SPC_REQUIRE(p.mode == 0 || p.mode == 2, SPC_ERR_INVALID_ARG,
-                "matrix %d: batches run wavefront tiles (mode 0) or test tiles (mode 2), got mode %d", i, p.mode);
+    SPC_REQUIRE(p.mode == 0 || p.mode == 2 || p.mode == 3 || p.mode == 4, SPC_ERR_INVALID_ARG,
+                "matrix %d: batches run wavefront tiles (modes 0, 2, 3 and 4), got mode %d", i, p.mode);
     SPC_REQUIRE(p.mode != 2 || (v.r * v.c == 8), SPC_ERR_UNSUPPORTED_SHAPE,
                 "matrix %d: test tiles are for beta(1,8) and beta(2,4)", i);
+    SPC_REQUIRE(p.mode != 4 || (v.r == 1 && v.c == 8), SPC_ERR_UNSUPPORTED_SHAPE,
+                "matrix %d: value lanes are for beta(1,8)", i);
     SPC_REQUIRE(p.pipeline == 0 && p.wave_tiles <= 1, SPC_ERR_INVALID_ARG,
                 "matrix %d: batches run one tile per wavefront (pipeline 0, wave_tiles 0 or 1)", i);
     return SPC_OK;
@@ -80,10 +83,12 @@ spc_status launch_all(spc_batch *b, int accumulate, int grid_blocks, hipStream_t
                               -1, stream);
     for (const BatchGroup &g : b->groups) {
         const spc_status st =
-            g.mode == 2 ? batched_launch_test(b->dtype, g.shape, g.kq, b->d_mats, b->d_tiles + g.off, g.n, accumulate,
-                                              grid_blocks, stream)
-                        : batched_launch(b->dtype, g.kq, b->d_mats, b->d_tiles + g.off, g.n, accumulate, grid_blocks,
-                                         g.shape, stream);
+            g.mode == 2   ? batched_launch_test(b->dtype, g.shape, g.kq, b->d_mats, b->d_tiles + g.off, g.n,
+                                                accumulate, grid_blocks, stream)
+            : g.mode >= 3 ? batched_launch_lanes(b->dtype, g.mode, g.shape, g.kq, b->d_mats, b->d_tiles + g.off, g.n,
+                                                 accumulate, grid_blocks, stream)
+                          : batched_launch(b->dtype, g.kq, b->d_mats, b->d_tiles + g.off, g.n, accumulate,
+                                           grid_blocks, g.shape, stream);
         if (st != SPC_OK) return st;
     }
     return SPC_OK;

@@ -106,6 +106,11 @@ spc_status batched_launch(int dtype, int kq, const BatchMat *d_mats, const TileD
 // holds (matrix index << 1) | long flag. grid_blocks as above.
 spc_status batched_launch_test(int dtype, int shape, int kq, const BatchMat *d_mats, const TileDesc *d_tiles,
                                int64_t n_tiles, int accumulate, int grid_blocks, hipStream_t stream);
+// Batched block-row-lane (mode 3) or value-lane (mode 4, beta(1,8)) tiles of
+// one shape and chunk count; TileDesc::reserved holds the matrix index.
+spc_status batched_launch_lanes(int dtype, int mode, int shape, int kq, const BatchMat *d_mats,
+                                const TileDesc *d_tiles, int64_t n_tiles, int accumulate, int grid_blocks,
+                                hipStream_t stream);
 
 // Workgroups of the pipelined mode-0 kernel resident at once (occupancy x CUs).
 spc_status spmv_resident_groups(int shape, int dtype, int kq, int *out);

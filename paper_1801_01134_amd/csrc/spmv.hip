@@ -1783,6 +1783,78 @@ void launch_batched_test(int kq, unsigned grid, const BatchMat *d_mats, const Ti
     }
 }
 
+// Batched block-row-lane (mode 3) and value-lane (mode 4) tiles:
+// TileDesc::reserved holds the matrix index; an interval beyond a tile's
+// values or blocks takes the long path, as in the single-matrix kernels. A
+// wavefront loops over the tiles t, t + S, ... (S = 4 x grid).
+template <int R, int C, class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_batched_brow(const BatchMat *__restrict__ mats,
+                                                                const TileDesc *__restrict__ tiles, int64_t n_tiles,
+                                                                int accumulate) {
+    using Sh = Shape<R, C>;
+    using SM = BrowSmem<Sh, T, KQ>;
+    __shared__ SM smem[kWaves];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t step = (int64_t)gridDim.x * kWaves;
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += step) {
+        const TileDesc d = tiles[t];
+        const SpmvArgs a = batch_args(mats[d.reserved], tiles, accumulate);
+        wave_sync();  // the previous tile's LDS reads are done before this tile writes
+        if (d.b1 - d.b0 > SM::NBX || d.nv > SM::VCAP) {
+            wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+        } else {
+            const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+            brow_tile<Sh, T, KQ>(a, d, xr, smem[wid]);
+        }
+    }
+}
+
+template <class T, int KQ>
+__global__ __launch_bounds__(kThreads) void k_spmv_batched_vlane(const BatchMat *__restrict__ mats,
+                                                                 const TileDesc *__restrict__ tiles, int64_t n_tiles,
+                                                                 int accumulate) {
+    using Sh = Shape<1, 8>;
+    using SM = VlaneSmem<Sh, T, KQ>;
+    __shared__ SM smem[kWaves];
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t step = (int64_t)gridDim.x * kWaves;
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + wid; t < n_tiles; t += step) {
+        const TileDesc d = tiles[t];
+        const SpmvArgs a = batch_args(mats[d.reserved], tiles, accumulate);
+        wave_sync();
+        if (d.b1 - d.b0 > SM::NBX || d.nv > SM::VCAP) {
+            wave_long<Sh, T>(a, d.i0, d.b0, d.b1, d.vbase);
+        } else {
+            const auto xr = rsrc(a.x, (uint32_t)(a.n_cols * (int64_t)sizeof(T)));
+            vlane_tile<Sh, T, KQ>(a, d, xr, smem[wid]);
+        }
+    }
+}
+
+template <int R, int C, class T>
+void launch_batched_brow(int kq, unsigned grid, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
+                         int accumulate, hipStream_t stream) {
+    const dim3 g(grid), b(kThreads);
+    switch (kq) {
+    case 2: hipLaunchKernelGGL((k_spmv_batched_brow<R, C, T, 2>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    case 6: hipLaunchKernelGGL((k_spmv_batched_brow<R, C, T, 6>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    case 8: hipLaunchKernelGGL((k_spmv_batched_brow<R, C, T, 8>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    default: hipLaunchKernelGGL((k_spmv_batched_brow<R, C, T, 4>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    }
+}
+
+template <class T>
+void launch_batched_vlane(int kq, unsigned grid, const BatchMat *d_mats, const TileDesc *d_tiles, int64_t n_tiles,
+                          int accumulate, hipStream_t stream) {
+    const dim3 g(grid), b(kThreads);
+    switch (kq) {
+    case 2: hipLaunchKernelGGL((k_spmv_batched_vlane<T, 2>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    case 6: hipLaunchKernelGGL((k_spmv_batched_vlane<T, 6>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    case 8: hipLaunchKernelGGL((k_spmv_batched_vlane<T, 8>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    default: hipLaunchKernelGGL((k_spmv_batched_vlane<T, 4>), g, b, 0, stream, d_mats, d_tiles, n_tiles, accumulate); break;
+    }
+}
+
 template <int R, int C, class T>
 spc_status launch_wg(int tb, dim3 grid, const SpmvArgs &a, hipStream_t stream) {
     switch (tb) {
@@ -1920,6 +1992,30 @@ spc_status batched_launch_test(int dtype, int shape, int kq, const BatchMat *d_m
         using T = decltype(tv);
         if (shape == 0) launch_batched_test<1, 8, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
         else launch_batched_test<2, 4, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
+        SPC_HIP(hipGetLastError());
+        return SPC_OK;
+    });
+}
+
+spc_status batched_launch_lanes(int dtype, int mode, int shape, int kq, const BatchMat *d_mats,
+                                const TileDesc *d_tiles, int64_t n_tiles, int accumulate, int grid_blocks,
+                                hipStream_t stream) {
+    SPC_REQUIRE(mode == 3 || (mode == 4 && shape == 0), SPC_ERR_UNSUPPORTED_SHAPE,
+                "batched lanes: mode 3, or mode 4 for beta(1,8)");
+    if (n_tiles == 0) return SPC_OK;
+    const int64_t groups = div_up(n_tiles, kWaves);
+    const unsigned grid = (unsigned)(grid_blocks > 0 && grid_blocks < groups ? grid_blocks : groups);
+    return with_dtype(dtype, [&](auto tv) -> spc_status {
+        using T = decltype(tv);
+        if (mode == 4) {
+            launch_batched_vlane<T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
+        } else {
+            with_shape(shape, [&](auto sh) {
+                using Sh = decltype(sh);
+                launch_batched_brow<Sh::R, Sh::C, T>(kq, grid, d_mats, d_tiles, n_tiles, accumulate, stream);
+                return 0;
+            });
+        }
         SPC_HIP(hipGetLastError());
         return SPC_OK;
     });

@@ -125,8 +125,8 @@ def test_batch_refuses_bad_arguments():
         b.set_vectors([torch.zeros(3, dtype=torch.float64, device="cuda")],
                       [torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")])
     B44 = spc.csr_to_beta(4, 4, A.rowptr, A.colidx, torch.from_numpy(A.values), A.n_cols)
-    for params, mats_ in [({"mode": 1}, [B64]), ({"mode": 2}, [B44]), ({"mode": 0, "pipeline": 1}, [B64]),
-                          ({"mode": 0, "wave_tiles": 2}, [B64])]:
+    for params, mats_ in [({"mode": 1}, [B64]), ({"mode": 2}, [B44]), ({"mode": 4}, [B44]), ({"mode": 5}, [B64]),
+                          ({"mode": 0, "pipeline": 1}, [B64]), ({"mode": 0, "wave_tiles": 2}, [B64])]:
         with pytest.raises(spc.SpcError):
             spc.Batch(mats_, params=params)
     with pytest.raises(ValueError):
@@ -138,14 +138,25 @@ def test_batch_refuses_bad_arguments():
         mixed.set_kernel(True)
     with pytest.raises(spc.SpcError):
         spc.Batch([B64, B44], params=[{"mode": 0, "wave_chunks": 2}, {"mode": 0, "wave_chunks": 4}]).set_kernel(True)
+    with pytest.raises(spc.SpcError):
+        spc.Batch([B64, B44], params=[{"mode": 4, "wave_chunks": 4}, {"mode": 3, "wave_chunks": 4}]).set_kernel(True)
 
 
 def _mixed_params(shapes):
     """Per matrix: test tiles (mode 2) for every other one-byte-mask matrix,
-    wavefront tiles otherwise; chunk counts cycling over 2, 4, 6, 8."""
+    value lanes (mode 4) for the other beta(1,8) ones, block-row lanes
+    (mode 3) for every third of the rest, wavefront tiles (mode 0)
+    otherwise; chunk counts cycling over 2, 4, 6, 8."""
     out = []
     for k, (r, c) in enumerate(shapes):
-        mode = 2 if (r * c == 8 and k % 2 == 0) else 0
+        if r * c == 8 and k % 2 == 0:
+            mode = 2
+        elif (r, c) == (1, 8):
+            mode = 4
+        elif k % 3 == 1:
+            mode = 3
+        else:
+            mode = 0
         out.append({"mode": mode, "wave_chunks": (2, 4, 6, 8)[k % 4]})
     return out
 
@@ -165,7 +176,7 @@ def test_grouped_batch_mixed_modes_and_chunks(dtype):
         ys.append(torch.full((A.n_rows,), 7.0, dtype=dtype, device="cuda"))
         refs.append(oracle.csr_spmv(A, x))
     params = _mixed_params(shapes)
-    assert any(p["mode"] == 2 for p in params)
+    assert {p["mode"] for p in params} == {0, 2, 3, 4}
     batch = spc.Batch(Bs, params=params).set_vectors(xs, ys)
     info = batch.info()
     keys = {(p["mode"], shapes[k], p["wave_chunks"]) for k, p in enumerate(params)}

@@ -515,13 +515,13 @@ def test_block_row_lanes_integers_and_nonfinite(rc, dtype):
 
 
 def test_block_row_lanes_refusals():
-    """Mode 3 takes neither two tiles per wavefront nor the pipeline; SpMM,
-    CG and batches refuse its plans; mode 4 does not exist."""
+    """Mode 3 takes neither two tiles per wavefront nor the pipeline; SpMM
+    and CG refuse its plans; mode 5 does not exist."""
     say("[brow-refuse]")
     A = case("stencil13")
     B = to_beta(A, 2, 4, torch.float64)
     for bad in (dict(mode=3, wave_chunks=4, wave_tiles=2), dict(mode=3, wave_chunks=4, pipeline=1),
-                dict(mode=4, wave_chunks=4)):
+                dict(mode=5, wave_chunks=4)):
         with pytest.raises(spc.SpcError):
             spc.plan_from(B, bad)
     P = B.plan(0, 0, 3, 4)
@@ -530,8 +530,6 @@ def test_block_row_lanes_refusals():
         spc.spmm(B, X, plan=P)
     with pytest.raises(spc.SpcError):
         spc.cg(B, X, rel_tol=1e-6, max_iter=5, check_every=5, plan=P)
-    with pytest.raises(spc.SpcError):
-        spc.Batch([B], params=[dict(mode=3, wave_chunks=4)])
 
 
 @pytest.mark.parametrize("rc", spc.SHAPES, ids=lambda s: f"b{s[0]}x{s[1]}")
