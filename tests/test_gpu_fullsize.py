@@ -16,7 +16,7 @@ on the host), so these compare all outputs, not a sample:
     and k = 16, FP32 to 1e-5, with the true residual recomputed by the
     oracle;
   * 8 of the 64 batched matrices (rows log-uniform in [10k, 500k]) in one
-    launch.
+    launch, then grouped in block-row and value lanes.
 """
 import sys
 
@@ -170,7 +170,7 @@ def test_cg_192_k16_fp32():
 
 
 def test_batched_config_sample():
-    say("[full] 8 batched matrices, one launch")
+    say("[full] 8 batched matrices, one launch; then the lane modes the bench's batch picks")
     mats = [synth.batched_matrix(i) for i in range(8)]
     Bs, xs, ys, refs = [], [], [], []
     for i, A in enumerate(mats):
@@ -184,3 +184,12 @@ def test_batched_config_sample():
     torch.cuda.synchronize()
     for i, (y, ref) in enumerate(zip(ys, refs)):
         check(y.cpu().numpy(), ref, 1e-13, f"batched {i}")
+    # value lanes for the beta(1,8) matrices, block-row lanes for the others
+    params = [{"mode": 4 if spc.SHAPES[i % 6] == (1, 8) else 3, "wave_chunks": (2, 4, 6, 8)[i % 4]}
+              for i in range(len(Bs))]
+    for y in ys:
+        y.fill_(-1.0)
+    spc.Batch(Bs, params=params).set_vectors(xs, ys).run()
+    torch.cuda.synchronize()
+    for i, (y, ref) in enumerate(zip(ys, refs)):
+        check(y.cpu().numpy(), ref, 1e-13, f"batched lanes {i}")
