@@ -83,7 +83,7 @@ def test_records_collect_writes_complete_lines():
             assert rec["features"][8 + k] == pytest.approx(A.nnz / nb[k], rel=1e-6)
         assert len(rec["us"]) == 6 and all(t > 0 for t in rec["us"])
         assert rec["gflops"] == pytest.approx([2.0 * A.nnz / (t * 1e-6) / 1e9 for t in rec["us"]])
-        assert len(rec["params"]) == 6 and all(p["mode"] in (0, 1, 3) for p in rec["params"])
+        assert len(rec["params"]) == 6 and all(p["mode"] in (0, 1, 3, 4) for p in rec["params"])
         assert all(n > 0 for n in rec["n_tiles"])
         # the test kernels (Algorithm 2) of beta(1,8) and beta(2,4) as classes of their own
         assert len(rec["us_test"]) == 2 and all(t > 0 for t in rec["us_test"])

@@ -80,9 +80,9 @@ def test_stencil128_all_rows_all_plans(rc, dtype):
     plans += [dict(mode=0, wave_chunks=8, wave_tiles=2, cu_groups=4)]
     if rc in ((1, 8), (2, 4)):
         plans += [dict(mode=2, wave_chunks=q) for q in (4, 8)]
-    plans += [dict(mode=3, wave_chunks=q, cu_groups=cap) for q in (4, 6, 8) for cap in (0, 4)]
+    plans += [dict(mode=3, wave_chunks=q) for q in (2, 4, 6, 8)] + [dict(mode=3, wave_chunks=4, cu_groups=4)]
     if rc == (1, 8):
-        plans += [dict(mode=4, wave_chunks=q, cu_groups=cap) for q in (4, 6, 8) for cap in (0, 4)]
+        plans += [dict(mode=4, wave_chunks=q) for q in (2, 4, 6, 8)] + [dict(mode=4, wave_chunks=4, cu_groups=4)]
     plans += [dict(mode=0, wave_chunks=q, pipeline=1) for q in (2, 4, 6, 8)]
     plans += [dict(mode=1, tile_bits=tb, tile_order=o) for tb in (1024, 4032) for o in (0, 1)]
     plans += [B.default_params()]
