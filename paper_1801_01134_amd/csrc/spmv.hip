@@ -640,32 +640,45 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
         const char *__restrict__ bb = reinterpret_cast<const char *>(sm.w.buf);
         const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.w.zero) - bb);
         const int hi_row = hi_slot * R;
+        // G rounds' gathers are issued before the first of their sums (two;
+        // one for FP64 with one row per block, whose registers would
+        // otherwise cost more residency than the overlap gains)
+        constexpr int G = (sizeof(T) == 8 && R == 1) ? 1 : 2;
         double acc[SM::NBR];
 #pragma unroll
-        for (int k = 0; k < SM::NBR; ++k) {
-            if (64 * k >= hi_row) break;
-            const int br = lane + 64 * k;
-            const int s = br / R, rho = br % R;
-            const bool ok = s < hi_slot;
-            uint32_t mk, first;
-            sm.get(ok ? s : 0, mk, first);
-            const int col = __builtin_amdgcn_ds_bpermute((s % 64) * 4, in.colr[k / R]);
-            mk = ok ? mk : 0u;
-            uint32_t rm = (mk >> (rho * C)) & Sh::CMASK;
-            const uint32_t voff = (uint32_t)shift + first + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
-            T xg[C], v[C];
-            int n = 0;   // steps taken: the most bits of any lane's block row (uniform)
+        for (int k0 = 0; k0 < SM::NBR; k0 += G) {
+            if (64 * k0 >= hi_row) break;
+            T xg[G][C], v[G][C];
+            int n[G];   // steps taken per round: the most bits of any lane's block row (uniform)
 #pragma unroll
-            for (int it = 0; it < C; ++it) {
-                if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
-                const bool on = rm != 0u;
-                const int t = __builtin_ctz(rm | (1u << C));
-                xg[it] = buf_load<T>(xr, on ? (uint32_t)(col + t) * (uint32_t)sizeof(T) : 0xffffffffu);
-                v[it] = *reinterpret_cast<const T *>(bb + (on ? (voff + (uint32_t)it) * (uint32_t)sizeof(T) : zbyte));
-                rm &= rm - 1u;
-                n = it + 1;
+            for (int g = 0; g < G; ++g) {
+                const int k = k0 + g;
+                n[g] = 0;
+                if (k >= SM::NBR || 64 * k >= hi_row) continue;
+                const int br = lane + 64 * k;
+                const int s = br / R, rho = br % R;
+                const bool ok = s < hi_slot;
+                uint32_t mk, first;
+                sm.get(ok ? s : 0, mk, first);
+                const int col = __builtin_amdgcn_ds_bpermute((s % 64) * 4, in.colr[k / R]);
+                mk = ok ? mk : 0u;
+                uint32_t rm = (mk >> (rho * C)) & Sh::CMASK;
+                const uint32_t voff = (uint32_t)shift + first + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
+#pragma unroll
+                for (int it = 0; it < C; ++it) {
+                    if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
+                    const bool on = rm != 0u;
+                    const int t = __builtin_ctz(rm | (1u << C));
+                    xg[g][it] = buf_load<T>(xr, on ? (uint32_t)(col + t) * (uint32_t)sizeof(T) : 0xffffffffu);
+                    v[g][it] =
+                        *reinterpret_cast<const T *>(bb + (on ? (voff + (uint32_t)it) * (uint32_t)sizeof(T) : zbyte));
+                    rm &= rm - 1u;
+                    n[g] = it + 1;
+                }
             }
-            acc[k] = block_row_sum<T, C>(v, xg, n);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (k0 + g < SM::NBR) acc[k0 + g] = block_row_sum<T, C>(v[g], xg[g], n[g]);
         }
         wave_sync();  // all values are read before the partials overwrite them
         double *__restrict__ part = reinterpret_cast<double *>(sm.w.buf);
