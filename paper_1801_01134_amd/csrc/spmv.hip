@@ -640,10 +640,11 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
         const char *__restrict__ bb = reinterpret_cast<const char *>(sm.w.buf);
         const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.w.zero) - bb);
         const int hi_row = hi_slot * R;
-        // G rounds' gathers are issued before the first of their sums (two;
-        // one for FP64 with one row per block, whose registers would
-        // otherwise cost more residency than the overlap gains)
-        constexpr int G = (sizeof(T) == 8 && R == 1) ? 1 : 2;
+        // G rounds' gathers are issued before the first of their sums: two;
+        // four for FP32 with 4-column blocks (half the registers per
+        // gather); one for FP64 with one row per block, whose registers
+        // would otherwise cost more residency than the overlap gains
+        constexpr int G = (sizeof(T) == 8 && R == 1) ? 1 : (sizeof(T) == 4 && C == 4) ? 4 : 2;
         double acc[SM::NBR];
 #pragma unroll
         for (int k0 = 0; k0 < SM::NBR; k0 += G) {
