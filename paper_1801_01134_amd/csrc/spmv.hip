@@ -37,6 +37,17 @@
 namespace spc {
 namespace {
 
+// One 16-byte chunk per lane from a buffer straight into LDS (no registers).
+// The builtin and its LDS address space exist for the device target only;
+// in the host pass, which emits no device code, the body is empty (it would
+// otherwise make every function template that reaches it invalid there).
+__device__ __forceinline__ void chunk_to_lds(__amdgpu_buffer_rsrc_t vr, void *lds, uint32_t voff, int soff) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(vr, (__attribute__((address_space(3))) void *)lds, 16, voff, soff, 0,
+                                             dev::kNT);
+#endif
+}
+
 using namespace dev;
 
 constexpr int kWaves = 4;
@@ -423,9 +434,7 @@ __device__ __forceinline__ void tile_issue(const SpmvArgs &a, const TileDesc &d,
     const auto vr = rsrc(vals + abase, (uint32_t)q_tail * 16u);
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            vr, (__attribute__((address_space(3))) void *)(s_vals + 64 * k * E), 16, (uint32_t)(lane * 16), 1024 * k,
-            0, kNT);
+        chunk_to_lds(vr, s_vals + 64 * k * E, (uint32_t)(lane * 16), 1024 * k);
 }
 
 // Everything after the stream loads: the x gathers and products, the row
@@ -694,16 +703,12 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
     tile_sums<Sh, T, false, 1>(a, d, lo_slot, w0, sm.w.brow, reinterpret_cast<const double *>(sm.w.buf));
 }
 
-// The host pass of this file never emits device code; the body is compiled
-// for the device only.
 template <class Sh, class T, int KQ>
 __device__ __forceinline__ void brow_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
                                           BrowSmem<Sh, T, KQ> &sm) {
-#if defined(__HIP_DEVICE_COMPILE__)
     TileIn<Sh, T, KQ, Sh::BPW> in;
     tile_issue<Sh, T, KQ>(a, d, in, sm.w.buf);
     brow_run<Sh, T, KQ>(a, d, in, xr, sm);
-#endif
 }
 
 // ---------------------------------------------------------------------------
@@ -849,11 +854,9 @@ __device__ void vlane_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ
 template <class Sh, class T, int KQ>
 __device__ __forceinline__ void vlane_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
                                            VlaneSmem<Sh, T, KQ> &sm) {
-#if defined(__HIP_DEVICE_COMPILE__)
     TileIn<Sh, T, KQ, Sh::BPW> in;
     tile_issue<Sh, T, KQ>(a, d, in, sm.w.buf);
     vlane_run<Sh, T, KQ>(a, d, in, xr, sm);
-#endif
 }
 
 // The KQ 16-byte chunks of a wavefront's value range, lane l taking bytes
@@ -864,9 +867,7 @@ __device__ __forceinline__ void values_to_lds(__amdgpu_buffer_rsrc_t vr, T *s_va
     const int lane = lane_id();
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            vr, (__attribute__((address_space(3))) void *)(s_vals + 64 * k * E), 16, (uint32_t)(lane * 16), 1024 * k,
-            0, kNT);
+        chunk_to_lds(vr, s_vals + 64 * k * E, (uint32_t)(lane * 16), 1024 * k);
 }
 
 using V4u = __attribute__((ext_vector_type(4))) unsigned int;
@@ -1411,9 +1412,7 @@ __device__ __forceinline__ void tile_issue_lds(const SpmvArgs &a, const TileDesc
     const auto vr = rsrc(vals + abase, on ? (uint32_t)q_tail * 16u : 0u);
 #pragma unroll
     for (int k = 0; k < KQ; ++k)
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            vr, (__attribute__((address_space(3))) void *)(s_vals + 64 * k * E), 16, (uint32_t)(lane * 16), 1024 * k,
-            0, kNT);
+        chunk_to_lds(vr, s_vals + 64 * k * E, (uint32_t)(lane * 16), 1024 * k);
 }
 
 // The compute of a tile whose values are in s_vals (chunk order). prefetch()
