@@ -574,28 +574,18 @@ struct BrowSmem {
     }
 };
 
-// One block row's products, T = double: fused multiply-adds in double.
-// T = float: products and their sum in single precision, as mode 0 forms
-// them (no contraction into fused operations).
-template <class T, int C>
-__device__ __forceinline__ double block_row_sum(const T (&v)[C], const T (&xg)[C], int n) {
-    if constexpr (sizeof(T) == 8) {
-        double s = 0.0;
+// Adds n products of one block row to s, in order: T = double, fused
+// multiply-adds in double; T = float, products and their sum in single
+// precision, as mode 0 forms them (no contraction into fused operations).
+template <class T, int N>
+__device__ __forceinline__ T block_row_acc(const T (&v)[N], const T (&xg)[N], int n, T s) {
 #pragma unroll
-        for (int it = 0; it < C; ++it) {
-            if (it >= n) break;
-            s = __builtin_fma(v[it], xg[it], s);
-        }
-        return s;
-    } else {
-        float s = 0.f;
-#pragma unroll
-        for (int it = 0; it < C; ++it) {
-            if (it >= n) break;
-            s = __fadd_rn(s, __fmul_rn(v[it], xg[it]));
-        }
-        return (double)s;
+    for (int it = 0; it < N; ++it) {
+        if (it >= n) break;
+        if constexpr (sizeof(T) == 8) s = __builtin_fma(v[it], xg[it], s);
+        else s = __fadd_rn(s, __fmul_rn(v[it], xg[it]));
     }
+    return s;
 }
 
 template <class Sh, class T, int KQ>
@@ -652,18 +642,29 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
         // G rounds' gathers are issued before the first of their sums: two;
         // four for FP32 with 4-column blocks (half the registers per
         // gather); one for FP64 with one row per block, whose registers
-        // would otherwise cost more residency than the overlap gains
+        // would otherwise cost more residency than the overlap gains. With
+        // several rounds a round takes at most SC of its block rows' bits
+        // (fewer registers); the rare block rows with more take their
+        // remaining bits afterwards, in the same order, so the sums are the
+        // same.
         constexpr int G = (sizeof(T) == 8 && R == 1) ? 1 : (sizeof(T) == 4 && C == 4) ? 4 : 2;
+        constexpr int SC = (G > 1 && C > 4) ? 4 : C;
         double acc[SM::NBR];
 #pragma unroll
         for (int k0 = 0; k0 < SM::NBR; k0 += G) {
             if (64 * k0 >= hi_row) break;
-            T xg[G][C], v[G][C];
-            int n[G];   // steps taken per round: the most bits of any lane's block row (uniform)
+            T xg[G][SC], v[G][SC];
+            int n[G];             // steps taken per round (uniform)
+            uint32_t rest[G];     // bits beyond the first SC
+            int colg[G];
+            uint32_t voffg[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int k = k0 + g;
                 n[g] = 0;
+                rest[g] = 0u;
+                colg[g] = 0;
+                voffg[g] = 0u;
                 if (k >= SM::NBR || 64 * k >= hi_row) continue;
                 const int br = lane + 64 * k;
                 const int s = br / R, rho = br % R;
@@ -675,7 +676,7 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
                 uint32_t rm = (mk >> (rho * C)) & Sh::CMASK;
                 const uint32_t voff = (uint32_t)shift + first + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
 #pragma unroll
-                for (int it = 0; it < C; ++it) {
+                for (int it = 0; it < SC; ++it) {
                     if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
                     const bool on = rm != 0u;
                     const int t = __builtin_ctz(rm | (1u << C));
@@ -685,10 +686,37 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
                     rm &= rm - 1u;
                     n[g] = it + 1;
                 }
+                rest[g] = rm;
+                colg[g] = col;
+                voffg[g] = voff + (uint32_t)SC;
+            }
+            T sum[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) sum[g] = block_row_acc<T, SC>(v[g], xg[g], n[g], T(0));
+            if constexpr (SC < C) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    uint32_t rm = rest[g];
+                    if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) continue;
+                    T x2[C - SC], v2[C - SC];
+                    int n2 = 0;
+#pragma unroll
+                    for (int it = 0; it < C - SC; ++it) {
+                        if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
+                        const bool on = rm != 0u;
+                        const int t = __builtin_ctz(rm | (1u << C));
+                        x2[it] = buf_load<T>(xr, on ? (uint32_t)(colg[g] + t) * (uint32_t)sizeof(T) : 0xffffffffu);
+                        v2[it] = *reinterpret_cast<const T *>(
+                            bb + (on ? (voffg[g] + (uint32_t)it) * (uint32_t)sizeof(T) : zbyte));
+                        rm &= rm - 1u;
+                        n2 = it + 1;
+                    }
+                    sum[g] = block_row_acc<T, C - SC>(v2, x2, n2, sum[g]);
+                }
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                if (k0 + g < SM::NBR) acc[k0 + g] = block_row_sum<T, C>(v[g], xg[g], n[g]);
+                if (k0 + g < SM::NBR) acc[k0 + g] = (double)sum[g];
         }
         wave_sync();  // all values are read before the partials overwrite them
         double *__restrict__ part = reinterpret_cast<double *>(sm.w.buf);
