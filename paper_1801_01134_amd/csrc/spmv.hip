@@ -464,56 +464,118 @@ __device__ void tile_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ>
     sm.brow[lane] = in.br[0] - b0;
     sm.brow[lane + 64] = in.br[1] - b0;
     if (lane < 2) sm.zero[lane] = 0.0;
-    // the values have landed in LDS (they were loaded last); the chunk
-    // reaching past nnz came back as zeros and is filled value by value
-    if constexpr (PEND >= 0) wait_vm_n<PEND>();
-    if (q_tail < nq && lane < E) {
-        const int64_t g = abase + (int64_t)q_tail * E + lane;
-        if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
-    }
-    wave_sync();
-
     // 2. products, lane = mask bit, words walked on the scalar unit. Per
-    // word: the lane's value (LDS, at the count of set bits below it plus the
-    // word's running offset; zero where its bit is clear) and its x gather (a
-    // lane whose bit is clear gathers out of range: 0, no memory access).
+    // word: the lane's x gather (a lane whose bit is clear gathers out of
+    // range: 0, no memory access) and its value (LDS, at the count of set bits
+    // below it plus the word's running offset; zero where its bit is clear).
     // Each word's mask is used in this pass only. Once all values are read,
     // each word's products are added over each block row's C lanes and one
     // partial per (block, block row) replaces the values in LDS. The last
     // word keeps the bits of the next tile's blocks; their partials are never
     // read.
-    if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
+    // The gathers need only the block columns and the masks: tiles of 8
+    // chunks (the most mask words) issue all of them before the wait for the
+    // values, so their latency runs under the value stream's. Smaller tiles,
+    // and FP32 tiles of 16- and 32-bit masks, gather word by word after the
+    // wait (measured faster for them).
+    constexpr bool EARLY = KQ >= 8 && (sizeof(T) == 8 || Sh::RC == 8);
+    if constexpr (EARLY) {
         constexpr int NWM = SM::NWMAX;
-        constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
-        constexpr int W = Sh::C / PPR;
         static_assert(NWM <= 64, "a tile's mask words fit one per lane");
         const int slot = lane / Sh::RC;
-        const int kcol = (lane % Sh::RC) % Sh::C;
-        const char *__restrict__ bb = reinterpret_cast<const char *>(sm.buf);
-        // lanes of clear bits read a zero from LDS instead of a value
-        const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.zero) - bb);
-        // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
-        // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes); all
-        // of the tile's cross-lane moves are issued before the first is used
-        int colj[NWM];
+        // The NWM gathers are issued in every tile, so that the wait below counts
+        // them: a tile of empty intervals has no words, its masks read as 0 (an
+        // empty range) and none of its gathers touches memory.
+        T xv[NWM];
+        {
+            const int kcol = (lane % Sh::RC) % Sh::C;
+            // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
+            // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes); all
+            // of the tile's cross-lane moves are issued before the first is used
+            int colj[NWM];
 #pragma unroll
-        for (int j = 0; j < NWM; ++j)
-            colj[j] = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, in.colr[(j * Sh::BPW) / 64]);
-        T xv[NWM], pv[NWM];
-        uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
+            for (int j = 0; j < NWM; ++j)
+                colj[j] = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, in.colr[(j * Sh::BPW) / 64]);
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) {
-            uint64_t m = readlane64(in.m, j);
-            if (j == 0) m &= lo_mask;
-            xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(colj[j] + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
-            pv[j] = *reinterpret_cast<const T *>(bb + pick(m, lane_rank(m) * (uint32_t)sizeof(T) + vbyte, zbyte));
-            vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
+            for (int j = 0; j < NWM; ++j) {
+                uint64_t m = readlane64(in.m, j);
+                if (j == 0) m &= lo_mask;
+                xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(colj[j] + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+            }
         }
-        wave_sync();  // all values are read before the partials overwrite them
-        double *__restrict__ mine = reinterpret_cast<double *>(sm.buf) + lane / W;
-        const bool keeper = (lane % W) == 0;
+        // the values have landed in LDS (they were loaded before the NWM gathers
+        // and the PEND later operations); the chunk reaching past nnz came back
+        // as zeros and is filled value by value
+        if constexpr (PEND >= 0) wait_vm_n<(PEND + NWM < 63 ? PEND + NWM : 63)>();
+        if (q_tail < nq && lane < E) {
+            const int64_t g = abase + (int64_t)q_tail * E + lane;
+            if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+        }
+        wave_sync();
+        if (nw > 0) {
+            constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+            constexpr int W = Sh::C / PPR;
+            const char *__restrict__ bb = reinterpret_cast<const char *>(sm.buf);
+            // lanes of clear bits read a zero from LDS instead of a value
+            const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.zero) - bb);
+            T pv[NWM];
+            uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
 #pragma unroll
-        for (int j = 0; j < NWM; ++j) store_partial_at<Sh, T>(mine, keeper, j, pv[j] * xv[j]);
+            for (int j = 0; j < NWM; ++j) {
+                uint64_t m = readlane64(in.m, j);
+                if (j == 0) m &= lo_mask;
+                pv[j] = *reinterpret_cast<const T *>(bb + pick(m, lane_rank(m) * (uint32_t)sizeof(T) + vbyte, zbyte));
+                vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
+            }
+            wave_sync();  // all values are read before the partials overwrite them
+            double *__restrict__ mine = reinterpret_cast<double *>(sm.buf) + lane / W;
+            const bool keeper = (lane % W) == 0;
+#pragma unroll
+            for (int j = 0; j < NWM; ++j) store_partial_at<Sh, T>(mine, keeper, j, pv[j] * xv[j]);
+        }
+    } else {
+        // the values have landed in LDS (they were loaded last); the chunk
+        // reaching past nnz came back as zeros and is filled value by value
+        if constexpr (PEND >= 0) wait_vm_n<PEND>();
+        if (q_tail < nq && lane < E) {
+            const int64_t g = abase + (int64_t)q_tail * E + lane;
+            if (g < a.nnz) sm.buf[q_tail * E + lane] = vals[g];
+        }
+        wave_sync();
+
+        if (nw > 0) {  // a tile of empty intervals has no words (and maybe no masks array)
+            constexpr int NWM = SM::NWMAX;
+            constexpr int PPR = sizeof(T) == 8 ? 2 : 1;
+            constexpr int W = Sh::C / PPR;
+            static_assert(NWM <= 64, "a tile's mask words fit one per lane");
+            const int slot = lane / Sh::RC;
+            const int kcol = (lane % Sh::RC) % Sh::C;
+            const char *__restrict__ bb = reinterpret_cast<const char *>(sm.buf);
+            // lanes of clear bits read a zero from LDS instead of a value
+            const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.zero) - bb);
+            // the column of slot j BPW + slot sits in register (j BPW) / 64 of lane
+            // (j BPW + slot) mod 64 (a word's slots never straddle 64 lanes); all
+            // of the tile's cross-lane moves are issued before the first is used
+            int colj[NWM];
+#pragma unroll
+            for (int j = 0; j < NWM; ++j)
+                colj[j] = __builtin_amdgcn_ds_bpermute(((j * Sh::BPW) % 64 + slot) * 4, in.colr[(j * Sh::BPW) / 64]);
+            T xv[NWM], pv[NWM];
+            uint32_t vbyte = (uint32_t)shift * (uint32_t)sizeof(T);   // byte offset of the word's first value
+#pragma unroll
+            for (int j = 0; j < NWM; ++j) {
+                uint64_t m = readlane64(in.m, j);
+                if (j == 0) m &= lo_mask;
+                xv[j] = buf_load<T>(xr, pick(m, (uint32_t)(colj[j] + kcol) * (uint32_t)sizeof(T), 0xffffffffu));
+                pv[j] = *reinterpret_cast<const T *>(bb + pick(m, lane_rank(m) * (uint32_t)sizeof(T) + vbyte, zbyte));
+                vbyte += (uint32_t)__popcll(m) * (uint32_t)sizeof(T);
+            }
+            wave_sync();  // all values are read before the partials overwrite them
+            double *__restrict__ mine = reinterpret_cast<double *>(sm.buf) + lane / W;
+            const bool keeper = (lane % W) == 0;
+#pragma unroll
+            for (int j = 0; j < NWM; ++j) store_partial_at<Sh, T>(mine, keeper, j, pv[j] * xv[j]);
+        }
     }
     wave_sync();
     tile_sums<Sh, T>(a, d, lo_slot, w0, sm.brow, reinterpret_cast<const double *>(sm.buf));
@@ -731,12 +793,214 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
     tile_sums<Sh, T, false, 1>(a, d, lo_slot, w0, sm.w.brow, reinterpret_cast<const double *>(sm.w.buf));
 }
 
+// Block-row lanes with the first group's gathers ahead of the wait for the
+// values (FP64): the arithmetic and its order are brow_run's; pass A's
+// results stay in registers for the first group, and the slot table is
+// written to LDS after the wait for the groups that follow.
+template <class Sh, class T, int KQ>
+__device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ, Sh::BPW> &in,
+                               __amdgpu_buffer_rsrc_t xr, BrowSmem<Sh, T, KQ> &sm) {
+    using SM = BrowSmem<Sh, T, KQ>;
+    constexpr int E = SM::W::E;
+    constexpr int R = Sh::R, C = Sh::C, BPW = Sh::BPW;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ vals = static_cast<const T *>(a.vals);
+    const int b0 = d.b0, b1 = d.b1, nv = d.nv;
+    const int64_t abase = d.vbase & ~(int64_t)(E - 1);
+    const int shift = (int)(d.vbase - abase);
+    const int nq = (shift + nv + E - 1) / E;
+    const int q_tail = (abase + (int64_t)nq * E > a.nnz) ? nq - 1 : nq;
+    const int w0 = b0 / BPW;
+    const int lo_slot = b0 - w0 * BPW;
+    const int hi_slot = lo_slot + (b1 - b0);   // the tile's blocks are slots [lo_slot, hi_slot)
+    sm.w.brow[lane] = in.br[0] - b0;
+    sm.w.brow[lane + 64] = in.br[1] - b0;
+    if (lane < 2) sm.w.zero[lane] = 0.0;
+    const char *__restrict__ bb = reinterpret_cast<const char *>(sm.w.buf);
+    const uint32_t zbyte = (uint32_t)(reinterpret_cast<const char *>(sm.w.zero) - bb);
+    const int hi_row = hi_slot * R;
+    static_assert(sizeof(T) == 8, "FP64 tiles");
+    // brow_run's groups for FP64: G rounds' gathers are issued before the
+    // first of their sums (one round with one row per block, else two), and
+    // with two rounds a round takes at most SC of its block rows' bits; the
+    // rare block rows with more take the rest afterwards, in the same order.
+    constexpr int G = R == 1 ? 1 : 2;
+    constexpr int SC = (G > 1 && C > 4) ? 4 : C;
+    // one group of rounds: per round, the lane's block row, its bits, its
+    // block column and its first value
+    struct Group {
+        T xg[G][SC];
+        int n[G];             // steps taken per round (uniform)
+        uint32_t cnt[G];      // the lane's bits among the first SC
+        uint32_t rest[G];     // bits beyond the first SC
+        int colg[G];
+        uint32_t voffg[G];
+    };
+    // pass A's results in registers: round r holds slots 64 r .. 64 r + 63
+    uint32_t amk[SM::NSR], afirst[SM::NSR];
+    // Issues the gathers of the rounds k0 .. k0 + G - 1: lane = block row, its
+    // set bits in turn; lanes out of bits gather nothing (an out of range
+    // offset reads 0). The slots of a round share one register of block
+    // columns (k / R), and one of pass A's rounds. The first group takes its
+    // slots from pass A's registers (REGS), the others from LDS.
+    auto gathers = [&](const int k0, Group &q, const bool REGS) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int k = k0 + g;
+            q.n[g] = 0;
+            q.cnt[g] = 0u;
+            q.rest[g] = 0u;
+            q.colg[g] = 0;
+            q.voffg[g] = 0u;
+            if (k >= SM::NBR || 64 * k >= hi_row) continue;
+            const int br = lane + 64 * k;
+            const int s = br / R, rho = br % R;
+            const bool ok = s < hi_slot;
+            uint32_t mk, first;
+            if (REGS) {
+                mk = (uint32_t)__builtin_amdgcn_ds_bpermute((s % 64) * 4, (int)amk[k / R]);
+                first = (uint32_t)__builtin_amdgcn_ds_bpermute((s % 64) * 4, (int)afirst[k / R]);
+            } else {
+                sm.get(ok ? s : 0, mk, first);
+            }
+            const int col = __builtin_amdgcn_ds_bpermute((s % 64) * 4, in.colr[k / R]);
+            mk = ok ? mk : 0u;
+            uint32_t rm = (mk >> (rho * C)) & Sh::CMASK;
+            const uint32_t voff = (uint32_t)shift + first + (uint32_t)__popc(mk & ((1u << (rho * C)) - 1u));
+            q.cnt[g] = (uint32_t)__popc(rm);
+#pragma unroll
+            for (int it = 0; it < SC; ++it) {
+                if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
+                const bool on = rm != 0u;
+                const int t = __builtin_ctz(rm | (1u << C));
+                q.xg[g][it] = buf_load<T>(xr, on ? (uint32_t)(col + t) * (uint32_t)sizeof(T) : 0xffffffffu);
+                rm &= rm - 1u;
+                q.n[g] = it + 1;
+            }
+            q.rest[g] = rm;
+            q.colg[g] = col;
+            q.voffg[g] = voff;
+        }
+    };
+    // The values of the rounds k0 .. k0 + G - 1 (LDS; the zero for lanes out
+    // of bits) and their sums in bit order; block rows with more than SC bits
+    // then take the rest.
+    auto sums = [&](const int k0, Group &q, double (&acc)[SM::NBR]) {
+        T sum[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            T v[SC];
+#pragma unroll
+            for (int it = 0; it < SC; ++it) {
+                if (it >= q.n[g]) break;
+                v[it] = *reinterpret_cast<const T *>(
+                    bb + ((uint32_t)it < q.cnt[g] ? (q.voffg[g] + (uint32_t)it) * (uint32_t)sizeof(T) : zbyte));
+            }
+            sum[g] = block_row_acc<T, SC>(v, q.xg[g], q.n[g], T(0));
+        }
+        if constexpr (SC < C) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                uint32_t rm = q.rest[g];
+                if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) continue;
+                T x2[C - SC], v2[C - SC];
+                int n2 = 0;
+                const uint32_t voff2 = q.voffg[g] + (uint32_t)SC;
+#pragma unroll
+                for (int it = 0; it < C - SC; ++it) {
+                    if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) break;
+                    const bool on = rm != 0u;
+                    const int t = __builtin_ctz(rm | (1u << C));
+                    x2[it] = buf_load<T>(xr, on ? (uint32_t)(q.colg[g] + t) * (uint32_t)sizeof(T) : 0xffffffffu);
+                    v2[it] = *reinterpret_cast<const T *>(
+                        bb + (on ? (voff2 + (uint32_t)it) * (uint32_t)sizeof(T) : zbyte));
+                    rm &= rm - 1u;
+                    n2 = it + 1;
+                }
+                sum[g] = block_row_acc<T, C - SC>(v2, x2, n2, sum[g]);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (k0 + g < SM::NBR) acc[k0 + g] = (double)sum[g];
+    };
+    // A. lane = slot: its mask bits (from the lane holding its word) and its
+    // first value (a prefix over the slots' value counts), kept in registers.
+    // Pass A needs only the masks, and the first group's gathers only its
+    // results and the block columns, so both run before the wait for the
+    // values and the gathers' latency runs under the value stream's. (An LDS
+    // access before the wait would wait for the values too: the compiler
+    // cannot tell the value loads' LDS destination from the slot table, which
+    // is written after.)
+    Group q0;
+    if (b1 > b0) {
+        const int mlo = (int)(uint32_t)in.m, mhi = (int)(uint32_t)(in.m >> 32);
+        int carry = 0;
+#pragma unroll
+        for (int k = 0; k < SM::NSR; ++k) {
+            amk[k] = 0u;
+            afirst[k] = 0u;
+            if (64 * k >= hi_slot) continue;
+            const int s = lane + 64 * k;
+            const int src = (s / BPW) * 4;   // word s / BPW < 64
+            const uint64_t w = ((uint64_t)(uint32_t)__builtin_amdgcn_ds_bpermute(src, mhi) << 32) |
+                               (uint32_t)__builtin_amdgcn_ds_bpermute(src, mlo);
+            const bool mine = s >= lo_slot && s < hi_slot;
+            const uint32_t mk = mine ? (uint32_t)(w >> ((s % BPW) * Sh::RC)) & Sh::RCMASK : 0u;
+            const int pc = __popc(mk);
+            const int incl = wave_scan_dpp(pc);
+            amk[k] = mk;
+            afirst[k] = (uint32_t)(carry + incl - pc);
+            carry += __builtin_amdgcn_readlane(incl, 63);
+        }
+        gathers(0, q0, true);
+    }
+    wait_vm_all();   // the values have landed in LDS; the chunk past nnz is filled value by value
+    if (q_tail < nq && lane < E) {
+        const int64_t g = abase + (int64_t)q_tail * E + lane;
+        if (g < a.nnz) sm.w.buf[q_tail * E + lane] = vals[g];
+    }
+    if (b1 > b0 && SM::NBR > G) {   // the slot table, for the groups after the first
+#pragma unroll
+        for (int k = 0; k < SM::NSR; ++k) {
+            if (64 * k >= hi_slot) break;
+            sm.put(lane + 64 * k, amk[k], afirst[k]);
+        }
+    }
+    wave_sync();
+    if (b1 > b0) {
+        // B. lane = block row: G rounds at a time, every gather of a group
+        // issued before its first product
+        double acc[SM::NBR];
+        sums(0, q0, acc);
+#pragma unroll
+        for (int k0 = G; k0 < SM::NBR; k0 += G) {
+            if (64 * k0 >= hi_row) break;
+            Group q;
+            gathers(k0, q, false);
+            sums(k0, q, acc);
+        }
+        wave_sync();  // all values are read before the partials overwrite them
+        double *__restrict__ part = reinterpret_cast<double *>(sm.w.buf);
+#pragma unroll
+        for (int k = 0; k < SM::NBR; ++k) {
+            if (64 * k >= hi_row) break;
+            const int br = lane + 64 * k;
+            if (br < hi_row) part[br] = acc[k];   // entry s R + rho
+        }
+    }
+    wave_sync();
+    tile_sums<Sh, T, false, 1>(a, d, lo_slot, w0, sm.w.brow, reinterpret_cast<const double *>(sm.w.buf));
+}
+
 template <class Sh, class T, int KQ>
 __device__ __forceinline__ void brow_tile(const SpmvArgs &a, const TileDesc &d, __amdgpu_buffer_rsrc_t xr,
                                           BrowSmem<Sh, T, KQ> &sm) {
     TileIn<Sh, T, KQ, Sh::BPW> in;
     tile_issue<Sh, T, KQ>(a, d, in, sm.w.buf);
-    brow_run<Sh, T, KQ>(a, d, in, xr, sm);
+    // FP64 gathers before the wait; FP32 after it (measured faster for each)
+    if constexpr (sizeof(T) == 8) brow_run_early<Sh, T, KQ>(a, d, in, xr, sm);
+    else brow_run<Sh, T, KQ>(a, d, in, xr, sm);
 }
 
 // ---------------------------------------------------------------------------
