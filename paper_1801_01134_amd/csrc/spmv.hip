@@ -793,6 +793,19 @@ __device__ void brow_run(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, T, KQ,
     tile_sums<Sh, T, false, 1>(a, d, lo_slot, w0, sm.w.brow, reinterpret_cast<const double *>(sm.w.buf));
 }
 
+// One group of block-row rounds: per round, the lane's gathers, its steps,
+// its bits, its block column and its first value.
+template <class T, int NG_, int SC>
+struct BrowGroup {
+    static constexpr int NG = NG_;
+    T xg[NG][SC];
+    int n[NG];             // steps taken per round (uniform)
+    uint32_t cnt[NG];      // the lane's bits among the first SC
+    uint32_t rest[NG];     // bits beyond the first SC
+    int colg[NG];
+    uint32_t voffg[NG];
+};
+
 // Block-row lanes with the first group's gathers ahead of the wait for the
 // values (FP64): the arithmetic and its order are brow_run's; pass A's
 // results stay in registers for the first group, and the slot table is
@@ -824,18 +837,13 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
     // first of their sums (one round with one row per block, else two), and
     // with two rounds a round takes at most SC of its block rows' bits; the
     // rare block rows with more take the rest afterwards, in the same order.
+    // The first group, issued while the values stream in, takes up to G0 = 4
+    // rounds with several rows per block: on the 3-D stencil the registers
+    // the kernels already hold fit them (2, 3, 6 and 8 rounds measured
+    // slower).
     constexpr int G = R == 1 ? 1 : 2;
     constexpr int SC = (G > 1 && C > 4) ? 4 : C;
-    // one group of rounds: per round, the lane's block row, its bits, its
-    // block column and its first value
-    struct Group {
-        T xg[G][SC];
-        int n[G];             // steps taken per round (uniform)
-        uint32_t cnt[G];      // the lane's bits among the first SC
-        uint32_t rest[G];     // bits beyond the first SC
-        int colg[G];
-        uint32_t voffg[G];
-    };
+    constexpr int G0 = R == 1 ? 1 : (4 < SM::NBR ? 4 : SM::NBR);
     // pass A's results in registers: round r holds slots 64 r .. 64 r + 63
     uint32_t amk[SM::NSR], afirst[SM::NSR];
     // Issues the gathers of the rounds k0 .. k0 + G - 1: lane = block row, its
@@ -843,9 +851,10 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
     // offset reads 0). The slots of a round share one register of block
     // columns (k / R), and one of pass A's rounds. The first group takes its
     // slots from pass A's registers (REGS), the others from LDS.
-    auto gathers = [&](const int k0, Group &q, const bool REGS) {
+    auto gathers = [&](const int k0, auto &q, const bool REGS) {
+        constexpr int NG = std::remove_reference_t<decltype(q)>::NG;
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < NG; ++g) {
             const int k = k0 + g;
             q.n[g] = 0;
             q.cnt[g] = 0u;
@@ -885,10 +894,11 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
     // The values of the rounds k0 .. k0 + G - 1 (LDS; the zero for lanes out
     // of bits) and their sums in bit order; block rows with more than SC bits
     // then take the rest.
-    auto sums = [&](const int k0, Group &q, double (&acc)[SM::NBR]) {
-        T sum[G];
+    auto sums = [&](const int k0, auto &q, double (&acc)[SM::NBR]) {
+        constexpr int NG = std::remove_reference_t<decltype(q)>::NG;
+        T sum[NG];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
+        for (int g = 0; g < NG; ++g) {
             T v[SC];
 #pragma unroll
             for (int it = 0; it < SC; ++it) {
@@ -900,7 +910,7 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
         }
         if constexpr (SC < C) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
+            for (int g = 0; g < NG; ++g) {
                 uint32_t rm = q.rest[g];
                 if (__builtin_amdgcn_ballot_w64(rm != 0u) == 0) continue;
                 T x2[C - SC], v2[C - SC];
@@ -921,7 +931,7 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
             }
         }
 #pragma unroll
-        for (int g = 0; g < G; ++g)
+        for (int g = 0; g < NG; ++g)
             if (k0 + g < SM::NBR) acc[k0 + g] = (double)sum[g];
     };
     // A. lane = slot: its mask bits (from the lane holding its word) and its
@@ -932,7 +942,7 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
     // access before the wait would wait for the values too: the compiler
     // cannot tell the value loads' LDS destination from the slot table, which
     // is written after.)
-    Group q0;
+    BrowGroup<T, G0, SC> q0;
     if (b1 > b0) {
         const int mlo = (int)(uint32_t)in.m, mhi = (int)(uint32_t)(in.m >> 32);
         int carry = 0;
@@ -960,7 +970,7 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
         const int64_t g = abase + (int64_t)q_tail * E + lane;
         if (g < a.nnz) sm.w.buf[q_tail * E + lane] = vals[g];
     }
-    if (b1 > b0 && SM::NBR > G) {   // the slot table, for the groups after the first
+    if (b1 > b0 && SM::NBR > G0) {   // the slot table, for the groups after the first
 #pragma unroll
         for (int k = 0; k < SM::NSR; ++k) {
             if (64 * k >= hi_slot) break;
@@ -974,9 +984,9 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
         double acc[SM::NBR];
         sums(0, q0, acc);
 #pragma unroll
-        for (int k0 = G; k0 < SM::NBR; k0 += G) {
+        for (int k0 = G0; k0 < SM::NBR; k0 += G) {
             if (64 * k0 >= hi_row) break;
-            Group q;
+            BrowGroup<T, G, SC> q;
             gathers(k0, q, false);
             sums(k0, q, acc);
         }
