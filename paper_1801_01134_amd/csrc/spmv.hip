@@ -837,13 +837,15 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
     // first of their sums (one round with one row per block, else two), and
     // with two rounds a round takes at most SC of its block rows' bits; the
     // rare block rows with more take the rest afterwards, in the same order.
-    // The first group, issued while the values stream in, takes up to G0 = 4
-    // rounds with several rows per block: on the 3-D stencil the registers
-    // the kernels already hold fit them (2, 3, 6 and 8 rounds measured
-    // slower).
+    // The first group, issued while the values stream in, takes up to four
+    // rounds with several rows per block and two with one (of up to C bits
+    // each): on the 3-D stencil the registers the kernels already hold fit
+    // them (2, 3, 6 and 8 rounds measured slower for the former, 1 and 3
+    // for the latter).
     constexpr int G = R == 1 ? 1 : 2;
     constexpr int SC = (G > 1 && C > 4) ? 4 : C;
-    constexpr int G0 = R == 1 ? 1 : (4 < SM::NBR ? 4 : SM::NBR);
+    constexpr int G0W = R == 1 ? 2 : 4;
+    constexpr int G0 = G0W < SM::NBR ? G0W : SM::NBR;
     // pass A's results in registers: round r holds slots 64 r .. 64 r + 63
     uint32_t amk[SM::NSR], afirst[SM::NSR];
     // Issues the gathers of the rounds k0 .. k0 + G - 1: lane = block row, its
