@@ -800,7 +800,7 @@ struct BrowGroup {
     static constexpr int NG = NG_;
     T xg[NG][SC];
     int n[NG];             // steps taken per round (uniform)
-    uint32_t cnt[NG];      // the lane's bits among the first SC
+    uint32_t cnt[NG];      // the bits of the lane's block row
     uint32_t rest[NG];     // bits beyond the first SC
     int colg[NG];
     uint32_t voffg[NG];
@@ -840,15 +840,15 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
     // The first group, issued while the values stream in, takes up to four
     // rounds with several rows per block and two with one (of up to C bits
     // each): on the 3-D stencil the registers the kernels already hold fit
-    // them (2, 3, 6 and 8 rounds measured slower for the former, 1 and 3
-    // for the latter).
+    // them (2, 3, 6 and 8 rounds were no faster for the former, 1 and 3 for
+    // the latter).
     constexpr int G = R == 1 ? 1 : 2;
     constexpr int SC = (G > 1 && C > 4) ? 4 : C;
     constexpr int G0W = R == 1 ? 2 : 4;
     constexpr int G0 = G0W < SM::NBR ? G0W : SM::NBR;
     // pass A's results in registers: round r holds slots 64 r .. 64 r + 63
     uint32_t amk[SM::NSR], afirst[SM::NSR];
-    // Issues the gathers of the rounds k0 .. k0 + G - 1: lane = block row, its
+    // Issues the gathers of the rounds k0 .. k0 + NG - 1: lane = block row, its
     // set bits in turn; lanes out of bits gather nothing (an out of range
     // offset reads 0). The slots of a round share one register of block
     // columns (k / R), and one of pass A's rounds. The first group takes its
@@ -893,7 +893,7 @@ __device__ void brow_run_early(const SpmvArgs &a, const TileDesc &d, TileIn<Sh, 
             q.voffg[g] = voff;
         }
     };
-    // The values of the rounds k0 .. k0 + G - 1 (LDS; the zero for lanes out
+    // The values of the rounds k0 .. k0 + NG - 1 (LDS; the zero for lanes out
     // of bits) and their sums in bit order; block rows with more than SC bits
     // then take the rest.
     auto sums = [&](const int k0, auto &q, double (&acc)[SM::NBR]) {
